@@ -1,0 +1,761 @@
+/*
+ * nlo.c - plain FP64 CPU oracle for the P1 nonlocal stiffness assembly of
+ * D'Elia, Gunzburger, Vollmann, arXiv:2005.10775.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product library.
+ *
+ * What it computes, with the passages it follows:
+ *   - the D-form (Eq. (bform0)) discretised with P1 elements and assembled over
+ *     every ordered element pair (k, k') of Omega u Omega_I, as in Eq.
+ *     (bformhj) with the approximate ball of Sec. 4 in place of the exact one
+ *     (Eqs. (bform3h), (bformjqqh)); the (A-B-C) recipe of Sec. 7.2 is the
+ *     split of the full matrix D into A = D[free,free] and the right-hand side
+ *     b = G - D[free, Dirichlet] g (Eqs. (appr), (intcon), (lfunchj));
+ *   - balls: barycenter (Eq. (baryball)) and the intersection ball of
+ *     Sec. 4.2.1 (inscribed polygon, "nocaps") with caps either replaced by
+ *     triangles over equal arcs (Sec. 4.2.2) or integrated by the one-point
+ *     centroid rule of Sec. 5.2 (the cap weight is the cap area of
+ *     Eq. (areacap); the factor 1/4 printed next to the centroid formula is
+ *     read as 1/2, which is what Eq. (areacap) gives);
+ *   - the geometric tasks 1-6 of Sec. 7.1 (vertex test, edge-circle quadratic,
+ *     counter-clockwise ordering and fan triangulation from the first point);
+ *   - composite inner rules of Eq. (cqr1), outer rule of Sec. 6 (optionally
+ *     switched per pair as in Sec. 8: rule 2 for |b_k - b_k'| < switch_dist).
+ * Every +,-,* is rounded separately (built with -ffp-contract=off), the
+ * barycenter is ((v0+v1)+v2)/3 and an outer point ((l0 v0 + l1 v1) + l2 v2),
+ * so the pair list is reproducible by any IEEE implementation of the same
+ * expressions.
+ *
+ * Parity pins: see tests/test_oracle_pins.py (rule moments, kernel
+ * normalisation, closed-form whole pairs, exact ball area/second moment with
+ * analytic caps, brute-force region moments, matrix invariants, load vector,
+ * the paper's printed L2 errors of Sec. 8).
+ */
+#include "nlo.h"
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NLO_MAXCAP 256
+#define NLO_MAXSUB (4 + 3 * NLO_MAXCAP + 8)
+
+static const double NLO_PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------ mesh */
+static void tri_vertices(const nlo_mesh *m, int k, double V[6])
+{
+    for (int a = 0; a < 3; a++) {
+        int j = m->tri[3 * k + a];
+        V[2 * a] = m->xy[2 * j];
+        V[2 * a + 1] = m->xy[2 * j + 1];
+    }
+}
+
+/* task 1 of Sec. 7.1: the barycenter is the vertex average */
+static void barycenter(const double V[6], double b[2])
+{
+    b[0] = ((V[0] + V[2]) + V[4]) / 3.0;
+    b[1] = ((V[1] + V[3]) + V[5]) / 3.0;
+}
+
+static void map_point(const double V[6], const double lam[3], double x[2])
+{
+    x[0] = (lam[0] * V[0] + lam[1] * V[2]) + lam[2] * V[4];
+    x[1] = (lam[0] * V[1] + lam[1] * V[3]) + lam[2] * V[5];
+}
+
+static double twice_area(const double V[6])
+{
+    return fabs((V[2] - V[0]) * (V[5] - V[1]) - (V[3] - V[1]) * (V[4] - V[0]));
+}
+
+static double max_vertex_dist(const double V[6], const double b[2])
+{
+    double r = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double dx = V[2 * a] - b[0], dy = V[2 * a + 1] - b[1];
+        double d = sqrt(dx * dx + dy * dy);
+        if (d > r) r = d;
+    }
+    return r;
+}
+
+/* P1 basis of element V at point y: barycentric coordinates */
+static void basis_at(const double V[6], const double y[2], double beta[3])
+{
+    double det = (V[2] - V[0]) * (V[5] - V[1]) - (V[3] - V[1]) * (V[4] - V[0]);
+    double b1 = ((y[0] - V[0]) * (V[5] - V[1]) - (y[1] - V[1]) * (V[4] - V[0])) / det;
+    double b2 = ((V[2] - V[0]) * (y[1] - V[1]) - (V[3] - V[1]) * (y[0] - V[0])) / det;
+    beta[0] = 1.0 - b1 - b2;
+    beta[1] = b1;
+    beta[2] = b2;
+}
+
+/* ------------------------------------------------------------ kernel psi */
+static double kernel_psi(const nlo_problem *p, const double x[2], const double y[2])
+{
+    if (p->kernel == 0) return p->kc;
+    double dx = x[0] - y[0], dy = x[1] - y[1];
+    double r = sqrt(dx * dx + dy * dy);
+    return p->kc * pow(r, -(2.0 + 2.0 * p->ks));
+}
+
+/* ------------------------------------------------------ ball predicates */
+/* barycenter ball, Eq. (baryball): E_k' belongs to B(x) iff |x - b_k'| <= delta */
+static int bary_in(const double x[2], const double b[2], double dd)
+{
+    double dx = x[0] - b[0], dy = x[1] - b[1];
+    return dx * dx + dy * dy <= dd;
+}
+
+/* closed ball B_delta(x) meets the triangle V (tasks 2-4 of Sec. 7.1):
+ * a vertex within delta, or x inside the triangle, or an edge whose interior
+ * comes within delta (projection strictly inside the edge, squared distance
+ * c^2/L <= delta^2 written without division). */
+static int ball_meets_triangle(const double x[2], const double V[6], double dd)
+{
+    for (int a = 0; a < 3; a++) {
+        double dx = V[2 * a] - x[0], dy = V[2 * a + 1] - x[1];
+        if (dx * dx + dy * dy <= dd) return 1;
+    }
+    int inside = 1;
+    for (int a = 0; a < 3; a++) {
+        int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = x[0] - V[2 * a], py = x[1] - V[2 * a + 1];
+        double o = ex * py - ey * px;
+        if (o < 0.0) inside = 0;
+    }
+    if (inside) return 1;
+    for (int a = 0; a < 3; a++) {
+        int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = x[0] - V[2 * a], py = x[1] - V[2 * a + 1];
+        double t = ex * px + ey * py;
+        double L = ex * ex + ey * ey;
+        if (t > 0.0 && t < L) {
+            double c = ex * py - ey * px;
+            if (c * c <= dd * L) return 1;
+        }
+    }
+    return 0;
+}
+
+/* which outer rule a pair uses (Sec. 8 switch; one rule when n_out2 == 0) */
+static void pair_rule(const nlo_problem *p, const double bk[2], const double bkp[2],
+                      int *nq, const double **lam, const double **w)
+{
+    *nq = p->n_out;
+    *lam = p->out_lam;
+    *w = p->out_w;
+    if (p->n_out2 > 0) {
+        double dx = bk[0] - bkp[0], dy = bk[1] - bkp[1];
+        if (dx * dx + dy * dy < p->switch_dist * p->switch_dist) {
+            *nq = p->n_out2;
+            *lam = p->out2_lam;
+            *w = p->out2_w;
+        }
+    }
+}
+
+static int pair_interacts(const nlo_problem *p, const double Vk[6], const double bk[2],
+                          const double Vkp[6], const double bkp[2])
+{
+    double dd = p->delta * p->delta;
+    int nq;
+    const double *lam, *w;
+    pair_rule(p, bk, bkp, &nq, &lam, &w);
+    for (int q = 0; q < nq; q++) {
+        double x[2];
+        map_point(Vk, lam + 3 * q, x);
+        if (p->ball == 0) {
+            if (bary_in(x, bkp, dd)) return 1;
+        } else {
+            if (ball_meets_triangle(x, Vkp, dd)) return 1;
+        }
+    }
+    return 0;
+}
+
+/* cheap conservative reject: a point of E_k' within delta of a point of E_k
+ * needs |b_k - b_k'| <= delta + r_k + r_k' (barycenter ball: delta + r_k). */
+static int maybe_pair(const nlo_problem *p, const double bk[2], double rk,
+                      const double bkp[2], double rkp)
+{
+    double reach = p->delta + rk + (p->ball == 0 ? 0.0 : rkp);
+    reach = reach * (1.0 + 1e-9) + 1e-14;
+    double dx = bk[0] - bkp[0], dy = bk[1] - bkp[1];
+    return dx * dx + dy * dy <= reach * reach;
+}
+
+/* ------------------------------------------------ intersection ball region */
+typedef struct { double x, y; int type; } rpoint;   /* type 0 vertex, 1 entry, 2 exit */
+
+/* tasks 3-6 of Sec. 7.1: walk the edges v0->v1->v2->v0, keep vertices inside
+ * the closed ball, and the roots lambda in (0,1) of |v_i + lambda e - x|^2 =
+ * delta^2 in increasing order (smaller root = entry, larger = exit). */
+static int build_polygon(const double x[2], const double V[6], double dd, rpoint *P)
+{
+    int n = 0;
+    for (int a = 0; a < 3; a++) {
+        int b = (a + 1) % 3;
+        double px = V[2 * a] - x[0], py = V[2 * a + 1] - x[1];
+        if (px * px + py * py <= dd) {
+            P[n].x = V[2 * a];
+            P[n].y = V[2 * a + 1];
+            P[n].type = 0;
+            n++;
+        }
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double L = ex * ex + ey * ey;
+        double B = ex * px + ey * py;
+        double C = (px * px + py * py) - dd;
+        double disc = B * B - L * C;
+        if (disc > 0.0) {
+            double s = sqrt(disc);
+            double l1 = (-B - s) / L, l2 = (-B + s) / L;
+            if (l1 > 0.0 && l1 < 1.0) {
+                P[n].x = V[2 * a] + l1 * ex;
+                P[n].y = V[2 * a + 1] + l1 * ey;
+                P[n].type = 1;
+                n++;
+            }
+            if (l2 > 0.0 && l2 < 1.0) {
+                P[n].x = V[2 * a] + l2 * ex;
+                P[n].y = V[2 * a + 1] + l2 * ey;
+                P[n].type = 2;
+                n++;
+            }
+        }
+    }
+    return n;
+}
+
+static void put_tri(double *sub, int *ns, double ax, double ay, double bx, double by,
+                    double cx, double cy)
+{
+    double *t = sub + 6 * (*ns);
+    t[0] = ax; t[1] = ay; t[2] = bx; t[3] = by; t[4] = cx; t[5] = cy;
+    (*ns)++;
+}
+
+/* The region E_k' n B_{delta,h}(x) of the intersection ball as a list of
+ * triangles (polygon fan + cap triangles) and, for exact caps, a list of
+ * one-point cap rules (point, weight).  Returns the number of triangles, or
+ * -1 when the ball lies inside the triangle without reaching any edge. */
+int nlo_region(const nlo_problem *p, const double x[2], const double V[6],
+               double *sub, int32_t cap, double *cap_pts, double *cap_w, int32_t *n_cap)
+{
+    double dd = p->delta * p->delta;
+    rpoint P[12];
+    int n = build_polygon(x, V, dd, P);
+    int ns = 0;
+    *n_cap = 0;
+    if (n == 0) {
+        /* no vertex inside and no crossing: empty, unless x is inside E (ball inside triangle) */
+        int inside = 1;
+        for (int a = 0; a < 3; a++) {
+            int b = (a + 1) % 3;
+            double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+            double o = ex * (x[1] - V[2 * a + 1]) - ey * (x[0] - V[2 * a]);
+            if (o < 0.0) inside = 0;
+        }
+        return inside ? -1 : 0;
+    }
+    for (int i = 1; i + 1 < n; i++) {
+        if (ns >= cap) return -2;
+        put_tri(sub, &ns, P[0].x, P[0].y, P[i].x, P[i].y, P[i + 1].x, P[i + 1].y);
+    }
+    for (int i = 0; i < n; i++) {
+        const rpoint *X = &P[i], *N = &P[(i + 1) % n];
+        if (X->type != 2 || N->type != 1) continue;
+        double tx = atan2(X->y - x[1], X->x - x[0]);
+        double tn = atan2(N->y - x[1], N->x - x[0]);
+        double D = tn - tx;
+        if (D < 0.0) D += 2.0 * NLO_PI;             /* counter-clockwise span from X to N */
+        /* a cap inside a triangle of diameter <= delta spans less than pi; a
+         * larger span only arises from rounding when X and N coincide */
+        if (!(D > 0.0) || D > NLO_PI) continue;
+        if (p->cap_mode == 1) {
+            double th = 0.5 * D;
+            double seg = 2.0 * th - sin(2.0 * th);
+            if (th < 1e-2) {                        /* series of 2t - sin 2t, cancellation-free */
+                double u = 2.0 * th, u2 = u * u;
+                seg = u * u2 / 6.0 * (1.0 - u2 / 20.0 * (1.0 - u2 / 42.0 * (1.0 - u2 / 72.0)));
+            }
+            if (!(seg > 0.0)) continue;
+            double s3 = sin(th);
+            double dist = 4.0 * p->delta * s3 * s3 * s3 / (3.0 * seg);
+            double ang = tx + th;
+            cap_pts[2 * (*n_cap)] = x[0] + dist * cos(ang);
+            cap_pts[2 * (*n_cap) + 1] = x[1] + dist * sin(ang);
+            cap_w[*n_cap] = 0.5 * dd * seg;
+            (*n_cap)++;
+        } else if (p->cap_edges >= 2) {
+            double mx = 0.5 * (X->x + N->x), my = 0.5 * (X->y + N->y);
+            double px = X->x, py = X->y;
+            for (int j = 1; j <= p->cap_edges; j++) {
+                double cx, cy;
+                if (j == p->cap_edges) {
+                    cx = N->x;
+                    cy = N->y;
+                } else {
+                    double ang = tx + D * (double)j / (double)p->cap_edges;
+                    cx = x[0] + p->delta * cos(ang);
+                    cy = x[1] + p->delta * sin(ang);
+                }
+                if (ns >= cap) return -2;
+                put_tri(sub, &ns, mx, my, px, py, cx, cy);
+                px = cx;
+                py = cy;
+            }
+        }
+    }
+    return ns;
+}
+
+/* composite inner rule (Eq. (cqr1)) of psi, psi*beta_b, psi*beta_b*beta_b'
+ * over the region of (x, E_k').  Returns 0, or a negative status. */
+int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
+                   double s0[1], double s1[3], double s2[9])
+{
+    static const double whole_lam[3] = {0, 0, 0};
+    (void)whole_lam;
+    s0[0] = 0.0;
+    for (int b = 0; b < 3; b++) s1[b] = 0.0;
+    for (int b = 0; b < 9; b++) s2[b] = 0.0;
+    double dd = p->delta * p->delta;
+    double sub[6 * NLO_MAXSUB];
+    double cpt[2 * 8], cw[8];
+    int ns = 0, nc = 0;
+    if (p->ball == 0) {
+        double b[2];
+        barycenter(V, b);
+        if (!bary_in(x, b, dd)) return 0;
+        memcpy(sub, V, 6 * sizeof(double));
+        ns = 1;
+    } else {
+        ns = nlo_region(p, x, V, sub, NLO_MAXSUB, cpt, cw, &nc);
+        if (ns < 0) return ns;
+    }
+    for (int t = 0; t < ns; t++) {
+        const double *T = sub + 6 * t;
+        double a2 = twice_area(T);
+        for (int q = 0; q < p->n_in; q++) {
+            double y[2], beta[3];
+            map_point(T, p->in_lam + 3 * q, y);
+            double wq = p->in_w[q] * a2 * kernel_psi(p, x, y);
+            basis_at(V, y, beta);
+            s0[0] += wq;
+            for (int b = 0; b < 3; b++) {
+                s1[b] += wq * beta[b];
+                for (int c = 0; c < 3; c++) s2[3 * b + c] += wq * beta[b] * beta[c];
+            }
+        }
+    }
+    for (int c = 0; c < nc; c++) {
+        double y[2] = {cpt[2 * c], cpt[2 * c + 1]}, beta[3];
+        double wq = cw[c] * kernel_psi(p, x, y);
+        basis_at(V, y, beta);
+        s0[0] += wq;
+        for (int b = 0; b < 3; b++) {
+            s1[b] += wq * beta[b];
+            for (int e = 0; e < 3; e++) s2[3 * b + e] += wq * beta[b] * beta[e];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------ near-diagonal pairs */
+static int shares_vertex(const nlo_mesh *m, int k, int kp)
+{
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            if (m->tri[3 * k + a] == m->tri[3 * kp + b]) return 1;
+    return 0;
+}
+
+int nlo_duffy_block(const nlo_mesh *m, const nlo_problem *p, int k, int kp, double blk[36]);
+
+/* ------------------------------------------------ local pair block */
+/* The 6x6 local block of pair (k, k') in slot order (a0,a1,a2,b0,b1,b2):
+ *   [[Mxx, -Mxy], [-Mxy^T, Myy]],
+ *   Mxx_aa' = sum_q W_q alpha_a alpha_a' S0_q,  Mxy_ab = sum_q W_q alpha_a S1_qb,
+ *   Myy_bb' = sum_q W_q S2_qbb',  W_q = 2|E_k| w_q, alpha = outer barycentrics;
+ * the expansion of (phi_j(x)-phi_j(y))(phi_j'(x)-phi_j'(y)) of Eq. (bformhj)
+ * over the nodes of E_k (x) and E_k' (y).  D[g(i), g(j)] += blk[i][j]. */
+int nlo_pair_block(const nlo_mesh *m, const nlo_problem *p, int32_t k, int32_t kp,
+                   double mxy[9], double myy[9], double s0q[64], double blk[36])
+{
+    double Vk[6], Vkp[6], bk[2], bkp[2];
+    tri_vertices(m, k, Vk);
+    tri_vertices(m, kp, Vkp);
+    barycenter(Vk, bk);
+    barycenter(Vkp, bkp);
+    for (int i = 0; i < 9; i++) { mxy[i] = 0.0; myy[i] = 0.0; }
+    for (int i = 0; i < 36; i++) blk[i] = 0.0;
+    if (p->kernel == 1 && shares_vertex(m, k, kp)) return nlo_duffy_block(m, p, k, kp, blk);
+    int nq;
+    const double *lam, *w;
+    pair_rule(p, bk, bkp, &nq, &lam, &w);
+    double ak2 = twice_area(Vk);
+    double mxx[9] = {0};
+    for (int q = 0; q < nq; q++) {
+        double x[2], S0, S1[3], S2[9];
+        map_point(Vk, lam + 3 * q, x);
+        int st = nlo_inner_sums(p, x, Vkp, &S0, S1, S2);
+        if (st < 0) return st;
+        double Wq = w[q] * ak2;
+        const double *al = lam + 3 * q;
+        if (q < 64) s0q[q] = S0;
+        for (int a = 0; a < 3; a++) {
+            for (int c = 0; c < 3; c++) mxx[3 * a + c] += Wq * al[a] * al[c] * S0;
+            for (int b = 0; b < 3; b++) mxy[3 * a + b] += Wq * al[a] * S1[b];
+        }
+        for (int i = 0; i < 9; i++) myy[i] += Wq * S2[i];
+    }
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++) {
+            blk[6 * a + c] = mxx[3 * a + c];
+            blk[6 * a + 3 + c] = -mxy[3 * a + c];
+            blk[6 * (3 + c) + a] = -mxy[3 * a + c];
+            blk[6 * (3 + a) + 3 + c] = myy[3 * a + c];
+        }
+    return 0;
+}
+
+/* ------------------------------------------------ pair lists */
+typedef struct { double *b; double *r; double *V; } elemdata;
+
+static elemdata elem_precompute(const nlo_mesh *m)
+{
+    elemdata e;
+    e.b = (double *)malloc(sizeof(double) * 2 * m->nt);
+    e.r = (double *)malloc(sizeof(double) * m->nt);
+    e.V = (double *)malloc(sizeof(double) * 6 * m->nt);
+    for (int k = 0; k < m->nt; k++) {
+        tri_vertices(m, k, e.V + 6 * k);
+        barycenter(e.V + 6 * k, e.b + 2 * k);
+        e.r[k] = max_vertex_dist(e.V + 6 * k, e.b + 2 * k);
+    }
+    return e;
+}
+
+static void elem_free(elemdata *e) { free(e->b); free(e->r); free(e->V); }
+
+static int pairs_of(const nlo_mesh *m, const nlo_problem *p, const elemdata *e, int k,
+                    int32_t *kp, int32_t cap)
+{
+    int n = 0;
+    for (int j = 0; j < m->nt; j++) {
+        if (p->skip_ixi && !m->tri_in_omega[k] && !m->tri_in_omega[j]) continue;
+        if (!maybe_pair(p, e->b + 2 * k, e->r[k], e->b + 2 * j, e->r[j])) continue;
+        if (!pair_interacts(p, e->V + 6 * k, e->b + 2 * k, e->V + 6 * j, e->b + 2 * j)) continue;
+        if (n < cap) kp[n] = j;
+        n++;
+    }
+    return n;
+}
+
+/* all k' interacting with outer element k, ascending (task 2 of Sec. 7.1 done
+ * as an all-elements loop) */
+int nlo_pairs_of(const nlo_mesh *m, const nlo_problem *p, int32_t k, int32_t *kp, int32_t cap)
+{
+    elemdata e = elem_precompute(m);
+    int n = pairs_of(m, p, &e, k, kp, cap);
+    elem_free(&e);
+    return n;
+}
+
+/* ------------------------------------------------ assembly */
+struct nlo_result {
+    int64_t n_pairs, nnz;
+    int32_t status, nv, nt;
+    int64_t *pair_ptr;
+    int32_t *pair_kp;
+    int64_t *rowptr;
+    int32_t *col;
+    double *val;
+};
+
+static int64_t find_col(const int64_t *rowptr, const int32_t *col, int r, int c)
+{
+    int64_t lo = rowptr[r], hi = rowptr[r + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (col[mid] == c) return mid;
+        if (col[mid] < c) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+/* Neumaier's compensated summation step */
+static void neumaier_add(double *s, double *c, double v)
+{
+    double t = *s + v;
+    if (fabs(*s) >= fabs(v)) *c += (*s - t) + v;
+    else *c += (v - t) + *s;
+    *s = t;
+}
+
+nlo_result *nlo_assemble(const nlo_mesh *m, const nlo_problem *p, int32_t nthreads)
+{
+    nlo_result *r = (nlo_result *)calloc(1, sizeof(nlo_result));
+    r->nv = m->nv;
+    r->nt = m->nt;
+    int K = m->nt, J = m->nv;
+    elemdata e = elem_precompute(m);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    /* pass 1: pair counts, then the canonical (k asc, k' asc) list */
+    int32_t *cnt = (int32_t *)calloc(K, sizeof(int32_t));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < K; k++) cnt[k] = pairs_of(m, p, &e, k, NULL, 0);
+    r->pair_ptr = (int64_t *)malloc(sizeof(int64_t) * (K + 1));
+    r->pair_ptr[0] = 0;
+    for (int k = 0; k < K; k++) r->pair_ptr[k + 1] = r->pair_ptr[k] + cnt[k];
+    r->n_pairs = r->pair_ptr[K];
+    r->pair_kp = (int32_t *)malloc(sizeof(int32_t) * (r->n_pairs > 0 ? r->n_pairs : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < K; k++) pairs_of(m, p, &e, k, r->pair_kp + r->pair_ptr[k], cnt[k]);
+    free(cnt);
+    /* pattern: every node pair of E_k x E_k' in both orders (a dense bitmap of
+     * the J x J index set, then CSR) */
+    int64_t words = ((int64_t)J * J + 63) / 64;
+    uint64_t *bits = (uint64_t *)calloc(words, sizeof(uint64_t));
+    for (int k = 0; k < K; k++)
+        for (int64_t t = r->pair_ptr[k]; t < r->pair_ptr[k + 1]; t++) {
+            int kp = r->pair_kp[t];
+            int g[6];
+            for (int a = 0; a < 3; a++) { g[a] = m->tri[3 * k + a]; g[3 + a] = m->tri[3 * kp + a]; }
+            for (int i = 0; i < 6; i++)
+                for (int j = 0; j < 6; j++) {
+                    int64_t bit = (int64_t)g[i] * J + g[j];
+                    bits[bit >> 6] |= (uint64_t)1 << (bit & 63);
+                }
+        }
+    r->rowptr = (int64_t *)calloc(J + 1, sizeof(int64_t));
+    int64_t nnz = 0;
+    for (int i = 0; i < J; i++) {
+        for (int j = 0; j < J; j++) {
+            int64_t bit = (int64_t)i * J + j;
+            if (bits[bit >> 6] >> (bit & 63) & 1) nnz++;
+        }
+        r->rowptr[i + 1] = nnz;
+    }
+    r->nnz = nnz;
+    r->col = (int32_t *)malloc(sizeof(int32_t) * (nnz > 0 ? nnz : 1));
+    nnz = 0;
+    for (int i = 0; i < J; i++)
+        for (int j = 0; j < J; j++) {
+            int64_t bit = (int64_t)i * J + j;
+            if (bits[bit >> 6] >> (bit & 63) & 1) r->col[nnz++] = j;
+        }
+    free(bits);
+    /* values: blocks computed in parallel chunks of outer elements, then added
+     * serially in (k, k', i, j) order with Neumaier compensation */
+    double *sum = (double *)calloc(nnz > 0 ? nnz : 1, sizeof(double));
+    double *cmp = (double *)calloc(nnz > 0 ? nnz : 1, sizeof(double));
+    const int CH = 256;
+    int status = 0;
+    for (int k0 = 0; k0 < K; k0 += CH) {
+        int k1 = k0 + CH < K ? k0 + CH : K;
+        int64_t base = r->pair_ptr[k0], np = r->pair_ptr[k1] - base;
+        double *blks = (double *)malloc(sizeof(double) * 36 * (np > 0 ? np : 1));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int k = k0; k < k1; k++)
+            for (int64_t t = r->pair_ptr[k]; t < r->pair_ptr[k + 1]; t++) {
+                double mxy[9], myy[9], s0q[64];
+                int st = nlo_pair_block(m, p, k, r->pair_kp[t], mxy, myy, s0q, blks + 36 * (t - base));
+                if (st < 0) {
+#pragma omp critical
+                    status = st;
+                }
+            }
+        for (int k = k0; k < k1; k++)
+            for (int64_t t = r->pair_ptr[k]; t < r->pair_ptr[k + 1]; t++) {
+                int kp = r->pair_kp[t];
+                int g[6];
+                for (int a = 0; a < 3; a++) { g[a] = m->tri[3 * k + a]; g[3 + a] = m->tri[3 * kp + a]; }
+                const double *B = blks + 36 * (t - base);
+                for (int i = 0; i < 6; i++)
+                    for (int j = 0; j < 6; j++) {
+                        int64_t at = find_col(r->rowptr, r->col, g[i], g[j]);
+                        neumaier_add(&sum[at], &cmp[at], B[6 * i + j]);
+                    }
+            }
+        free(blks);
+    }
+    r->val = (double *)malloc(sizeof(double) * (nnz > 0 ? nnz : 1));
+    for (int64_t i = 0; i < nnz; i++) r->val[i] = sum[i] + cmp[i];
+    free(sum);
+    free(cmp);
+    elem_free(&e);
+    r->status = status;
+    return r;
+}
+
+void nlo_result_sizes(const nlo_result *r, int64_t *n_pairs, int64_t *nnz, int32_t *status)
+{
+    *n_pairs = r->n_pairs;
+    *nnz = r->nnz;
+    *status = r->status;
+}
+
+void nlo_result_copy(const nlo_result *r, int64_t *pair_ptr, int32_t *pair_kp,
+                     int64_t *rowptr, int32_t *col, double *val)
+{
+    if (pair_ptr) memcpy(pair_ptr, r->pair_ptr, sizeof(int64_t) * (r->nt + 1));
+    if (pair_kp) memcpy(pair_kp, r->pair_kp, sizeof(int32_t) * r->n_pairs);
+    if (rowptr) memcpy(rowptr, r->rowptr, sizeof(int64_t) * (r->nv + 1));
+    if (col) memcpy(col, r->col, sizeof(int32_t) * r->nnz);
+    if (val) memcpy(val, r->val, sizeof(double) * r->nnz);
+}
+
+void nlo_result_free(nlo_result *r)
+{
+    if (!r) return;
+    free(r->pair_ptr); free(r->pair_kp); free(r->rowptr); free(r->col); free(r->val);
+    free(r);
+}
+
+/* one row D[j, :] of the full matrix, from every pair with node j in E_k or
+ * E_k'; columns ascending.  Returns the number of columns or a negative status. */
+int nlo_row(const nlo_mesh *m, const nlo_problem *p, int32_t j, int32_t *cols, double *vals,
+            int32_t cap)
+{
+    int K = m->nt, J = m->nv;
+    elemdata e = elem_precompute(m);
+    double *sum = (double *)calloc(J, sizeof(double));
+    double *cmp = (double *)calloc(J, sizeof(double));
+    uint8_t *hit = (uint8_t *)calloc(J, 1);
+    int32_t *kp = (int32_t *)malloc(sizeof(int32_t) * K);
+    int status = 0;
+    for (int k = 0; k < K && status == 0; k++) {
+        int kin = 0;
+        for (int a = 0; a < 3; a++) kin |= m->tri[3 * k + a] == j;
+        if (!kin) {
+            /* pairs (k, k') with j a node of E_k' only */
+            for (int kk = 0; kk < K; kk++) {
+                int jin = 0;
+                for (int a = 0; a < 3; a++) jin |= m->tri[3 * kk + a] == j;
+                if (!jin) continue;
+                if (p->skip_ixi && !m->tri_in_omega[k] && !m->tri_in_omega[kk]) continue;
+                if (!maybe_pair(p, e.b + 2 * k, e.r[k], e.b + 2 * kk, e.r[kk])) continue;
+                if (!pair_interacts(p, e.V + 6 * k, e.b + 2 * k, e.V + 6 * kk, e.b + 2 * kk)) continue;
+                double mxy[9], myy[9], s0q[64], B[36];
+                int st = nlo_pair_block(m, p, k, kk, mxy, myy, s0q, B);
+                if (st < 0) { status = st; break; }
+                int g[6];
+                for (int a = 0; a < 3; a++) { g[a] = m->tri[3 * k + a]; g[3 + a] = m->tri[3 * kk + a]; }
+                for (int i = 3; i < 6; i++) {
+                    if (g[i] != j) continue;
+                    for (int c = 0; c < 6; c++) { neumaier_add(&sum[g[c]], &cmp[g[c]], B[6 * i + c]); hit[g[c]] = 1; }
+                }
+            }
+            continue;
+        }
+        int n = pairs_of(m, p, &e, k, kp, K);
+        for (int t = 0; t < n; t++) {
+            double mxy[9], myy[9], s0q[64], B[36];
+            int st = nlo_pair_block(m, p, k, kp[t], mxy, myy, s0q, B);
+            if (st < 0) { status = st; break; }
+            int g[6];
+            for (int a = 0; a < 3; a++) { g[a] = m->tri[3 * k + a]; g[3 + a] = m->tri[3 * kp[t] + a]; }
+            for (int i = 0; i < 6; i++) {
+                if (g[i] != j) continue;
+                for (int c = 0; c < 6; c++) { neumaier_add(&sum[g[c]], &cmp[g[c]], B[6 * i + c]); hit[g[c]] = 1; }
+            }
+        }
+    }
+    int nc = 0;
+    for (int c = 0; c < J; c++)
+        if (hit[c]) {
+            if (nc < cap) { cols[nc] = c; vals[nc] = sum[c] + cmp[c]; }
+            nc++;
+        }
+    free(sum); free(cmp); free(hit); free(kp);
+    elem_free(&e);
+    return status < 0 ? status : nc;
+}
+
+/* G_j = sum over elements of Omega of sum_q W_q phi_j(x_q) f(x_q) (Eq. (lfunchj)),
+ * f given at the outer points of the main outer rule, f_outer[k][q]. */
+void nlo_load(const nlo_mesh *m, const nlo_problem *p, const double *f_outer, double *G)
+{
+    for (int j = 0; j < m->nv; j++) G[j] = 0.0;
+    for (int k = 0; k < m->nt; k++) {
+        if (!m->tri_in_omega[k]) continue;
+        double V[6];
+        tri_vertices(m, k, V);
+        double a2 = twice_area(V);
+        for (int q = 0; q < p->n_out; q++) {
+            const double *al = p->out_lam + 3 * q;
+            double Wq = p->out_w[q] * a2;
+            for (int a = 0; a < 3; a++) G[m->tri[3 * k + a]] += Wq * al[a] * f_outer[(int64_t)k * p->n_out + q];
+        }
+    }
+}
+
+void nlo_outer_points(const nlo_mesh *m, const nlo_problem *p, double *xq)
+{
+    for (int k = 0; k < m->nt; k++) {
+        double V[6];
+        tri_vertices(m, k, V);
+        for (int q = 0; q < p->n_out; q++) map_point(V, p->out_lam + 3 * q, xq + 2 * ((int64_t)k * p->n_out + q));
+    }
+}
+
+/* Work census over outer elements [k0, k1): counts of
+ * out[0] pairs, [1] whole items, [2] partial items, [3] empty items,
+ * [4] polygon (fan) triangles, [5] caps, [6] cap triangles, [7] inner points. */
+int64_t nlo_flops_census(const nlo_mesh *m, const nlo_problem *p, int32_t k0, int32_t k1, int64_t out[8])
+{
+    for (int i = 0; i < 8; i++) out[i] = 0;
+    elemdata e = elem_precompute(m);
+    int32_t *kp = (int32_t *)malloc(sizeof(int32_t) * m->nt);
+    double dd = p->delta * p->delta;
+    for (int k = k0; k < k1; k++) {
+        int n = pairs_of(m, p, &e, k, kp, m->nt);
+        out[0] += n;
+        for (int t = 0; t < n; t++) {
+            const double *Vk = e.V + 6 * k, *Vj = e.V + 6 * kp[t];
+            for (int q = 0; q < p->n_out; q++) {
+                double x[2];
+                map_point(Vk, p->out_lam + 3 * q, x);
+                if (p->ball == 0) {
+                    if (bary_in(x, e.b + 2 * kp[t], dd)) { out[1]++; out[4]++; out[7] += p->n_in; }
+                    else out[3]++;
+                    continue;
+                }
+                int nin = 0;
+                for (int a = 0; a < 3; a++) {
+                    double dx = Vj[2 * a] - x[0], dy = Vj[2 * a + 1] - x[1];
+                    nin += dx * dx + dy * dy <= dd;
+                }
+                if (nin == 3) { out[1]++; out[4]++; out[7] += p->n_in; continue; }
+                rpoint P[12];
+                int np_ = build_polygon(x, Vj, dd, P);
+                if (np_ == 0) { out[3]++; continue; }
+                out[2]++;
+                if (np_ >= 3) { out[4] += np_ - 2; out[7] += (int64_t)(np_ - 2) * p->n_in; }
+                for (int i = 0; i < np_; i++)
+                    if (P[i].type == 2 && P[(i + 1) % np_].type == 1) {
+                        out[5]++;
+                        out[6] += p->cap_edges;
+                        out[7] += (int64_t)p->cap_edges * p->n_in;
+                    }
+            }
+        }
+    }
+    free(kp);
+    elem_free(&e);
+    return out[0];
+}
