@@ -1,0 +1,177 @@
+/*
+ * nlasm.h - C ABI of libnlasm.so, the MI355X (gfx950) assembler for the P1
+ * finite element discretisation of the 2D nonlocal diffusion problem of
+ * D'Elia, Gunzburger, Vollmann, "A cookbook for finite element methods for
+ * nonlocal problems, including quadrature rules and approximate Euclidean
+ * balls" (arXiv:2005.10775).
+ *
+ * Problem (Sec. 2.1, Eqs. (prob), (oper), (inter)): -L u = f on Omega,
+ * u = g on the interaction layer Omega_I, with
+ *     L u(x) = 2 int (u(y) - u(x)) gamma(x,y) dy,
+ *     gamma(x,y) = psi(x,y) chi_{B_delta(x)}(y).
+ * The library assembles the full matrix D of the D-form (Eq. (bform0)) over
+ * every ordered pair of elements (k, k') of Omega u Omega_I (Eq. (bformhj)),
+ * with the Euclidean ball replaced by an approximate ball B_{delta,h}(x)
+ * (Sec. 4: the barycenter ball of Eq. (baryball), or the retriangulated
+ * intersection ball of Secs. 4.2.1-4.2.2 with caps filled by triangles over
+ * equal arcs) and both integrals replaced by quadrature (Eqs. (cqr1),
+ * (bformjqqh)).  The stiffness matrix is A = D[free, free] and the load
+ * vector b = G - D[free, Dirichlet] g, with g interpolated at the nodes of
+ * Omega_I (Eqs. (appr), (intcon), (lfunchj); the (A-B-C) recipe of Sec. 7.2).
+ *
+ * Conventions for every call:
+ *  - Status: 0 (NLA_OK) or a negative NLA_E_* code; nla_last_error() returns
+ *    a message for the calling thread's last failure.  No C++ exception
+ *    crosses this boundary.
+ *  - Memory: arguments documented "host" are read during the call only and
+ *    may be freed afterwards (create calls copy them).  Arguments documented
+ *    "device" are caller-owned device allocations on the plan's GPU.  Views
+ *    returned by *_view calls are owned by the plan and stay valid until the
+ *    next nla_assemble on that plan or nla_plan_destroy.
+ *  - Streams: every call that touches the GPU is ordered on the HIP stream
+ *    passed in (hipStream_t cast to void*; NULL = default stream).  A plan
+ *    must not be used from two threads at once.
+ *  - Determinism: pair lists and CSR patterns are bitwise reproducible, and
+ *    all reductions run in a fixed order, so repeated calls give bitwise
+ *    identical values; D is bitwise symmetric.
+ *  - Validation: all mesh and problem checks run on the host before any GPU
+ *    work, so invalid input is reported without touching the device.
+ */
+#ifndef NLASM_H
+#define NLASM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NLA_OK = 0,
+    NLA_E_INVALID = -1,        /* bad argument (null pointer, out-of-range value) */
+    NLA_E_MESH = -2,           /* mesh violates the rules of Sec. 3.1 (orientation, labels, indices) */
+    NLA_E_NOMEM = -3,          /* device allocation failed or exceeds NLA_MAX_DEVICE_BYTES */
+    NLA_E_DEVICE = -4,         /* a HIP runtime call failed */
+    NLA_E_UNSUPPORTED = -5,    /* valid but outside what the kernels handle (see each field) */
+    NLA_E_NOT_CONVERGED = -6,  /* CG reached maxit before rtol */
+    NLA_E_STATE = -7           /* call out of order (e.g. a view before nla_assemble) */
+};
+
+enum { NLA_KERNEL_CONSTANT = 0, NLA_KERNEL_FRACTIONAL = 1 };
+enum { NLA_BALL_BARYCENTER = 0, NLA_BALL_RETRI = 1 };
+enum { NLA_FP64 = 0, NLA_FP32 = 1, NLA_FP32_LEARNED = 2 };
+enum { NLA_DTYPE_F64 = 0, NLA_DTYPE_F32 = 1 };
+enum { NLA_SKIP_IXI = 1u };     /* flags: drop Omega_I x Omega_I pairs (A and b unchanged) */
+
+/* Mesh of Omega u Omega_I (Sec. 3.1): matching triangulations of the two
+ * parts, all host arrays. */
+typedef struct {
+    int32_t n_vertices;          /* J */
+    int32_t n_triangles;         /* K */
+    const double *xy;            /* [J][2] vertex coordinates */
+    const int32_t *tri;          /* [K][3] vertex indices, counter-clockwise */
+    const uint8_t *tri_in_omega; /* [K] 1 = element of Omega, 0 = element of Omega_I */
+    const uint8_t *node_free;    /* [J] 1 = node in the open Omega, 0 = node of Omega_I
+                                    (boundary nodes of Omega count as Omega_I, Sec. 3.1) */
+} nla_mesh;
+
+/* Triangle quadrature rule in barycentric form (host arrays).  Weights sum
+ * to 1/2, the area of the reference triangle (as in Sec. 6's 7-point rule). */
+typedef struct {
+    int32_t n;                   /* points, 1..16 for outer rules, 1..32 for inner rules */
+    const double *lambda;        /* [n][3] barycentric coordinates */
+    const double *w;             /* [n] weights */
+} nla_rule;
+
+typedef struct {
+    double delta;                /* horizon, > 0 */
+    int32_t kernel;              /* NLA_KERNEL_CONSTANT: psi = kernel_c;
+                                    NLA_KERNEL_FRACTIONAL: psi = kernel_c |x-y|^-(2+2 kernel_s)
+                                    (truncated to the approximate ball) */
+    double kernel_c, kernel_s;
+    nla_rule outer;              /* outer rule on every E_k (Sec. 6) */
+    nla_rule inner;              /* inner rule on every subtriangle (Sec. 5.3) */
+    int32_t duffy_n;             /* fractional kernel: Gauss-Legendre order on [0,1] for
+                                    element pairs sharing a vertex (0 = not used) */
+    const double *duffy_x;       /* [duffy_n] host, nodes on [0,1] */
+    const double *duffy_w;       /* [duffy_n] host, weights summing to 1 */
+    int32_t ball;                /* NLA_BALL_BARYCENTER | NLA_BALL_RETRI */
+    int32_t cap_edges;           /* retri: equal arcs per cap, 0 (= inscribed polygon) or 2..64 */
+    int32_t precision;           /* NLA_FP64 | NLA_FP32 (compensated) | NLA_FP32_LEARNED */
+    const void *mlp;             /* NLA_FP32_LEARNED: an nla_mlp* ; else NULL */
+    double fallback_band;        /* learned caps: exact path when min_a | |v_a - x| - delta | <
+                                    fallback_band * delta */
+    uint32_t flags;              /* NLA_SKIP_IXI */
+} nla_problem;
+
+typedef struct nla_plan nla_plan;
+
+typedef struct {
+    int64_t n_pairs;             /* interacting ordered element pairs */
+    int64_t nnz_full;            /* nonzeros of D (J x J) */
+    int64_t nnz_free;            /* nonzeros of A = D[free, free] */
+    int32_t n_free;              /* J_Omega */
+    int32_t n_outer;             /* outer points per element */
+    int64_t n_codes;             /* contributions summed by the segmented sum */
+    int64_t n_near;              /* vertex-sharing pairs handled by the singular rule */
+    int64_t items[4];            /* after nla_assemble: (k,q,k') items whole, partial, empty, learned */
+    int64_t subtriangles;        /* after nla_assemble: polygon + cap triangles integrated */
+} nla_info;
+
+const char *nla_last_error(void);
+
+/* Builds the plan: element data, the canonical pair list (k ascending, k'
+ * ascending within k) of pairs with at least one outer point x_{k,q} whose
+ * approximate ball reaches E_k' (Sec. 7.1 tasks 1-4; barycenter ball:
+ * |x - b_k'| <= delta; retri: the closed ball meets E_k'), and the CSR
+ * pattern of D.  Retri needs every element diameter <= delta
+ * (NLA_E_UNSUPPORTED otherwise: a ball inside a triangle is not retriangulated).
+ * *out receives a new plan; destroy it with nla_plan_destroy. */
+int nla_plan_create(const nla_mesh *mesh, const nla_problem *prob, void *stream, nla_plan **out);
+int nla_plan_info(const nla_plan *plan, nla_info *info);
+
+/* Device views of the pair list: pair_ptr [K+1] (int64), pair_kp [n_pairs] (int32). */
+int nla_pairs_view(const nla_plan *plan, const int64_t **pair_ptr, const int32_t **pair_kp);
+
+/* Writes the outer quadrature points x_{k,q} = l0 v0 + l1 v1 + l2 v2 to
+ * xq [K][n_outer][2] (device, f64), so a caller can sample f there. */
+int nla_outer_points(const nla_plan *plan, double *xq, void *stream);
+
+/* Numeric assembly: D (CSR), A = D[free,free] and b = G - D[free,Dir] g.
+ * f_outer [K][n_outer] device f64: f at the outer points (rows of Omega_I
+ * elements are ignored).  g_node [J] device f64: g at the nodes (read at
+ * Omega_I nodes).  Either may be NULL to skip the load vector. */
+int nla_assemble(nla_plan *plan, const double *f_outer, const double *g_node, void *stream);
+
+/* which = 0: full D (J x J); which = 1: A (n_free x n_free, rows/cols in
+ * increasing node order of the free nodes).  val_dtype = NLA_DTYPE_F64 or
+ * NLA_DTYPE_F32 (FP32 modes).  All pointers are device views. */
+int nla_csr_view(const nla_plan *plan, int32_t which, const int64_t **rowptr, const int32_t **col,
+                 const void **val, int32_t *val_dtype);
+
+/* b [n_free] (device f64) after nla_assemble with f_outer and g_node. */
+int nla_load_view(const nla_plan *plan, const double **b);
+
+/* Free-node indices [n_free] (device int32, increasing). */
+int nla_free_nodes_view(const nla_plan *plan, const int32_t **free_nodes);
+
+/* Per-pair local blocks (test hook): mxy [n_pairs][9] holds -Mxy_ab (row-major a,b),
+ * myy [n_pairs][6] holds Myy (b<=b': 00,01,02,11,12,22), mxx [K][6] holds the
+ * element block Mxx (same order).  Entries of vertex-sharing pairs under the
+ * singular rule are in near [n_near][21] (upper triangle of the 6x6 slot block,
+ * row-major) with their pair indices in near_pair [n_near].  dtype as in nla_csr_view. */
+int nla_blocks_view(const nla_plan *plan, const void **mxy, const void **myy, const void **mxx,
+                    const void **near, const int64_t **near_pair, int32_t *dtype);
+
+/* Conjugate gradients on A (after nla_assemble): b [n_free] device, u [n_free]
+ * device (in: x0, out: solution), FP64 residuals and fixed-order dot
+ * products.  Returns NLA_E_NOT_CONVERGED (with u holding the last iterate)
+ * if ||r|| > rtol ||b|| after maxit iterations. */
+int nla_cg(const nla_plan *plan, const double *b, double *u, double rtol, int32_t maxit,
+           int32_t *iters, double *relres, void *stream);
+
+void nla_plan_destroy(nla_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,249 @@
+"""ctypes binding of libnlasm.so (argument marshalling only).
+
+Every step of the assembly runs in the library's HIP kernels; PyTorch only
+provides device memory and the current HIP stream.  Importing this module
+raises if the built library is missing: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnlasm.so")
+
+NLA_OK = 0
+ERRORS = {-1: "NLA_E_INVALID", -2: "NLA_E_MESH", -3: "NLA_E_NOMEM", -4: "NLA_E_DEVICE",
+          -5: "NLA_E_UNSUPPORTED", -6: "NLA_E_NOT_CONVERGED", -7: "NLA_E_STATE"}
+KERNELS = {"constant": 0, "fractional": 1}
+BALLS = {"barycenter": 0, "retri": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "learned": 2}
+NLA_SKIP_IXI = 1
+
+
+class NlaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class nla_mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int32), ("n_triangles", C.c_int32), ("xy", C.c_void_p),
+                ("tri", C.c_void_p), ("tri_in_omega", C.c_void_p), ("node_free", C.c_void_p)]
+
+
+class nla_rule(C.Structure):
+    _fields_ = [("n", C.c_int32), ("lam", C.c_void_p), ("w", C.c_void_p)]
+
+
+class nla_problem(C.Structure):
+    _fields_ = [("delta", C.c_double), ("kernel", C.c_int32), ("kernel_c", C.c_double),
+                ("kernel_s", C.c_double), ("outer", nla_rule), ("inner", nla_rule),
+                ("duffy_n", C.c_int32), ("duffy_x", C.c_void_p), ("duffy_w", C.c_void_p),
+                ("ball", C.c_int32), ("cap_edges", C.c_int32), ("precision", C.c_int32),
+                ("mlp", C.c_void_p), ("fallback_band", C.c_double), ("flags", C.c_uint32)]
+
+
+class nla_info(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("nnz_full", C.c_int64), ("nnz_free", C.c_int64),
+                ("n_free", C.c_int32), ("n_outer", C.c_int32), ("n_codes", C.c_int64),
+                ("n_near", C.c_int64), ("items", C.c_int64 * 4), ("subtriangles", C.c_int64)]
+
+
+_LIB = None
+_HIP = None
+
+
+def lib():
+    """The loaded libnlasm.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libnlasm.so is not built (run __graft_entry__.build()); no fallback exists")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.nla_last_error.restype = C.c_char_p
+        L.nla_plan_create.argtypes = [P, P, P, C.POINTER(P)]
+        L.nla_plan_info.argtypes = [P, P]
+        L.nla_pairs_view.argtypes = [P, C.POINTER(P), C.POINTER(P)]
+        L.nla_outer_points.argtypes = [P, P, P]
+        L.nla_assemble.argtypes = [P, P, P, P]
+        L.nla_csr_view.argtypes = [P, I32, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
+        L.nla_load_view.argtypes = [P, C.POINTER(P)]
+        L.nla_free_nodes_view.argtypes = [P, C.POINTER(P)]
+        L.nla_blocks_view.argtypes = [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P),
+                                      C.POINTER(P), C.POINTER(I32)]
+        L.nla_cg.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P]
+        L.nla_plan_destroy.argtypes = [P]
+        L.nla_plan_destroy.restype = None
+        for name in ("nla_plan_create", "nla_plan_info", "nla_pairs_view", "nla_outer_points", "nla_assemble",
+                     "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg"):
+            getattr(L, name).restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _hip():
+    global _HIP
+    if _HIP is None:
+        _HIP = C.CDLL("libamdhip64.so.7")  # the runtime already loaded (by torch), matched by soname
+        _HIP.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        _HIP.hipMemcpyAsync.restype = C.c_int
+    return _HIP
+
+
+def _check(code):
+    if code != NLA_OK:
+        raise NlaError(code, lib().nla_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _copy_from_device(ptr, count, dtype, stream=None):
+    """A torch tensor holding a copy of `count` elements at device address ptr."""
+    out = torch.empty(count, dtype=dtype, device="cuda")
+    if count:
+        st = _hip().hipMemcpyAsync(C.c_void_p(out.data_ptr()), C.c_void_p(ptr),
+                                   count * out.element_size(), 3, _stream(stream))
+        if st != 0:
+            raise RuntimeError("hipMemcpyAsync failed (%d)" % st)
+    return out
+
+
+def _rule(r, keep):
+    lam = np.ascontiguousarray(r.lam, dtype=np.float64)
+    w = np.ascontiguousarray(r.w, dtype=np.float64)
+    keep += [lam, w]
+    return nla_rule(r.n, lam.ctypes.data, w.ctypes.data)
+
+
+class Plan:
+    """A plan for one mesh and problem (nla_plan_create ... nla_plan_destroy)."""
+
+    def __init__(self, mesh, prob, stream=None):
+        from workloads.rules import get_rule, gauss_legendre01
+        keep = []
+        self.mesh = mesh
+        self.problem = prob
+        xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+        tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
+        tin = np.ascontiguousarray(mesh.tri_in_omega, dtype=np.uint8)
+        nfr = np.ascontiguousarray(mesh.node_free, dtype=np.uint8)
+        keep += [xy, tri, tin, nfr]
+        m = nla_mesh(xy.shape[0], tri.shape[0], xy.ctypes.data, tri.ctypes.data, tin.ctypes.data, nfr.ctypes.data)
+        p = nla_problem()
+        p.delta = prob.delta
+        p.kernel = KERNELS[prob.kernel]
+        p.kernel_c = prob.kernel_c
+        p.kernel_s = prob.kernel_s
+        self.outer_rule = get_rule(prob.outer)
+        p.outer = _rule(self.outer_rule, keep)
+        p.inner = _rule(get_rule(prob.inner), keep)
+        if prob.duffy_order > 0:
+            gx, gw = gauss_legendre01(prob.duffy_order)
+            keep += [gx, gw]
+            p.duffy_n, p.duffy_x, p.duffy_w = prob.duffy_order, gx.ctypes.data, gw.ctypes.data
+        p.ball = BALLS[prob.ball]
+        if prob.cap_mode != "poly":
+            raise ValueError("the GPU path fills caps with equal-arc triangles (cap_mode='poly')")
+        p.cap_edges = prob.cap_edges
+        p.precision = PRECISIONS[prob.precision]
+        p.fallback_band = prob.fallback_band
+        p.flags = NLA_SKIP_IXI if prob.skip_ixi else 0
+        h = C.c_void_p()
+        _check(lib().nla_plan_create(C.byref(m), C.byref(p), _stream(stream), C.byref(h)))
+        self._h = h
+        self.K = mesh.n_triangles
+        self.J = mesh.n_vertices
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nla_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = nla_info()
+        _check(lib().nla_plan_info(self._h, C.byref(i)))
+        return dict(n_pairs=i.n_pairs, nnz_full=i.nnz_full, nnz_free=i.nnz_free, n_free=i.n_free,
+                    n_outer=i.n_outer, n_codes=i.n_codes, n_near=i.n_near,
+                    items=dict(whole=i.items[0], partial=i.items[1], empty=i.items[2], learned=i.items[3]),
+                    subtriangles=i.subtriangles)
+
+    def pairs(self, stream=None):
+        """(pair_ptr [K+1] int64, pair_kp [n_pairs] int32) as device tensors (copies)."""
+        a, b = C.c_void_p(), C.c_void_p()
+        _check(lib().nla_pairs_view(self._h, C.byref(a), C.byref(b)))
+        n = self.info()["n_pairs"]
+        return (_copy_from_device(a.value, self.K + 1, torch.int64, stream),
+                _copy_from_device(b.value, n, torch.int32, stream))
+
+    def outer_points(self, stream=None):
+        xq = torch.empty((self.K, self.outer_rule.n, 2), dtype=torch.float64, device="cuda")
+        _check(lib().nla_outer_points(self._h, C.c_void_p(xq.data_ptr()), _stream(stream)))
+        return xq
+
+    def assemble(self, f_outer=None, g_node=None, stream=None):
+        fp = C.c_void_p(f_outer.data_ptr()) if f_outer is not None else None
+        gp = C.c_void_p(g_node.data_ptr()) if g_node is not None else None
+        if f_outer is not None:
+            assert f_outer.dtype == torch.float64 and f_outer.is_cuda and f_outer.is_contiguous()
+            assert f_outer.numel() == self.K * self.outer_rule.n
+        if g_node is not None:
+            assert g_node.dtype == torch.float64 and g_node.is_cuda and g_node.numel() == self.J
+        _check(lib().nla_assemble(self._h, fp, gp, _stream(stream)))
+
+    def csr(self, which=0, stream=None):
+        """(rowptr, col, val) of D (which=0) or A (which=1) as device tensor copies."""
+        rp, ci, v, dt = C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_int32()
+        _check(lib().nla_csr_view(self._h, which, C.byref(rp), C.byref(ci), C.byref(v), C.byref(dt)))
+        info = self.info()
+        n = self.J if which == 0 else info["n_free"]
+        nnz = info["nnz_full"] if which == 0 else info["nnz_free"]
+        rowptr = _copy_from_device(rp.value, n + 1, torch.int64, stream)
+        col = _copy_from_device(ci.value, nnz, torch.int32, stream)
+        val = _copy_from_device(v.value, nnz, torch.float64 if dt.value == 0 else torch.float32, stream)
+        return rowptr, col, val
+
+    def load(self, stream=None):
+        b = C.c_void_p()
+        _check(lib().nla_load_view(self._h, C.byref(b)))
+        return _copy_from_device(b.value, self.info()["n_free"], torch.float64, stream)
+
+    def free_nodes(self, stream=None):
+        f = C.c_void_p()
+        _check(lib().nla_free_nodes_view(self._h, C.byref(f)))
+        return _copy_from_device(f.value, self.info()["n_free"], torch.int32, stream)
+
+    def blocks(self, stream=None):
+        """Per-pair -Mxy [P,3,3], Myy [P,6], per-element Mxx [K,6] (copies)."""
+        a, b, c, d, e, dt = (C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_int32())
+        _check(lib().nla_blocks_view(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(e),
+                                     C.byref(dt)))
+        info = self.info()
+        n = info["n_pairs"]
+        t = torch.float64 if dt.value == 0 else torch.float32
+        return dict(neg_mxy=_copy_from_device(a.value, 9 * n, t, stream).view(n, 3, 3),
+                    myy=_copy_from_device(b.value, 6 * n, t, stream).view(n, 6),
+                    mxx=_copy_from_device(c.value, 6 * self.K, t, stream).view(self.K, 6),
+                    near=_copy_from_device(d.value, 21 * info["n_near"], t, stream).view(-1, 21),
+                    near_pair=_copy_from_device(e.value, info["n_near"], torch.int64, stream))
+
+    def cg(self, b, u0=None, rtol=1e-12, maxit=10000, stream=None):
+        n = self.info()["n_free"]
+        u = torch.zeros(n, dtype=torch.float64, device="cuda") if u0 is None else u0.clone()
+        it, rr = C.c_int32(), C.c_double()
+        code = lib().nla_cg(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(u.data_ptr()), rtol, maxit,
+                            C.byref(it), C.byref(rr), _stream(stream))
+        _check(code)
+        return u, it.value, rr.value

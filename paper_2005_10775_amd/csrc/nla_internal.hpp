@@ -1,0 +1,129 @@
+// Internal declarations shared by the translation units of libnlasm.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <cstdarg>
+#include <vector>
+#include "../../include/nlasm.h"
+
+#define NLA_MAX_OUTER 16
+#define NLA_MAX_INNER 32
+#define NLA_MAX_CAP 64
+#define NLA_MAX_PAIRS_PER_K 4096
+#define NLA_MAX_DUFFY 24
+
+void nla_set_error(const char *fmt, ...);
+
+#define NLA_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            nla_set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),        \
+                          __FILE__, __LINE__);                                          \
+            return NLA_E_DEVICE;                                                        \
+        }                                                                               \
+    } while (0)
+
+#define NLA_TRY(expr)                                                                   \
+    do {                                                                                \
+        int s_ = (expr);                                                                \
+        if (s_ != NLA_OK) return s_;                                                    \
+    } while (0)
+
+// Quadrature data as the kernels read it: outer/inner points plus the inner
+// rule's own first and second barycentric moments (sum w mu_i, sum w mu_i mu_j),
+// which let a constant-psi inner integral over a subtriangle be evaluated
+// from the values of the P1 basis at its three vertices (the rule applied
+// with its sums reordered, not a different rule).
+struct RuleSet {
+    int32_t n_out, n_in, duffy_n, pad;
+    double out_lam[NLA_MAX_OUTER][3];
+    double out_w[NLA_MAX_OUTER];
+    double in_lam[NLA_MAX_INNER][3];
+    double in_w[NLA_MAX_INNER];
+    double in_wsum;
+    double in_m1[3];
+    double in_m2[3][3];
+    double duffy_x[NLA_MAX_DUFFY];
+    double duffy_w[NLA_MAX_DUFFY];
+};
+
+// Element data, structure of arrays, K entries each.
+struct ElemSoA {
+    double *vx0, *vy0, *vx1, *vy1, *vx2, *vy2; // vertices
+    double *bx, *by;                           // barycenter ((v0+v1)+v2)/3
+    double *a2;                                // twice the area
+    double *r;                                 // max vertex distance from the barycenter
+};
+
+struct DeviceArena {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    ~DeviceArena();
+    int alloc(void **p, size_t n);
+    template <class T> int get(T **p, size_t count) { return alloc((void **)p, count * sizeof(T)); }
+};
+
+struct nla_plan {
+    int device = 0;
+    int32_t K = 0, J = 0, n_free = 0;
+    nla_problem prob{};
+    RuleSet rules{};
+    RuleSet *d_rules = nullptr;
+    DeviceArena arena;         // plan-lifetime allocations
+    // mesh
+    double *xy = nullptr;
+    int32_t *tri = nullptr;
+    uint8_t *tin = nullptr, *nfree = nullptr;
+    ElemSoA E{};
+    double *xq = nullptr;      // [K][n_out][2]
+    // pairs
+    int64_t n_pairs = 0;
+    int64_t *pair_ptr = nullptr;
+    int32_t *pair_kp = nullptr;
+    int32_t *pair_k = nullptr;
+    // pattern of D
+    int64_t nnz = 0;
+    int64_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    int64_t *mirror = nullptr;  // index of (col,row) for every entry
+    // segmented sum: upper-triangle entries and their contribution codes
+    int64_t n_up = 0, n_codes = 0;
+    int64_t *up_dst = nullptr;  // [n_up] entry index of the upper entry
+    int64_t *up_ptr = nullptr;  // [n_up+1]
+    int32_t *codes = nullptr;   // [n_codes] indices into the contribution array
+    // near-diagonal pairs (singular kernel)
+    int64_t n_near = 0;
+    int64_t *near_pair = nullptr;
+    // contributions and values
+    int64_t n_contrib = 0;      // 9P + 6P + 6K + 21 n_near
+    void *contrib = nullptr;    // f64 or f32 [n_contrib]
+    void *val = nullptr;        // [nnz]
+    // A = D[free, free]
+    int64_t nnz_free = 0;
+    int32_t *free_nodes = nullptr;
+    int32_t *node_to_free = nullptr;
+    int64_t *a_rowptr = nullptr;
+    int32_t *a_col = nullptr;
+    int64_t *a_src = nullptr;
+    void *a_val = nullptr;
+    // load vector
+    int32_t *n2e_ptr = nullptr; // [J+1] node -> (element*3+slot) of Omega elements
+    int32_t *n2e = nullptr;
+    double *Gk = nullptr;       // [K][3]
+    double *b = nullptr;        // [n_free]
+    // counters: whole, partial, empty, learned, subtriangles
+    unsigned long long *counters = nullptr;
+    unsigned long long host_counters[5] = {0, 0, 0, 0, 0};
+    bool assembled = false;
+    bool have_load = false;
+    int val_dtype = NLA_DTYPE_F64;
+};
+
+// translation-unit entry points
+int nla_build_pairs(nla_plan *P, hipStream_t s);
+int nla_build_pattern(nla_plan *P, hipStream_t s);
+int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStream_t s);
+int nla_cg_run(const nla_plan *P, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+               double *relres, hipStream_t s);

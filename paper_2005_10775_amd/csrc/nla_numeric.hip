@@ -1,0 +1,516 @@
+// Numeric phase of libnlasm: pair quadrature, deterministic segmented sum
+// into the CSR values of D, extraction of A = D[free,free] and the load vector.
+#include "nla_internal.hpp"
+#include <cmath>
+
+static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// inner-rule moments as the kernels use them
+struct RuleMom {
+    double wsum, m1[3], m2[3][3];
+};
+
+__device__ __forceinline__ RuleMom load_moments(const RuleSet *__restrict__ R)
+{
+    RuleMom M;
+    M.wsum = R->in_wsum;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        M.m1[i] = R->in_m1[i];
+#pragma unroll
+        for (int j = 0; j < 3; j++) M.m2[i][j] = R->in_m2[i][j];
+    }
+    return M;
+}
+
+// geometric inner sums of one (x, E') item with psi = 1 (psi is constant and
+// applied per pair): s0 = |region| / wsum-scaled, s1_b = int beta_b,
+// s2 = int beta_b beta_b' (upper triangle 00,01,02,11,12,22)
+struct Acc {
+    double a2;     // sum of twice-areas (times wsum gives the area-weighted rule sum)
+    double s1[3];
+    double s2[6];
+};
+
+// P1 basis of E' in coordinates relative to the outer point: beta1, beta2 from
+// the offset to vertex 0 and the inverse of the edge matrix, beta0 = 1 - beta1 - beta2.
+struct Basis {
+    double x0, y0, i11, i12, i21, i22;
+};
+
+__device__ __forceinline__ void basis_at(const Basis &B, double px, double py, double (&b)[3])
+{
+    double dx = px - B.x0, dy = py - B.y0;
+    b[1] = dx * B.i11 + dy * B.i12;
+    b[2] = dx * B.i21 + dy * B.i22;
+    b[0] = 1.0 - b[1] - b[2];
+}
+
+// the inner rule on the subtriangle (a, b, c), evaluated from the basis
+// values at its vertices: sum_q w_q beta(y_q) = sum_i m1_i beta(t_i) and
+// sum_q w_q beta beta^T = B^T M2 B, B = basis values at the vertices
+__device__ __forceinline__ void tri_accum(double ax, double ay, const double (&ba)[3], double bx, double by,
+                                          const double (&bb)[3], double cx, double cy, const double (&bc)[3],
+                                          const RuleMom &M, Acc &A)
+{
+    double a2 = fabs((bx - ax) * (cy - ay) - (by - ay) * (cx - ax));
+    A.a2 += a2;
+    double U[3][3];
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        A.s1[l] += a2 * (M.m1[0] * ba[l] + M.m1[1] * bb[l] + M.m1[2] * bc[l]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) U[i][l] = M.m2[i][0] * ba[l] + M.m2[i][1] * bb[l] + M.m2[i][2] * bc[l];
+    }
+    const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+        const int j = jj[t], l = ll[t];
+        A.s2[t] += a2 * (ba[j] * U[0][l] + bb[j] * U[1][l] + bc[j] * U[2][l]);
+    }
+}
+
+// one cap: the arc of the circle |p| = delta from exit X counter-clockwise to
+// entry N, split into ncap equal arcs whose points are fanned from the chord
+// midpoint (Sec. 4.2.2); a span not in (0, pi] comes only from rounding of
+// coincident X and N and is dropped
+__device__ __forceinline__ void cap_accum(double Xx, double Xy, const double (&bX)[3], double Nx, double Ny,
+                                          const double (&bN)[3], int ncap, const Basis &B, const RuleMom &M,
+                                          Acc &A, int &nsub)
+{
+    double cr = Xx * Ny - Xy * Nx, dt = Xx * Nx + Xy * Ny;
+    double D = atan2(cr, dt);
+    if (!(D > 0.0) || ncap < 2) return;
+    double Mx = 0.5 * (Xx + Nx), My = 0.5 * (Xy + Ny);
+    double bM[3] = {0.5 * (bX[0] + bN[0]), 0.5 * (bX[1] + bN[1]), 0.5 * (bX[2] + bN[2])};
+    double s, c;
+    sincos(D / (double)ncap, &s, &c);
+    double ux = Xx, uy = Xy;
+    double bu[3] = {bX[0], bX[1], bX[2]};
+    for (int j = 1; j <= ncap; j++) {
+        double vx, vy, bv[3];
+        if (j == ncap) {
+            vx = Nx;
+            vy = Ny;
+            bv[0] = bN[0];
+            bv[1] = bN[1];
+            bv[2] = bN[2];
+        } else {
+            vx = c * ux - s * uy;
+            vy = s * ux + c * uy;
+            basis_at(B, vx, vy, bv);
+        }
+        tri_accum(Mx, My, bM, ux, uy, bu, vx, vy, bv, M, A);
+        nsub++;
+        ux = vx;
+        uy = vy;
+        bu[0] = bv[0];
+        bu[1] = bv[1];
+        bu[2] = bv[2];
+    }
+}
+
+// E' n B_delta(x) retriangulated (Sec. 4.2.1 and Sec. 7.1 tasks 3-6):
+// the edges are walked v0->v1->v2, vertices inside the closed ball and the
+// roots lambda in (0,1) of |v_a + lambda e - x|^2 = delta^2 (smaller root
+// entry, larger exit) are streamed in order; each new point closes a fan
+// triangle with the first point, and every exit followed by an entry
+// (cyclically) bounds a cap.  V holds E' in absolute coordinates.
+__device__ void partial_item(double xx, double xy, const double (&V)[6], double dd, int ncap, const RuleMom &M,
+                             Acc &A, int &nsub)
+{
+    double P[6];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        P[2 * a] = V[2 * a] - xx;
+        P[2 * a + 1] = V[2 * a + 1] - xy;
+    }
+    Basis B;
+    {
+        double e1x = V[2] - V[0], e1y = V[3] - V[1], e2x = V[4] - V[0], e2y = V[5] - V[1];
+        double id = 1.0 / (e1x * e2y - e1y * e2x);
+        B.x0 = P[0];
+        B.y0 = P[1];
+        B.i11 = e2y * id;
+        B.i12 = -e2x * id;
+        B.i21 = -e1y * id;
+        B.i22 = e1x * id;
+    }
+    int cnt = 0, ft = 0, pt = 0;
+    double fx = 0, fy = 0, fb[3] = {0, 0, 0};
+    double qx = 0, qy = 0, qb[3] = {0, 0, 0};
+    auto emit = [&](double nx, double ny, double b0, double b1, double b2, int nt) {
+        double nb[3] = {b0, b1, b2};
+        if (cnt == 0) {
+            fx = nx; fy = ny; fb[0] = b0; fb[1] = b1; fb[2] = b2; ft = nt;
+        } else {
+            if (cnt >= 2) {
+                tri_accum(fx, fy, fb, qx, qy, qb, nx, ny, nb, M, A);
+                nsub++;
+            }
+            if (pt == 2 && nt == 1) cap_accum(qx, qy, qb, nx, ny, nb, ncap, B, M, A, nsub);
+        }
+        qx = nx; qy = ny; qb[0] = b0; qb[1] = b1; qb[2] = b2; pt = nt;
+        cnt++;
+    };
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        double px = P[2 * a], py = P[2 * a + 1];
+        double r2 = px * px + py * py;
+        if (r2 <= dd) emit(V[2 * a] - xx, V[2 * a + 1] - xy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0, 0);
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double L = ex * ex + ey * ey;
+        double Bq = ex * px + ey * py;
+        double Cq = r2 - dd;
+        double disc = Bq * Bq - L * Cq;
+        if (disc > 0.0) {
+            double s = sqrt(disc);
+            double l1 = (-Bq - s) / L, l2 = (-Bq + s) / L;
+            double w[3];
+            if (l1 > 0.0 && l1 < 1.0) {
+                w[a] = 1.0 - l1; w[b] = l1; w[3 - a - b] = 0.0;
+                emit(px + l1 * ex, py + l1 * ey, w[0], w[1], w[2], 1);
+            }
+            if (l2 > 0.0 && l2 < 1.0) {
+                w[a] = 1.0 - l2; w[b] = l2; w[3 - a - b] = 0.0;
+                emit(px + l2 * ex, py + l2 * ey, w[0], w[1], w[2], 2);
+            }
+        }
+    }
+    if (cnt >= 2 && pt == 2 && ft == 1) cap_accum(qx, qy, qb, fx, fy, fb, ncap, B, M, A, nsub);
+}
+
+__device__ __forceinline__ bool meets_edges(double xx, double xy, const double (&V)[6], double dd)
+{
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        if (ex * py - ey * px < 0.0) inside = false;
+    }
+    if (inside) return true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        double t = ex * px + ey * py, L = ex * ex + ey * ey;
+        if (t > 0.0 && t < L) {
+            double c = ex * py - ey * px;
+            if (c * c <= dd * L) return true;
+        }
+    }
+    return false;
+}
+
+// One wavefront per outer element k (Eq. (bformhj) restricted to the pairs
+// of k).  Phase 1: every lane takes one pair (k, k'), classifies its items
+// (x_{k,q}, E_k') as whole / partial / empty; whole items (all of E_k' in the
+// ball, or the barycenter inside for the barycenter ball) only add their
+// outer weights, since with constant psi their inner sums are rule
+// constants times |E_k'|.  Partial items are queued in LDS.  Phase 2: the
+// wave takes queued items 64 at a time (dense, regardless of owner),
+// retriangulates them, and each owner adds its items' sums in q order.
+// Outputs per pair: -Mxy (9), Myy (6); per element Mxx (6) from the
+// fixed-order lane reduction of sum_k' S0(x_q).
+__global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
+                                                         const int32_t *__restrict__ pair_kp, ElemSoA E,
+                                                         const double *__restrict__ xq, const RuleSet *__restrict__ R,
+                                                         double dd, double psi, int ball, int ncap,
+                                                         double *__restrict__ Cxy, double *__restrict__ Cyy,
+                                                         double *__restrict__ Cxx,
+                                                         unsigned long long *__restrict__ counters)
+{
+    __shared__ double sW[NLA_MAX_OUTER][4];
+    __shared__ double sX[NLA_MAX_OUTER][2];
+    __shared__ double sV[64][7];
+    __shared__ unsigned short queue[64 * NLA_MAX_OUTER];
+    __shared__ double res[64][10];
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const int nq = R->n_out;
+    const double a2k = E.a2[k];
+    if (lane < nq) {
+        double W = R->out_w[lane] * a2k;
+        sW[lane][0] = W;
+        sW[lane][1] = W * R->out_lam[lane][0];
+        sW[lane][2] = W * R->out_lam[lane][1];
+        sW[lane][3] = W * R->out_lam[lane][2];
+        sX[lane][0] = xq[2 * ((int64_t)k * nq + lane)];
+        sX[lane][1] = xq[2 * ((int64_t)k * nq + lane) + 1];
+    }
+    __syncthreads();
+    const RuleMom M = load_moments(R);
+    double m0[NLA_MAX_OUTER];
+#pragma unroll
+    for (int q = 0; q < NLA_MAX_OUTER; q++) m0[q] = 0.0;
+    unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0;
+    const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
+    for (int64_t base = p0; base < p1; base += 64) {
+        const int64_t p = base + lane;
+        const bool act = p < p1;
+        double V[6] = {0, 0, 0, 0, 0, 0};
+        double a2p = 0.0, bxp = 0.0, byp = 0.0;
+        if (act) {
+            int kp = pair_kp[p];
+            V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
+            a2p = E.a2[kp];
+            bxp = E.bx[kp];
+            byp = E.by[kp];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; i++) sV[lane][i] = V[i];
+        double ws = 0.0, aw[3] = {0.0, 0.0, 0.0};
+        unsigned pmask = 0;
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < NLA_MAX_OUTER; q++) {
+                if (q >= nq) break;
+                const double xx = sX[q][0], xy = sX[q][1];
+                bool whole = false, part = false;
+                if (ball == NLA_BALL_BARYCENTER) {
+                    double dx = xx - bxp, dy = xy - byp;
+                    whole = dx * dx + dy * dy <= dd;
+                } else {
+                    int nin = 0;
+#pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
+                        nin += dx * dx + dy * dy <= dd;
+                    }
+                    whole = nin == 3;
+                    part = !whole && (nin > 0 || meets_edges(xx, xy, V, dd));
+                }
+                if (whole) {
+                    ws += sW[q][0];
+                    aw[0] += sW[q][1];
+                    aw[1] += sW[q][2];
+                    aw[2] += sW[q][3];
+                    m0[q] += a2p * M.wsum;
+                    c_whole++;
+                } else if (part) {
+                    pmask |= 1u << q;
+                    c_part++;
+                } else {
+                    c_empty++;
+                }
+            }
+        }
+        double axy[3][3], ayy[6];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) axy[a][b] = aw[a] * a2p * M.m1[b];
+        {
+            const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+            for (int t = 0; t < 6; t++) ayy[t] = ws * a2p * M.m2[jj[t]][ll[t]];
+        }
+        // queue the partial items: exclusive prefix over lanes of popcounts
+        const int cnt = __popc(pmask);
+        int pre = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int v = __shfl_up(pre, off, 64);
+            if (lane >= off) pre += v;
+        }
+        const int total = __shfl(pre, 63, 64);
+        pre -= cnt;
+        {
+            int o = pre;
+            unsigned mm = pmask;
+            while (mm) {
+                int q = __ffs(mm) - 1;
+                mm &= mm - 1;
+                queue[o++] = (unsigned short)((lane << 8) | q);
+            }
+        }
+        __syncthreads();
+        for (int ib = 0; ib < total; ib += 64) {
+            const int i = ib + lane;
+            if (i < total) {
+                const int e = queue[i], owner = e >> 8, q = e & 0xff;
+                double W6[6];
+#pragma unroll
+                for (int t = 0; t < 6; t++) W6[t] = sV[owner][t];
+                Acc A;
+                A.a2 = 0.0;
+#pragma unroll
+                for (int t = 0; t < 3; t++) A.s1[t] = 0.0;
+#pragma unroll
+                for (int t = 0; t < 6; t++) A.s2[t] = 0.0;
+                int ns = 0;
+                partial_item(sX[q][0], sX[q][1], W6, dd, ncap, M, A, ns);
+                c_sub += ns;
+                res[lane][0] = A.a2 * M.wsum;
+#pragma unroll
+                for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t];
+#pragma unroll
+                for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t];
+            }
+            __syncthreads();
+            const int j0 = pre > ib ? pre : ib;
+            const int j1 = (pre + cnt) < (ib + 64) ? (pre + cnt) : (ib + 64);
+            for (int j = j0; j < j1; j++) {
+                const int q = queue[j] & 0xff;
+                const double *r = res[j - ib];
+#pragma unroll
+                for (int qq = 0; qq < NLA_MAX_OUTER; qq++)
+                    if (qq == q) m0[qq] += r[0];
+                const double W = sW[q][0];
+#pragma unroll
+                for (int a = 0; a < 3; a++)
+#pragma unroll
+                    for (int b = 0; b < 3; b++) axy[a][b] += sW[q][1 + a] * r[1 + b];
+#pragma unroll
+                for (int t = 0; t < 6; t++) ayy[t] += W * r[4 + t];
+            }
+            __syncthreads();
+        }
+        if (act) {
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int b = 0; b < 3; b++) Cxy[9 * p + 3 * a + b] = -psi * axy[a][b];
+#pragma unroll
+            for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * ayy[t];
+        }
+    }
+    // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
+    // lanes, then lane 0's sum is broadcast
+#pragma unroll
+    for (int q = 0; q < NLA_MAX_OUTER; q++) {
+        double x = m0[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        m0[q] = __shfl(x, 0, 64);
+    }
+    if (lane < 6) {
+        const int aa[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
+        const int a = aa[lane], c = cc[lane];
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NLA_MAX_OUTER; q++)
+            if (q < nq) s += sW[q][1 + a] * R->out_lam[q][c] * m0[q];
+        Cxx[6 * (int64_t)k + lane] = psi * s;
+    }
+    // work counters
+    unsigned long long v[4] = {c_whole, c_part, c_empty, c_sub};
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        unsigned long long x = v[i];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        v[i] = x;
+    }
+    if (lane == 0) {
+        atomicAdd(&counters[0], v[0]);
+        atomicAdd(&counters[1], v[1]);
+        atomicAdd(&counters[2], v[2]);
+        atomicAdd(&counters[4], v[3]);
+    }
+}
+
+// Deterministic COO->CSR sum: every upper-triangle entry adds its
+// contributions in the fixed order of its code list and writes the sum to
+// both mirrored positions, so D is bitwise symmetric and run-to-run identical.
+__global__ void k_segsum_f64(int64_t n_up, const int64_t *__restrict__ up_ptr, const int32_t *__restrict__ codes,
+                             const int64_t *__restrict__ up_dst, const int64_t *__restrict__ mirror,
+                             const double *__restrict__ C, double *__restrict__ val)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_up) return;
+    double s = 0.0;
+    for (int64_t t = up_ptr[u]; t < up_ptr[u + 1]; t++) s += C[codes[t]];
+    int64_t d = up_dst[u];
+    val[d] = s;
+    val[mirror[d]] = s;
+}
+
+template <class T>
+__global__ void k_extract(int64_t n, const int64_t *__restrict__ src, const T *__restrict__ val, T *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = val[src[i]];
+}
+
+// G restricted to one element of Omega: sum_q W_q alpha_a(q) f(x_q) (Eq. (lfunchj))
+__global__ void k_load_elem(int K, const uint8_t *__restrict__ tin, const double *__restrict__ a2,
+                            const RuleSet *__restrict__ R, const double *__restrict__ f, double *__restrict__ Gk)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double g[3] = {0.0, 0.0, 0.0};
+    if (tin[k]) {
+        const int nq = R->n_out;
+        for (int q = 0; q < nq; q++) {
+            double Wf = R->out_w[q] * a2[k] * f[(int64_t)k * nq + q];
+            for (int a = 0; a < 3; a++) g[a] += Wf * R->out_lam[q][a];
+        }
+    }
+    for (int a = 0; a < 3; a++) Gk[3 * (int64_t)k + a] = g[a];
+}
+
+// b_i = G_j - sum_{Dirichlet nodes l} D[j,l] g_l for free node j (Eqs. (appr), (intcon))
+template <class T>
+__global__ void k_load_rhs(int n_free, const int32_t *__restrict__ free_nodes, const int32_t *__restrict__ n2e_ptr,
+                           const int32_t *__restrict__ n2e, const double *__restrict__ Gk,
+                           const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           const T *__restrict__ val, const int32_t *__restrict__ n2f, const double *__restrict__ g,
+                           double *__restrict__ b)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_free) return;
+    int j = free_nodes[i];
+    double s = 0.0;
+    for (int e = n2e_ptr[j]; e < n2e_ptr[j + 1]; e++) s += Gk[n2e[e]];
+    for (int64_t t = rowptr[j]; t < rowptr[j + 1]; t++) {
+        int c = col[t];
+        if (n2f[c] < 0) s -= (double)val[t] * g[c];
+    }
+    b[i] = s;
+}
+
+int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStream_t s)
+{
+    const nla_problem &pr = P->prob;
+    if (pr.kernel != NLA_KERNEL_CONSTANT || pr.precision != NLA_FP64) {
+        nla_set_error("this build assembles the constant kernel in FP64 only");
+        return NLA_E_UNSUPPORTED;
+    }
+    const int64_t NP = P->n_pairs;
+    const int K = P->K;
+    if (!P->contrib) {
+        P->n_contrib = 15 * NP + 6 * (int64_t)K;
+        NLA_TRY(P->arena.alloc(&P->contrib, sizeof(double) * P->n_contrib));
+        NLA_TRY(P->arena.alloc(&P->val, sizeof(double) * P->nnz));
+        NLA_TRY(P->arena.alloc(&P->a_val, sizeof(double) * (P->nnz_free > 0 ? P->nnz_free : 1)));
+        NLA_TRY(P->arena.get(&P->Gk, 3 * (size_t)K));
+        NLA_TRY(P->arena.get(&P->b, P->n_free > 0 ? P->n_free : 1));
+    }
+    double *C = (double *)P->contrib;
+    NLA_HIP(hipMemsetAsync(P->counters, 0, sizeof(unsigned long long) * 5, s));
+    k_pairs_const_fp64<<<K, 64, 0, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta,
+                                        pr.kernel_c, pr.ball, pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0, C, C + 9 * NP,
+                                        C + 15 * NP, P->counters);
+    NLA_HIP(hipGetLastError());
+    if (P->n_up > 0)
+        k_segsum_f64<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes, P->up_dst, P->mirror, C,
+                                                           (double *)P->val);
+    if (P->nnz_free > 0)
+        k_extract<double><<<grid_for(P->nnz_free, 256), 256, 0, s>>>(P->nnz_free, P->a_src, (const double *)P->val,
+                                                                    (double *)P->a_val);
+    P->have_load = false;
+    if (f_outer && g_node) {
+        k_load_elem<<<grid_for(K, 256), 256, 0, s>>>(K, P->tin, P->E.a2, P->d_rules, f_outer, P->Gk);
+        if (P->n_free > 0)
+            k_load_rhs<double><<<grid_for(P->n_free, 256), 256, 0, s>>>(
+                P->n_free, P->free_nodes, P->n2e_ptr, P->n2e, P->Gk, P->rowptr, P->col, (const double *)P->val,
+                P->node_to_free, g_node, P->b);
+        P->have_load = true;
+    }
+    NLA_HIP(hipGetLastError());
+    P->val_dtype = NLA_DTYPE_F64;
+    P->assembled = true;
+    return NLA_OK;
+}

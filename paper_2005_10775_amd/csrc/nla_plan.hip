@@ -1,0 +1,1034 @@
+// Plan phase of libnlasm: host validation, element data, binning, the
+// canonical pair list and the CSR pattern of D with its contribution map.
+//
+// Built with -ffp-contract=off: every +,-,* of the pair predicate is rounded
+// separately so that the pair list is bitwise the one any IEEE evaluation of
+// the same expressions produces (barycenter ((v0+v1)+v2)/3, outer point
+// ((l0 v0 + l1 v1) + l2 v2), squared distances without sqrt or division).
+#include "nla_internal.hpp"
+#include <cstring>
+#include <cmath>
+#include <cstdlib>
+#include <algorithm>
+#include <string>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_select.hpp>
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[1024] = "";
+
+void nla_set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+extern "C" const char *nla_last_error(void) { return g_err; }
+
+// ------------------------------------------------------------------ arena
+static size_t device_byte_cap()
+{
+    const char *e = getenv("NLA_MAX_DEVICE_BYTES");
+    if (!e) return (size_t)-1;
+    return (size_t)strtoull(e, nullptr, 10);
+}
+
+DeviceArena::~DeviceArena()
+{
+    for (void *p : ptrs) (void)hipFree(p);
+}
+
+int DeviceArena::alloc(void **p, size_t n)
+{
+    *p = nullptr;
+    if (n == 0) n = 8;
+    if (bytes + n > device_byte_cap()) {
+        nla_set_error("device allocation of %zu bytes exceeds NLA_MAX_DEVICE_BYTES", n);
+        return NLA_E_NOMEM;
+    }
+    hipError_t e = hipMalloc(p, n);
+    if (e != hipSuccess) {
+        nla_set_error("hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+        return NLA_E_NOMEM;
+    }
+    ptrs.push_back(*p);
+    bytes += n;
+    return NLA_OK;
+}
+
+// temporary buffers for one build step
+struct Scratch {
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    ~Scratch()
+    {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <class T> int get(T **p, size_t count)
+    {
+        size_t n = count * sizeof(T);
+        if (n == 0) n = 8;
+        if (n > device_byte_cap()) {
+            nla_set_error("scratch allocation of %zu bytes exceeds NLA_MAX_DEVICE_BYTES", n);
+            return NLA_E_NOMEM;
+        }
+        hipError_t e = hipMalloc((void **)p, n);
+        if (e != hipSuccess) {
+            nla_set_error("hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+            return NLA_E_NOMEM;
+        }
+        ptrs.push_back((void *)*p);
+        return NLA_OK;
+    }
+};
+
+static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ------------------------------------------------------------- validation
+static int validate(const nla_mesh *m, const nla_problem *p)
+{
+    if (!m || !p) { nla_set_error("null mesh or problem"); return NLA_E_INVALID; }
+    if (m->n_vertices < 3 || m->n_triangles < 1 || !m->xy || !m->tri || !m->tri_in_omega || !m->node_free) {
+        nla_set_error("mesh arrays missing or empty");
+        return NLA_E_MESH;
+    }
+    if (!(p->delta > 0.0) || !std::isfinite(p->delta)) { nla_set_error("delta must be > 0"); return NLA_E_INVALID; }
+    if (p->kernel != NLA_KERNEL_CONSTANT && p->kernel != NLA_KERNEL_FRACTIONAL) {
+        nla_set_error("unknown kernel %d", p->kernel);
+        return NLA_E_INVALID;
+    }
+    if (!std::isfinite(p->kernel_c) || p->kernel_c <= 0.0) { nla_set_error("kernel_c must be > 0"); return NLA_E_INVALID; }
+    if (p->ball != NLA_BALL_BARYCENTER && p->ball != NLA_BALL_RETRI) { nla_set_error("unknown ball %d", p->ball); return NLA_E_INVALID; }
+    if (p->cap_edges < 0 || p->cap_edges == 1 || p->cap_edges > NLA_MAX_CAP) {
+        nla_set_error("cap_edges must be 0 or 2..%d", NLA_MAX_CAP);
+        return NLA_E_INVALID;
+    }
+    if (p->precision != NLA_FP64 && p->precision != NLA_FP32 && p->precision != NLA_FP32_LEARNED) {
+        nla_set_error("unknown precision %d", p->precision);
+        return NLA_E_INVALID;
+    }
+    if (p->precision == NLA_FP32_LEARNED) {
+        nla_set_error("learned caps are not available in this build");
+        return NLA_E_UNSUPPORTED;
+    }
+    if (p->kernel == NLA_KERNEL_FRACTIONAL && p->precision == NLA_FP64 && p->duffy_n == 0) {
+        nla_set_error("fractional kernel needs duffy_n > 0 for vertex-sharing pairs");
+        return NLA_E_INVALID;
+    }
+    if (p->kernel == NLA_KERNEL_FRACTIONAL) {
+        if (p->duffy_n < 1 || p->duffy_n > NLA_MAX_DUFFY || !p->duffy_x || !p->duffy_w) {
+            nla_set_error("duffy_n must be 1..%d with nodes and weights", NLA_MAX_DUFFY);
+            return NLA_E_INVALID;
+        }
+        if (!(p->kernel_s > -1.0 && p->kernel_s < 1.0)) { nla_set_error("kernel_s must be in (-1,1)"); return NLA_E_INVALID; }
+    }
+    const nla_rule *rs[2] = {&p->outer, &p->inner};
+    const int mx[2] = {NLA_MAX_OUTER, NLA_MAX_INNER};
+    for (int r = 0; r < 2; r++) {
+        if (rs[r]->n < 1 || rs[r]->n > mx[r] || !rs[r]->lambda || !rs[r]->w) {
+            nla_set_error("%s rule must have 1..%d points", r ? "inner" : "outer", mx[r]);
+            return NLA_E_INVALID;
+        }
+        double ws = 0;
+        for (int q = 0; q < rs[r]->n; q++) {
+            const double *l = rs[r]->lambda + 3 * q;
+            if (!(l[0] >= 0 && l[1] >= 0 && l[2] >= 0) || std::fabs(l[0] + l[1] + l[2] - 1.0) > 1e-12) {
+                nla_set_error("%s rule point %d is not barycentric", r ? "inner" : "outer", q);
+                return NLA_E_INVALID;
+            }
+            ws += rs[r]->w[q];
+        }
+        if (std::fabs(ws - 0.5) > 1e-12) { nla_set_error("rule weights must sum to 1/2"); return NLA_E_INVALID; }
+    }
+    if (p->flags & ~(uint32_t)NLA_SKIP_IXI) { nla_set_error("unknown flags"); return NLA_E_INVALID; }
+    // mesh rules of Sec. 3.1
+    const int J = m->n_vertices, K = m->n_triangles;
+    for (int i = 0; i < 2 * J; i++)
+        if (!std::isfinite(m->xy[i])) { nla_set_error("vertex %d not finite", i / 2); return NLA_E_MESH; }
+    double dmax = 0.0;
+    for (int k = 0; k < K; k++) {
+        const int32_t *t = m->tri + 3 * k;
+        for (int a = 0; a < 3; a++)
+            if (t[a] < 0 || t[a] >= J) { nla_set_error("triangle %d has vertex index %d out of range", k, t[a]); return NLA_E_MESH; }
+        if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2]) { nla_set_error("triangle %d repeats a vertex", k); return NLA_E_MESH; }
+        const double *A = m->xy + 2 * t[0], *B = m->xy + 2 * t[1], *Cc = m->xy + 2 * t[2];
+        double cr = (B[0] - A[0]) * (Cc[1] - A[1]) - (B[1] - A[1]) * (Cc[0] - A[0]);
+        if (!(cr > 0.0)) { nla_set_error("triangle %d is not counter-clockwise", k); return NLA_E_MESH; }
+        if (m->tri_in_omega[k] > 1) { nla_set_error("tri_in_omega[%d] not 0/1", k); return NLA_E_MESH; }
+        const double *V[3] = {A, B, Cc};
+        for (int a = 0; a < 3; a++) {
+            double dx = V[a][0] - V[(a + 1) % 3][0], dy = V[a][1] - V[(a + 1) % 3][1];
+            dmax = std::max(dmax, std::sqrt(dx * dx + dy * dy));
+        }
+    }
+    for (int j = 0; j < J; j++)
+        if (m->node_free[j] > 1) { nla_set_error("node_free[%d] not 0/1", j); return NLA_E_MESH; }
+    // a free node must not touch an element of Omega_I (Sec. 3.1: nodes on the boundary belong to Omega_I)
+    for (int k = 0; k < K; k++)
+        if (!m->tri_in_omega[k])
+            for (int a = 0; a < 3; a++)
+                if (m->node_free[m->tri[3 * k + a]]) {
+                    nla_set_error("free node %d belongs to Omega_I element %d", m->tri[3 * k + a], k);
+                    return NLA_E_MESH;
+                }
+    if (p->ball == NLA_BALL_RETRI && dmax > p->delta) {
+        nla_set_error("retriangulated ball needs element diameter (%g) <= delta (%g)", dmax, p->delta);
+        return NLA_E_UNSUPPORTED;
+    }
+    return NLA_OK;
+}
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_elem(int K, const double *__restrict__ xy, const int32_t *__restrict__ tri, ElemSoA E,
+                       const RuleSet *__restrict__ R, double *__restrict__ xq)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    int i0 = tri[3 * k], i1 = tri[3 * k + 1], i2 = tri[3 * k + 2];
+    double x0 = xy[2 * i0], y0 = xy[2 * i0 + 1];
+    double x1 = xy[2 * i1], y1 = xy[2 * i1 + 1];
+    double x2 = xy[2 * i2], y2 = xy[2 * i2 + 1];
+    E.vx0[k] = x0; E.vy0[k] = y0; E.vx1[k] = x1; E.vy1[k] = y1; E.vx2[k] = x2; E.vy2[k] = y2;
+    double bx = ((x0 + x1) + x2) / 3.0;
+    double by = ((y0 + y1) + y2) / 3.0;
+    E.bx[k] = bx;
+    E.by[k] = by;
+    E.a2[k] = fabs((x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0));
+    double r = 0.0;
+    double px[3] = {x0, x1, x2}, py[3] = {y0, y1, y2};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        double dx = px[a] - bx, dy = py[a] - by;
+        r = fmax(r, sqrt(dx * dx + dy * dy));
+    }
+    E.r[k] = r;
+    const int nq = R->n_out;
+    for (int q = 0; q < nq; q++) {
+        const double l0 = R->out_lam[q][0], l1 = R->out_lam[q][1], l2 = R->out_lam[q][2];
+        xq[2 * ((int64_t)k * nq + q)] = (l0 * x0 + l1 * x1) + l2 * x2;
+        xq[2 * ((int64_t)k * nq + q) + 1] = (l0 * y0 + l1 * y1) + l2 * y2;
+    }
+}
+
+struct Grid {
+    double x0, y0, inv_cs;
+    int nx, ny;
+};
+
+__device__ __forceinline__ int cell_of(const Grid &g, double bx, double by, int *cx, int *cy)
+{
+    int ix = (int)floor((bx - g.x0) * g.inv_cs);
+    int iy = (int)floor((by - g.y0) * g.inv_cs);
+    ix = ix < 0 ? 0 : (ix >= g.nx ? g.nx - 1 : ix);
+    iy = iy < 0 ? 0 : (iy >= g.ny ? g.ny - 1 : iy);
+    *cx = ix;
+    *cy = iy;
+    return iy * g.nx + ix;
+}
+
+__global__ void k_bin_count(int K, ElemSoA E, Grid g, int32_t *__restrict__ cellof, int32_t *__restrict__ cnt)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    int cx, cy;
+    int c = cell_of(g, E.bx[k], E.by[k], &cx, &cy);
+    cellof[k] = c;
+    atomicAdd(&cnt[c], 1);
+}
+
+__global__ void k_bin_scatter(int K, const int32_t *__restrict__ cellof, const int32_t *__restrict__ start,
+                              int32_t *__restrict__ cursor, int32_t *__restrict__ elems)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    int c = cellof[k];
+    int slot = atomicAdd(&cursor[c], 1);
+    elems[start[c] + slot] = k;
+}
+
+// ---- the pair predicate (Eq. (baryball); tasks 2-4 of Sec. 7.1)
+__device__ __forceinline__ bool bary_in(double xx, double xy, double bx, double by, double dd)
+{
+    double dx = xx - bx, dy = xy - by;
+    return dx * dx + dy * dy <= dd;
+}
+
+__device__ __forceinline__ bool ball_meets(double xx, double xy, const double (&V)[6], double dd)
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
+        if (dx * dx + dy * dy <= dd) return true;
+    }
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        double o = ex * py - ey * px;
+        if (o < 0.0) inside = false;
+    }
+    if (inside) return true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        double t = ex * px + ey * py;
+        double L = ex * ex + ey * ey;
+        if (t > 0.0 && t < L) {
+            double c = ex * py - ey * px;
+            if (c * c <= dd * L) return true;
+        }
+    }
+    return false;
+}
+
+struct PairQuery {
+    Grid g;
+    const int32_t *cell_start;   // [ncell+1]
+    const int32_t *cell_elems;
+    const uint8_t *tin;
+    const double *xq;
+    double delta, dd;
+    int nq, ball, skip_ixi;
+};
+
+// candidate ranges of the 3x3 cells around element k
+__device__ __forceinline__ int gather_ranges(const PairQuery &Q, double bx, double by, int (&lo)[9], int (&n)[9])
+{
+    int cx, cy;
+    cell_of(Q.g, bx, by, &cx, &cy);
+    int tot = 0, i = 0;
+    for (int dy = -1; dy <= 1; dy++)
+        for (int dx = -1; dx <= 1; dx++, i++) {
+            int x = cx + dx, y = cy + dy;
+            if (x < 0 || y < 0 || x >= Q.g.nx || y >= Q.g.ny) {
+                lo[i] = 0;
+                n[i] = 0;
+                continue;
+            }
+            int c = y * Q.g.nx + x;
+            lo[i] = Q.cell_start[c];
+            n[i] = Q.cell_start[c + 1] - lo[i];
+            tot += n[i];
+        }
+    return tot;
+}
+
+__device__ __forceinline__ int candidate_at(const PairQuery &Q, const int (&lo)[9], const int (&n)[9], int i)
+{
+    int c = 0;
+    while (i >= n[c]) {
+        i -= n[c];
+        c++;
+    }
+    return Q.cell_elems[lo[c] + i];
+}
+
+__device__ __forceinline__ bool pair_test(const PairQuery &Q, const ElemSoA &E, int k, int kp, double bk_x, double bk_y,
+                                          double rk, const double *xs)
+{
+    if (Q.skip_ixi && !Q.tin[k] && !Q.tin[kp]) return false;
+    double bx = E.bx[kp], by = E.by[kp];
+    double reach = Q.delta + rk + (Q.ball == NLA_BALL_BARYCENTER ? 0.0 : E.r[kp]);
+    reach = reach * (1.0 + 1e-9) + 1e-14;
+    double ddx = bk_x - bx, ddy = bk_y - by;
+    if (!(ddx * ddx + ddy * ddy <= reach * reach)) return false;
+    if (Q.ball == NLA_BALL_BARYCENTER) {
+        for (int q = 0; q < Q.nq; q++)
+            if (bary_in(xs[2 * q], xs[2 * q + 1], bx, by, Q.dd)) return true;
+        return false;
+    }
+    double V[6] = {E.vx0[kp], E.vy0[kp], E.vx1[kp], E.vy1[kp], E.vx2[kp], E.vy2[kp]};
+    for (int q = 0; q < Q.nq; q++)
+        if (ball_meets(xs[2 * q], xs[2 * q + 1], V, Q.dd)) return true;
+    return false;
+}
+
+__global__ __launch_bounds__(256) void k_pair_count(int K, PairQuery Q, ElemSoA E, int32_t *__restrict__ cnt)
+{
+    __shared__ double xs[2 * NLA_MAX_OUTER];
+    __shared__ int red[256 / 64];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    if (tid < 2 * Q.nq) xs[tid] = Q.xq[2 * (int64_t)k * Q.nq + tid];
+    __syncthreads();
+    const double bx = E.bx[k], by = E.by[k], rk = E.r[k];
+    int lo[9], n[9];
+    const int tot = gather_ranges(Q, bx, by, lo, n);
+    int c = 0;
+    for (int i = tid; i < tot; i += blockDim.x) {
+        int kp = candidate_at(Q, lo, n, i);
+        c += pair_test(Q, E, k, kp, bx, by, rk, xs) ? 1 : 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = c;
+    __syncthreads();
+    if (tid == 0) {
+        int s = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) s += red[w];
+        cnt[k] = s;
+    }
+}
+
+// Emits the pairs of k: candidates are tested by the whole workgroup, hits
+// are compacted into LDS with a wavefront ballot and prefix popcount, and
+// then written in ascending k' order (each hit's rank = number of smaller hits).
+__global__ __launch_bounds__(256) void k_pair_emit(int K, PairQuery Q, ElemSoA E, const int64_t *__restrict__ ptr,
+                                                   int32_t *__restrict__ out)
+{
+    __shared__ double xs[2 * NLA_MAX_OUTER];
+    __shared__ int hits[NLA_MAX_PAIRS_PER_K];
+    __shared__ int nh;
+    const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    if (tid < 2 * Q.nq) xs[tid] = Q.xq[2 * (int64_t)k * Q.nq + tid];
+    if (tid == 0) nh = 0;
+    __syncthreads();
+    const double bx = E.bx[k], by = E.by[k], rk = E.r[k];
+    int lo[9], n[9];
+    const int tot = gather_ranges(Q, bx, by, lo, n);
+    const int rounds = (tot + (int)blockDim.x - 1) / (int)blockDim.x;
+    for (int r = 0; r < rounds; r++) {
+        int i = r * blockDim.x + tid;
+        int kp = -1;
+        bool hit = false;
+        if (i < tot) {
+            kp = candidate_at(Q, lo, n, i);
+            hit = pair_test(Q, E, k, kp, bx, by, rk, xs);
+        }
+        unsigned long long mask = __ballot(hit);
+        int wcnt = __popcll(mask);
+        int before = __popcll(mask & ((1ull << lane) - 1ull));
+        int base = 0;
+        if (lane == 0 && wcnt) base = atomicAdd(&nh, wcnt);
+        base = __shfl(base, 0, 64);
+        if (hit && base + before < NLA_MAX_PAIRS_PER_K) hits[base + before] = kp;
+    }
+    __syncthreads();
+    const int m = nh < NLA_MAX_PAIRS_PER_K ? nh : NLA_MAX_PAIRS_PER_K;
+    const int64_t o = ptr[k];
+    for (int i = tid; i < m; i += blockDim.x) {
+        int v = hits[i], rank = 0;
+        for (int j = 0; j < m; j++) rank += hits[j] < v;
+        out[o + rank] = v;
+    }
+}
+
+// ------------------------------------------------------ pattern kernels
+__global__ void k_pair_k(int K, const int64_t *__restrict__ ptr, int32_t *__restrict__ pk)
+{
+    int k = blockIdx.x;
+    for (int64_t p = ptr[k] + threadIdx.x; p < ptr[k + 1]; p += blockDim.x) pk[p] = k;
+}
+
+__global__ void k_appears(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, uint8_t *app)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    app[pk[p]] = 1;
+    app[pkp[p]] = 1;
+}
+
+__global__ void k_keys_pairs(int64_t P, int J, const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
+                             const int32_t *__restrict__ pkp, uint64_t *__restrict__ keys)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int k = pk[p], kp = pkp[p];
+    uint64_t g[3], h[3];
+    for (int a = 0; a < 3; a++) {
+        g[a] = (uint64_t)tri[3 * k + a];
+        h[a] = (uint64_t)tri[3 * kp + a];
+    }
+    uint64_t *o = keys + 18 * p;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            o[2 * (3 * a + b)] = g[a] * (uint64_t)J + h[b];
+            o[2 * (3 * a + b) + 1] = h[b] * (uint64_t)J + g[a];
+        }
+}
+
+__global__ void k_keys_elems(int K, int J, const int32_t *__restrict__ tri, const uint8_t *__restrict__ app,
+                             uint64_t sentinel, uint64_t *__restrict__ keys)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < 3; c++)
+            keys[9 * (int64_t)k + 3 * a + c] =
+                app[k] ? (uint64_t)tri[3 * k + a] * (uint64_t)J + (uint64_t)tri[3 * k + c] : sentinel;
+}
+
+__device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *a, int64_t n, uint64_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t lower_bound_u32(const uint32_t *a, int64_t n, uint32_t v)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_rowptr(int J, const uint64_t *__restrict__ uk, int64_t nnz, int64_t *__restrict__ rowptr)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > J) return;
+    rowptr[r] = lower_bound_u64(uk, nnz, (uint64_t)r * (uint64_t)J);
+}
+
+__global__ void k_cols(int64_t nnz, int J, const uint64_t *__restrict__ uk, int32_t *__restrict__ col,
+                       int64_t *__restrict__ mirror, uint8_t *__restrict__ upflag)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnz) return;
+    uint64_t key = uk[t];
+    uint64_t r = key / (uint64_t)J, c = key % (uint64_t)J;
+    col[t] = (int32_t)c;
+    mirror[t] = lower_bound_u64(uk, nnz, c * (uint64_t)J + r);
+    upflag[t] = r <= c;
+}
+
+__global__ void k_up_index(int64_t nnz, const uint8_t *__restrict__ upflag, const int64_t *__restrict__ upscan,
+                           int64_t *__restrict__ up_dst, int64_t *__restrict__ up_of)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnz) return;
+    if (upflag[t]) {
+        int64_t u = upscan[t];
+        up_dst[u] = t;
+        up_of[t] = u;
+    } else {
+        up_of[t] = -1;
+    }
+}
+
+__device__ __forceinline__ uint32_t upper_of(const uint64_t *uk, int64_t nnz, const int64_t *up_of, int J, int r, int c)
+{
+    int lo = r < c ? r : c, hi = r < c ? c : r;
+    int64_t t = lower_bound_u64(uk, nnz, (uint64_t)lo * (uint64_t)J + (uint64_t)hi);
+    return (uint32_t)up_of[t];
+}
+
+// contribution slots per pair: 9 Mxy, 3 for shared-node duplicates, 6 Myy
+__global__ void k_codes_pairs(int64_t P, int J, const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
+                              const int32_t *__restrict__ pkp, const uint64_t *__restrict__ uk, int64_t nnz,
+                              const int64_t *__restrict__ up_of, uint32_t sentinel, uint32_t *__restrict__ key,
+                              int32_t *__restrict__ code)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int k = pk[p], kp = pkp[p];
+    int g[3], h[3];
+    for (int a = 0; a < 3; a++) {
+        g[a] = tri[3 * k + a];
+        h[a] = tri[3 * kp + a];
+    }
+    uint32_t *ko = key + 18 * p;
+    int32_t *co = code + 18 * p;
+    int ndup = 0;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            uint32_t u = upper_of(uk, nnz, up_of, J, g[a], h[b]);
+            ko[3 * a + b] = u;
+            co[3 * a + b] = (int32_t)(9 * p + 3 * a + b);
+            if (g[a] == h[b]) {           // diagonal entry receives both mirrored terms
+                ko[9 + ndup] = u;
+                co[9 + ndup] = (int32_t)(9 * p + 3 * a + b);
+                ndup++;
+            }
+        }
+    for (int i = ndup; i < 3; i++) {
+        ko[9 + i] = sentinel;
+        co[9 + i] = -1;
+    }
+    const int bb[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    for (int i = 0; i < 6; i++) {
+        ko[12 + i] = upper_of(uk, nnz, up_of, J, h[bb[i][0]], h[bb[i][1]]);
+        co[12 + i] = (int32_t)(9 * P + 6 * p + i);
+    }
+}
+
+__global__ void k_codes_elems(int K, int64_t P, int J, const int32_t *__restrict__ tri, const int64_t *__restrict__ ptr,
+                              const uint64_t *__restrict__ uk, int64_t nnz, const int64_t *__restrict__ up_of,
+                              uint32_t sentinel, uint32_t *__restrict__ key, int32_t *__restrict__ code)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const int aa[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    bool has = ptr[k + 1] > ptr[k];
+    for (int i = 0; i < 6; i++) {
+        int64_t s = 18 * P + 6 * (int64_t)k + i;
+        if (has) {
+            key[s] = upper_of(uk, nnz, up_of, J, tri[3 * k + aa[i][0]], tri[3 * k + aa[i][1]]);
+            code[s] = (int32_t)(15 * P + 6 * (int64_t)k + i);
+        } else {
+            key[s] = sentinel;
+            code[s] = -1;
+        }
+    }
+}
+
+__global__ void k_up_ptr(int64_t n_up, const uint32_t *__restrict__ skeys, int64_t n, int64_t *__restrict__ up_ptr)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u > n_up) return;
+    up_ptr[u] = lower_bound_u32(skeys, n, (uint32_t)u);
+}
+
+__global__ void k_a_count(int n_free, const int32_t *__restrict__ free_nodes, const int64_t *__restrict__ rowptr,
+                          const int32_t *__restrict__ col, const int32_t *__restrict__ n2f, int64_t *__restrict__ cnt)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_free) return;
+    int r = free_nodes[i];
+    int64_t c = 0;
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) c += n2f[col[t]] >= 0;
+    cnt[i] = c;
+}
+
+__global__ void k_a_fill(int n_free, const int32_t *__restrict__ free_nodes, const int64_t *__restrict__ rowptr,
+                         const int32_t *__restrict__ col, const int32_t *__restrict__ n2f,
+                         const int64_t *__restrict__ a_rowptr, int32_t *__restrict__ a_col, int64_t *__restrict__ a_src)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_free) return;
+    int r = free_nodes[i];
+    int64_t o = a_rowptr[i];
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; t++) {
+        int f = n2f[col[t]];
+        if (f >= 0) {
+            a_col[o] = f;
+            a_src[o] = t;
+            o++;
+        }
+    }
+}
+
+// ------------------------------------------------------------ build steps
+static int bits_for(uint64_t v)
+{
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) b++;
+    return b < 1 ? 1 : b;
+}
+
+int nla_build_pairs(nla_plan *P, hipStream_t s)
+{
+    const int K = P->K;
+    const nla_problem &pr = P->prob;
+    // grid of barycenters with cells no smaller than the largest reach
+    std::vector<double> hx(2 * (size_t)P->J);
+    NLA_HIP(hipMemcpyAsync(hx.data(), P->xy, sizeof(double) * 2 * P->J, hipMemcpyDeviceToHost, s));
+    std::vector<double> hr(K);
+    NLA_HIP(hipMemcpyAsync(hr.data(), P->E.r, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    double xmin = hx[0], xmax = hx[0], ymin = hx[1], ymax = hx[1];
+    for (int j = 0; j < P->J; j++) {
+        xmin = std::min(xmin, hx[2 * j]); xmax = std::max(xmax, hx[2 * j]);
+        ymin = std::min(ymin, hx[2 * j + 1]); ymax = std::max(ymax, hx[2 * j + 1]);
+    }
+    double rmax = 0;
+    for (double r : hr) rmax = std::max(rmax, r);
+    double reach = pr.delta + rmax + (pr.ball == NLA_BALL_BARYCENTER ? 0.0 : rmax);
+    double cs = reach * (1.0 + 1e-6) + 1e-12;
+    Grid g;
+    g.x0 = xmin;
+    g.y0 = ymin;
+    g.inv_cs = 1.0 / cs;
+    g.nx = (int)std::floor((xmax - xmin) / cs) + 1;
+    g.ny = (int)std::floor((ymax - ymin) / cs) + 1;
+    if ((int64_t)g.nx * g.ny > (1 << 24)) { nla_set_error("binning grid too large"); return NLA_E_UNSUPPORTED; }
+    const int ncell = g.nx * g.ny;
+    Scratch S;
+    int32_t *cellof, *cnt, *start, *cursor, *elems, *pcnt;
+    NLA_TRY(S.get(&cellof, K));
+    NLA_TRY(S.get(&cnt, ncell));
+    NLA_TRY(S.get(&start, ncell + 1));
+    NLA_TRY(S.get(&cursor, ncell));
+    NLA_TRY(S.get(&elems, K));
+    NLA_TRY(S.get(&pcnt, K));
+    NLA_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * ncell, s));
+    NLA_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * ncell, s));
+    k_bin_count<<<grid_for(K, 256), 256, 0, s>>>(K, P->E, g, cellof, cnt);
+    std::vector<int32_t> hc(ncell), hs(ncell + 1);
+    NLA_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * ncell, hipMemcpyDeviceToHost, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    hs[0] = 0;
+    for (int c = 0; c < ncell; c++) hs[c + 1] = hs[c] + hc[c];
+    NLA_HIP(hipMemcpyAsync(start, hs.data(), sizeof(int32_t) * (ncell + 1), hipMemcpyHostToDevice, s));
+    k_bin_scatter<<<grid_for(K, 256), 256, 0, s>>>(K, cellof, start, cursor, elems);
+    PairQuery Q;
+    Q.g = g;
+    Q.cell_start = start;
+    Q.cell_elems = elems;
+    Q.tin = P->tin;
+    Q.xq = P->xq;
+    Q.delta = pr.delta;
+    Q.dd = pr.delta * pr.delta;
+    Q.nq = P->rules.n_out;
+    Q.ball = pr.ball;
+    Q.skip_ixi = (pr.flags & NLA_SKIP_IXI) ? 1 : 0;
+    k_pair_count<<<K, 256, 0, s>>>(K, Q, P->E, pcnt);
+    std::vector<int32_t> hp(K);
+    NLA_HIP(hipMemcpyAsync(hp.data(), pcnt, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> hptr(K + 1);
+    hptr[0] = 0;
+    int maxc = 0;
+    for (int k = 0; k < K; k++) {
+        hptr[k + 1] = hptr[k] + hp[k];
+        maxc = std::max(maxc, hp[k]);
+    }
+    if (maxc > NLA_MAX_PAIRS_PER_K) {
+        nla_set_error("an element has %d interacting elements (limit %d)", maxc, NLA_MAX_PAIRS_PER_K);
+        return NLA_E_UNSUPPORTED;
+    }
+    P->n_pairs = hptr[K];
+    if (15 * P->n_pairs + 6 * (int64_t)K >= (int64_t)INT32_MAX) {
+        nla_set_error("too many pairs (%lld) for 32-bit contribution codes", (long long)P->n_pairs);
+        return NLA_E_UNSUPPORTED;
+    }
+    NLA_TRY(P->arena.get(&P->pair_ptr, K + 1));
+    NLA_TRY(P->arena.get(&P->pair_kp, P->n_pairs));
+    NLA_TRY(P->arena.get(&P->pair_k, P->n_pairs));
+    NLA_HIP(hipMemcpyAsync(P->pair_ptr, hptr.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, s));
+    k_pair_emit<<<K, 256, 0, s>>>(K, Q, P->E, P->pair_ptr, P->pair_kp);
+    k_pair_k<<<K, 256, 0, s>>>(K, P->pair_ptr, P->pair_k);
+    NLA_HIP(hipGetLastError());
+    NLA_HIP(hipStreamSynchronize(s));
+    return NLA_OK;
+}
+
+int nla_build_pattern(nla_plan *P, hipStream_t s)
+{
+    const int K = P->K, J = P->J;
+    const int64_t NP = P->n_pairs;
+    Scratch S;
+    uint8_t *app;
+    NLA_TRY(S.get(&app, K));
+    NLA_HIP(hipMemsetAsync(app, 0, K, s));
+    if (NP > 0) k_appears<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->pair_k, P->pair_kp, app);
+    const int64_t nkeys = 18 * NP + 9 * (int64_t)K;
+    const uint64_t sentinel = (uint64_t)J * (uint64_t)J;
+    uint64_t *keys, *skeys, *ukeys;
+    NLA_TRY(S.get(&keys, nkeys));
+    NLA_TRY(S.get(&skeys, nkeys));
+    if (NP > 0) k_keys_pairs<<<grid_for(NP, 256), 256, 0, s>>>(NP, J, P->tri, P->pair_k, P->pair_kp, keys);
+    k_keys_elems<<<grid_for(K, 256), 256, 0, s>>>(K, J, P->tri, app, sentinel, keys + 18 * NP);
+    const int kbits = bits_for(sentinel);
+    size_t tb = 0;
+    NLA_HIP(rocprim::radix_sort_keys(nullptr, tb, keys, skeys, (size_t)nkeys, 0, kbits, s));
+    void *tmp;
+    NLA_TRY(S.get((char **)&tmp, tb));
+    NLA_HIP(rocprim::radix_sort_keys(tmp, tb, keys, skeys, (size_t)nkeys, 0, kbits, s));
+    // unique keys -> pattern (reuse `keys` as output)
+    ukeys = keys;
+    int64_t *nuniq;
+    NLA_TRY(S.get(&nuniq, 1));
+    size_t tb2 = 0;
+    NLA_HIP(rocprim::unique(nullptr, tb2, skeys, ukeys, nuniq, (size_t)nkeys, rocprim::equal_to<uint64_t>(), s));
+    void *tmp2;
+    NLA_TRY(S.get((char **)&tmp2, tb2));
+    NLA_HIP(rocprim::unique(tmp2, tb2, skeys, ukeys, nuniq, (size_t)nkeys, rocprim::equal_to<uint64_t>(), s));
+    int64_t hu = 0;
+    NLA_HIP(hipMemcpyAsync(&hu, nuniq, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    uint64_t last = 0;
+    NLA_HIP(hipMemcpy(&last, ukeys + hu - 1, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    const int64_t nnz = (last == sentinel) ? hu - 1 : hu;
+    P->nnz = nnz;
+    NLA_TRY(P->arena.get(&P->rowptr, J + 1));
+    NLA_TRY(P->arena.get(&P->col, nnz));
+    NLA_TRY(P->arena.get(&P->mirror, nnz));
+    uint8_t *upflag;
+    int64_t *upscan, *up_of;
+    NLA_TRY(S.get(&upflag, nnz));
+    NLA_TRY(S.get(&upscan, nnz));
+    NLA_TRY(S.get(&up_of, nnz));
+    k_rowptr<<<grid_for(J + 1, 256), 256, 0, s>>>(J, ukeys, nnz, P->rowptr);
+    k_cols<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, J, ukeys, P->col, P->mirror, upflag);
+    // exclusive scan of the upper-triangle flags (host; one-time, nnz bytes)
+    std::vector<uint8_t> hf(nnz);
+    NLA_HIP(hipMemcpyAsync(hf.data(), upflag, nnz, hipMemcpyDeviceToHost, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> hsc(nnz);
+    int64_t acc = 0;
+    for (int64_t t = 0; t < nnz; t++) {
+        hsc[t] = acc;
+        acc += hf[t];
+    }
+    P->n_up = acc;
+    NLA_HIP(hipMemcpyAsync(upscan, hsc.data(), sizeof(int64_t) * nnz, hipMemcpyHostToDevice, s));
+    NLA_TRY(P->arena.get(&P->up_dst, P->n_up));
+    k_up_index<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, upflag, upscan, P->up_dst, up_of);
+    // contribution codes, sorted by upper entry (stable: generation order within an entry)
+    const int64_t nslots = 18 * NP + 6 * (int64_t)K;
+    const uint32_t csent = (uint32_t)P->n_up;
+    uint32_t *ck, *sck;
+    int32_t *cv, *scv;
+    NLA_TRY(S.get(&ck, nslots));
+    NLA_TRY(S.get(&sck, nslots));
+    NLA_TRY(S.get(&cv, nslots));
+    NLA_TRY(S.get(&scv, nslots));
+    if (NP > 0)
+        k_codes_pairs<<<grid_for(NP, 256), 256, 0, s>>>(NP, J, P->tri, P->pair_k, P->pair_kp, ukeys, nnz, up_of, csent,
+                                                        ck, cv);
+    k_codes_elems<<<grid_for(K, 256), 256, 0, s>>>(K, NP, J, P->tri, P->pair_ptr, ukeys, nnz, up_of, csent, ck, cv);
+    const int cbits = bits_for((uint64_t)csent);
+    size_t tb3 = 0;
+    NLA_HIP(rocprim::radix_sort_pairs(nullptr, tb3, ck, sck, cv, scv, (size_t)nslots, 0, cbits, s));
+    void *tmp3;
+    NLA_TRY(S.get((char **)&tmp3, tb3));
+    NLA_HIP(rocprim::radix_sort_pairs(tmp3, tb3, ck, sck, cv, scv, (size_t)nslots, 0, cbits, s));
+    NLA_TRY(P->arena.get(&P->up_ptr, P->n_up + 1));
+    k_up_ptr<<<grid_for(P->n_up + 1, 256), 256, 0, s>>>(P->n_up, sck, nslots, P->up_ptr);
+    int64_t ncodes = 0;
+    NLA_HIP(hipMemcpyAsync(&ncodes, P->up_ptr + P->n_up, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    P->n_codes = ncodes;
+    NLA_TRY(P->arena.get(&P->codes, ncodes));
+    NLA_HIP(hipMemcpyAsync(P->codes, scv, sizeof(int32_t) * ncodes, hipMemcpyDeviceToDevice, s));
+    // A = D[free, free]
+    const int nf = P->n_free;
+    if (nf > 0) {
+        int64_t *acnt;
+        NLA_TRY(S.get(&acnt, nf));
+        k_a_count<<<grid_for(nf, 256), 256, 0, s>>>(nf, P->free_nodes, P->rowptr, P->col, P->node_to_free, acnt);
+        std::vector<int64_t> hac(nf), har(nf + 1);
+        NLA_HIP(hipMemcpyAsync(hac.data(), acnt, sizeof(int64_t) * nf, hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+        har[0] = 0;
+        for (int i = 0; i < nf; i++) har[i + 1] = har[i] + hac[i];
+        P->nnz_free = har[nf];
+        NLA_TRY(P->arena.get(&P->a_rowptr, nf + 1));
+        NLA_TRY(P->arena.get(&P->a_col, P->nnz_free));
+        NLA_TRY(P->arena.get(&P->a_src, P->nnz_free));
+        NLA_HIP(hipMemcpyAsync(P->a_rowptr, har.data(), sizeof(int64_t) * (nf + 1), hipMemcpyHostToDevice, s));
+        k_a_fill<<<grid_for(nf, 256), 256, 0, s>>>(nf, P->free_nodes, P->rowptr, P->col, P->node_to_free, P->a_rowptr,
+                                                    P->a_col, P->a_src);
+    }
+    NLA_HIP(hipGetLastError());
+    NLA_HIP(hipStreamSynchronize(s));
+    return NLA_OK;
+}
+
+// ------------------------------------------------------------------- API
+static void fill_rules(const nla_problem *p, RuleSet *R)
+{
+    memset(R, 0, sizeof(*R));
+    R->n_out = p->outer.n;
+    R->n_in = p->inner.n;
+    for (int q = 0; q < p->outer.n; q++) {
+        for (int a = 0; a < 3; a++) R->out_lam[q][a] = p->outer.lambda[3 * q + a];
+        R->out_w[q] = p->outer.w[q];
+    }
+    for (int q = 0; q < p->inner.n; q++) {
+        for (int a = 0; a < 3; a++) R->in_lam[q][a] = p->inner.lambda[3 * q + a];
+        R->in_w[q] = p->inner.w[q];
+        R->in_wsum += p->inner.w[q];
+        for (int i = 0; i < 3; i++) {
+            R->in_m1[i] += p->inner.w[q] * p->inner.lambda[3 * q + i];
+            for (int j = 0; j < 3; j++)
+                R->in_m2[i][j] += p->inner.w[q] * p->inner.lambda[3 * q + i] * p->inner.lambda[3 * q + j];
+        }
+    }
+    if (p->kernel == NLA_KERNEL_FRACTIONAL) {
+        R->duffy_n = p->duffy_n;
+        for (int i = 0; i < p->duffy_n; i++) {
+            R->duffy_x[i] = p->duffy_x[i];
+            R->duffy_w[i] = p->duffy_w[i];
+        }
+    }
+}
+
+static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, nla_plan *P)
+{
+    NLA_HIP(hipGetDevice(&P->device));
+    P->K = m->n_triangles;
+    P->J = m->n_vertices;
+    P->prob = *p;
+    P->prob.duffy_x = nullptr;
+    P->prob.duffy_w = nullptr;
+    P->prob.outer.lambda = P->prob.outer.w = nullptr;
+    P->prob.inner.lambda = P->prob.inner.w = nullptr;
+    fill_rules(p, &P->rules);
+    const int K = P->K, J = P->J;
+    NLA_TRY(P->arena.get(&P->d_rules, 1));
+    NLA_TRY(P->arena.get(&P->xy, 2 * (size_t)J));
+    NLA_TRY(P->arena.get(&P->tri, 3 * (size_t)K));
+    NLA_TRY(P->arena.get(&P->tin, K));
+    NLA_TRY(P->arena.get(&P->nfree, J));
+    double *eb;
+    NLA_TRY(P->arena.get(&eb, 10 * (size_t)K));
+    double **f[10] = {&P->E.vx0, &P->E.vy0, &P->E.vx1, &P->E.vy1, &P->E.vx2, &P->E.vy2,
+                      &P->E.bx, &P->E.by, &P->E.a2, &P->E.r};
+    for (int i = 0; i < 10; i++) *f[i] = eb + (size_t)i * K;
+    NLA_TRY(P->arena.get(&P->xq, 2 * (size_t)K * P->rules.n_out));
+    NLA_HIP(hipMemcpyAsync(P->d_rules, &P->rules, sizeof(RuleSet), hipMemcpyHostToDevice, s));
+    NLA_HIP(hipMemcpyAsync(P->xy, m->xy, sizeof(double) * 2 * J, hipMemcpyHostToDevice, s));
+    NLA_HIP(hipMemcpyAsync(P->tri, m->tri, sizeof(int32_t) * 3 * K, hipMemcpyHostToDevice, s));
+    NLA_HIP(hipMemcpyAsync(P->tin, m->tri_in_omega, K, hipMemcpyHostToDevice, s));
+    NLA_HIP(hipMemcpyAsync(P->nfree, m->node_free, J, hipMemcpyHostToDevice, s));
+    // free nodes, node -> free index, node -> Omega element adjacency (host, mesh only)
+    std::vector<int32_t> fn, n2f(J, -1);
+    for (int j = 0; j < J; j++)
+        if (m->node_free[j]) {
+            n2f[j] = (int32_t)fn.size();
+            fn.push_back(j);
+        }
+    P->n_free = (int32_t)fn.size();
+    std::vector<int32_t> n2e_ptr(J + 1, 0), n2e;
+    for (int k = 0; k < K; k++)
+        if (m->tri_in_omega[k])
+            for (int a = 0; a < 3; a++) n2e_ptr[m->tri[3 * k + a] + 1]++;
+    for (int j = 0; j < J; j++) n2e_ptr[j + 1] += n2e_ptr[j];
+    n2e.resize(n2e_ptr[J]);
+    std::vector<int32_t> fill(n2e_ptr.begin(), n2e_ptr.end() - 1);
+    for (int k = 0; k < K; k++)
+        if (m->tri_in_omega[k])
+            for (int a = 0; a < 3; a++) n2e[fill[m->tri[3 * k + a]]++] = 3 * k + a;
+    NLA_TRY(P->arena.get(&P->free_nodes, fn.size()));
+    NLA_TRY(P->arena.get(&P->node_to_free, J));
+    NLA_TRY(P->arena.get(&P->n2e_ptr, J + 1));
+    NLA_TRY(P->arena.get(&P->n2e, n2e.size()));
+    if (!fn.empty()) NLA_HIP(hipMemcpyAsync(P->free_nodes, fn.data(), sizeof(int32_t) * fn.size(), hipMemcpyHostToDevice, s));
+    NLA_HIP(hipMemcpyAsync(P->node_to_free, n2f.data(), sizeof(int32_t) * J, hipMemcpyHostToDevice, s));
+    NLA_HIP(hipMemcpyAsync(P->n2e_ptr, n2e_ptr.data(), sizeof(int32_t) * (J + 1), hipMemcpyHostToDevice, s));
+    if (!n2e.empty()) NLA_HIP(hipMemcpyAsync(P->n2e, n2e.data(), sizeof(int32_t) * n2e.size(), hipMemcpyHostToDevice, s));
+    k_elem<<<grid_for(K, 128), 128, 0, s>>>(K, P->xy, P->tri, P->E, P->d_rules, P->xq);
+    NLA_HIP(hipGetLastError());
+    NLA_TRY(nla_build_pairs(P, s));
+    NLA_TRY(nla_build_pattern(P, s));
+    NLA_TRY(P->arena.get(&P->counters, 5));
+    return NLA_OK;
+}
+
+extern "C" int nla_plan_create(const nla_mesh *mesh, const nla_problem *prob, void *stream, nla_plan **out)
+{
+    if (!out) { nla_set_error("out is null"); return NLA_E_INVALID; }
+    *out = nullptr;
+    int st = validate(mesh, prob);
+    if (st != NLA_OK) return st;
+    nla_plan *P = new (std::nothrow) nla_plan();
+    if (!P) { nla_set_error("host allocation failed"); return NLA_E_NOMEM; }
+    try {
+        st = plan_create(mesh, prob, (hipStream_t)stream, P);
+    } catch (...) {
+        nla_set_error("unexpected exception in plan creation");
+        st = NLA_E_DEVICE;
+    }
+    if (st != NLA_OK) {
+        delete P;
+        return st;
+    }
+    *out = P;
+    return NLA_OK;
+}
+
+extern "C" int nla_plan_info(const nla_plan *P, nla_info *info)
+{
+    if (!P || !info) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    info->n_pairs = P->n_pairs;
+    info->nnz_full = P->nnz;
+    info->nnz_free = P->nnz_free;
+    info->n_free = P->n_free;
+    info->n_outer = P->rules.n_out;
+    info->n_codes = P->n_codes;
+    info->n_near = P->n_near;
+    unsigned long long c[5] = {0, 0, 0, 0, 0};
+    if (P->assembled) NLA_HIP(hipMemcpy(c, P->counters, sizeof(c), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 4; i++) info->items[i] = (int64_t)c[i];
+    info->subtriangles = (int64_t)c[4];
+    return NLA_OK;
+}
+
+extern "C" int nla_pairs_view(const nla_plan *P, const int64_t **pair_ptr, const int32_t **pair_kp)
+{
+    if (!P || !pair_ptr || !pair_kp) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    *pair_ptr = P->pair_ptr;
+    *pair_kp = P->pair_kp;
+    return NLA_OK;
+}
+
+extern "C" int nla_outer_points(const nla_plan *P, double *xq, void *stream)
+{
+    if (!P || !xq) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    NLA_HIP(hipMemcpyAsync(xq, P->xq, sizeof(double) * 2 * (size_t)P->K * P->rules.n_out, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return NLA_OK;
+}
+
+extern "C" int nla_csr_view(const nla_plan *P, int32_t which, const int64_t **rowptr, const int32_t **col,
+                            const void **val, int32_t *val_dtype)
+{
+    if (!P || !rowptr || !col || !val || !val_dtype) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    if (which != 0 && which != 1) { nla_set_error("which must be 0 or 1"); return NLA_E_INVALID; }
+    if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
+    *rowptr = which ? P->a_rowptr : P->rowptr;
+    *col = which ? P->a_col : P->col;
+    *val = which ? P->a_val : P->val;
+    *val_dtype = P->val_dtype;
+    return NLA_OK;
+}
+
+extern "C" int nla_load_view(const nla_plan *P, const double **b)
+{
+    if (!P || !b) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    if (!P->have_load) { nla_set_error("no load vector assembled"); return NLA_E_STATE; }
+    *b = P->b;
+    return NLA_OK;
+}
+
+extern "C" int nla_free_nodes_view(const nla_plan *P, const int32_t **free_nodes)
+{
+    if (!P || !free_nodes) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    *free_nodes = P->free_nodes;
+    return NLA_OK;
+}
+
+extern "C" int nla_blocks_view(const nla_plan *P, const void **mxy, const void **myy, const void **mxx,
+                               const void **near, const int64_t **near_pair, int32_t *dtype)
+{
+    if (!P || !mxy || !myy || !mxx || !near || !near_pair || !dtype) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
+    const size_t es = P->val_dtype == NLA_DTYPE_F64 ? 8 : 4;
+    const char *c = (const char *)P->contrib;
+    *mxy = c;
+    *myy = c + es * 9 * P->n_pairs;
+    *mxx = c + es * 15 * P->n_pairs;
+    *near = c + es * (15 * P->n_pairs + 6 * (int64_t)P->K);
+    *near_pair = P->near_pair;
+    *dtype = P->val_dtype;
+    return NLA_OK;
+}
+
+extern "C" int nla_cg(const nla_plan *P, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+                      double *relres, void *stream)
+{
+    if (!P || !b || !u || !iters || !relres) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
+    if (maxit < 1 || !(rtol > 0)) { nla_set_error("maxit >= 1 and rtol > 0 required"); return NLA_E_INVALID; }
+    return nla_cg_run(P, b, u, rtol, maxit, iters, relres, (hipStream_t)stream);
+}
+
+extern "C" int nla_assemble(nla_plan *P, const double *f_outer, const double *g_node, void *stream)
+{
+    if (!P) { nla_set_error("null plan"); return NLA_E_INVALID; }
+    if ((f_outer == nullptr) != (g_node == nullptr)) { nla_set_error("pass both f_outer and g_node, or neither"); return NLA_E_INVALID; }
+    return nla_numeric(P, f_outer, g_node, (hipStream_t)stream);
+}
+
+extern "C" void nla_plan_destroy(nla_plan *P) { delete P; }
