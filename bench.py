@@ -1,0 +1,186 @@
+"""Benchmark: numeric assembly throughput of the nonlocal P1 stiffness matrix.
+
+One step = one nla_assemble (pair quadrature, segmented sum into the CSR of
+D, extraction of A, load vector) of the 8-arc-cap retriangulated-ball
+workload on the jittered h = delta/8 mesh (delta = 0.1, constant kernel,
+7-point outer x 16-point inner rules, FP64), inputs resident on the GPU.
+Prints one JSON line.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "element-pair quadratures/s + assembly time, learned/FP32 vs FP64 plain at L2 err"
+FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
+
+# Algorithmic FP64 operations of the pair kernel per unit of work (counted
+# from the arithmetic the method needs per unit; an FMA counts 2, sqrt, div
+# and transcendental calls count 1).
+COST = dict(item=15,           # classification: 3 squared vertex distances
+            whole=6,           # whole item: outer-weight sums and S0
+            partial=114,       # polygon walk (3 edge quadratics, basis map, roots) + owner accumulation
+            subtriangle=115,   # factorised inner rule on one subtriangle (area, S1, S2)
+            cap=20,            # arc span, chord midpoint, rotation step
+            arc_point=16,      # one rotated arc point and its basis values
+            pair=45)           # per-pair accumulator set-up and output
+
+
+def algorithmic_flops(info, n_pairs, ncap):
+    it = info["items"]
+    items = it["whole"] + it["partial"] + it["empty"]
+    return (COST["item"] * items + COST["whole"] * it["whole"] + COST["partial"] * it["partial"] +
+            COST["subtriangle"] * info["subtriangles"] + COST["cap"] * info["caps"] +
+            COST["arc_point"] * info["caps"] * max(ncap - 1, 0) + COST["pair"] * n_pairs)
+
+
+def l2_error(mesh, U, u_exact):
+    """||u - u_h|| on Omega with the degree-5 7-point rule (exact for quadratic u)."""
+    from workloads import get_rule
+    r = get_rule("dunavant7")
+    ks = np.nonzero(mesh.tri_in_omega)[0]
+    V = mesh.xy[mesh.tri[ks]]                       # [n,3,2]
+    a2 = np.abs((V[:, 1, 0] - V[:, 0, 0]) * (V[:, 2, 1] - V[:, 0, 1]) -
+                (V[:, 1, 1] - V[:, 0, 1]) * (V[:, 2, 0] - V[:, 0, 0]))
+    X = np.einsum("qa,nac->nqc", r.lam, V)
+    uh = np.einsum("qa,na->nq", r.lam, U[mesh.tri[ks]])
+    e = (u_exact(X[..., 0], X[..., 1]) - uh) ** 2
+    return float(math.sqrt(np.sum(e * r.w[None, :] * a2[:, None])))
+
+
+def source_digest():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2005_10775_amd", "csrc", "nla_numeric.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel, digest):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or was taken on other source."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_digest") != digest:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(mesh, prob, sample_elems):
+    """The FP64 oracle timed on a bounded sample of outer elements (all their
+    pairs: search + local blocks), on this host's cores."""
+    import oracle
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    op = oracle.OracleProblem(mesh, prob)
+    K = mesh.n_triangles
+    n = min(sample_elems, K)
+    k0 = (K - n) // 2            # a band of whole mesh rows through the middle (layer and Omega)
+    t0 = time.perf_counter()
+    total, _ = oracle.blocks_range(op, k0, k0 + n, cores)
+    dt = time.perf_counter() - t0
+    return {"value": total / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+            "sample": "outer elements [%d, %d) of %d with all their pairs (%d pairs), %.2f s wall" % (
+                k0, k0 + n, K, total, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="outer elements in the CPU-baseline sample")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the assembler shards by outer element across GPUs only in design "
+              "(see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2005_10775_amd import Plan
+    from workloads import make_config, manufactured
+
+    torch.cuda.set_device(0)
+    mesh, prob, man = make_config(args.config)
+    u, f = manufactured(man)
+    t0 = time.perf_counter()
+    plan = Plan(mesh, prob)
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    xq = plan.outer_points()
+    fo = f(xq[..., 0], xq[..., 1]).contiguous()
+    g = torch.tensor(u(mesh.xy[:, 0], mesh.xy[:, 1]), dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        plan.assemble(fo, g)
+    plan.set_timing(args.steps)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.assemble(fo, g)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    phase, ntimed = plan.timings()
+    assert ntimed == args.steps
+    info = plan.info()
+    n_pairs = info["n_pairs"]
+    value = n_pairs / (ms * 1e-3)
+
+    # roofline of the dominant kernel (pair quadrature): algorithmic FP64 work per launch
+    flops = algorithmic_flops(info, n_pairs, prob.cap_edges if prob.ball == "retri" else 0)
+    t_pair = phase["pairs"] * 1e-3
+    achieved = flops / t_pair / 1e12
+    digest = source_digest()
+    roofline = {"bound": "alu", "kernel": "k_pairs_const_fp64", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                "traffic": traffic_from_profile("k_pairs_const_fp64", digest),
+                "flops_per_launch": flops, "kernel_ms": phase["pairs"]}
+
+    # validation solve and L2 error (outside the timed region)
+    U, its, rel = plan.cg(plan.load(), rtol=1e-12)
+    Ufull = u(mesh.xy[:, 0], mesh.xy[:, 1]).copy()
+    Ufull[plan.free_nodes().cpu().numpy()] = U.cpu().numpy()
+    l2 = l2_error(mesh, Ufull, u)
+
+    out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if prob.precision == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": "%s: delta=%g h=%g K=%d %s%s %sx%s %s kernel" % (
+               args.config, prob.delta, mesh.h, mesh.n_triangles, prob.ball,
+               "-%d-arc caps" % prob.cap_edges if prob.ball == "retri" else "", prob.outer, prob.inner, prob.kernel),
+               "n_pairs": n_pairs, "nnz_full": info["nnz_full"], "n_free": info["n_free"],
+               "jitter": mesh.meta.get("jitter", 0.0)},
+           "assembly_ms": ms, "plan_ms": plan_ms, "phase_ms": phase,
+           "items": info["items"], "subtriangles": info["subtriangles"], "caps": info["caps"],
+           "l2_err": l2, "cg": {"iters": its, "relres": rel},
+           "roofline": roofline, "source_digest": digest}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mesh, prob, args.cpu_sample)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -115,7 +115,12 @@ typedef struct {
     int64_t n_near;              /* vertex-sharing pairs handled by the singular rule */
     int64_t items[4];            /* after nla_assemble: (k,q,k') items whole, partial, empty, learned */
     int64_t subtriangles;        /* after nla_assemble: polygon + cap triangles integrated */
+    int64_t caps;                /* after nla_assemble: caps filled with triangles */
 } nla_info;
+
+/* phases timed by nla_last_timings */
+enum { NLA_PHASE_PAIRS = 0, NLA_PHASE_NEAR = 1, NLA_PHASE_SEGSUM = 2, NLA_PHASE_EXTRACT = 3, NLA_PHASE_LOAD = 4,
+       NLA_NPHASE = 5 };
 
 const char *nla_last_error(void);
 
@@ -154,13 +159,17 @@ int nla_load_view(const nla_plan *plan, const double **b);
 /* Free-node indices [n_free] (device int32, increasing). */
 int nla_free_nodes_view(const nla_plan *plan, const int32_t **free_nodes);
 
-/* Per-pair local blocks (test hook): mxy [n_pairs][9] holds -Mxy_ab (row-major a,b),
- * myy [n_pairs][6] holds Myy (b<=b': 00,01,02,11,12,22), mxx [K][6] holds the
- * element block Mxx (same order).  Entries of vertex-sharing pairs under the
- * singular rule are in near [n_near][21] (upper triangle of the 6x6 slot block,
- * row-major) with their pair indices in near_pair [n_near].  dtype as in nla_csr_view. */
-int nla_blocks_view(const nla_plan *plan, const void **mxy, const void **myy, const void **mxx,
-                    const void **near, const int64_t **near_pair, int32_t *dtype);
+/* Intermediate blocks (test hook), device views valid as for the CSR views:
+ *   myy  [n_pairs][6]  Myy of each pair (b<=b': 00,01,02,11,12,22);
+ *   mxx  [K][6]        Mxx of each outer element (same order);
+ *   elem [K][6]        element block E(k) = Mxx(k) + sum_k' Myy(k', k);
+ *   rows               for outer element k, the row block R_k [3][|C_k|] at
+ *                      offset 3*col_off[k]: R_k[a][c] = -sum over pairs (k,k') and
+ *                      slots b with node(k',b) = colset[col_off[k]+c] of Mxy_ab;
+ *   col_off [K+1] (int64) and colset [sum |C_k|] (int32, nodes ascending per k).
+ * dtype as in nla_csr_view. */
+int nla_blocks_view(const nla_plan *plan, const void **myy, const void **mxx, const void **elem, const void **rows,
+                    const int64_t **col_off, const int32_t **colset, int32_t *dtype);
 
 /* Conjugate gradients on A (after nla_assemble): b [n_free] device, u [n_free]
  * device (in: x0, out: solution), FP64 residuals and fixed-order dot
@@ -168,6 +177,14 @@ int nla_blocks_view(const nla_plan *plan, const void **mxy, const void **myy, co
  * if ||r|| > rtol ||b|| after maxit iterations. */
 int nla_cg(const nla_plan *plan, const double *b, double *u, double rtol, int32_t maxit,
            int32_t *iters, double *relres, void *stream);
+
+/* Timing: nla_set_timing(plan, n) with n > 0 makes the next n calls of
+ * nla_assemble record HIP events on their stream around each phase (n = 0
+ * turns it off).  nla_timings waits for the last recorded event and writes
+ * the mean elapsed milliseconds per phase over those calls (ms[NLA_NPHASE],
+ * host; 0 for phases that did not run) and how many calls were timed. */
+int nla_set_timing(nla_plan *plan, int32_t n);
+int nla_timings(const nla_plan *plan, double *ms, int32_t *count);
 
 void nla_plan_destroy(nla_plan *plan);
 

@@ -6,9 +6,9 @@ import this package.  ``liboracle.so`` is built from ``nlo.c`` (plain C99,
 plain dense/CG solves and the L2 error of Sec. 8.
 """
 from .binding import (build, OracleProblem, assemble, pairs_of, pair_block, row,
-                      load_vector, outer_points, inner_sums, region, census,
+                      load_vector, outer_points, inner_sums, region, census, blocks_range,
                       system_from_full, cg, l2_error, solve_problem)
 
 __all__ = ["build", "OracleProblem", "assemble", "pairs_of", "pair_block", "row",
-           "load_vector", "outer_points", "inner_sums", "region", "census",
+           "load_vector", "outer_points", "inner_sums", "region", "census", "blocks_range",
            "system_from_full", "cg", "l2_error", "solve_problem"]

@@ -66,6 +66,8 @@ def _lib():
         L.nlo_row.restype = C.c_int
         L.nlo_load.argtypes = [P, P, P, P]
         L.nlo_outer_points.argtypes = [P, P, P]
+        L.nlo_blocks_range.argtypes = [P, P, I32, I32, I32, P]
+        L.nlo_blocks_range.restype = I64
         L.nlo_flops_census.argtypes = [P, P, I32, I32, P]
         L.nlo_flops_census.restype = I64
         _LIB = L
@@ -220,6 +222,14 @@ def region(op, x, tri_xy, cap=2048):
     if n < 0:
         raise RuntimeError("region status %d" % n)
     return sub[:6 * n].reshape(n, 3, 2).copy(), cp[:2 * nc.value].reshape(-1, 2).copy(), cw[:nc.value].copy()
+
+
+def blocks_range(op, k0, k1, nthreads=0):
+    """Pair lists + local blocks of outer elements [k0, k1); returns (pairs, checksum)."""
+    L = _lib()
+    cs = C.c_double()
+    n = L.nlo_blocks_range(*op.args, int(k0), int(k1), int(nthreads), C.byref(cs))
+    return n, cs.value
 
 
 def census(op, k0=0, k1=None):

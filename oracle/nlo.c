@@ -759,3 +759,34 @@ int64_t nlo_flops_census(const nlo_mesh *m, const nlo_problem *p, int32_t k0, in
     elem_free(&e);
     return out[0];
 }
+
+/* Pair lists and local blocks of the outer elements [k0, k1), threads over
+ * k; returns the number of pairs and a checksum of the blocks.  Used to time
+ * the oracle on a bounded sample of a workload. */
+int64_t nlo_blocks_range(const nlo_mesh *m, const nlo_problem *p, int32_t k0, int32_t k1, int32_t nthreads,
+                         double *checksum)
+{
+    elemdata e = elem_precompute(m);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int64_t total = 0;
+    double cs = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total, cs)
+    for (int k = k0; k < k1; k++) {
+        int32_t *kp = (int32_t *)malloc(sizeof(int32_t) * m->nt);
+        int n = pairs_of(m, p, &e, k, kp, m->nt);
+        for (int t = 0; t < n; t++) {
+            double mxy[9], myy[9], s0q[64], blk[36];
+            nlo_pair_block(m, p, k, kp[t], mxy, myy, s0q, blk);
+            cs += blk[0] + blk[9];
+        }
+        total += n;
+        free(kp);
+    }
+    elem_free(&e);
+    *checksum = cs;
+    return total;
+}

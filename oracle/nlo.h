@@ -56,6 +56,8 @@ void nlo_result_free(nlo_result *r);
 int nlo_row(const nlo_mesh *m, const nlo_problem *p, int32_t j, int32_t *cols, double *vals, int32_t cap);
 void nlo_load(const nlo_mesh *m, const nlo_problem *p, const double *f_outer, double *G);
 void nlo_outer_points(const nlo_mesh *m, const nlo_problem *p, double *xq);
+int64_t nlo_blocks_range(const nlo_mesh *m, const nlo_problem *p, int32_t k0, int32_t k1, int32_t nthreads,
+                         double *checksum);
 int64_t nlo_flops_census(const nlo_mesh *m, const nlo_problem *p, int32_t k0, int32_t k1, int64_t out[8]);
 #ifdef __cplusplus
 }

@@ -48,7 +48,11 @@ class nla_problem(C.Structure):
 class nla_info(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("nnz_full", C.c_int64), ("nnz_free", C.c_int64),
                 ("n_free", C.c_int32), ("n_outer", C.c_int32), ("n_codes", C.c_int64),
-                ("n_near", C.c_int64), ("items", C.c_int64 * 4), ("subtriangles", C.c_int64)]
+                ("n_near", C.c_int64), ("items", C.c_int64 * 4), ("subtriangles", C.c_int64),
+                ("caps", C.c_int64)]
+
+
+PHASES = ("pairs", "near", "segsum", "extract", "load")
 
 
 _LIB = None
@@ -73,12 +77,15 @@ def lib():
         L.nla_load_view.argtypes = [P, C.POINTER(P)]
         L.nla_free_nodes_view.argtypes = [P, C.POINTER(P)]
         L.nla_blocks_view.argtypes = [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P),
-                                      C.POINTER(P), C.POINTER(I32)]
+                                      C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
         L.nla_cg.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P]
+        L.nla_set_timing.argtypes = [P, I32]
+        L.nla_timings.argtypes = [P, P, C.POINTER(I32)]
         L.nla_plan_destroy.argtypes = [P]
         L.nla_plan_destroy.restype = None
         for name in ("nla_plan_create", "nla_plan_info", "nla_pairs_view", "nla_outer_points", "nla_assemble",
-                     "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg"):
+                     "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg",
+                     "nla_set_timing", "nla_timings"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -178,7 +185,18 @@ class Plan:
         return dict(n_pairs=i.n_pairs, nnz_full=i.nnz_full, nnz_free=i.nnz_free, n_free=i.n_free,
                     n_outer=i.n_outer, n_codes=i.n_codes, n_near=i.n_near,
                     items=dict(whole=i.items[0], partial=i.items[1], empty=i.items[2], learned=i.items[3]),
-                    subtriangles=i.subtriangles)
+                    subtriangles=i.subtriangles, caps=i.caps)
+
+    def set_timing(self, n):
+        """Time the next n assemblies per phase (HIP events on their stream); 0 = off."""
+        _check(lib().nla_set_timing(self._h, int(n)))
+
+    def timings(self):
+        """(mean milliseconds per phase, number of timed assemblies)."""
+        ms = (C.c_double * len(PHASES))()
+        n = C.c_int32()
+        _check(lib().nla_timings(self._h, ms, C.byref(n)))
+        return dict(zip(PHASES, list(ms))), n.value
 
     def pairs(self, stream=None):
         """(pair_ptr [K+1] int64, pair_kp [n_pairs] int32) as device tensors (copies)."""
@@ -226,18 +244,21 @@ class Plan:
         return _copy_from_device(f.value, self.info()["n_free"], torch.int32, stream)
 
     def blocks(self, stream=None):
-        """Per-pair -Mxy [P,3,3], Myy [P,6], per-element Mxx [K,6] (copies)."""
-        a, b, c, d, e, dt = (C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_int32())
+        """Intermediate blocks (copies): Myy [P,6], Mxx [K,6], element blocks [K,6],
+        row blocks R (flat), col_off [K+1], colset."""
+        a, b, c, d, e, f, dt = (C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(), C.c_void_p(),
+                                C.c_void_p(), C.c_int32())
         _check(lib().nla_blocks_view(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d), C.byref(e),
-                                     C.byref(dt)))
-        info = self.info()
-        n = info["n_pairs"]
+                                     C.byref(f), C.byref(dt)))
+        n = self.info()["n_pairs"]
         t = torch.float64 if dt.value == 0 else torch.float32
-        return dict(neg_mxy=_copy_from_device(a.value, 9 * n, t, stream).view(n, 3, 3),
-                    myy=_copy_from_device(b.value, 6 * n, t, stream).view(n, 6),
-                    mxx=_copy_from_device(c.value, 6 * self.K, t, stream).view(self.K, 6),
-                    near=_copy_from_device(d.value, 21 * info["n_near"], t, stream).view(-1, 21),
-                    near_pair=_copy_from_device(e.value, info["n_near"], torch.int64, stream))
+        col_off = _copy_from_device(e.value, self.K + 1, torch.int64, stream)
+        ncols = int(col_off[-1].item())
+        return dict(myy=_copy_from_device(a.value, 6 * n, t, stream).view(n, 6),
+                    mxx=_copy_from_device(b.value, 6 * self.K, t, stream).view(self.K, 6),
+                    elem=_copy_from_device(c.value, 6 * self.K, t, stream).view(self.K, 6),
+                    rows=_copy_from_device(d.value, 3 * ncols, t, stream),
+                    col_off=col_off, colset=_copy_from_device(f.value, ncols, torch.int32, stream))
 
     def cg(self, b, u0=None, rtol=1e-12, maxit=10000, stream=None):
         n = self.info()["n_free"]

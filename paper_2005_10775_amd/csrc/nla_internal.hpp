@@ -93,11 +93,24 @@ struct nla_plan {
     int64_t *up_dst = nullptr;  // [n_up] entry index of the upper entry
     int64_t *up_ptr = nullptr;  // [n_up+1]
     int32_t *codes = nullptr;   // [n_codes] indices into the contribution array
+    // column sets: for outer element k the sorted nodes C_k of all its inner
+    // elements; the pair kernel reduces -Mxy into R_k[a][c] (3 x |C_k|)
+    int64_t n_cols = 0;         // sum_k |C_k|
+    int32_t max_cols = 0;       // max_k |C_k|
+    int64_t *col_off = nullptr; // [K+1]
+    int32_t *colset = nullptr;  // [n_cols] node ids
+    int32_t *colent_ptr = nullptr; // [n_cols+1] per column slot: contributions (p_local << 2 | b), p ascending
+    uint16_t *colent = nullptr;    // [3 n_pairs]
+    int32_t *n2e_all_ptr = nullptr; // [J+1] node -> (3k+a) over all elements
+    int32_t *n2e_all = nullptr;
+    // transposed pair order: pairs (k, k') grouped by k', k ascending within
+    int64_t *tptr = nullptr;    // [K+1]
+    int32_t *tperm = nullptr;   // [n_pairs]
     // near-diagonal pairs (singular kernel)
     int64_t n_near = 0;
     int64_t *near_pair = nullptr;
     // contributions and values
-    int64_t n_contrib = 0;      // 9P + 6P + 6K + 21 n_near
+    int64_t n_contrib = 0;      // 6P (Myy) + 6K (Mxx) + 6K (element blocks) + 3 n_cols (R) + 21 n_near
     void *contrib = nullptr;    // f64 or f32 [n_contrib]
     void *val = nullptr;        // [nnz]
     // A = D[free, free]
@@ -113,9 +126,17 @@ struct nla_plan {
     int32_t *n2e = nullptr;
     double *Gk = nullptr;       // [K][3]
     double *b = nullptr;        // [n_free]
-    // counters: whole, partial, empty, learned, subtriangles
+    // counters: whole, partial, empty, learned, subtriangles, caps
     unsigned long long *counters = nullptr;
-    unsigned long long host_counters[5] = {0, 0, 0, 0, 0};
+    // phase timing: (NLA_NPHASE + 1) events per timed assembly
+    int timing_slots = 0, timing_count = 0;
+    std::vector<hipEvent_t> ev;
+    bool ran[8] = {};
+    ~nla_plan()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
     bool assembled = false;
     bool have_load = false;
     int val_dtype = NLA_DTYPE_F64;

@@ -81,6 +81,7 @@ __device__ __forceinline__ void cap_accum(double Xx, double Xy, const double (&b
     double cr = Xx * Ny - Xy * Nx, dt = Xx * Nx + Xy * Ny;
     double D = atan2(cr, dt);
     if (!(D > 0.0) || ncap < 2) return;
+    nsub += 1 << 16;   // one cap (counted in the high half)
     double Mx = 0.5 * (Xx + Nx), My = 0.5 * (Xy + Ny);
     double bM[3] = {0.5 * (bX[0] + bN[0]), 0.5 * (bX[1] + bN[1]), 0.5 * (bX[2] + bN[2])};
     double s, c;
@@ -214,16 +215,22 @@ __device__ __forceinline__ bool meets_edges(double xx, double xy, const double (
 // constants times |E_k'|.  Partial items are queued in LDS.  Phase 2: the
 // wave takes queued items 64 at a time (dense, regardless of owner),
 // retriangulates them, and each owner adds its items' sums in q order.
-// Outputs per pair: -Mxy (9), Myy (6); per element Mxx (6) from the
-// fixed-order lane reduction of sum_k' S0(x_q).
+// Outputs: per pair Myy (6); per element Mxx (6) from the fixed-order lane
+// reduction of sum_k' S0(x_q), and the row block R_k[a][c] = sum of -Mxy_ab
+// over the pairs whose inner slot b is node C_k[c], reduced in LDS column by
+// column in pair order (each column owned by one lane).
 __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
                                                          const int32_t *__restrict__ pair_kp, ElemSoA E,
                                                          const double *__restrict__ xq, const RuleSet *__restrict__ R,
                                                          double dd, double psi, int ball, int ncap,
-                                                         double *__restrict__ Cxy, double *__restrict__ Cyy,
-                                                         double *__restrict__ Cxx,
-                                                         unsigned long long *__restrict__ counters)
+                                                         const int64_t *__restrict__ col_off,
+                                                         const int32_t *__restrict__ colent_ptr,
+                                                         const uint16_t *__restrict__ colent, double *__restrict__ Rout,
+                                                         double *__restrict__ Cyy, double *__restrict__ Cxx,
+                                                         int max_cols, unsigned long long *__restrict__ counters)
 {
+    extern __shared__ double dyn[];
+    __shared__ double mxy_l[64][9];
     __shared__ double sW[NLA_MAX_OUTER][4];
     __shared__ double sX[NLA_MAX_OUTER][2];
     __shared__ double sV[64][7];
@@ -243,10 +250,20 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
     }
     __syncthreads();
     const RuleMom M = load_moments(R);
+    const int64_t coff = col_off[k];
+    const int nC = (int)(col_off[k + 1] - coff);
+    double *R_l = dyn;                                  // [3][nC]
+    int *cur_l = (int *)(dyn + 3 * (size_t)max_cols);   // [nC]
+    for (int c = lane; c < nC; c += 64) {
+        R_l[c] = 0.0;
+        R_l[nC + c] = 0.0;
+        R_l[2 * nC + c] = 0.0;
+        cur_l[c] = colent_ptr[coff + c];
+    }
     double m0[NLA_MAX_OUTER];
 #pragma unroll
     for (int q = 0; q < NLA_MAX_OUTER; q++) m0[q] = 0.0;
-    unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0;
+    unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
     for (int64_t base = p0; base < p1; base += 64) {
         const int64_t p = base + lane;
@@ -343,7 +360,8 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
                 for (int t = 0; t < 6; t++) A.s2[t] = 0.0;
                 int ns = 0;
                 partial_item(sX[q][0], sX[q][1], W6, dd, ncap, M, A, ns);
-                c_sub += ns;
+                c_sub += ns & 0xffff;
+                c_cap += ns >> 16;
                 res[lane][0] = A.a2 * M.wsum;
 #pragma unroll
                 for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t];
@@ -373,11 +391,37 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
 #pragma unroll
             for (int a = 0; a < 3; a++)
 #pragma unroll
-                for (int b = 0; b < 3; b++) Cxy[9 * p + 3 * a + b] = -psi * axy[a][b];
+                for (int b = 0; b < 3; b++) mxy_l[lane][3 * a + b] = -psi * axy[a][b];
 #pragma unroll
             for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * ayy[t];
         }
+        __syncthreads();
+        {
+            const int lo = (int)(base - p0), hi = lo + 64;
+            for (int c = lane; c < nC; c += 64) {
+                int cur = cur_l[c];
+                const int end = colent_ptr[coff + c + 1];
+                double r0 = R_l[c], r1 = R_l[nC + c], r2 = R_l[2 * nC + c];
+                while (cur < end) {
+                    const int e = colent[cur];
+                    const int pl = e >> 2;
+                    if (pl >= hi) break;
+                    const int b = e & 3;
+                    const double *mm = mxy_l[pl - lo];
+                    r0 += mm[b];
+                    r1 += mm[3 + b];
+                    r2 += mm[6 + b];
+                    cur++;
+                }
+                R_l[c] = r0;
+                R_l[nC + c] = r1;
+                R_l[2 * nC + c] = r2;
+                cur_l[c] = cur;
+            }
+        }
+        __syncthreads();
     }
+    for (int i = lane; i < 3 * nC; i += 64) Rout[3 * coff + i] = R_l[i];
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
     // lanes, then lane 0's sum is broadcast
 #pragma unroll
@@ -396,9 +440,9 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
         Cxx[6 * (int64_t)k + lane] = psi * s;
     }
     // work counters
-    unsigned long long v[4] = {c_whole, c_part, c_empty, c_sub};
+    unsigned long long v[5] = {c_whole, c_part, c_empty, c_sub, c_cap};
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < 5; i++) {
         unsigned long long x = v[i];
         for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
         v[i] = x;
@@ -408,6 +452,37 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
         atomicAdd(&counters[1], v[1]);
         atomicAdd(&counters[2], v[2]);
         atomicAdd(&counters[4], v[3]);
+        atomicAdd(&counters[5], v[4]);
+    }
+}
+
+// Element blocks E(k') = Mxx(k') + sum_k Myy(k, k'): one wavefront per k'
+// over its pairs in the transposed order (k ascending); lane l takes every
+// 64th pair from l, lanes are combined by a fixed butterfly.
+template <class T>
+__global__ __launch_bounds__(64) void k_elem_blocks(int K, const int64_t *__restrict__ tptr,
+                                                    const int32_t *__restrict__ tperm, const T *__restrict__ Cyy,
+                                                    const T *__restrict__ Cxx, T *__restrict__ Ce)
+{
+    const int k = blockIdx.x, lane = threadIdx.x;
+    double y[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t t = tptr[k] + lane; t < tptr[k + 1]; t += 64) {
+        const int64_t p = tperm[t];
+#pragma unroll
+        for (int i = 0; i < 6; i++) y[i] += (double)Cyy[6 * p + i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        double v = y[i];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        y[i] = v;
+    }
+    if (lane < 6) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; i++)
+            if (i == lane) v = y[i];
+        Ce[6 * (int64_t)k + lane] = (T)(v + (double)Cxx[6 * (int64_t)k + lane]);
     }
 }
 
@@ -481,25 +556,46 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
     const int64_t NP = P->n_pairs;
     const int K = P->K;
     if (!P->contrib) {
-        P->n_contrib = 15 * NP + 6 * (int64_t)K;
+        P->n_contrib = 6 * NP + 12 * (int64_t)K + 3 * P->n_cols;
         NLA_TRY(P->arena.alloc(&P->contrib, sizeof(double) * P->n_contrib));
         NLA_TRY(P->arena.alloc(&P->val, sizeof(double) * P->nnz));
         NLA_TRY(P->arena.alloc(&P->a_val, sizeof(double) * (P->nnz_free > 0 ? P->nnz_free : 1)));
         NLA_TRY(P->arena.get(&P->Gk, 3 * (size_t)K));
         NLA_TRY(P->arena.get(&P->b, P->n_free > 0 ? P->n_free : 1));
     }
-    double *C = (double *)P->contrib;
-    NLA_HIP(hipMemsetAsync(P->counters, 0, sizeof(unsigned long long) * 5, s));
-    k_pairs_const_fp64<<<K, 64, 0, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta,
-                                        pr.kernel_c, pr.ball, pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0, C, C + 9 * NP,
-                                        C + 15 * NP, P->counters);
+    double *Cyy = (double *)P->contrib;
+    double *Cxx = Cyy + 6 * NP;
+    double *V = Cxx + 6 * (int64_t)K;          // [R (3 n_cols) | E (6K)]: the values the codes index
+    double *Ce = V + 3 * P->n_cols;
+    const bool timed = P->timing_count < P->timing_slots;
+    hipEvent_t *ev = timed ? &P->ev[(size_t)P->timing_count * (NLA_NPHASE + 1)] : nullptr;
+    auto mark = [&](int i) -> int {
+        if (timed) NLA_HIP(hipEventRecord(ev[i], s));
+        return NLA_OK;
+    };
+    for (int i = 0; i < NLA_NPHASE; i++) P->ran[i] = false;
+    NLA_HIP(hipMemsetAsync(P->counters, 0, sizeof(unsigned long long) * 6, s));
+    NLA_TRY(mark(NLA_PHASE_PAIRS));
+    const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
+    k_pairs_const_fp64<<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta,
+                                          pr.kernel_c, pr.ball, pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0,
+                                          P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx, P->max_cols,
+                                          P->counters);
     NLA_HIP(hipGetLastError());
+    P->ran[NLA_PHASE_PAIRS] = true;
+    NLA_TRY(mark(NLA_PHASE_NEAR));
+    NLA_TRY(mark(NLA_PHASE_SEGSUM));
+    k_elem_blocks<double><<<K, 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
     if (P->n_up > 0)
-        k_segsum_f64<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes, P->up_dst, P->mirror, C,
+        k_segsum_f64<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes, P->up_dst, P->mirror, V,
                                                            (double *)P->val);
+    P->ran[NLA_PHASE_SEGSUM] = true;
+    NLA_TRY(mark(NLA_PHASE_EXTRACT));
     if (P->nnz_free > 0)
         k_extract<double><<<grid_for(P->nnz_free, 256), 256, 0, s>>>(P->nnz_free, P->a_src, (const double *)P->val,
                                                                     (double *)P->a_val);
+    P->ran[NLA_PHASE_EXTRACT] = true;
+    NLA_TRY(mark(NLA_PHASE_LOAD));
     P->have_load = false;
     if (f_outer && g_node) {
         k_load_elem<<<grid_for(K, 256), 256, 0, s>>>(K, P->tin, P->E.a2, P->d_rules, f_outer, P->Gk);
@@ -508,7 +604,10 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
                 P->n_free, P->free_nodes, P->n2e_ptr, P->n2e, P->Gk, P->rowptr, P->col, (const double *)P->val,
                 P->node_to_free, g_node, P->b);
         P->have_load = true;
+        P->ran[NLA_PHASE_LOAD] = true;
     }
+    NLA_TRY(mark(NLA_NPHASE));
+    if (timed) P->timing_count++;
     NLA_HIP(hipGetLastError());
     P->val_dtype = NLA_DTYPE_F64;
     P->assembled = true;

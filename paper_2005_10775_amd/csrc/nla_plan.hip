@@ -522,63 +522,117 @@ __device__ __forceinline__ uint32_t upper_of(const uint64_t *uk, int64_t nnz, co
     return (uint32_t)up_of[t];
 }
 
-// contribution slots per pair: 9 Mxy, 3 for shared-node duplicates, 6 Myy
-__global__ void k_codes_pairs(int64_t P, int J, const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
-                              const int32_t *__restrict__ pkp, const uint64_t *__restrict__ uk, int64_t nnz,
-                              const int64_t *__restrict__ up_of, uint32_t sentinel, uint32_t *__restrict__ key,
-                              int32_t *__restrict__ code)
+// ---- column sets and contribution lists of the -Mxy reduction
+__global__ void k_colkeys(int64_t P, const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
+                          const int32_t *__restrict__ pkp, uint64_t *__restrict__ keys)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    int k = pk[p], kp = pkp[p];
-    int g[3], h[3];
-    for (int a = 0; a < 3; a++) {
-        g[a] = tri[3 * k + a];
-        h[a] = tri[3 * kp + a];
-    }
-    uint32_t *ko = key + 18 * p;
-    int32_t *co = code + 18 * p;
-    int ndup = 0;
-    for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++) {
-            uint32_t u = upper_of(uk, nnz, up_of, J, g[a], h[b]);
-            ko[3 * a + b] = u;
-            co[3 * a + b] = (int32_t)(9 * p + 3 * a + b);
-            if (g[a] == h[b]) {           // diagonal entry receives both mirrored terms
-                ko[9 + ndup] = u;
-                co[9 + ndup] = (int32_t)(9 * p + 3 * a + b);
-                ndup++;
-            }
-        }
-    for (int i = ndup; i < 3; i++) {
-        ko[9 + i] = sentinel;
-        co[9 + i] = -1;
-    }
-    const int bb[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-    for (int i = 0; i < 6; i++) {
-        ko[12 + i] = upper_of(uk, nnz, up_of, J, h[bb[i][0]], h[bb[i][1]]);
-        co[12 + i] = (int32_t)(9 * P + 6 * p + i);
+    const uint64_t k = (uint64_t)pk[p];
+    for (int b = 0; b < 3; b++) keys[3 * p + b] = (k << 32) | (uint64_t)tri[3 * pkp[p] + b];
+}
+
+__global__ void k_col_off(int K, const uint64_t *__restrict__ U, int64_t nu, int64_t *__restrict__ off)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > K) return;
+    off[k] = lower_bound_u64(U, nu, (uint64_t)k << 32);
+}
+
+__global__ void k_colset(int64_t nu, const uint64_t *__restrict__ U, int32_t *__restrict__ colset)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nu) colset[i] = (int32_t)(U[i] & 0xffffffffull);
+}
+
+// slot key (global column slot) and value (p_local << 2 | b) of every (pair, b)
+__global__ void k_colent_keys(int64_t P, const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
+                              const int32_t *__restrict__ pkp, const int64_t *__restrict__ pair_ptr,
+                              const uint64_t *__restrict__ U, int64_t nu, uint32_t *__restrict__ key,
+                              uint16_t *__restrict__ val)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const uint64_t k = (uint64_t)pk[p];
+    const int pl = (int)(p - pair_ptr[k]);
+    for (int b = 0; b < 3; b++) {
+        int64_t slot = lower_bound_u64(U, nu, (k << 32) | (uint64_t)tri[3 * pkp[p] + b]);
+        key[3 * p + b] = (uint32_t)slot;
+        val[3 * p + b] = (uint16_t)((pl << 2) | b);
     }
 }
 
-__global__ void k_codes_elems(int K, int64_t P, int J, const int32_t *__restrict__ tri, const int64_t *__restrict__ ptr,
-                              const uint64_t *__restrict__ uk, int64_t nnz, const int64_t *__restrict__ up_of,
-                              uint32_t sentinel, uint32_t *__restrict__ key, int32_t *__restrict__ code)
+__global__ void k_slot_ptr(int64_t nu, const uint32_t *__restrict__ sk, int64_t n, int32_t *__restrict__ ptr)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    const int aa[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-    bool has = ptr[k + 1] > ptr[k];
-    for (int i = 0; i < 6; i++) {
-        int64_t s = 18 * P + 6 * (int64_t)k + i;
-        if (has) {
-            key[s] = upper_of(uk, nnz, up_of, J, tri[3 * k + aa[i][0]], tri[3 * k + aa[i][1]]);
-            code[s] = (int32_t)(15 * P + 6 * (int64_t)k + i);
-        } else {
-            key[s] = sentinel;
-            code[s] = -1;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > nu) return;
+    ptr[i] = (int32_t)lower_bound_u32(sk, n, (uint32_t)i);
+}
+
+__device__ __forceinline__ int find_col(const int32_t *cs, int n, int node)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cs[mid] < node) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && cs[lo] == node) ? lo : -1;
+}
+
+// Codes of one upper entry (j, c), j <= c, in the value array [R | E]:
+//   F[j,c]: for every element k with node j (slot a), R_k[a][c] if c in C_k;
+//   F[c,j]: for every element k with node c (slot a), R_k[a][j] if j in C_k;
+//   E: for every element containing both nodes, its element block entry.
+// With fill == 0 only the count is written.
+__global__ void k_entry_codes(int64_t n_up, int J, const int64_t *__restrict__ up_dst, const int64_t *__restrict__ rowptr_unused,
+                              const uint64_t *__restrict__ uk, const int32_t *__restrict__ tri,
+                              const int32_t *__restrict__ n2e_ptr, const int32_t *__restrict__ n2e,
+                              const int64_t *__restrict__ col_off, const int32_t *__restrict__ colset, int64_t e_base,
+                              int fill, int32_t *__restrict__ cnt, const int64_t *__restrict__ up_ptr,
+                              int32_t *__restrict__ codes)
+{
+    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_up) return;
+    const uint64_t key = uk[up_dst[u]];
+    const int j = (int)(key / (uint64_t)J), c = (int)(key % (uint64_t)J);
+    int n = 0;
+    int64_t o = fill ? up_ptr[u] : 0;
+    for (int pass = 0; pass < 2; pass++) {
+        const int r = pass ? c : j, t = pass ? j : c;
+        for (int e = n2e_ptr[r]; e < n2e_ptr[r + 1]; e++) {
+            const int k = n2e[e] / 3, a = n2e[e] % 3;
+            const int64_t off = col_off[k];
+            const int nc = (int)(col_off[k + 1] - off);
+            const int lc = find_col(colset + off, nc, t);
+            if (lc < 0) continue;
+            if (fill) codes[o + n] = (int32_t)(3 * off + (int64_t)a * nc + lc);
+            n++;
         }
     }
+    const int idx[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    for (int e = n2e_ptr[j]; e < n2e_ptr[j + 1]; e++) {
+        const int k = n2e[e] / 3, a = n2e[e] % 3;
+        int ac = -1;
+        for (int b = 0; b < 3; b++)
+            if (tri[3 * k + b] == c) ac = b;
+        if (ac < 0) continue;
+        if (fill) codes[o + n] = (int32_t)(e_base + 6 * (int64_t)k + idx[a][ac]);
+        n++;
+    }
+    if (!fill) cnt[u] = n;
+}
+
+__global__ void k_iota(int64_t n, int32_t *__restrict__ v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (int32_t)i;
+}
+
+__global__ void k_tptr(int K, const uint32_t *__restrict__ skp, int64_t P, int64_t *__restrict__ tptr)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > K) return;
+    tptr[k] = lower_bound_u32(skp, P, (uint32_t)k);
 }
 
 __global__ void k_up_ptr(int64_t n_up, const uint32_t *__restrict__ skeys, int64_t n, int64_t *__restrict__ up_ptr)
@@ -697,8 +751,8 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         return NLA_E_UNSUPPORTED;
     }
     P->n_pairs = hptr[K];
-    if (15 * P->n_pairs + 6 * (int64_t)K >= (int64_t)INT32_MAX) {
-        nla_set_error("too many pairs (%lld) for 32-bit contribution codes", (long long)P->n_pairs);
+    if (3 * P->n_pairs >= (int64_t)INT32_MAX) {
+        nla_set_error("too many pairs (%lld) for 32-bit contribution indices", (long long)P->n_pairs);
         return NLA_E_UNSUPPORTED;
     }
     NLA_TRY(P->arena.get(&P->pair_ptr, K + 1));
@@ -774,33 +828,115 @@ int nla_build_pattern(nla_plan *P, hipStream_t s)
     NLA_HIP(hipMemcpyAsync(upscan, hsc.data(), sizeof(int64_t) * nnz, hipMemcpyHostToDevice, s));
     NLA_TRY(P->arena.get(&P->up_dst, P->n_up));
     k_up_index<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, upflag, upscan, P->up_dst, up_of);
-    // contribution codes, sorted by upper entry (stable: generation order within an entry)
-    const int64_t nslots = 18 * NP + 6 * (int64_t)K;
-    const uint32_t csent = (uint32_t)P->n_up;
-    uint32_t *ck, *sck;
-    int32_t *cv, *scv;
-    NLA_TRY(S.get(&ck, nslots));
-    NLA_TRY(S.get(&sck, nslots));
-    NLA_TRY(S.get(&cv, nslots));
-    NLA_TRY(S.get(&scv, nslots));
-    if (NP > 0)
-        k_codes_pairs<<<grid_for(NP, 256), 256, 0, s>>>(NP, J, P->tri, P->pair_k, P->pair_kp, ukeys, nnz, up_of, csent,
-                                                        ck, cv);
-    k_codes_elems<<<grid_for(K, 256), 256, 0, s>>>(K, NP, J, P->tri, P->pair_ptr, ukeys, nnz, up_of, csent, ck, cv);
-    const int cbits = bits_for((uint64_t)csent);
-    size_t tb3 = 0;
-    NLA_HIP(rocprim::radix_sort_pairs(nullptr, tb3, ck, sck, cv, scv, (size_t)nslots, 0, cbits, s));
-    void *tmp3;
-    NLA_TRY(S.get((char **)&tmp3, tb3));
-    NLA_HIP(rocprim::radix_sort_pairs(tmp3, tb3, ck, sck, cv, scv, (size_t)nslots, 0, cbits, s));
+    // column sets C_k (sorted unique nodes of the inner elements of k)
+    const int64_t n3 = 3 * NP;
+    uint64_t *ck64, *sck64, *U;
+    int64_t *nu_d;
+    NLA_TRY(S.get(&ck64, n3));
+    NLA_TRY(S.get(&sck64, n3));
+    NLA_TRY(S.get(&U, n3));
+    NLA_TRY(S.get(&nu_d, 1));
+    int64_t nu = 0;
+    if (NP > 0) {
+        k_colkeys<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->tri, P->pair_k, P->pair_kp, ck64);
+        const int b64 = 32 + bits_for((uint64_t)K);
+        size_t t1 = 0;
+        NLA_HIP(rocprim::radix_sort_keys(nullptr, t1, ck64, sck64, (size_t)n3, 0, b64, s));
+        void *tm1;
+        NLA_TRY(S.get((char **)&tm1, t1));
+        NLA_HIP(rocprim::radix_sort_keys(tm1, t1, ck64, sck64, (size_t)n3, 0, b64, s));
+        size_t t2 = 0;
+        NLA_HIP(rocprim::unique(nullptr, t2, sck64, U, nu_d, (size_t)n3, rocprim::equal_to<uint64_t>(), s));
+        void *tm2;
+        NLA_TRY(S.get((char **)&tm2, t2));
+        NLA_HIP(rocprim::unique(tm2, t2, sck64, U, nu_d, (size_t)n3, rocprim::equal_to<uint64_t>(), s));
+        NLA_HIP(hipMemcpyAsync(&nu, nu_d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+    }
+    P->n_cols = nu;
+    if (3 * nu + 12 * (int64_t)K + 6 * NP >= (int64_t)INT32_MAX) {
+        nla_set_error("value array too large for 32-bit codes");
+        return NLA_E_UNSUPPORTED;
+    }
+    NLA_TRY(P->arena.get(&P->col_off, K + 1));
+    NLA_TRY(P->arena.get(&P->colset, nu));
+    NLA_TRY(P->arena.get(&P->colent_ptr, nu + 1));
+    NLA_TRY(P->arena.get(&P->colent, n3));
+    k_col_off<<<grid_for(K + 1, 256), 256, 0, s>>>(K, U, nu, P->col_off);
+    if (nu > 0) k_colset<<<grid_for(nu, 256), 256, 0, s>>>(nu, U, P->colset);
+    {
+        std::vector<int64_t> hoff(K + 1);
+        NLA_HIP(hipMemcpyAsync(hoff.data(), P->col_off, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+        int64_t mc = 0;
+        for (int k = 0; k < K; k++) mc = std::max(mc, hoff[k + 1] - hoff[k]);
+        P->max_cols = (int32_t)mc;
+        if (mc > 1536) {
+            nla_set_error("an element reaches %lld nodes (limit 1536)", (long long)mc);
+            return NLA_E_UNSUPPORTED;
+        }
+    }
+    // per column slot: contributions (p_local, b) in pair order (stable sort by slot)
+    if (NP > 0) {
+        uint32_t *sk, *skk;
+        uint16_t *sv;
+        NLA_TRY(S.get(&sk, n3));
+        NLA_TRY(S.get(&skk, n3));
+        NLA_TRY(S.get(&sv, n3));
+        k_colent_keys<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->tri, P->pair_k, P->pair_kp, P->pair_ptr, U, nu, sk, sv);
+        const int sb = bits_for((uint64_t)nu);
+        size_t t3 = 0;
+        NLA_HIP(rocprim::radix_sort_pairs(nullptr, t3, sk, skk, sv, P->colent, (size_t)n3, 0, sb, s));
+        void *tm3;
+        NLA_TRY(S.get((char **)&tm3, t3));
+        NLA_HIP(rocprim::radix_sort_pairs(tm3, t3, sk, skk, sv, P->colent, (size_t)n3, 0, sb, s));
+        k_slot_ptr<<<grid_for(nu + 1, 256), 256, 0, s>>>(nu, skk, n3, P->colent_ptr);
+    } else {
+        NLA_HIP(hipMemsetAsync(P->colent_ptr, 0, sizeof(int32_t), s));
+    }
+    // codes of every upper entry into the value array [R (3 n_cols) | E (6K)]
+    const int64_t e_base = 3 * nu;
+    int32_t *ecnt;
+    NLA_TRY(S.get(&ecnt, P->n_up));
     NLA_TRY(P->arena.get(&P->up_ptr, P->n_up + 1));
-    k_up_ptr<<<grid_for(P->n_up + 1, 256), 256, 0, s>>>(P->n_up, sck, nslots, P->up_ptr);
-    int64_t ncodes = 0;
-    NLA_HIP(hipMemcpyAsync(&ncodes, P->up_ptr + P->n_up, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    NLA_HIP(hipStreamSynchronize(s));
-    P->n_codes = ncodes;
-    NLA_TRY(P->arena.get(&P->codes, ncodes));
-    NLA_HIP(hipMemcpyAsync(P->codes, scv, sizeof(int32_t) * ncodes, hipMemcpyDeviceToDevice, s));
+    k_entry_codes<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, J, P->up_dst, nullptr, ukeys, P->tri, P->n2e_all_ptr,
+                                                        P->n2e_all, P->col_off, P->colset, e_base, 0, ecnt, nullptr,
+                                                        nullptr);
+    {
+        std::vector<int32_t> hc(P->n_up);
+        std::vector<int64_t> hp(P->n_up + 1);
+        NLA_HIP(hipMemcpyAsync(hc.data(), ecnt, sizeof(int32_t) * P->n_up, hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+        hp[0] = 0;
+        for (int64_t u = 0; u < P->n_up; u++) hp[u + 1] = hp[u] + hc[u];
+        P->n_codes = hp[P->n_up];
+        NLA_HIP(hipMemcpyAsync(P->up_ptr, hp.data(), sizeof(int64_t) * (P->n_up + 1), hipMemcpyHostToDevice, s));
+    }
+    NLA_TRY(P->arena.get(&P->codes, P->n_codes));
+    k_entry_codes<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, J, P->up_dst, nullptr, ukeys, P->tri, P->n2e_all_ptr,
+                                                        P->n2e_all, P->col_off, P->colset, e_base, 1, nullptr,
+                                                        P->up_ptr, P->codes);
+    // transposed pair order (k' major, k ascending within: stable radix sort of k')
+    NLA_TRY(P->arena.get(&P->tptr, K + 1));
+    NLA_TRY(P->arena.get(&P->tperm, NP));
+    if (NP > 0) {
+        uint32_t *skp;
+        int32_t *iota;
+        NLA_TRY(S.get(&skp, NP));
+        NLA_TRY(S.get(&iota, NP));
+        k_iota<<<grid_for(NP, 256), 256, 0, s>>>(NP, iota);
+        size_t tb4 = 0;
+        const int kb = bits_for((uint64_t)K);
+        NLA_HIP(rocprim::radix_sort_pairs(nullptr, tb4, (const uint32_t *)P->pair_kp, skp, iota, P->tperm, (size_t)NP, 0,
+                                          kb, s));
+        void *tmp4;
+        NLA_TRY(S.get((char **)&tmp4, tb4));
+        NLA_HIP(rocprim::radix_sort_pairs(tmp4, tb4, (const uint32_t *)P->pair_kp, skp, iota, P->tperm, (size_t)NP, 0,
+                                          kb, s));
+        k_tptr<<<grid_for(K + 1, 256), 256, 0, s>>>(K, skp, NP, P->tptr);
+    } else {
+        NLA_HIP(hipMemsetAsync(P->tptr, 0, sizeof(int64_t) * (K + 1), s));
+    }
     // A = D[free, free]
     const int nf = P->n_free;
     if (nf > 0) {
@@ -900,6 +1036,20 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
     for (int k = 0; k < K; k++)
         if (m->tri_in_omega[k])
             for (int a = 0; a < 3; a++) n2e[fill[m->tri[3 * k + a]]++] = 3 * k + a;
+    std::vector<int32_t> na_ptr(J + 1, 0), na;
+    for (int k = 0; k < K; k++)
+        for (int a = 0; a < 3; a++) na_ptr[m->tri[3 * k + a] + 1]++;
+    for (int j = 0; j < J; j++) na_ptr[j + 1] += na_ptr[j];
+    na.resize(na_ptr[J]);
+    {
+        std::vector<int32_t> f2(na_ptr.begin(), na_ptr.end() - 1);
+        for (int k = 0; k < K; k++)
+            for (int a = 0; a < 3; a++) na[f2[m->tri[3 * k + a]]++] = 3 * k + a;
+    }
+    NLA_TRY(P->arena.get(&P->n2e_all_ptr, J + 1));
+    NLA_TRY(P->arena.get(&P->n2e_all, na.size()));
+    NLA_HIP(hipMemcpyAsync(P->n2e_all_ptr, na_ptr.data(), sizeof(int32_t) * (J + 1), hipMemcpyHostToDevice, s));
+    NLA_HIP(hipMemcpyAsync(P->n2e_all, na.data(), sizeof(int32_t) * na.size(), hipMemcpyHostToDevice, s));
     NLA_TRY(P->arena.get(&P->free_nodes, fn.size()));
     NLA_TRY(P->arena.get(&P->node_to_free, J));
     NLA_TRY(P->arena.get(&P->n2e_ptr, J + 1));
@@ -912,7 +1062,7 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
     NLA_HIP(hipGetLastError());
     NLA_TRY(nla_build_pairs(P, s));
     NLA_TRY(nla_build_pattern(P, s));
-    NLA_TRY(P->arena.get(&P->counters, 5));
+    NLA_TRY(P->arena.get(&P->counters, 6));
     return NLA_OK;
 }
 
@@ -948,10 +1098,11 @@ extern "C" int nla_plan_info(const nla_plan *P, nla_info *info)
     info->n_outer = P->rules.n_out;
     info->n_codes = P->n_codes;
     info->n_near = P->n_near;
-    unsigned long long c[5] = {0, 0, 0, 0, 0};
+    unsigned long long c[6] = {0, 0, 0, 0, 0, 0};
     if (P->assembled) NLA_HIP(hipMemcpy(c, P->counters, sizeof(c), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; i++) info->items[i] = (int64_t)c[i];
     info->subtriangles = (int64_t)c[4];
+    info->caps = (int64_t)c[5];
     return NLA_OK;
 }
 
@@ -999,18 +1150,22 @@ extern "C" int nla_free_nodes_view(const nla_plan *P, const int32_t **free_nodes
     return NLA_OK;
 }
 
-extern "C" int nla_blocks_view(const nla_plan *P, const void **mxy, const void **myy, const void **mxx,
-                               const void **near, const int64_t **near_pair, int32_t *dtype)
+extern "C" int nla_blocks_view(const nla_plan *P, const void **myy, const void **mxx, const void **elem,
+                               const void **rows, const int64_t **col_off, const int32_t **colset, int32_t *dtype)
 {
-    if (!P || !mxy || !myy || !mxx || !near || !near_pair || !dtype) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    if (!P || !myy || !mxx || !elem || !rows || !col_off || !colset || !dtype) {
+        nla_set_error("null argument");
+        return NLA_E_INVALID;
+    }
     if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
     const size_t es = P->val_dtype == NLA_DTYPE_F64 ? 8 : 4;
     const char *c = (const char *)P->contrib;
-    *mxy = c;
-    *myy = c + es * 9 * P->n_pairs;
-    *mxx = c + es * 15 * P->n_pairs;
-    *near = c + es * (15 * P->n_pairs + 6 * (int64_t)P->K);
-    *near_pair = P->near_pair;
+    *myy = c;
+    *mxx = c + es * 6 * P->n_pairs;
+    *rows = c + es * (6 * P->n_pairs + 6 * (int64_t)P->K);
+    *elem = c + es * (6 * P->n_pairs + 6 * (int64_t)P->K + 3 * P->n_cols);
+    *col_off = P->col_off;
+    *colset = P->colset;
     *dtype = P->val_dtype;
     return NLA_OK;
 }
@@ -1029,6 +1184,41 @@ extern "C" int nla_assemble(nla_plan *P, const double *f_outer, const double *g_
     if (!P) { nla_set_error("null plan"); return NLA_E_INVALID; }
     if ((f_outer == nullptr) != (g_node == nullptr)) { nla_set_error("pass both f_outer and g_node, or neither"); return NLA_E_INVALID; }
     return nla_numeric(P, f_outer, g_node, (hipStream_t)stream);
+}
+
+extern "C" int nla_set_timing(nla_plan *P, int32_t n)
+{
+    if (!P || n < 0) { nla_set_error("null plan or negative count"); return NLA_E_INVALID; }
+    for (auto &e : P->ev)
+        if (e) NLA_HIP(hipEventDestroy(e));
+    P->ev.clear();
+    P->timing_slots = n;
+    P->timing_count = 0;
+    if (n > 0) {
+        P->ev.assign((size_t)n * (NLA_NPHASE + 1), nullptr);
+        for (auto &e : P->ev) NLA_HIP(hipEventCreate(&e));
+    }
+    return NLA_OK;
+}
+
+extern "C" int nla_timings(const nla_plan *P, double *ms, int32_t *count)
+{
+    if (!P || !ms || !count) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    const int n = P->timing_count;
+    *count = n;
+    for (int i = 0; i < NLA_NPHASE; i++) ms[i] = 0.0;
+    if (n == 0) return NLA_OK;
+    NLA_HIP(hipEventSynchronize(P->ev[(size_t)(n - 1) * (NLA_NPHASE + 1) + NLA_NPHASE]));
+    for (int c = 0; c < n; c++) {
+        const hipEvent_t *e = &P->ev[(size_t)c * (NLA_NPHASE + 1)];
+        for (int i = 0; i < NLA_NPHASE; i++) {
+            if (!P->ran[i]) continue;
+            float t = 0.f;
+            NLA_HIP(hipEventElapsedTime(&t, e[i], e[i + 1]));
+            ms[i] += t / n;
+        }
+    }
+    return NLA_OK;
 }
 
 extern "C" void nla_plan_destroy(nla_plan *P) { delete P; }

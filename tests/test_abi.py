@@ -1,0 +1,106 @@
+"""The C ABI without a GPU: the library loads, exports every function
+declared in include/nlasm.h, and rejects invalid input on the host with the
+documented status codes (no device call is made before validation)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "nlasm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nla_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    path = os.path.join(ROOT, "paper_2005_10775_amd", "libnlasm.so")
+    if not os.path.exists(path):
+        from paper_2005_10775_amd import build
+        build.build()
+    return C.CDLL(path)
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+
+
+from paper_2005_10775_amd import binding as B  # noqa: E402  (ctypes structs only)
+from workloads import Problem, constant_kernel_c, get_rule, structured_mesh  # noqa: E402
+
+
+def _create(L, mesh, prob, mutate_mesh=None):
+    keep = []
+    xy = np.ascontiguousarray(mesh.xy)
+    tri = np.ascontiguousarray(mesh.tri)
+    tin = np.ascontiguousarray(mesh.tri_in_omega)
+    nfr = np.ascontiguousarray(mesh.node_free)
+    if mutate_mesh:
+        xy, tri, tin, nfr = mutate_mesh(xy.copy(), tri.copy(), tin.copy(), nfr.copy())
+    keep += [xy, tri, tin, nfr]
+    m = B.nla_mesh(xy.shape[0], tri.shape[0], xy.ctypes.data, tri.ctypes.data, tin.ctypes.data, nfr.ctypes.data)
+    p = B.nla_problem()
+    p.delta, p.kernel, p.kernel_c, p.kernel_s = prob.delta, B.KERNELS[prob.kernel], prob.kernel_c, prob.kernel_s
+    p.outer = B._rule(get_rule(prob.outer), keep)
+    p.inner = B._rule(get_rule(prob.inner), keep)
+    p.ball, p.cap_edges, p.precision = B.BALLS[prob.ball], prob.cap_edges, B.PRECISIONS[prob.precision]
+    h = C.c_void_p()
+    L.nla_last_error.restype = C.c_char_p
+    code = L.nla_plan_create(C.byref(m), C.byref(p), None, C.byref(h))
+    return code, L.nla_last_error().decode()
+
+
+@pytest.fixture
+def small():
+    d = 0.1
+    return structured_mesh(d, 0.05), Problem(delta=d, kernel_c=constant_kernel_c(d), ball="retri", cap_edges=8)
+
+
+def test_clockwise_triangle_rejected(L, small):
+    def flip(xy, tri, tin, nfr):
+        tri[3] = tri[3][[0, 2, 1]]
+        return xy, tri, tin, nfr
+    code, msg = _create(L, *small, mutate_mesh=flip)
+    assert code == -2 and "counter-clockwise" in msg
+
+
+def test_index_out_of_range_rejected(L, small):
+    def bad(xy, tri, tin, nfr):
+        tri[0, 1] = xy.shape[0] + 5
+        return xy, tri, tin, nfr
+    assert _create(L, *small, mutate_mesh=bad)[0] == -2
+
+
+def test_free_node_on_layer_rejected(L, small):
+    def bad(xy, tri, tin, nfr):
+        nfr[tri[np.nonzero(tin == 0)[0][0], 0]] = 1
+        return xy, tri, tin, nfr
+    code, msg = _create(L, *small, mutate_mesh=bad)
+    assert code == -2 and "free node" in msg
+
+
+def test_invalid_problem_fields(L, small):
+    mesh, prob = small
+    from dataclasses import replace
+    assert _create(L, mesh, replace(prob, delta=-1.0))[0] == -1
+    assert _create(L, mesh, replace(prob, cap_edges=1))[0] == -1
+    assert _create(L, mesh, replace(prob, cap_edges=65))[0] == -1
+    assert _create(L, mesh, replace(prob, kernel_c=0.0))[0] == -1
+
+
+def test_ball_inside_triangle_unsupported(L):
+    """The retriangulated ball needs element diameters <= delta."""
+    d = 0.05
+    code, msg = _create(L, structured_mesh(0.1, 0.05), Problem(delta=d, kernel_c=1.0, ball="retri"))
+    # delta is snapped to the mesh layer (0.1); use a coarse mesh instead
+    mesh = structured_mesh(0.5, 0.5)
+    code, msg = _create(L, mesh, Problem(delta=0.5, kernel_c=1.0, ball="retri", cap_edges=8))
+    assert code == -5 and "diameter" in msg
