@@ -30,8 +30,9 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
 COST = dict(item=15,           # classification: 3 squared vertex distances
             whole=6,           # whole item: outer-weight sums and S0
             partial=114,       # polygon walk (3 edge quadratics, basis map, roots) + owner accumulation
-            subtriangle=115,   # factorised inner rule on one subtriangle (area, S1, S2)
-            cap=20,            # arc span, chord midpoint, rotation step
+            subtriangle=81,    # inner rule on one subtriangle from its vertex basis values (area, S1, S2),
+                               # symmetric-rule form
+            cap=30,            # arc span, chord midpoint, rotation by half angles
             arc_point=16,      # one rotated arc point and its basis values
             pair=45)           # per-pair accumulator set-up and output
 

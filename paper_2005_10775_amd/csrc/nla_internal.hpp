@@ -37,7 +37,7 @@ void nla_set_error(const char *fmt, ...);
 // from the values of the P1 basis at its three vertices (the rule applied
 // with its sums reordered, not a different rule).
 struct RuleSet {
-    int32_t n_out, n_in, duffy_n, pad;
+    int32_t n_out, n_in, duffy_n, in_sym;   // in_sym: inner rule symmetric under vertex permutations
     double out_lam[NLA_MAX_OUTER][3];
     double out_w[NLA_MAX_OUTER];
     double in_lam[NLA_MAX_INNER][3];

@@ -5,9 +5,12 @@
 
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// inner-rule moments as the kernels use them
+// inner-rule moments as the kernels use them; sym = the rule is invariant
+// under permutations of the barycentric coordinates, so sum_q w mu_i = m1c and
+// sum_q w mu_i mu_j = o + dm [i == j]
 struct RuleMom {
     double wsum, m1[3], m2[3][3];
+    double m1c, o, dm;
 };
 
 __device__ __forceinline__ RuleMom load_moments(const RuleSet *__restrict__ R)
@@ -20,14 +23,17 @@ __device__ __forceinline__ RuleMom load_moments(const RuleSet *__restrict__ R)
 #pragma unroll
         for (int j = 0; j < 3; j++) M.m2[i][j] = R->in_m2[i][j];
     }
+    M.m1c = R->in_m1[0];
+    M.o = R->in_m2[0][1];
+    M.dm = R->in_m2[0][0] - R->in_m2[0][1];
     return M;
 }
 
 // geometric inner sums of one (x, E') item with psi = 1 (psi is constant and
-// applied per pair): s0 = |region| / wsum-scaled, s1_b = int beta_b,
-// s2 = int beta_b beta_b' (upper triangle 00,01,02,11,12,22)
+// applied per pair): a2 = sum of twice-areas, s1_b ~ int beta_b (times m1c
+// in the symmetric case), s2 = int beta_b beta_b' (upper triangle 00,01,02,11,12,22)
 struct Acc {
-    double a2;     // sum of twice-areas (times wsum gives the area-weighted rule sum)
+    double a2;
     double s1[3];
     double s2[6];
 };
@@ -38,148 +44,218 @@ struct Basis {
     double x0, y0, i11, i12, i21, i22;
 };
 
-__device__ __forceinline__ void basis_at(const Basis &B, double px, double py, double (&b)[3])
+__device__ __forceinline__ void basis_at(const Basis &B, double px, double py, double &b0, double &b1, double &b2)
 {
     double dx = px - B.x0, dy = py - B.y0;
-    b[1] = dx * B.i11 + dy * B.i12;
-    b[2] = dx * B.i21 + dy * B.i22;
-    b[0] = 1.0 - b[1] - b[2];
+    b1 = dx * B.i11 + dy * B.i12;
+    b2 = dx * B.i21 + dy * B.i22;
+    b0 = 1.0 - b1 - b2;
 }
 
-// the inner rule on the subtriangle (a, b, c), evaluated from the basis
-// values at its vertices: sum_q w_q beta(y_q) = sum_i m1_i beta(t_i) and
-// sum_q w_q beta beta^T = B^T M2 B, B = basis values at the vertices
-__device__ __forceinline__ void tri_accum(double ax, double ay, const double (&ba)[3], double bx, double by,
-                                          const double (&bb)[3], double cx, double cy, const double (&bc)[3],
-                                          const RuleMom &M, Acc &A)
+// the inner rule on the subtriangle with vertices t[i] = (x, y, beta0, beta1, beta2),
+// evaluated from the basis values at its vertices: sum_q w_q beta(y_q) =
+// sum_i m1_i beta(t_i) and sum_q w_q beta beta^T = B^T M2 B (B = vertex values);
+// for a symmetric rule B^T M2 B = o cs cs^T + dm B^T B, cs = column sums of B
+template <bool SYM>
+__device__ __forceinline__ void tri_accum(const double (&t)[3][5], const RuleMom &M, Acc &A)
 {
-    double a2 = fabs((bx - ax) * (cy - ay) - (by - ay) * (cx - ax));
+    const double a2 = fabs((t[1][0] - t[0][0]) * (t[2][1] - t[0][1]) - (t[1][1] - t[0][1]) * (t[2][0] - t[0][0]));
     A.a2 += a2;
-    double U[3][3];
-#pragma unroll
-    for (int l = 0; l < 3; l++) {
-        A.s1[l] += a2 * (M.m1[0] * ba[l] + M.m1[1] * bb[l] + M.m1[2] * bc[l]);
-#pragma unroll
-        for (int i = 0; i < 3; i++) U[i][l] = M.m2[i][0] * ba[l] + M.m2[i][1] * bb[l] + M.m2[i][2] * bc[l];
-    }
     const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+    if (SYM) {
+        double cs[3];
 #pragma unroll
-    for (int t = 0; t < 6; t++) {
-        const int j = jj[t], l = ll[t];
-        A.s2[t] += a2 * (ba[j] * U[0][l] + bb[j] * U[1][l] + bc[j] * U[2][l]);
-    }
-}
-
-// one cap: the arc of the circle |p| = delta from exit X counter-clockwise to
-// entry N, split into ncap equal arcs whose points are fanned from the chord
-// midpoint (Sec. 4.2.2); a span not in (0, pi] comes only from rounding of
-// coincident X and N and is dropped
-__device__ __forceinline__ void cap_accum(double Xx, double Xy, const double (&bX)[3], double Nx, double Ny,
-                                          const double (&bN)[3], int ncap, const Basis &B, const RuleMom &M,
-                                          Acc &A, int &nsub)
-{
-    double cr = Xx * Ny - Xy * Nx, dt = Xx * Nx + Xy * Ny;
-    double D = atan2(cr, dt);
-    if (!(D > 0.0) || ncap < 2) return;
-    nsub += 1 << 16;   // one cap (counted in the high half)
-    double Mx = 0.5 * (Xx + Nx), My = 0.5 * (Xy + Ny);
-    double bM[3] = {0.5 * (bX[0] + bN[0]), 0.5 * (bX[1] + bN[1]), 0.5 * (bX[2] + bN[2])};
-    double s, c;
-    sincos(D / (double)ncap, &s, &c);
-    double ux = Xx, uy = Xy;
-    double bu[3] = {bX[0], bX[1], bX[2]};
-    for (int j = 1; j <= ncap; j++) {
-        double vx, vy, bv[3];
-        if (j == ncap) {
-            vx = Nx;
-            vy = Ny;
-            bv[0] = bN[0];
-            bv[1] = bN[1];
-            bv[2] = bN[2];
-        } else {
-            vx = c * ux - s * uy;
-            vy = s * ux + c * uy;
-            basis_at(B, vx, vy, bv);
+        for (int l = 0; l < 3; l++) {
+            cs[l] = t[0][2 + l] + t[1][2 + l] + t[2][2 + l];
+            A.s1[l] += a2 * cs[l];
         }
-        tri_accum(Mx, My, bM, ux, uy, bu, vx, vy, bv, M, A);
-        nsub++;
-        ux = vx;
-        uy = vy;
-        bu[0] = bv[0];
-        bu[1] = bv[1];
-        bu[2] = bv[2];
+        const double w = a2 * M.o, v = a2 * M.dm;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const int j = jj[e], l = ll[e];
+            double q = t[0][2 + j] * t[0][2 + l] + t[1][2 + j] * t[1][2 + l] + t[2][2 + j] * t[2][2 + l];
+            A.s2[e] += w * (cs[j] * cs[l]) + v * q;
+        }
+    } else {
+        double U[3][3];
+#pragma unroll
+        for (int l = 0; l < 3; l++) {
+            A.s1[l] += a2 * (M.m1[0] * t[0][2 + l] + M.m1[1] * t[1][2 + l] + M.m1[2] * t[2][2 + l]);
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                U[i][l] = M.m2[i][0] * t[0][2 + l] + M.m2[i][1] * t[1][2 + l] + M.m2[i][2] * t[2][2 + l];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const int j = jj[e], l = ll[e];
+            A.s2[e] += a2 * (t[0][2 + j] * U[0][l] + t[1][2 + j] * U[1][l] + t[2][2 + j] * U[2][l]);
+        }
     }
 }
 
-// E' n B_delta(x) retriangulated (Sec. 4.2.1 and Sec. 7.1 tasks 3-6):
-// the edges are walked v0->v1->v2, vertices inside the closed ball and the
-// roots lambda in (0,1) of |v_a + lambda e - x|^2 = delta^2 (smaller root
-// entry, larger exit) are streamed in order; each new point closes a fan
-// triangle with the first point, and every exit followed by an entry
-// (cyclically) bounds a cap.  V holds E' in absolute coordinates.
-__device__ void partial_item(double xx, double xy, const double (&V)[6], double dd, int ncap, const RuleMom &M,
+__device__ __forceinline__ void set5(double (&d)[5], double x, double y, double b0, double b1, double b2)
+{
+    d[0] = x; d[1] = y; d[2] = b0; d[3] = b1; d[4] = b2;
+}
+
+// E' n B_delta(x) retriangulated (Sec. 4.2.1-4.2.2 and Sec. 7.1 tasks 3-6),
+// written as one generator loop so that a single copy of the subtriangle
+// quadrature is inlined.  The edges are walked v0->v1->v2: vertices inside
+// the closed ball and the roots lambda in (0,1) of |v_a + lambda e - x|^2 =
+// delta^2 (smaller root entry, larger exit) arrive in order; every new point
+// closes the fan triangle (first, previous, new), and every exit followed by
+// an entry (cyclically) opens a cap: the arc from exit X counter-clockwise to
+// entry N split into ncap equal arcs fanned from the chord midpoint.  A cap
+// span not in (0, pi] only arises from rounding when X and N coincide and is
+// dropped (cross product <= 0).  POW2: ncap is a power of two and the
+// rotation comes from half-angle steps instead of atan2/sincos.  Vl: E' in absolute coordinates (6 values); coordinates below are
+// relative to the outer point.
+template <bool SYM, bool POW2>
+__device__ void partial_item(double xx, double xy, const double *Vl, double dd, int ncap, const RuleMom &M,
                              Acc &A, int &nsub)
 {
-    double P[6];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        P[2 * a] = V[2 * a] - xx;
-        P[2 * a + 1] = V[2 * a + 1] - xy;
-    }
     Basis B;
     {
-        double e1x = V[2] - V[0], e1y = V[3] - V[1], e2x = V[4] - V[0], e2y = V[5] - V[1];
-        double id = 1.0 / (e1x * e2y - e1y * e2x);
-        B.x0 = P[0];
-        B.y0 = P[1];
+        const double e1x = Vl[2] - Vl[0], e1y = Vl[3] - Vl[1], e2x = Vl[4] - Vl[0], e2y = Vl[5] - Vl[1];
+        const double id = 1.0 / (e1x * e2y - e1y * e2x);
+        B.x0 = Vl[0] - xx;
+        B.y0 = Vl[1] - xy;
         B.i11 = e2y * id;
         B.i12 = -e2x * id;
         B.i21 = -e1y * id;
         B.i22 = e1x * id;
     }
-    int cnt = 0, ft = 0, pt = 0;
-    double fx = 0, fy = 0, fb[3] = {0, 0, 0};
-    double qx = 0, qy = 0, qb[3] = {0, 0, 0};
-    auto emit = [&](double nx, double ny, double b0, double b1, double b2, int nt) {
-        double nb[3] = {b0, b1, b2};
-        if (cnt == 0) {
-            fx = nx; fy = ny; fb[0] = b0; fb[1] = b1; fb[2] = b2; ft = nt;
+    int ev = 0, cnt = 0, ft = 0, pt = 0, ea = 0, eb = 0;
+    double f[5] = {0, 0, 0, 0, 0}, q[5] = {0, 0, 0, 0, 0};
+    double epx = 0, epy = 0, eex = 0, eey = 0, el1 = 2.0, el2 = 2.0;
+    int cj = 0;
+    bool wrapped = false;
+    double Mc[5] = {0, 0, 0, 0, 0}, u[5] = {0, 0, 0, 0, 0}, N[5] = {0, 0, 0, 0, 0};
+    double cc = 1.0, ss = 0.0;
+    auto start_cap = [&](const double (&X)[5], const double (&Y)[5]) {
+        const double cr = X[0] * Y[1] - X[1] * Y[0], dt = X[0] * Y[0] + X[1] * Y[1];
+        if (!(cr > 0.0) || ncap < 2) return;      // span in (0, pi): counter-clockwise from X to N
+        if (POW2) {
+            // rotation by D/ncap from cos D, sin D by repeated half angles:
+            // cos(t/2) = sqrt((1 + cos t)/2), sin(t/2) = sin t / (2 cos(t/2))
+            const double r = 1.0 / sqrt((X[0] * X[0] + X[1] * X[1]) * (Y[0] * Y[0] + Y[1] * Y[1]));
+            cc = dt * r;
+            ss = cr * r;
+            for (int m = ncap; m > 1; m >>= 1) {
+                const double ch = sqrt(0.5 * (1.0 + cc));
+                ss = ss / (2.0 * ch);
+                cc = ch;
+            }
         } else {
-            if (cnt >= 2) {
-                tri_accum(fx, fy, fb, qx, qy, qb, nx, ny, nb, M, A);
-                nsub++;
-            }
-            if (pt == 2 && nt == 1) cap_accum(qx, qy, qb, nx, ny, nb, ncap, B, M, A, nsub);
+            const double D = atan2(cr, dt);
+            sincos(D / (double)ncap, &ss, &cc);
         }
-        qx = nx; qy = ny; qb[0] = b0; qb[1] = b1; qb[2] = b2; pt = nt;
-        cnt++;
-    };
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const int b = (a + 1) % 3;
-        double px = P[2 * a], py = P[2 * a + 1];
-        double r2 = px * px + py * py;
-        if (r2 <= dd) emit(V[2 * a] - xx, V[2 * a + 1] - xy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0, 0);
-        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
-        double L = ex * ex + ey * ey;
-        double Bq = ex * px + ey * py;
-        double Cq = r2 - dd;
-        double disc = Bq * Bq - L * Cq;
-        if (disc > 0.0) {
-            double s = sqrt(disc);
-            double l1 = (-Bq - s) / L, l2 = (-Bq + s) / L;
-            double w[3];
-            if (l1 > 0.0 && l1 < 1.0) {
-                w[a] = 1.0 - l1; w[b] = l1; w[3 - a - b] = 0.0;
-                emit(px + l1 * ex, py + l1 * ey, w[0], w[1], w[2], 1);
-            }
-            if (l2 > 0.0 && l2 < 1.0) {
-                w[a] = 1.0 - l2; w[b] = l2; w[3 - a - b] = 0.0;
-                emit(px + l2 * ex, py + l2 * ey, w[0], w[1], w[2], 2);
-            }
+        for (int i = 0; i < 5; i++) {
+            Mc[i] = 0.5 * (X[i] + Y[i]);
+            u[i] = X[i];
+            N[i] = Y[i];
         }
+        cj = 1;
+        nsub += 1 << 16;
+    };
+    while (true) {
+        double t[3][5];
+        if (cj > 0) {
+            double v[5];
+            if (cj == ncap) {
+#pragma unroll
+                for (int i = 0; i < 5; i++) v[i] = N[i];
+                cj = 0;
+            } else {
+                v[0] = cc * u[0] - ss * u[1];
+                v[1] = ss * u[0] + cc * u[1];
+                basis_at(B, v[0], v[1], v[2], v[3], v[4]);
+                cj++;
+            }
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                t[0][i] = Mc[i];
+                t[1][i] = u[i];
+                t[2][i] = v[i];
+                u[i] = v[i];
+            }
+        } else {
+            bool got = false;
+            double n[5];
+            int nt = 0;
+            while (ev < 9 && !got) {
+                const int a = ev / 3, kind = ev - 3 * (ev / 3);
+                ev++;
+                if (kind == 0) {
+                    const int b = a == 2 ? 0 : a + 1;
+                    const double ax = Vl[2 * a], ay = Vl[2 * a + 1];
+                    epx = ax - xx;
+                    epy = ay - xy;
+                    eex = Vl[2 * b] - ax;
+                    eey = Vl[2 * b + 1] - ay;
+                    ea = a;
+                    eb = b;
+                    const double r2 = epx * epx + epy * epy;
+                    const double L = eex * eex + eey * eey;
+                    const double Bq = eex * epx + eey * epy;
+                    const double disc = Bq * Bq - L * (r2 - dd);
+                    el1 = 2.0;
+                    el2 = 2.0;
+                    if (disc > 0.0) {
+                        const double sq = sqrt(disc);
+                        const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
+                        if (l1 > 0.0 && l1 < 1.0) el1 = l1;
+                        if (l2 > 0.0 && l2 < 1.0) el2 = l2;
+                    }
+                    if (r2 <= dd) {
+                        set5(n, epx, epy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0);
+                        nt = 0;
+                        got = true;
+                    }
+                } else {
+                    const double l = kind == 1 ? el1 : el2;
+                    if (l < 1.5) {
+                        const double w1 = 1.0 - l;
+                        set5(n, epx + l * eex, epy + l * eey, ea == 0 ? w1 : (eb == 0 ? l : 0.0),
+                             ea == 1 ? w1 : (eb == 1 ? l : 0.0), ea == 2 ? w1 : (eb == 2 ? l : 0.0));
+                        nt = kind;
+                        got = true;
+                    }
+                }
+            }
+            if (!got) {
+                if (!wrapped && cnt >= 2 && pt == 2 && ft == 1) {
+                    wrapped = true;
+                    start_cap(q, f);
+                    continue;
+                }
+                break;
+            }
+            const bool fan = cnt >= 2;
+            if (fan) {
+#pragma unroll
+                for (int i = 0; i < 5; i++) {
+                    t[0][i] = f[i];
+                    t[1][i] = q[i];
+                    t[2][i] = n[i];
+                }
+            }
+            if (cnt >= 1 && pt == 2 && nt == 1) start_cap(q, n);
+            if (cnt == 0) {
+#pragma unroll
+                for (int i = 0; i < 5; i++) f[i] = n[i];
+                ft = nt;
+            }
+#pragma unroll
+            for (int i = 0; i < 5; i++) q[i] = n[i];
+            pt = nt;
+            cnt++;
+            if (!fan) continue;
+        }
+        tri_accum<SYM>(t, M, A);
+        nsub++;
     }
-    if (cnt >= 2 && pt == 2 && ft == 1) cap_accum(qx, qy, qb, fx, fy, fb, ncap, B, M, A, nsub);
 }
 
 __device__ __forceinline__ bool meets_edges(double xx, double xy, const double (&V)[6], double dd)
@@ -219,7 +295,8 @@ __device__ __forceinline__ bool meets_edges(double xx, double xy, const double (
 // reduction of sum_k' S0(x_q), and the row block R_k[a][c] = sum of -Mxy_ab
 // over the pairs whose inner slot b is node C_k[c], reduced in LDS column by
 // column in pair order (each column owned by one lane).
-__global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
+template <int NQ, bool SYM, bool POW2>
+__global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
                                                          const int32_t *__restrict__ pair_kp, ElemSoA E,
                                                          const double *__restrict__ xq, const RuleSet *__restrict__ R,
                                                          double dd, double psi, int ball, int ncap,
@@ -230,12 +307,13 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
                                                          int max_cols, unsigned long long *__restrict__ counters)
 {
     extern __shared__ double dyn[];
-    __shared__ double mxy_l[64][9];
-    __shared__ double sW[NLA_MAX_OUTER][4];
-    __shared__ double sX[NLA_MAX_OUTER][2];
+    __shared__ double sW[NQ][4];
+    __shared__ double sX[NQ][2];
     __shared__ double sV[64][7];
-    __shared__ unsigned short queue[64 * NLA_MAX_OUTER];
+    __shared__ unsigned short queue[64 * NQ];
+    // item results of a phase-2 round, later the chunk's -Mxy (never live together)
     __shared__ double res[64][10];
+    double (*mxy_l)[10] = res;
     const int k = blockIdx.x, lane = threadIdx.x;
     const int nq = R->n_out;
     const double a2k = E.a2[k];
@@ -260,9 +338,9 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
         R_l[2 * nC + c] = 0.0;
         cur_l[c] = colent_ptr[coff + c];
     }
-    double m0[NLA_MAX_OUTER];
+    double m0[NQ];
 #pragma unroll
-    for (int q = 0; q < NLA_MAX_OUTER; q++) m0[q] = 0.0;
+    for (int q = 0; q < NQ; q++) m0[q] = 0.0;
     unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
     for (int64_t base = p0; base < p1; base += 64) {
@@ -283,7 +361,7 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
         unsigned pmask = 0;
         if (act) {
 #pragma unroll
-            for (int q = 0; q < NLA_MAX_OUTER; q++) {
+            for (int q = 0; q < NQ; q++) {
                 if (q >= nq) break;
                 const double xx = sX[q][0], xy = sX[q][1];
                 bool whole = false, part = false;
@@ -349,9 +427,6 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
             const int i = ib + lane;
             if (i < total) {
                 const int e = queue[i], owner = e >> 8, q = e & 0xff;
-                double W6[6];
-#pragma unroll
-                for (int t = 0; t < 6; t++) W6[t] = sV[owner][t];
                 Acc A;
                 A.a2 = 0.0;
 #pragma unroll
@@ -359,12 +434,12 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
 #pragma unroll
                 for (int t = 0; t < 6; t++) A.s2[t] = 0.0;
                 int ns = 0;
-                partial_item(sX[q][0], sX[q][1], W6, dd, ncap, M, A, ns);
+                partial_item<SYM, POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, M, A, ns);
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
                 res[lane][0] = A.a2 * M.wsum;
 #pragma unroll
-                for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t];
+                for (int t = 0; t < 3; t++) res[lane][1 + t] = SYM ? A.s1[t] * M.m1c : A.s1[t];
 #pragma unroll
                 for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t];
             }
@@ -375,7 +450,7 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
                 const int q = queue[j] & 0xff;
                 const double *r = res[j - ib];
 #pragma unroll
-                for (int qq = 0; qq < NLA_MAX_OUTER; qq++)
+                for (int qq = 0; qq < NQ; qq++)
                     if (qq == q) m0[qq] += r[0];
                 const double W = sW[q][0];
 #pragma unroll
@@ -425,7 +500,7 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
     // lanes, then lane 0's sum is broadcast
 #pragma unroll
-    for (int q = 0; q < NLA_MAX_OUTER; q++) {
+    for (int q = 0; q < NQ; q++) {
         double x = m0[q];
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
         m0[q] = __shfl(x, 0, 64);
@@ -435,7 +510,7 @@ __global__ __launch_bounds__(64) void k_pairs_const_fp64(const int64_t *__restri
         const int a = aa[lane], c = cc[lane];
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < NLA_MAX_OUTER; q++)
+        for (int q = 0; q < NQ; q++)
             if (q < nq) s += sW[q][1 + a] * R->out_lam[q][c] * m0[q];
         Cxx[6 * (int64_t)k + lane] = psi * s;
     }
@@ -526,24 +601,27 @@ __global__ void k_load_elem(int K, const uint8_t *__restrict__ tin, const double
     for (int a = 0; a < 3; a++) Gk[3 * (int64_t)k + a] = g[a];
 }
 
-// b_i = G_j - sum_{Dirichlet nodes l} D[j,l] g_l for free node j (Eqs. (appr), (intcon))
+// b_i = G_j - sum_{Dirichlet nodes l} D[j,l] g_l for free node j (Eqs. (appr), (intcon)):
+// one wavefront per free row, lanes stride the row, fixed butterfly reduction
 template <class T>
-__global__ void k_load_rhs(int n_free, const int32_t *__restrict__ free_nodes, const int32_t *__restrict__ n2e_ptr,
-                           const int32_t *__restrict__ n2e, const double *__restrict__ Gk,
-                           const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                           const T *__restrict__ val, const int32_t *__restrict__ n2f, const double *__restrict__ g,
-                           double *__restrict__ b)
+__global__ __launch_bounds__(256) void k_load_rhs(int n_free, const int32_t *__restrict__ free_nodes,
+                                                  const int32_t *__restrict__ n2e_ptr, const int32_t *__restrict__ n2e,
+                                                  const double *__restrict__ Gk, const int64_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                  const int32_t *__restrict__ n2f, const double *__restrict__ g,
+                                                  double *__restrict__ b)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (i >= n_free) return;
-    int j = free_nodes[i];
+    const int j = free_nodes[i];
     double s = 0.0;
-    for (int e = n2e_ptr[j]; e < n2e_ptr[j + 1]; e++) s += Gk[n2e[e]];
-    for (int64_t t = rowptr[j]; t < rowptr[j + 1]; t++) {
-        int c = col[t];
+    for (int e = n2e_ptr[j] + lane; e < n2e_ptr[j + 1]; e += 64) s += Gk[n2e[e]];
+    for (int64_t t = rowptr[j] + lane; t < rowptr[j + 1]; t += 64) {
+        const int c = col[t];
         if (n2f[c] < 0) s -= (double)val[t] * g[c];
     }
-    b[i] = s;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) b[i] = s;
 }
 
 int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStream_t s)
@@ -577,10 +655,19 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
     NLA_HIP(hipMemsetAsync(P->counters, 0, sizeof(unsigned long long) * 6, s));
     NLA_TRY(mark(NLA_PHASE_PAIRS));
     const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
-    k_pairs_const_fp64<<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta,
-                                          pr.kernel_c, pr.ball, pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0,
-                                          P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx, P->max_cols,
-                                          P->counters);
+    const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
+#define NLA_LAUNCH_PAIRS(NQ, SYM, POW2)                                                                            \
+    k_pairs_const_fp64<NQ, SYM, POW2><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules,          \
+                                                         pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap, P->col_off, \
+                                                         P->colent_ptr, P->colent, V, Cyy, Cxx, P->max_cols,          \
+                                                         P->counters)
+    const bool sym = P->rules.in_sym != 0;
+    const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
+    if (P->rules.n_out <= 8 && sym && pow2) NLA_LAUNCH_PAIRS(8, true, true);
+    else if (P->rules.n_out <= 8 && sym) NLA_LAUNCH_PAIRS(8, true, false);
+    else if (P->rules.n_out <= 8) NLA_LAUNCH_PAIRS(8, false, false);
+    else NLA_LAUNCH_PAIRS(16, false, false);
+#undef NLA_LAUNCH_PAIRS
     NLA_HIP(hipGetLastError());
     P->ran[NLA_PHASE_PAIRS] = true;
     NLA_TRY(mark(NLA_PHASE_NEAR));
@@ -600,7 +687,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
     if (f_outer && g_node) {
         k_load_elem<<<grid_for(K, 256), 256, 0, s>>>(K, P->tin, P->E.a2, P->d_rules, f_outer, P->Gk);
         if (P->n_free > 0)
-            k_load_rhs<double><<<grid_for(P->n_free, 256), 256, 0, s>>>(
+            k_load_rhs<double><<<grid_for(P->n_free, 4), 256, 0, s>>>(
                 P->n_free, P->free_nodes, P->n2e_ptr, P->n2e, P->Gk, P->rowptr, P->col, (const double *)P->val,
                 P->node_to_free, g_node, P->b);
         P->have_load = true;

@@ -981,6 +981,14 @@ static void fill_rules(const nla_problem *p, RuleSet *R)
                 R->in_m2[i][j] += p->inner.w[q] * p->inner.lambda[3 * q + i] * p->inner.lambda[3 * q + j];
         }
     }
+    {
+        const double tol = 1e-15;
+        bool sym = std::fabs(R->in_m1[1] - R->in_m1[0]) <= tol && std::fabs(R->in_m1[2] - R->in_m1[0]) <= tol;
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++)
+                sym = sym && std::fabs(R->in_m2[i][j] - (i == j ? R->in_m2[0][0] : R->in_m2[0][1])) <= tol;
+        R->in_sym = sym ? 1 : 0;
+    }
     if (p->kernel == NLA_KERNEL_FRACTIONAL) {
         R->duffy_n = p->duffy_n;
         for (int i = 0; i < p->duffy_n; i++) {
