@@ -171,6 +171,14 @@ int nla_free_nodes_view(const nla_plan *plan, const int32_t **free_nodes);
 int nla_blocks_view(const nla_plan *plan, const void **myy, const void **mxx, const void **elem, const void **rows,
                     const int64_t **col_off, const int32_t **colset, int32_t *dtype);
 
+/* Vertex-sharing pairs under the singular kernel (test hook): n_near, their
+ * pair indices near_pair [n_near] (int64, ascending) and merged 6x6 blocks
+ * blocks [n_near][21] (upper triangle, row-major over the slots a0,a1,a2,b0,b1,b2;
+ * a slot of E_k' whose node is also a node of E_k is merged into E_k's slot and
+ * holds zeros), dtype as in nla_csr_view; device views. */
+int nla_near_view(const nla_plan *plan, int64_t *n_near, const int64_t **near_pair, const void **blocks,
+                  int32_t *dtype);
+
 /* Conjugate gradients on A (after nla_assemble): b [n_free] device, u [n_free]
  * device (in: x0, out: solution), FP64 residuals and fixed-order dot
  * products.  Returns NLA_E_NOT_CONVERGED (with u holding the last iterate)

@@ -79,13 +79,14 @@ def lib():
         L.nla_blocks_view.argtypes = [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P),
                                       C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
         L.nla_cg.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P]
+        L.nla_near_view.argtypes = [P, C.POINTER(I64), C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
         L.nla_set_timing.argtypes = [P, I32]
         L.nla_timings.argtypes = [P, P, C.POINTER(I32)]
         L.nla_plan_destroy.argtypes = [P]
         L.nla_plan_destroy.restype = None
         for name in ("nla_plan_create", "nla_plan_info", "nla_pairs_view", "nla_outer_points", "nla_assemble",
                      "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg",
-                     "nla_set_timing", "nla_timings"):
+                     "nla_set_timing", "nla_timings", "nla_near_view"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -259,6 +260,14 @@ class Plan:
                     elem=_copy_from_device(c.value, 6 * self.K, t, stream).view(self.K, 6),
                     rows=_copy_from_device(d.value, 3 * ncols, t, stream),
                     col_off=col_off, colset=_copy_from_device(f.value, ncols, torch.int32, stream))
+
+    def near(self, stream=None):
+        """(near pair indices [n], merged blocks [n, 21]) of the singular-kernel pairs (copies)."""
+        n, a, b, dt = C.c_int64(), C.c_void_p(), C.c_void_p(), C.c_int32()
+        _check(lib().nla_near_view(self._h, C.byref(n), C.byref(a), C.byref(b), C.byref(dt)))
+        t = torch.float64 if dt.value == 0 else torch.float32
+        return (_copy_from_device(a.value, n.value, torch.int64, stream),
+                _copy_from_device(b.value, 21 * n.value, t, stream).view(-1, 21))
 
     def cg(self, b, u0=None, rtol=1e-12, maxit=10000, stream=None):
         n = self.info()["n_free"]

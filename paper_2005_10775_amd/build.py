@@ -21,6 +21,7 @@ UNITS = {
     "nla_plan.hip": ["-ffp-contract=off"],
     "nla_numeric.hip": [],
     "nla_cg.hip": [],
+    "nla_fp32.hip": [],
 }
 
 

@@ -1,0 +1,283 @@
+// Device helpers shared by the numeric kernels: inner-rule moments, the P1
+// basis of the inner element, subtriangle quadrature and the retriangulation
+// of E' n B_delta(x).
+#pragma once
+#include "nla_internal.hpp"
+
+// inner-rule moments as the kernels use them; sym = the rule is invariant
+// under permutations of the barycentric coordinates, so sum_q w mu_i = m1c and
+// sum_q w mu_i mu_j = o + dm [i == j]
+struct RuleMom {
+    double wsum, m1[3], m2[3][3];
+    double m1c, o, dm;
+};
+
+__device__ __forceinline__ RuleMom load_moments(const RuleSet *__restrict__ R)
+{
+    RuleMom M;
+    M.wsum = R->in_wsum;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        M.m1[i] = R->in_m1[i];
+#pragma unroll
+        for (int j = 0; j < 3; j++) M.m2[i][j] = R->in_m2[i][j];
+    }
+    M.m1c = R->in_m1[0];
+    M.o = R->in_m2[0][1];
+    M.dm = R->in_m2[0][0] - R->in_m2[0][1];
+    return M;
+}
+
+// geometric inner sums of one (x, E') item with psi = 1 (psi is constant and
+// applied per pair): a2 = sum of twice-areas, s1_b ~ int beta_b (times m1c
+// in the symmetric case), s2 = int beta_b beta_b' (upper triangle 00,01,02,11,12,22)
+struct Acc {
+    double a2;
+    double s1[3];
+    double s2[6];
+};
+
+// P1 basis of E' in coordinates relative to the outer point: beta1, beta2 from
+// the offset to vertex 0 and the inverse of the edge matrix, beta0 = 1 - beta1 - beta2.
+struct Basis {
+    double x0, y0, i11, i12, i21, i22;
+};
+
+__device__ __forceinline__ void basis_at(const Basis &B, double px, double py, double &b0, double &b1, double &b2)
+{
+    double dx = px - B.x0, dy = py - B.y0;
+    b1 = dx * B.i11 + dy * B.i12;
+    b2 = dx * B.i21 + dy * B.i22;
+    b0 = 1.0 - b1 - b2;
+}
+
+// the inner rule on the subtriangle with vertices t[i] = (x, y, beta0, beta1, beta2),
+// evaluated from the basis values at its vertices: sum_q w_q beta(y_q) =
+// sum_i m1_i beta(t_i) and sum_q w_q beta beta^T = B^T M2 B (B = vertex values);
+// for a symmetric rule B^T M2 B = o cs cs^T + dm B^T B, cs = column sums of B
+template <bool SYM>
+__device__ __forceinline__ void tri_accum(const double (&t)[3][5], const RuleMom &M, Acc &A)
+{
+    const double a2 = fabs((t[1][0] - t[0][0]) * (t[2][1] - t[0][1]) - (t[1][1] - t[0][1]) * (t[2][0] - t[0][0]));
+    A.a2 += a2;
+    const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+    if (SYM) {
+        double cs[3];
+#pragma unroll
+        for (int l = 0; l < 3; l++) {
+            cs[l] = t[0][2 + l] + t[1][2 + l] + t[2][2 + l];
+            A.s1[l] += a2 * cs[l];
+        }
+        const double w = a2 * M.o, v = a2 * M.dm;
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const int j = jj[e], l = ll[e];
+            double q = t[0][2 + j] * t[0][2 + l] + t[1][2 + j] * t[1][2 + l] + t[2][2 + j] * t[2][2 + l];
+            A.s2[e] += w * (cs[j] * cs[l]) + v * q;
+        }
+    } else {
+        double U[3][3];
+#pragma unroll
+        for (int l = 0; l < 3; l++) {
+            A.s1[l] += a2 * (M.m1[0] * t[0][2 + l] + M.m1[1] * t[1][2 + l] + M.m1[2] * t[2][2 + l]);
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                U[i][l] = M.m2[i][0] * t[0][2 + l] + M.m2[i][1] * t[1][2 + l] + M.m2[i][2] * t[2][2 + l];
+        }
+#pragma unroll
+        for (int e = 0; e < 6; e++) {
+            const int j = jj[e], l = ll[e];
+            A.s2[e] += a2 * (t[0][2 + j] * U[0][l] + t[1][2 + j] * U[1][l] + t[2][2 + j] * U[2][l]);
+        }
+    }
+}
+
+__device__ __forceinline__ void set5(double (&d)[5], double x, double y, double b0, double b1, double b2)
+{
+    d[0] = x; d[1] = y; d[2] = b0; d[3] = b1; d[4] = b2;
+}
+
+// E' n B_delta(x) retriangulated (Sec. 4.2.1-4.2.2 and Sec. 7.1 tasks 3-6),
+// written as one generator loop so that a single copy of the subtriangle
+// quadrature is inlined.  The edges are walked v0->v1->v2: vertices inside
+// the closed ball and the roots lambda in (0,1) of |v_a + lambda e - x|^2 =
+// delta^2 (smaller root entry, larger exit) arrive in order; every new point
+// closes the fan triangle (first, previous, new), and every exit followed by
+// an entry (cyclically) opens a cap: the arc from exit X counter-clockwise to
+// entry N split into ncap equal arcs fanned from the chord midpoint.  A cap
+// span not in (0, pi] only arises from rounding when X and N coincide and is
+// dropped (cross product <= 0).  Each subtriangle goes to tri(t).  POW2: ncap is a power of two and the
+// rotation comes from half-angle steps instead of atan2/sincos.  Vl: E' in absolute coordinates (6 values); coordinates below are
+// relative to the outer point.
+template <bool POW2, class TriF>
+__device__ void partial_item(double xx, double xy, const double *Vl, double dd, int ncap, TriF &tri, int &nsub)
+{
+    Basis B;
+    {
+        const double e1x = Vl[2] - Vl[0], e1y = Vl[3] - Vl[1], e2x = Vl[4] - Vl[0], e2y = Vl[5] - Vl[1];
+        const double id = 1.0 / (e1x * e2y - e1y * e2x);
+        B.x0 = Vl[0] - xx;
+        B.y0 = Vl[1] - xy;
+        B.i11 = e2y * id;
+        B.i12 = -e2x * id;
+        B.i21 = -e1y * id;
+        B.i22 = e1x * id;
+    }
+    int ev = 0, cnt = 0, ft = 0, pt = 0, ea = 0, eb = 0;
+    double f[5] = {0, 0, 0, 0, 0}, q[5] = {0, 0, 0, 0, 0};
+    double epx = 0, epy = 0, eex = 0, eey = 0, el1 = 2.0, el2 = 2.0;
+    int cj = 0;
+    bool wrapped = false;
+    double Mc[5] = {0, 0, 0, 0, 0}, u[5] = {0, 0, 0, 0, 0}, N[5] = {0, 0, 0, 0, 0};
+    double cc = 1.0, ss = 0.0;
+    auto start_cap = [&](const double (&X)[5], const double (&Y)[5]) {
+        const double cr = X[0] * Y[1] - X[1] * Y[0], dt = X[0] * Y[0] + X[1] * Y[1];
+        if (!(cr > 0.0) || ncap < 2) return;      // span in (0, pi): counter-clockwise from X to N
+        if (POW2) {
+            // rotation by D/ncap from cos D, sin D by repeated half angles:
+            // cos(t/2) = sqrt((1 + cos t)/2), sin(t/2) = sin t / (2 cos(t/2))
+            const double r = 1.0 / sqrt((X[0] * X[0] + X[1] * X[1]) * (Y[0] * Y[0] + Y[1] * Y[1]));
+            cc = dt * r;
+            ss = cr * r;
+            for (int m = ncap; m > 1; m >>= 1) {
+                const double ch = sqrt(0.5 * (1.0 + cc));
+                ss = ss / (2.0 * ch);
+                cc = ch;
+            }
+        } else {
+            const double D = atan2(cr, dt);
+            sincos(D / (double)ncap, &ss, &cc);
+        }
+#pragma unroll
+        for (int i = 0; i < 5; i++) {
+            Mc[i] = 0.5 * (X[i] + Y[i]);
+            u[i] = X[i];
+            N[i] = Y[i];
+        }
+        cj = 1;
+        nsub += 1 << 16;
+    };
+    while (true) {
+        double t[3][5];
+        if (cj > 0) {
+            double v[5];
+            if (cj == ncap) {
+#pragma unroll
+                for (int i = 0; i < 5; i++) v[i] = N[i];
+                cj = 0;
+            } else {
+                v[0] = cc * u[0] - ss * u[1];
+                v[1] = ss * u[0] + cc * u[1];
+                basis_at(B, v[0], v[1], v[2], v[3], v[4]);
+                cj++;
+            }
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                t[0][i] = Mc[i];
+                t[1][i] = u[i];
+                t[2][i] = v[i];
+                u[i] = v[i];
+            }
+        } else {
+            bool got = false;
+            double n[5];
+            int nt = 0;
+            while (ev < 9 && !got) {
+                const int a = ev / 3, kind = ev - 3 * (ev / 3);
+                ev++;
+                if (kind == 0) {
+                    const int b = a == 2 ? 0 : a + 1;
+                    const double ax = Vl[2 * a], ay = Vl[2 * a + 1];
+                    epx = ax - xx;
+                    epy = ay - xy;
+                    eex = Vl[2 * b] - ax;
+                    eey = Vl[2 * b + 1] - ay;
+                    ea = a;
+                    eb = b;
+                    const double r2 = epx * epx + epy * epy;
+                    const double L = eex * eex + eey * eey;
+                    const double Bq = eex * epx + eey * epy;
+                    const double disc = Bq * Bq - L * (r2 - dd);
+                    el1 = 2.0;
+                    el2 = 2.0;
+                    if (disc > 0.0) {
+                        const double sq = sqrt(disc);
+                        const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
+                        if (l1 > 0.0 && l1 < 1.0) el1 = l1;
+                        if (l2 > 0.0 && l2 < 1.0) el2 = l2;
+                    }
+                    if (r2 <= dd) {
+                        set5(n, epx, epy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0);
+                        nt = 0;
+                        got = true;
+                    }
+                } else {
+                    const double l = kind == 1 ? el1 : el2;
+                    if (l < 1.5) {
+                        const double w1 = 1.0 - l;
+                        set5(n, epx + l * eex, epy + l * eey, ea == 0 ? w1 : (eb == 0 ? l : 0.0),
+                             ea == 1 ? w1 : (eb == 1 ? l : 0.0), ea == 2 ? w1 : (eb == 2 ? l : 0.0));
+                        nt = kind;
+                        got = true;
+                    }
+                }
+            }
+            if (!got) {
+                if (!wrapped && cnt >= 2 && pt == 2 && ft == 1) {
+                    wrapped = true;
+                    start_cap(q, f);
+                    continue;
+                }
+                break;
+            }
+            const bool fan = cnt >= 2;
+            if (fan) {
+#pragma unroll
+                for (int i = 0; i < 5; i++) {
+                    t[0][i] = f[i];
+                    t[1][i] = q[i];
+                    t[2][i] = n[i];
+                }
+            }
+            if (cnt >= 1 && pt == 2 && nt == 1) start_cap(q, n);
+            if (cnt == 0) {
+#pragma unroll
+                for (int i = 0; i < 5; i++) f[i] = n[i];
+                ft = nt;
+            }
+#pragma unroll
+            for (int i = 0; i < 5; i++) q[i] = n[i];
+            pt = nt;
+            cnt++;
+            if (!fan) continue;
+        }
+        tri(t);
+        nsub++;
+    }
+}
+
+__device__ __forceinline__ bool meets_edges(double xx, double xy, const double (&V)[6], double dd)
+{
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        if (ex * py - ey * px < 0.0) inside = false;
+    }
+    if (inside) return true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        double t = ex * px + ey * py, L = ex * ex + ey * ey;
+        if (t > 0.0 && t < L) {
+            double c = ex * py - ey * px;
+            if (c * c <= dd * L) return true;
+        }
+    }
+    return false;
+}
+

@@ -47,6 +47,8 @@ struct RuleSet {
     double in_m2[3][3];
     double duffy_x[NLA_MAX_DUFFY];
     double duffy_w[NLA_MAX_DUFFY];
+    float in_lamf[NLA_MAX_INNER][3];   // FP32 copies for the FP32 point quadrature
+    float in_wf[NLA_MAX_INNER];
 };
 
 // Element data, structure of arrays, K entries each.
@@ -106,9 +108,15 @@ struct nla_plan {
     // transposed pair order: pairs (k, k') grouped by k', k ascending within
     int64_t *tptr = nullptr;    // [K+1]
     int32_t *tperm = nullptr;   // [n_pairs]
-    // near-diagonal pairs (singular kernel)
+    // near-diagonal pairs (singular kernel): pairs sharing a vertex, their 6x6
+    // merged blocks (upper triangle, 21 values) and codes of the upper entries
     int64_t n_near = 0;
-    int64_t *near_pair = nullptr;
+    int64_t *near_pair = nullptr;   // [n_near] pair indices, ascending
+    uint8_t *near_flag = nullptr;   // [n_pairs]
+    int64_t n_ncodes = 0;
+    int64_t *nup_ptr = nullptr;     // [n_up+1]
+    int32_t *ncodes = nullptr;      // [n_ncodes] indices into the near-block array
+    void *near_blk = nullptr;       // [n_near][21]
     // contributions and values
     int64_t n_contrib = 0;      // 6P (Myy) + 6K (Mxx) + 6K (element blocks) + 3 n_cols (R) + 21 n_near
     void *contrib = nullptr;    // f64 or f32 [n_contrib]
@@ -131,6 +139,7 @@ struct nla_plan {
     // phase timing: (NLA_NPHASE + 1) events per timed assembly
     int timing_slots = 0, timing_count = 0;
     std::vector<hipEvent_t> ev;
+    hipEvent_t *cur_ev = nullptr;   // events of the assembly being timed, or null
     bool ran[8] = {};
     ~nla_plan()
     {
@@ -146,5 +155,6 @@ struct nla_plan {
 int nla_build_pairs(nla_plan *P, hipStream_t s);
 int nla_build_pattern(nla_plan *P, hipStream_t s);
 int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStream_t s);
+int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, hipStream_t));
 int nla_cg_run(const nla_plan *P, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
                double *relres, hipStream_t s);

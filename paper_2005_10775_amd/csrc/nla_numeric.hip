@@ -5,283 +5,7 @@
 
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// inner-rule moments as the kernels use them; sym = the rule is invariant
-// under permutations of the barycentric coordinates, so sum_q w mu_i = m1c and
-// sum_q w mu_i mu_j = o + dm [i == j]
-struct RuleMom {
-    double wsum, m1[3], m2[3][3];
-    double m1c, o, dm;
-};
-
-__device__ __forceinline__ RuleMom load_moments(const RuleSet *__restrict__ R)
-{
-    RuleMom M;
-    M.wsum = R->in_wsum;
-#pragma unroll
-    for (int i = 0; i < 3; i++) {
-        M.m1[i] = R->in_m1[i];
-#pragma unroll
-        for (int j = 0; j < 3; j++) M.m2[i][j] = R->in_m2[i][j];
-    }
-    M.m1c = R->in_m1[0];
-    M.o = R->in_m2[0][1];
-    M.dm = R->in_m2[0][0] - R->in_m2[0][1];
-    return M;
-}
-
-// geometric inner sums of one (x, E') item with psi = 1 (psi is constant and
-// applied per pair): a2 = sum of twice-areas, s1_b ~ int beta_b (times m1c
-// in the symmetric case), s2 = int beta_b beta_b' (upper triangle 00,01,02,11,12,22)
-struct Acc {
-    double a2;
-    double s1[3];
-    double s2[6];
-};
-
-// P1 basis of E' in coordinates relative to the outer point: beta1, beta2 from
-// the offset to vertex 0 and the inverse of the edge matrix, beta0 = 1 - beta1 - beta2.
-struct Basis {
-    double x0, y0, i11, i12, i21, i22;
-};
-
-__device__ __forceinline__ void basis_at(const Basis &B, double px, double py, double &b0, double &b1, double &b2)
-{
-    double dx = px - B.x0, dy = py - B.y0;
-    b1 = dx * B.i11 + dy * B.i12;
-    b2 = dx * B.i21 + dy * B.i22;
-    b0 = 1.0 - b1 - b2;
-}
-
-// the inner rule on the subtriangle with vertices t[i] = (x, y, beta0, beta1, beta2),
-// evaluated from the basis values at its vertices: sum_q w_q beta(y_q) =
-// sum_i m1_i beta(t_i) and sum_q w_q beta beta^T = B^T M2 B (B = vertex values);
-// for a symmetric rule B^T M2 B = o cs cs^T + dm B^T B, cs = column sums of B
-template <bool SYM>
-__device__ __forceinline__ void tri_accum(const double (&t)[3][5], const RuleMom &M, Acc &A)
-{
-    const double a2 = fabs((t[1][0] - t[0][0]) * (t[2][1] - t[0][1]) - (t[1][1] - t[0][1]) * (t[2][0] - t[0][0]));
-    A.a2 += a2;
-    const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
-    if (SYM) {
-        double cs[3];
-#pragma unroll
-        for (int l = 0; l < 3; l++) {
-            cs[l] = t[0][2 + l] + t[1][2 + l] + t[2][2 + l];
-            A.s1[l] += a2 * cs[l];
-        }
-        const double w = a2 * M.o, v = a2 * M.dm;
-#pragma unroll
-        for (int e = 0; e < 6; e++) {
-            const int j = jj[e], l = ll[e];
-            double q = t[0][2 + j] * t[0][2 + l] + t[1][2 + j] * t[1][2 + l] + t[2][2 + j] * t[2][2 + l];
-            A.s2[e] += w * (cs[j] * cs[l]) + v * q;
-        }
-    } else {
-        double U[3][3];
-#pragma unroll
-        for (int l = 0; l < 3; l++) {
-            A.s1[l] += a2 * (M.m1[0] * t[0][2 + l] + M.m1[1] * t[1][2 + l] + M.m1[2] * t[2][2 + l]);
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-                U[i][l] = M.m2[i][0] * t[0][2 + l] + M.m2[i][1] * t[1][2 + l] + M.m2[i][2] * t[2][2 + l];
-        }
-#pragma unroll
-        for (int e = 0; e < 6; e++) {
-            const int j = jj[e], l = ll[e];
-            A.s2[e] += a2 * (t[0][2 + j] * U[0][l] + t[1][2 + j] * U[1][l] + t[2][2 + j] * U[2][l]);
-        }
-    }
-}
-
-__device__ __forceinline__ void set5(double (&d)[5], double x, double y, double b0, double b1, double b2)
-{
-    d[0] = x; d[1] = y; d[2] = b0; d[3] = b1; d[4] = b2;
-}
-
-// E' n B_delta(x) retriangulated (Sec. 4.2.1-4.2.2 and Sec. 7.1 tasks 3-6),
-// written as one generator loop so that a single copy of the subtriangle
-// quadrature is inlined.  The edges are walked v0->v1->v2: vertices inside
-// the closed ball and the roots lambda in (0,1) of |v_a + lambda e - x|^2 =
-// delta^2 (smaller root entry, larger exit) arrive in order; every new point
-// closes the fan triangle (first, previous, new), and every exit followed by
-// an entry (cyclically) opens a cap: the arc from exit X counter-clockwise to
-// entry N split into ncap equal arcs fanned from the chord midpoint.  A cap
-// span not in (0, pi] only arises from rounding when X and N coincide and is
-// dropped (cross product <= 0).  POW2: ncap is a power of two and the
-// rotation comes from half-angle steps instead of atan2/sincos.  Vl: E' in absolute coordinates (6 values); coordinates below are
-// relative to the outer point.
-template <bool SYM, bool POW2>
-__device__ void partial_item(double xx, double xy, const double *Vl, double dd, int ncap, const RuleMom &M,
-                             Acc &A, int &nsub)
-{
-    Basis B;
-    {
-        const double e1x = Vl[2] - Vl[0], e1y = Vl[3] - Vl[1], e2x = Vl[4] - Vl[0], e2y = Vl[5] - Vl[1];
-        const double id = 1.0 / (e1x * e2y - e1y * e2x);
-        B.x0 = Vl[0] - xx;
-        B.y0 = Vl[1] - xy;
-        B.i11 = e2y * id;
-        B.i12 = -e2x * id;
-        B.i21 = -e1y * id;
-        B.i22 = e1x * id;
-    }
-    int ev = 0, cnt = 0, ft = 0, pt = 0, ea = 0, eb = 0;
-    double f[5] = {0, 0, 0, 0, 0}, q[5] = {0, 0, 0, 0, 0};
-    double epx = 0, epy = 0, eex = 0, eey = 0, el1 = 2.0, el2 = 2.0;
-    int cj = 0;
-    bool wrapped = false;
-    double Mc[5] = {0, 0, 0, 0, 0}, u[5] = {0, 0, 0, 0, 0}, N[5] = {0, 0, 0, 0, 0};
-    double cc = 1.0, ss = 0.0;
-    auto start_cap = [&](const double (&X)[5], const double (&Y)[5]) {
-        const double cr = X[0] * Y[1] - X[1] * Y[0], dt = X[0] * Y[0] + X[1] * Y[1];
-        if (!(cr > 0.0) || ncap < 2) return;      // span in (0, pi): counter-clockwise from X to N
-        if (POW2) {
-            // rotation by D/ncap from cos D, sin D by repeated half angles:
-            // cos(t/2) = sqrt((1 + cos t)/2), sin(t/2) = sin t / (2 cos(t/2))
-            const double r = 1.0 / sqrt((X[0] * X[0] + X[1] * X[1]) * (Y[0] * Y[0] + Y[1] * Y[1]));
-            cc = dt * r;
-            ss = cr * r;
-            for (int m = ncap; m > 1; m >>= 1) {
-                const double ch = sqrt(0.5 * (1.0 + cc));
-                ss = ss / (2.0 * ch);
-                cc = ch;
-            }
-        } else {
-            const double D = atan2(cr, dt);
-            sincos(D / (double)ncap, &ss, &cc);
-        }
-#pragma unroll
-        for (int i = 0; i < 5; i++) {
-            Mc[i] = 0.5 * (X[i] + Y[i]);
-            u[i] = X[i];
-            N[i] = Y[i];
-        }
-        cj = 1;
-        nsub += 1 << 16;
-    };
-    while (true) {
-        double t[3][5];
-        if (cj > 0) {
-            double v[5];
-            if (cj == ncap) {
-#pragma unroll
-                for (int i = 0; i < 5; i++) v[i] = N[i];
-                cj = 0;
-            } else {
-                v[0] = cc * u[0] - ss * u[1];
-                v[1] = ss * u[0] + cc * u[1];
-                basis_at(B, v[0], v[1], v[2], v[3], v[4]);
-                cj++;
-            }
-#pragma unroll
-            for (int i = 0; i < 5; i++) {
-                t[0][i] = Mc[i];
-                t[1][i] = u[i];
-                t[2][i] = v[i];
-                u[i] = v[i];
-            }
-        } else {
-            bool got = false;
-            double n[5];
-            int nt = 0;
-            while (ev < 9 && !got) {
-                const int a = ev / 3, kind = ev - 3 * (ev / 3);
-                ev++;
-                if (kind == 0) {
-                    const int b = a == 2 ? 0 : a + 1;
-                    const double ax = Vl[2 * a], ay = Vl[2 * a + 1];
-                    epx = ax - xx;
-                    epy = ay - xy;
-                    eex = Vl[2 * b] - ax;
-                    eey = Vl[2 * b + 1] - ay;
-                    ea = a;
-                    eb = b;
-                    const double r2 = epx * epx + epy * epy;
-                    const double L = eex * eex + eey * eey;
-                    const double Bq = eex * epx + eey * epy;
-                    const double disc = Bq * Bq - L * (r2 - dd);
-                    el1 = 2.0;
-                    el2 = 2.0;
-                    if (disc > 0.0) {
-                        const double sq = sqrt(disc);
-                        const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
-                        if (l1 > 0.0 && l1 < 1.0) el1 = l1;
-                        if (l2 > 0.0 && l2 < 1.0) el2 = l2;
-                    }
-                    if (r2 <= dd) {
-                        set5(n, epx, epy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0);
-                        nt = 0;
-                        got = true;
-                    }
-                } else {
-                    const double l = kind == 1 ? el1 : el2;
-                    if (l < 1.5) {
-                        const double w1 = 1.0 - l;
-                        set5(n, epx + l * eex, epy + l * eey, ea == 0 ? w1 : (eb == 0 ? l : 0.0),
-                             ea == 1 ? w1 : (eb == 1 ? l : 0.0), ea == 2 ? w1 : (eb == 2 ? l : 0.0));
-                        nt = kind;
-                        got = true;
-                    }
-                }
-            }
-            if (!got) {
-                if (!wrapped && cnt >= 2 && pt == 2 && ft == 1) {
-                    wrapped = true;
-                    start_cap(q, f);
-                    continue;
-                }
-                break;
-            }
-            const bool fan = cnt >= 2;
-            if (fan) {
-#pragma unroll
-                for (int i = 0; i < 5; i++) {
-                    t[0][i] = f[i];
-                    t[1][i] = q[i];
-                    t[2][i] = n[i];
-                }
-            }
-            if (cnt >= 1 && pt == 2 && nt == 1) start_cap(q, n);
-            if (cnt == 0) {
-#pragma unroll
-                for (int i = 0; i < 5; i++) f[i] = n[i];
-                ft = nt;
-            }
-#pragma unroll
-            for (int i = 0; i < 5; i++) q[i] = n[i];
-            pt = nt;
-            cnt++;
-            if (!fan) continue;
-        }
-        tri_accum<SYM>(t, M, A);
-        nsub++;
-    }
-}
-
-__device__ __forceinline__ bool meets_edges(double xx, double xy, const double (&V)[6], double dd)
-{
-    bool inside = true;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const int b = (a + 1) % 3;
-        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
-        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
-        if (ex * py - ey * px < 0.0) inside = false;
-    }
-    if (inside) return true;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const int b = (a + 1) % 3;
-        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
-        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
-        double t = ex * px + ey * py, L = ex * ex + ey * ey;
-        if (t > 0.0 && t < L) {
-            double c = ex * py - ey * px;
-            if (c * c <= dd * L) return true;
-        }
-    }
-    return false;
-}
+#include "nla_device.hpp"
 
 // One wavefront per outer element k (Eq. (bformhj) restricted to the pairs
 // of k).  Phase 1: every lane takes one pair (k, k'), classifies its items
@@ -434,7 +158,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
 #pragma unroll
                 for (int t = 0; t < 6; t++) A.s2[t] = 0.0;
                 int ns = 0;
-                partial_item<SYM, POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, M, A, ns);
+                auto tri = [&](const double (&t)[3][5]) { tri_accum<SYM>(t, M, A); };
+                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns);
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
                 res[lane][0] = A.a2 * M.wsum;
@@ -624,79 +349,94 @@ __global__ __launch_bounds__(256) void k_load_rhs(int n_free, const int32_t *__r
     if (lane == 0) b[i] = s;
 }
 
+static void nla_mark(nla_plan *P, int i, hipStream_t s)
+{
+    if (P->cur_ev) (void)hipEventRecord(P->cur_ev[i], s);
+}
+
 int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStream_t s)
 {
     const nla_problem &pr = P->prob;
-    if (pr.kernel != NLA_KERNEL_CONSTANT || pr.precision != NLA_FP64) {
-        nla_set_error("this build assembles the constant kernel in FP64 only");
+    const bool fp64 = pr.precision == NLA_FP64;
+    if (fp64 && pr.kernel != NLA_KERNEL_CONSTANT) {
+        nla_set_error("the FP64 path assembles the constant kernel; use NLA_FP32 for the fractional kernel");
         return NLA_E_UNSUPPORTED;
     }
     const int64_t NP = P->n_pairs;
     const int K = P->K;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
     if (!P->contrib) {
         P->n_contrib = 6 * NP + 12 * (int64_t)K + 3 * P->n_cols;
-        NLA_TRY(P->arena.alloc(&P->contrib, sizeof(double) * P->n_contrib));
-        NLA_TRY(P->arena.alloc(&P->val, sizeof(double) * P->nnz));
-        NLA_TRY(P->arena.alloc(&P->a_val, sizeof(double) * (P->nnz_free > 0 ? P->nnz_free : 1)));
+        NLA_TRY(P->arena.alloc(&P->contrib, es * P->n_contrib));
+        NLA_TRY(P->arena.alloc(&P->val, es * P->nnz));
+        NLA_TRY(P->arena.alloc(&P->a_val, es * (P->nnz_free > 0 ? P->nnz_free : 1)));
+        NLA_TRY(P->arena.alloc(&P->near_blk, es * (P->n_near > 0 ? 21 * P->n_near : 1)));
         NLA_TRY(P->arena.get(&P->Gk, 3 * (size_t)K));
         NLA_TRY(P->arena.get(&P->b, P->n_free > 0 ? P->n_free : 1));
     }
-    double *Cyy = (double *)P->contrib;
-    double *Cxx = Cyy + 6 * NP;
-    double *V = Cxx + 6 * (int64_t)K;          // [R (3 n_cols) | E (6K)]: the values the codes index
-    double *Ce = V + 3 * P->n_cols;
     const bool timed = P->timing_count < P->timing_slots;
-    hipEvent_t *ev = timed ? &P->ev[(size_t)P->timing_count * (NLA_NPHASE + 1)] : nullptr;
-    auto mark = [&](int i) -> int {
-        if (timed) NLA_HIP(hipEventRecord(ev[i], s));
-        return NLA_OK;
-    };
+    P->cur_ev = timed ? &P->ev[(size_t)P->timing_count * (NLA_NPHASE + 1)] : nullptr;
     for (int i = 0; i < NLA_NPHASE; i++) P->ran[i] = false;
     NLA_HIP(hipMemsetAsync(P->counters, 0, sizeof(unsigned long long) * 6, s));
-    NLA_TRY(mark(NLA_PHASE_PAIRS));
-    const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
-    const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
+    if (fp64) {
+        double *Cyy = (double *)P->contrib;
+        double *Cxx = Cyy + 6 * NP;
+        double *V = Cxx + 6 * (int64_t)K;          // [R (3 n_cols) | E (6K)]: the values the codes index
+        double *Ce = V + 3 * P->n_cols;
+        nla_mark(P, NLA_PHASE_PAIRS, s);
+        const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
+        const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
 #define NLA_LAUNCH_PAIRS(NQ, SYM, POW2)                                                                            \
     k_pairs_const_fp64<NQ, SYM, POW2><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules,          \
                                                          pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap, P->col_off, \
                                                          P->colent_ptr, P->colent, V, Cyy, Cxx, P->max_cols,          \
                                                          P->counters)
-    const bool sym = P->rules.in_sym != 0;
-    const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
-    if (P->rules.n_out <= 8 && sym && pow2) NLA_LAUNCH_PAIRS(8, true, true);
-    else if (P->rules.n_out <= 8 && sym) NLA_LAUNCH_PAIRS(8, true, false);
-    else if (P->rules.n_out <= 8) NLA_LAUNCH_PAIRS(8, false, false);
-    else NLA_LAUNCH_PAIRS(16, false, false);
+        const bool sym = P->rules.in_sym != 0;
+        const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
+        if (P->rules.n_out <= 8 && sym && pow2) NLA_LAUNCH_PAIRS(8, true, true);
+        else if (P->rules.n_out <= 8 && sym) NLA_LAUNCH_PAIRS(8, true, false);
+        else if (P->rules.n_out <= 8) NLA_LAUNCH_PAIRS(8, false, false);
+        else NLA_LAUNCH_PAIRS(16, false, false);
 #undef NLA_LAUNCH_PAIRS
-    NLA_HIP(hipGetLastError());
-    P->ran[NLA_PHASE_PAIRS] = true;
-    NLA_TRY(mark(NLA_PHASE_NEAR));
-    NLA_TRY(mark(NLA_PHASE_SEGSUM));
-    k_elem_blocks<double><<<K, 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
-    if (P->n_up > 0)
-        k_segsum_f64<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes, P->up_dst, P->mirror, V,
-                                                           (double *)P->val);
-    P->ran[NLA_PHASE_SEGSUM] = true;
-    NLA_TRY(mark(NLA_PHASE_EXTRACT));
-    if (P->nnz_free > 0)
-        k_extract<double><<<grid_for(P->nnz_free, 256), 256, 0, s>>>(P->nnz_free, P->a_src, (const double *)P->val,
-                                                                    (double *)P->a_val);
-    P->ran[NLA_PHASE_EXTRACT] = true;
-    NLA_TRY(mark(NLA_PHASE_LOAD));
+        NLA_HIP(hipGetLastError());
+        P->ran[NLA_PHASE_PAIRS] = true;
+        nla_mark(P, NLA_PHASE_NEAR, s);
+        nla_mark(P, NLA_PHASE_SEGSUM, s);
+        k_elem_blocks<double><<<K, 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
+        if (P->n_up > 0)
+            k_segsum_f64<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes, P->up_dst, P->mirror, V,
+                                                               (double *)P->val);
+        P->ran[NLA_PHASE_SEGSUM] = true;
+        nla_mark(P, NLA_PHASE_EXTRACT, s);
+        if (P->nnz_free > 0)
+            k_extract<double><<<grid_for(P->nnz_free, 256), 256, 0, s>>>(P->nnz_free, P->a_src,
+                                                                        (const double *)P->val, (double *)P->a_val);
+        P->ran[NLA_PHASE_EXTRACT] = true;
+    } else {
+        NLA_TRY(nla_numeric_fp32(P, s, nla_mark));
+    }
+    nla_mark(P, NLA_PHASE_LOAD, s);
     P->have_load = false;
     if (f_outer && g_node) {
         k_load_elem<<<grid_for(K, 256), 256, 0, s>>>(K, P->tin, P->E.a2, P->d_rules, f_outer, P->Gk);
-        if (P->n_free > 0)
-            k_load_rhs<double><<<grid_for(P->n_free, 4), 256, 0, s>>>(
-                P->n_free, P->free_nodes, P->n2e_ptr, P->n2e, P->Gk, P->rowptr, P->col, (const double *)P->val,
-                P->node_to_free, g_node, P->b);
+        if (P->n_free > 0) {
+            if (fp64)
+                k_load_rhs<double><<<grid_for(P->n_free, 4), 256, 0, s>>>(
+                    P->n_free, P->free_nodes, P->n2e_ptr, P->n2e, P->Gk, P->rowptr, P->col, (const double *)P->val,
+                    P->node_to_free, g_node, P->b);
+            else
+                k_load_rhs<float><<<grid_for(P->n_free, 4), 256, 0, s>>>(
+                    P->n_free, P->free_nodes, P->n2e_ptr, P->n2e, P->Gk, P->rowptr, P->col, (const float *)P->val,
+                    P->node_to_free, g_node, P->b);
+        }
         P->have_load = true;
         P->ran[NLA_PHASE_LOAD] = true;
     }
-    NLA_TRY(mark(NLA_NPHASE));
+    nla_mark(P, NLA_NPHASE, s);
     if (timed) P->timing_count++;
+    P->cur_ev = nullptr;
     NLA_HIP(hipGetLastError());
-    P->val_dtype = NLA_DTYPE_F64;
+    P->val_dtype = fp64 ? NLA_DTYPE_F64 : NLA_DTYPE_F32;
     P->assembled = true;
     return NLA_OK;
 }

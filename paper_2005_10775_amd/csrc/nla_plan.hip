@@ -113,9 +113,9 @@ static int validate(const nla_mesh *m, const nla_problem *p)
         nla_set_error("learned caps are not available in this build");
         return NLA_E_UNSUPPORTED;
     }
-    if (p->kernel == NLA_KERNEL_FRACTIONAL && p->precision == NLA_FP64 && p->duffy_n == 0) {
-        nla_set_error("fractional kernel needs duffy_n > 0 for vertex-sharing pairs");
-        return NLA_E_INVALID;
+    if (p->kernel == NLA_KERNEL_FRACTIONAL && p->precision == NLA_FP64) {
+        nla_set_error("the fractional kernel is assembled in NLA_FP32 (FP64 geometry and near pairs)");
+        return NLA_E_UNSUPPORTED;
     }
     if (p->kernel == NLA_KERNEL_FRACTIONAL) {
         if (p->duffy_n < 1 || p->duffy_n > NLA_MAX_DUFFY || !p->duffy_x || !p->duffy_w) {
@@ -622,6 +622,64 @@ __global__ void k_entry_codes(int64_t n_up, int J, const int64_t *__restrict__ u
     if (!fill) cnt[u] = n;
 }
 
+// ---- vertex-sharing pairs under the singular kernel
+__global__ void k_near_flag(int64_t P, const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
+                            const int32_t *__restrict__ pkp, uint8_t *__restrict__ flag)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int k = pk[p], kp = pkp[p];
+    bool sh = false;
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) sh |= tri[3 * k + a] == tri[3 * kp + b];
+    flag[p] = sh ? 1 : 0;
+}
+
+__device__ __forceinline__ int upper_slot(int i, int j)
+{
+    // index of (min, max) in the row-major upper triangle of a 6x6 matrix
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return a * 6 - (a * (a - 1)) / 2 + (b - a);
+}
+
+// 36 slots per near pair: ordered slot pairs (I, J) whose nodes satisfy
+// node(I) <= node(J) (the mirror goes to the lower triangle), merged-away
+// slots (a node of E_k' that is also a node of E_k) excluded
+__global__ void k_near_codes(int64_t n_near, int J, const int64_t *__restrict__ near_pair,
+                             const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
+                             const int32_t *__restrict__ pkp, const uint64_t *__restrict__ uk, int64_t nnz,
+                             const int64_t *__restrict__ up_of, uint32_t sentinel, uint32_t *__restrict__ key,
+                             int32_t *__restrict__ code)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_near) return;
+    const int64_t p = near_pair[i];
+    const int k = pk[p], kp = pkp[p];
+    int g[6];
+    bool valid[6];
+    for (int a = 0; a < 3; a++) {
+        g[a] = tri[3 * k + a];
+        g[3 + a] = tri[3 * kp + a];
+        valid[a] = true;
+    }
+    for (int b = 0; b < 3; b++) {
+        valid[3 + b] = true;
+        for (int a = 0; a < 3; a++)
+            if (g[3 + b] == g[a]) valid[3 + b] = false;
+    }
+    for (int I = 0; I < 6; I++)
+        for (int Jj = 0; Jj < 6; Jj++) {
+            const int64_t s = 36 * i + 6 * I + Jj;
+            if (valid[I] && valid[Jj] && g[I] <= g[Jj] && (g[I] < g[Jj] || I == Jj)) {
+                key[s] = upper_of(uk, nnz, up_of, J, g[I], g[Jj]);
+                code[s] = (int32_t)(21 * i + upper_slot(I, Jj));
+            } else {
+                key[s] = sentinel;
+                code[s] = -1;
+            }
+        }
+}
+
 __global__ void k_iota(int64_t n, int32_t *__restrict__ v)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -916,6 +974,46 @@ int nla_build_pattern(nla_plan *P, hipStream_t s)
     k_entry_codes<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, J, P->up_dst, nullptr, ukeys, P->tri, P->n2e_all_ptr,
                                                         P->n2e_all, P->col_off, P->colset, e_base, 1, nullptr,
                                                         P->up_ptr, P->codes);
+    // vertex-sharing pairs of the singular kernel and the codes of their blocks
+    P->n_near = 0;
+    if (P->prob.kernel == NLA_KERNEL_FRACTIONAL && NP > 0) {
+        NLA_TRY(P->arena.get(&P->near_flag, NP));
+        k_near_flag<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->tri, P->pair_k, P->pair_kp, P->near_flag);
+        std::vector<uint8_t> hf(NP);
+        NLA_HIP(hipMemcpyAsync(hf.data(), P->near_flag, NP, hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+        std::vector<int64_t> nl;
+        for (int64_t p = 0; p < NP; p++)
+            if (hf[p]) nl.push_back(p);
+        P->n_near = (int64_t)nl.size();
+        NLA_TRY(P->arena.get(&P->near_pair, nl.size()));
+        NLA_HIP(hipMemcpyAsync(P->near_pair, nl.data(), sizeof(int64_t) * nl.size(), hipMemcpyHostToDevice, s));
+        const int64_t ns = 36 * P->n_near;
+        if (21 * P->n_near >= (int64_t)INT32_MAX) { nla_set_error("too many near pairs"); return NLA_E_UNSUPPORTED; }
+        uint32_t *nk, *snk;
+        int32_t *nv, *snv;
+        NLA_TRY(S.get(&nk, ns));
+        NLA_TRY(S.get(&snk, ns));
+        NLA_TRY(S.get(&nv, ns));
+        NLA_TRY(S.get(&snv, ns));
+        const uint32_t nsent = (uint32_t)P->n_up;
+        k_near_codes<<<grid_for(P->n_near, 256), 256, 0, s>>>(P->n_near, J, P->near_pair, P->tri, P->pair_k, P->pair_kp,
+                                                             ukeys, nnz, up_of, nsent, nk, nv);
+        size_t t5 = 0;
+        const int nb = bits_for((uint64_t)nsent);
+        NLA_HIP(rocprim::radix_sort_pairs(nullptr, t5, nk, snk, nv, snv, (size_t)ns, 0, nb, s));
+        void *tm5;
+        NLA_TRY(S.get((char **)&tm5, t5));
+        NLA_HIP(rocprim::radix_sort_pairs(tm5, t5, nk, snk, nv, snv, (size_t)ns, 0, nb, s));
+        NLA_TRY(P->arena.get(&P->nup_ptr, P->n_up + 1));
+        k_up_ptr<<<grid_for(P->n_up + 1, 256), 256, 0, s>>>(P->n_up, snk, ns, P->nup_ptr);
+        int64_t nn = 0;
+        NLA_HIP(hipMemcpyAsync(&nn, P->nup_ptr + P->n_up, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+        P->n_ncodes = nn;
+        NLA_TRY(P->arena.get(&P->ncodes, nn));
+        NLA_HIP(hipMemcpyAsync(P->ncodes, snv, sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s));
+    }
     // transposed pair order (k' major, k ascending within: stable radix sort of k')
     NLA_TRY(P->arena.get(&P->tptr, K + 1));
     NLA_TRY(P->arena.get(&P->tperm, NP));
@@ -972,8 +1070,12 @@ static void fill_rules(const nla_problem *p, RuleSet *R)
         R->out_w[q] = p->outer.w[q];
     }
     for (int q = 0; q < p->inner.n; q++) {
-        for (int a = 0; a < 3; a++) R->in_lam[q][a] = p->inner.lambda[3 * q + a];
+        for (int a = 0; a < 3; a++) {
+            R->in_lam[q][a] = p->inner.lambda[3 * q + a];
+            R->in_lamf[q][a] = (float)p->inner.lambda[3 * q + a];
+        }
         R->in_w[q] = p->inner.w[q];
+        R->in_wf[q] = (float)p->inner.w[q];
         R->in_wsum += p->inner.w[q];
         for (int i = 0; i < 3; i++) {
             R->in_m1[i] += p->inner.w[q] * p->inner.lambda[3 * q + i];
@@ -1174,6 +1276,18 @@ extern "C" int nla_blocks_view(const nla_plan *P, const void **myy, const void *
     *elem = c + es * (6 * P->n_pairs + 6 * (int64_t)P->K + 3 * P->n_cols);
     *col_off = P->col_off;
     *colset = P->colset;
+    *dtype = P->val_dtype;
+    return NLA_OK;
+}
+
+extern "C" int nla_near_view(const nla_plan *P, int64_t *n_near, const int64_t **near_pair, const void **blocks,
+                             int32_t *dtype)
+{
+    if (!P || !n_near || !near_pair || !blocks || !dtype) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
+    *n_near = P->n_near;
+    *near_pair = P->near_pair;
+    *blocks = P->near_blk;
     *dtype = P->val_dtype;
     return NLA_OK;
 }

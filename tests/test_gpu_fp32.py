@@ -1,0 +1,102 @@
+"""GPU parity of the FP32 path (compensated sums, FP64 geometry) and of the
+singular-kernel near-diagonal blocks, against the FP64 oracle.
+
+Bars: pair list and pattern bitwise; near-diagonal blocks (computed in FP64,
+stored in FP32) within 2e-7 of the oracle's, relative to the block; matrix
+entries row-scaled within 2e-5: the FP32 kernel evaluation 2^(e log2 r^2)
+carries ~|e log2 r^2| * 2^-24 * ln 2 ~ 2e-6 relative error (|e log2 r^2| <= 30
+here) and the FP32 quadrature sums another few 1e-7, while every
+accumulation beyond one subtriangle is compensated; 2e-5 leaves a factor
+~10 over that estimate for cancellation inside a row.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import gpu_assemble, host, row_scaled_error
+from workloads import Problem, constant_kernel_c, fractional_kernel_c, structured_mesh
+
+pytestmark = pytest.mark.gpu
+TOL32 = 2e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    oracle.build(force=False)
+    assert torch.cuda.is_available()
+
+
+def _check(mesh, prob, name):
+    _say("case", name, "K", mesh.n_triangles, prob)
+    plan = gpu_assemble(mesh, prob)
+    ref = oracle.solve_problem(mesh, prob, "quadratic", nthreads=0)
+    rr = ref["res"]
+    ptr, kp = (host(t) for t in plan.pairs())
+    assert np.array_equal(ptr, rr["pair_ptr"]) and np.array_equal(kp, rr["pair_kp"])
+    rowptr, col, val = (host(t) for t in plan.csr(0))
+    assert val.dtype == np.float32
+    assert np.array_equal(rowptr, rr["rowptr"]) and np.array_equal(col, rr["col"])
+    err = row_scaled_error(rowptr, val.astype(np.float64), rr["val"])
+    D = rr["D"].copy()
+    D.data = val.astype(np.float64)
+    assert (D != D.T).nnz == 0
+    _say("row-scaled entry error %.3e" % err)
+    assert err < TOL32
+    return plan, ref, err
+
+
+def test_fp32_constant_kernel_retri():
+    d = 0.1
+    mesh = structured_mesh(d, 0.025, jitter=0.1, seed=12)
+    prob = Problem(delta=d, kernel_c=constant_kernel_c(d), ball="retri", cap_edges=8, precision="fp32")
+    _check(mesh, prob, "fp32 const retri")
+
+
+def test_fp32_fractional_retri_with_near_pairs():
+    d, s = 0.2, 0.4
+    mesh = structured_mesh(d, 0.05, jitter=0.1, seed=13)
+    prob = Problem(delta=d, kernel="fractional", kernel_c=fractional_kernel_c(d, s), kernel_s=s, ball="retri",
+                   cap_edges=8, precision="fp32", duffy_order=12)
+    plan, ref, err = _check(mesh, prob, "fp32 fractional retri")
+    near_p, blocks = (host(t) for t in plan.near())
+    ptr = ref["res"]["pair_ptr"]
+    kp = ref["res"]["pair_kp"]
+    ks = np.repeat(np.arange(mesh.n_triangles), np.diff(ptr))
+    shares = np.array([len(set(mesh.tri[a]) & set(mesh.tri[b])) > 0 for a, b in zip(ks, kp)])
+    assert np.array_equal(near_p, np.nonzero(shares)[0])
+    op = ref["op"]
+    iu = np.triu_indices(6)
+    rng = np.random.default_rng(0)
+    for i in rng.choice(len(near_p), 40, replace=False):
+        p = near_p[i]
+        blk = oracle.pair_block(op, ks[p], kp[p])["blk"]
+        got = blocks[i].astype(np.float64)
+        assert np.max(np.abs(got - blk[iu])) <= 2e-7 * np.max(np.abs(blk))
+
+
+def test_fp32_barycenter_fractional():
+    d, s = 0.2, 0.4
+    mesh = structured_mesh(d, 0.05)
+    prob = Problem(delta=d, kernel="fractional", kernel_c=fractional_kernel_c(d, s), kernel_s=s, ball="barycenter",
+                   outer="dunavant7", inner="dunavant7", precision="fp32", duffy_order=12)
+    _check(mesh, prob, "fp32 fractional barycenter")
+
+
+def test_fp32_deterministic():
+    d, s = 0.2, 0.4
+    mesh = structured_mesh(d, 0.05, jitter=0.1, seed=14)
+    prob = Problem(delta=d, kernel="fractional", kernel_c=fractional_kernel_c(d, s), kernel_s=s, ball="retri",
+                   cap_edges=8, precision="fp32", duffy_order=8)
+    plan = gpu_assemble(mesh, prob)
+    v1 = host(plan.csr(0)[2]).copy()
+    plan.assemble()
+    torch.cuda.synchronize()
+    assert np.array_equal(v1.view(np.uint32), host(plan.csr(0)[2]).view(np.uint32))
