@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--duffy", type=int, default=0, help="override the singular-pair rule order")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="outer elements in the CPU-baseline sample")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,6 +125,9 @@ def main():
 
     torch.cuda.set_device(0)
     mesh, prob, man = make_config(args.config)
+    if args.duffy:
+        from dataclasses import replace
+        prob = replace(prob, duffy_order=args.duffy)
     u, f = manufactured(man)
     t0 = time.perf_counter()
     plan = Plan(mesh, prob)

@@ -507,7 +507,7 @@ __global__ __launch_bounds__(64) void k_near(int64_t n_near, const int64_t *__re
                 if (empty || !(rout > rin)) continue;
                 // J_m = kc (rout^(m+e0) - rin^(m+e0)) / (m + e0)
                 double J[3];
-                const double po = pow(rout, e0), pi = rin > 0.0 ? pow(rin, e0) : 0.0;
+                const double po = exp2(e0 * log2(rout)), pi = rin > 0.0 ? exp2(e0 * log2(rin)) : 0.0;
                 double ro = 1.0, ri = 1.0;
                 for (int m = 0; m < 3; m++) {
                     const double ex = m + e0;

@@ -71,7 +71,7 @@ def _c3():
     d, s = 0.05, 0.4
     p = Problem(delta=d, kernel="fractional", kernel_c=fractional_kernel_c(d, s), kernel_s=s,
                 ball="retri", cap_edges=8, outer="dunavant7", inner="dunavant16",
-                precision="fp32", duffy_order=12)
+                precision="fp32", duffy_order=8)
     return structured_mesh(d, d / 4), p, "quadratic"
 
 
@@ -106,7 +106,7 @@ def batch_instances(n=64, seed=20051):
             kern = dict(kernel="constant", kernel_c=constant_kernel_c(d))
         else:
             kern = dict(kernel="fractional", kernel_c=fractional_kernel_c(d, 0.4), kernel_s=0.4,
-                        duffy_order=12)
+                        duffy_order=8)
         if i % 4 in (0, 1):
             ball = dict(ball="barycenter", outer="dunavant7", inner="dunavant7")
         else:
