@@ -196,6 +196,39 @@ int nla_timings(const nla_plan *plan, double *ms, int32_t *count);
 
 void nla_plan_destroy(nla_plan *plan);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent problems (meshes, horizons, kernels, balls) assembled
+ * together.  All instances must use NLA_FP32, outer rules of at most 8
+ * points and cap counts that are 0 or powers of two (NLA_E_UNSUPPORTED
+ * otherwise).  mode 1 assembles all instances with one persistent launch of
+ * the pair kernel (a fixed grid taking (instance, outer element) work items,
+ * heaviest first, from a device cursor) followed by instance-batched near-pair,
+ * element-block, segmented-sum, extraction and load kernels, captured once in
+ * a hipGraph on a private stream and replayed (ordered after and before the
+ * caller's stream with events); mode 0 assembles the instances one after the
+ * other with their own launches.  Both give bitwise identical values. */
+typedef struct nla_batch nla_batch;
+typedef struct {
+    int32_t n;                   /* instances */
+    int64_t total_pairs, total_elements, total_near;
+    int32_t chunk;               /* work items taken per cursor fetch */
+    int32_t grid;                /* wavefronts of the persistent launch */
+} nla_batch_summary;
+
+/* meshes [n], probs [n] (host); the plans are owned by the batch. */
+int nla_batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *probs, void *stream, nla_batch **out);
+/* f_outer, g_node: host arrays of n device pointers (as in nla_assemble), or both NULL. */
+int nla_batch_assemble(nla_batch *batch, int32_t mode, const double *const *f_outer, const double *const *g_node,
+                       void *stream);
+/* the plan of instance i (owned by the batch; use the nla_*_view calls on it) */
+int nla_batch_plan(const nla_batch *batch, int32_t i, nla_plan **plan);
+int nla_batch_info(const nla_batch *batch, nla_batch_summary *info);
+/* picks (chunk, grid) by timing graph replays of every candidate on this
+ * batch; cache_path (may be NULL) is a text file of earlier choices keyed by
+ * the batch shape, read first and appended to. */
+int nla_batch_autotune(nla_batch *batch, const char *cache_path, void *stream);
+void nla_batch_destroy(nla_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

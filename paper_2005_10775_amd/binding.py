@@ -80,13 +80,21 @@ def lib():
                                       C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
         L.nla_cg.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P]
         L.nla_near_view.argtypes = [P, C.POINTER(I64), C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
+        L.nla_batch_create.argtypes = [I32, P, P, P, C.POINTER(P)]
+        L.nla_batch_assemble.argtypes = [P, I32, P, P, P]
+        L.nla_batch_plan.argtypes = [P, I32, C.POINTER(P)]
+        L.nla_batch_info.argtypes = [P, P]
+        L.nla_batch_autotune.argtypes = [P, C.c_char_p, P]
+        L.nla_batch_destroy.argtypes = [P]
+        L.nla_batch_destroy.restype = None
         L.nla_set_timing.argtypes = [P, I32]
         L.nla_timings.argtypes = [P, P, C.POINTER(I32)]
         L.nla_plan_destroy.argtypes = [P]
         L.nla_plan_destroy.restype = None
         for name in ("nla_plan_create", "nla_plan_info", "nla_pairs_view", "nla_outer_points", "nla_assemble",
                      "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg",
-                     "nla_set_timing", "nla_timings", "nla_near_view"):
+                     "nla_set_timing", "nla_timings", "nla_near_view", "nla_batch_create",
+                     "nla_batch_assemble", "nla_batch_plan", "nla_batch_info", "nla_batch_autotune"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -130,49 +138,66 @@ def _rule(r, keep):
     return nla_rule(r.n, lam.ctypes.data, w.ctypes.data)
 
 
+def marshal(mesh, prob, keep):
+    """(nla_mesh, nla_problem) structs for a workloads mesh and problem; the
+    numpy buffers they point to are appended to `keep`."""
+    from workloads.rules import get_rule, gauss_legendre01
+    xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+    tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
+    tin = np.ascontiguousarray(mesh.tri_in_omega, dtype=np.uint8)
+    nfr = np.ascontiguousarray(mesh.node_free, dtype=np.uint8)
+    keep += [xy, tri, tin, nfr]
+    m = nla_mesh(xy.shape[0], tri.shape[0], xy.ctypes.data, tri.ctypes.data, tin.ctypes.data, nfr.ctypes.data)
+    p = nla_problem()
+    p.delta = prob.delta
+    p.kernel = KERNELS[prob.kernel]
+    p.kernel_c = prob.kernel_c
+    p.kernel_s = prob.kernel_s
+    p.outer = _rule(get_rule(prob.outer), keep)
+    p.inner = _rule(get_rule(prob.inner), keep)
+    if prob.duffy_order > 0:
+        gx, gw = gauss_legendre01(prob.duffy_order)
+        keep += [gx, gw]
+        p.duffy_n, p.duffy_x, p.duffy_w = prob.duffy_order, gx.ctypes.data, gw.ctypes.data
+    p.ball = BALLS[prob.ball]
+    if prob.cap_mode != "poly":
+        raise ValueError("the GPU path fills caps with equal-arc triangles (cap_mode='poly')")
+    p.cap_edges = prob.cap_edges
+    p.precision = PRECISIONS[prob.precision]
+    p.fallback_band = prob.fallback_band
+    p.flags = NLA_SKIP_IXI if prob.skip_ixi else 0
+    return m, p
+
+
+class nla_batch_summary(C.Structure):
+    _fields_ = [("n", C.c_int32), ("total_pairs", C.c_int64), ("total_elements", C.c_int64),
+                ("total_near", C.c_int64), ("chunk", C.c_int32), ("grid", C.c_int32)]
+
+
 class Plan:
     """A plan for one mesh and problem (nla_plan_create ... nla_plan_destroy)."""
 
-    def __init__(self, mesh, prob, stream=None):
-        from workloads.rules import get_rule, gauss_legendre01
-        keep = []
+    def __init__(self, mesh, prob, stream=None, handle=None):
         self.mesh = mesh
         self.problem = prob
-        xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
-        tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
-        tin = np.ascontiguousarray(mesh.tri_in_omega, dtype=np.uint8)
-        nfr = np.ascontiguousarray(mesh.node_free, dtype=np.uint8)
-        keep += [xy, tri, tin, nfr]
-        m = nla_mesh(xy.shape[0], tri.shape[0], xy.ctypes.data, tri.ctypes.data, tin.ctypes.data, nfr.ctypes.data)
-        p = nla_problem()
-        p.delta = prob.delta
-        p.kernel = KERNELS[prob.kernel]
-        p.kernel_c = prob.kernel_c
-        p.kernel_s = prob.kernel_s
+        self.K = mesh.n_triangles
+        self.J = mesh.n_vertices
+        from workloads.rules import get_rule
         self.outer_rule = get_rule(prob.outer)
-        p.outer = _rule(self.outer_rule, keep)
-        p.inner = _rule(get_rule(prob.inner), keep)
-        if prob.duffy_order > 0:
-            gx, gw = gauss_legendre01(prob.duffy_order)
-            keep += [gx, gw]
-            p.duffy_n, p.duffy_x, p.duffy_w = prob.duffy_order, gx.ctypes.data, gw.ctypes.data
-        p.ball = BALLS[prob.ball]
-        if prob.cap_mode != "poly":
-            raise ValueError("the GPU path fills caps with equal-arc triangles (cap_mode='poly')")
-        p.cap_edges = prob.cap_edges
-        p.precision = PRECISIONS[prob.precision]
-        p.fallback_band = prob.fallback_band
-        p.flags = NLA_SKIP_IXI if prob.skip_ixi else 0
+        self._owned = handle is None
+        if handle is not None:
+            self._h = handle
+            return
+        keep = []
+        m, p = marshal(mesh, prob, keep)
         h = C.c_void_p()
         _check(lib().nla_plan_create(C.byref(m), C.byref(p), _stream(stream), C.byref(h)))
         self._h = h
-        self.K = mesh.n_triangles
-        self.J = mesh.n_vertices
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owned", False):
             lib().nla_plan_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -277,3 +302,55 @@ class Plan:
                             C.byref(it), C.byref(rr), _stream(stream))
         _check(code)
         return u, it.value, rr.value
+
+
+class Batch:
+    """Many instances assembled together (nla_batch_*)."""
+
+    def __init__(self, instances, stream=None):
+        keep = []
+        ms = (nla_mesh * len(instances))()
+        ps = (nla_problem * len(instances))()
+        for i, (mesh, prob) in enumerate(instances):
+            ms[i], ps[i] = marshal(mesh, prob, keep)
+        h = C.c_void_p()
+        _check(lib().nla_batch_create(len(instances), ms, ps, _stream(stream), C.byref(h)))
+        self._h = h
+        self.instances = instances
+        self.plans = []
+        for i, (mesh, prob) in enumerate(instances):
+            ph = C.c_void_p()
+            _check(lib().nla_batch_plan(self._h, i, C.byref(ph)))
+            self.plans.append(Plan(mesh, prob, handle=ph))
+
+    def assemble(self, mode=1, f_outer=None, g_node=None, stream=None):
+        n = len(self.instances)
+        if f_outer is not None:
+            fa = (C.c_void_p * n)(*[t.data_ptr() for t in f_outer])
+            ga = (C.c_void_p * n)(*[t.data_ptr() for t in g_node])
+        else:
+            fa = ga = None
+        _check(lib().nla_batch_assemble(self._h, mode, fa, ga, _stream(stream)))
+
+    def info(self):
+        i = nla_batch_summary()
+        _check(lib().nla_batch_info(self._h, C.byref(i)))
+        return dict(n=i.n, total_pairs=i.total_pairs, total_elements=i.total_elements, total_near=i.total_near,
+                    chunk=i.chunk, grid=i.grid)
+
+    def autotune(self, cache_path=None, stream=None):
+        _check(lib().nla_batch_autotune(self._h, cache_path.encode() if cache_path else None, _stream(stream)))
+        return self.info()
+
+    def close(self):
+        for p in self.plans:
+            p._h = None
+        if getattr(self, "_h", None):
+            lib().nla_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

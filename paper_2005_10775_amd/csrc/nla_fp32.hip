@@ -5,6 +5,9 @@
 // integrated in FP64 by a radial (Duffy-type) rule.
 #include "nla_device.hpp"
 #include <cmath>
+#include <cstring>
+#include <string>
+#include <algorithm>
 
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -38,13 +41,15 @@ struct AccF {
 // vertices).  FRAC: psi = kc r^(2*ex) evaluated at every rule point y in FP32
 // (r^2 = |y - x|^2); otherwise psi = kc and the rule is applied through its
 // moments (sym form, as in the FP64 kernel).
-template <bool FRAC>
+template <int FM>
 struct TriF32 {
     const RuleSet *R;
     float kc, ex, m1c, o, dm;
     AccF *A;
+    bool frac_rt;   // FM == 2: kernel chosen at run time (uniform per instance)
     __device__ __forceinline__ void operator()(const double (&t)[3][5]) const
     {
+        const bool FRAC = FM == 2 ? frac_rt : FM == 1;
         const double a2d = fabs((t[1][0] - t[0][0]) * (t[2][1] - t[0][1]) - (t[1][1] - t[0][1]) * (t[2][0] - t[0][0]));
         const float a2 = (float)a2d;
         float tb[3][3];
@@ -104,26 +109,33 @@ struct TriF32 {
 // the row block R_k in LDS per column in pair order (compensated), Myy per
 // pair and Mxx per element are written.  Pairs flagged near (vertex-sharing,
 // singular kernel) are skipped here.
-template <int NQ, bool FRAC, bool POW2>
-__global__ __launch_bounds__(64, 2) void k_pairs_fp32(const int64_t *__restrict__ pair_ptr,
-                                                     const int32_t *__restrict__ pair_kp, ElemSoA E,
-                                                     const double *__restrict__ xq, const RuleSet *__restrict__ R,
-                                                     double dd, float kc, float ex, int ball, int ncap,
-                                                     const uint8_t *__restrict__ near_flag,
-                                                     const int64_t *__restrict__ col_off,
-                                                     const int32_t *__restrict__ colent_ptr,
-                                                     const uint16_t *__restrict__ colent, float *__restrict__ Rout,
-                                                     float *__restrict__ Cyy, float *__restrict__ Cxx, int max_cols,
-                                                     unsigned long long *__restrict__ counters)
+template <int NQ, int FM, bool POW2>
+__device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
 {
-    extern __shared__ double dyn[];
+    const int64_t *__restrict__ pair_ptr = P.pair_ptr;
+    const int32_t *__restrict__ pair_kp = P.pair_kp;
+    const ElemSoA &E = P.E;
+    const double *__restrict__ xq = P.xq;
+    const RuleSet *__restrict__ R = P.R;
+    const double dd = P.dd;
+    const float kc = P.kc, ex = P.ex;
+    const int ball = P.ball, ncap = P.ncap, max_cols = P.max_cols;
+    const bool FRAC = FM == 2 ? P.frac != 0 : FM == 1;
+    const uint8_t *__restrict__ near_flag = P.near_flag;
+    const int64_t *__restrict__ col_off = P.col_off;
+    const int32_t *__restrict__ colent_ptr = P.colent_ptr;
+    const uint16_t *__restrict__ colent = P.colent;
+    float *__restrict__ Rout = P.Rout;
+    float *__restrict__ Cyy = P.Cyy;
+    float *__restrict__ Cxx = P.Cxx;
+    unsigned long long *__restrict__ counters = P.counters;
     __shared__ double sX[NQ][2];
     __shared__ float sW[NQ][4];
     __shared__ double sV[64][7];
     __shared__ unsigned short queue[64 * NQ];
     __shared__ float res[64][10];
     float(*mxy_l)[10] = res;
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int lane = threadIdx.x;
     const int nq = R->n_out;
     const double a2k = E.a2[k];
     if (lane < nq) {
@@ -201,7 +213,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32(const int64_t *__restrict_
                         // psi varies: the inner rule over all of E_k'
                         AccF A;
                         A.zero();
-                        TriF32<true> tri{R, kc, ex, m1c, o, dm, &A};
+                        TriF32<1> tri{R, kc, ex, m1c, o, dm, &A, true};
                         double t[3][5];
                         set5(t[0], V[0] - xx, V[1] - xy, 1.0, 0.0, 0.0);
                         set5(t[1], V[2] - xx, V[3] - xy, 0.0, 1.0, 0.0);
@@ -264,7 +276,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32(const int64_t *__restrict_
                 const int e = queue[i], owner = e >> 8, q = e & 0xff;
                 AccF A;
                 A.zero();
-                TriF32<FRAC> tri{R, kc, ex, m1c, o, dm, &A};
+                TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC};
                 int ns = 0;
                 partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns);
                 c_sub += ns & 0xffff;
@@ -365,6 +377,41 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32(const int64_t *__restrict_
         atomicAdd(&counters[4], v[3]);
         atomicAdd(&counters[5], v[4]);
     }
+    __syncthreads();
+}
+
+template <int NQ, int FM, bool POW2>
+__global__ __launch_bounds__(64, 2) void k_pairs_fp32(PairArgs P)
+{
+    extern __shared__ double dyn[];
+    pairs_fp32_body<NQ, FM, POW2>(P, blockIdx.x, dyn);
+}
+
+// Persistent form for a batch of instances: a fixed grid of wavefronts takes
+// work items (instance, outer element) from a global cursor, `chunk` at a
+// time, in the order of the work table (cost-sorted, heaviest first); every
+// wave leaves when the cursor has passed the end of the table.  Each item
+// writes only its own slots, so the result does not depend on which wave
+// took which item.
+template <int NQ, bool POW2>
+__global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs *__restrict__ inst,
+                                                                 const int2 *__restrict__ work, int n_work, int chunk,
+                                                                 int *__restrict__ cursor)
+{
+    extern __shared__ double dyn[];
+    __shared__ int base_s;
+    while (true) {
+        if (threadIdx.x == 0) base_s = atomicAdd(cursor, chunk);
+        __syncthreads();
+        const int base = base_s;
+        __syncthreads();
+        if (base >= n_work) break;
+        const int end = base + chunk < n_work ? base + chunk : n_work;
+        for (int j = base; j < end; j++) {
+            const int2 w = work[j];
+            pairs_fp32_body<NQ, 2, POW2>(inst[w.x], w.y, dyn);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- near pairs
@@ -378,14 +425,11 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32(const int64_t *__restrict_
 // capped at delta).  Per outer point the ray sums reduce to six angular
 // moments, then to the 21 upper entries of the block.  One wavefront per pair.
 template <class T>
-__global__ __launch_bounds__(64) void k_near(int64_t n_near, const int64_t *__restrict__ near_pair,
-                                             const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp,
-                                             const int32_t *__restrict__ tri, ElemSoA E, const RuleSet *__restrict__ R,
-                                             double delta, double kc, double ks, T *__restrict__ out)
+__device__ void near_body(const int64_t i, const int64_t *__restrict__ near_pair, const int32_t *__restrict__ pk,
+                          const int32_t *__restrict__ pkp, const int32_t *__restrict__ tri, const ElemSoA &E,
+                          const RuleSet *__restrict__ R, double delta, double kc, double ks, T *__restrict__ out)
 {
-    const int64_t i = blockIdx.x;
     const int lane = threadIdx.x;
-    if (i >= n_near) return;
     const int64_t p = near_pair[i];
     const int k = pk[p], kp = pkp[p];
     const double Vk[6] = {E.vx0[k], E.vy0[k], E.vx1[k], E.vy1[k], E.vx2[k], E.vy2[k]};
@@ -549,14 +593,23 @@ __global__ __launch_bounds__(64) void k_near(int64_t n_near, const int64_t *__re
     }
 }
 
+template <class T>
+__global__ __launch_bounds__(64) void k_near(int64_t n_near, const int64_t *__restrict__ near_pair,
+                                             const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp,
+                                             const int32_t *__restrict__ tri, ElemSoA E, const RuleSet *__restrict__ R,
+                                             double delta, double kc, double ks, T *__restrict__ out)
+{
+    if ((int64_t)blockIdx.x >= n_near) return;
+    near_body<T>(blockIdx.x, near_pair, pk, pkp, tri, E, R, delta, kc, ks, out);
+}
+
 // E(k') = Mxx(k') + sum_k Myy(k, k') in FP32 with compensation (lane-strided
 // partial sums, then lane 0 adds the 64 partials in lane order)
-__global__ __launch_bounds__(64) void k_elem_blocks_f32(int K, const int64_t *__restrict__ tptr,
-                                                        const int32_t *__restrict__ tperm, const float *__restrict__ Cyy,
-                                                        const float *__restrict__ Cxx, float *__restrict__ Ce)
+__device__ void elem_blocks_body(const int k, const int64_t *__restrict__ tptr, const int32_t *__restrict__ tperm,
+                                 const float *__restrict__ Cyy, const float *__restrict__ Cxx, float *__restrict__ Ce)
 {
     __shared__ float part[64][6];
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int lane = threadIdx.x;
     KahanF y[6];
 #pragma unroll
     for (int i = 0; i < 6; i++) y[i].zero();
@@ -575,17 +628,24 @@ __global__ __launch_bounds__(64) void k_elem_blocks_f32(int K, const int64_t *__
         for (int l = 0; l < 64; l++) s.add(part[l][lane]);
         Ce[6 * (int64_t)k + lane] = s.s;
     }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_elem_blocks_f32(int K, const int64_t *__restrict__ tptr,
+                                                        const int32_t *__restrict__ tperm, const float *__restrict__ Cyy,
+                                                        const float *__restrict__ Cxx, float *__restrict__ Ce)
+{
+    elem_blocks_body(blockIdx.x, tptr, tperm, Cyy, Cxx, Ce);
 }
 
 // compensated FP32 sum of every upper entry: its [R | E] codes, then its
 // near-pair block codes; both mirrored positions written
-__global__ void k_segsum_f32(int64_t n_up, const int64_t *__restrict__ up_ptr, const int32_t *__restrict__ codes,
-                             const int64_t *__restrict__ nup_ptr, const int32_t *__restrict__ ncodes,
-                             const int64_t *__restrict__ up_dst, const int64_t *__restrict__ mirror,
-                             const float *__restrict__ V, const float *__restrict__ N, float *__restrict__ val)
+__device__ __forceinline__ void segsum_body(const int64_t u, const int64_t *__restrict__ up_ptr,
+                                            const int32_t *__restrict__ codes, const int64_t *__restrict__ nup_ptr,
+                                            const int32_t *__restrict__ ncodes, const int64_t *__restrict__ up_dst,
+                                            const int64_t *__restrict__ mirror, const float *__restrict__ V,
+                                            const float *__restrict__ N, float *__restrict__ val)
 {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_up) return;
     KahanF s;
     s.zero();
     for (int64_t t = up_ptr[u]; t < up_ptr[u + 1]; t++) s.add(V[codes[t]]);
@@ -596,11 +656,52 @@ __global__ void k_segsum_f32(int64_t n_up, const int64_t *__restrict__ up_ptr, c
     val[mirror[d]] = s.s;
 }
 
+__global__ void k_segsum_f32(int64_t n_up, const int64_t *__restrict__ up_ptr, const int32_t *__restrict__ codes,
+                             const int64_t *__restrict__ nup_ptr, const int32_t *__restrict__ ncodes,
+                             const int64_t *__restrict__ up_dst, const int64_t *__restrict__ mirror,
+                             const float *__restrict__ V, const float *__restrict__ N, float *__restrict__ val)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_up) return;
+    segsum_body(u, up_ptr, codes, nup_ptr, ncodes, up_dst, mirror, V, N, val);
+}
+
 template <class T>
 __global__ void k_extract_t(int64_t n, const int64_t *__restrict__ src, const T *__restrict__ val, T *__restrict__ out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = val[src[i]];
+}
+
+PairArgs nla_pair_args(const nla_plan *P)
+{
+    const nla_problem &pr = P->prob;
+    const int64_t NP = P->n_pairs;
+    float *Cyy = (float *)P->contrib;
+    float *Cxx = Cyy + 6 * NP;
+    float *V = Cxx + 6 * (int64_t)P->K;
+    PairArgs A;
+    A.pair_ptr = P->pair_ptr;
+    A.pair_kp = P->pair_kp;
+    A.E = P->E;
+    A.xq = P->xq;
+    A.R = P->d_rules;
+    A.dd = pr.delta * pr.delta;
+    A.frac = pr.kernel == NLA_KERNEL_FRACTIONAL ? 1 : 0;
+    A.kc = (float)pr.kernel_c;
+    A.ex = A.frac ? (float)(-(1.0 + pr.kernel_s)) : 0.f;
+    A.ball = pr.ball;
+    A.ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
+    A.near_flag = P->near_flag;
+    A.col_off = P->col_off;
+    A.colent_ptr = P->colent_ptr;
+    A.colent = P->colent;
+    A.Rout = V;
+    A.Cyy = Cyy;
+    A.Cxx = Cxx;
+    A.max_cols = P->max_cols;
+    A.counters = P->counters;
+    return A;
 }
 
 int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, hipStream_t))
@@ -619,10 +720,8 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     const bool pow2 = (ncap & (ncap - 1)) == 0;
     const size_t lds = (size_t)P->max_cols * (6 * sizeof(float) + sizeof(int));
     mark(P, NLA_PHASE_PAIRS, s);
-#define NLA_LAUNCH32(NQ, FR, P2)                                                                                     \
-    k_pairs_fp32<NQ, FR, P2><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, \
-                                                kc, ex, pr.ball, ncap, P->near_flag, P->col_off, P->colent_ptr,         \
-                                                P->colent, V, Cyy, Cxx, P->max_cols, P->counters)
+    PairArgs A = nla_pair_args(P);
+#define NLA_LAUNCH32(NQ, FR, P2) k_pairs_fp32<NQ, FR, P2><<<K, 64, lds, s>>>(A)
     if (P->rules.n_out > 8) {
         nla_set_error("the FP32 path supports outer rules of at most 8 points");
         return NLA_E_UNSUPPORTED;
@@ -631,10 +730,10 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
         nla_set_error("the FP32 constant-kernel path needs a symmetric inner rule");
         return NLA_E_UNSUPPORTED;
     }
-    if (frac && pow2) NLA_LAUNCH32(8, true, true);
-    else if (frac) NLA_LAUNCH32(8, true, false);
-    else if (pow2) NLA_LAUNCH32(8, false, true);
-    else NLA_LAUNCH32(8, false, false);
+    if (frac && pow2) NLA_LAUNCH32(8, 1, true);
+    else if (frac) NLA_LAUNCH32(8, 1, false);
+    else if (pow2) NLA_LAUNCH32(8, 0, true);
+    else NLA_LAUNCH32(8, 0, false);
 #undef NLA_LAUNCH32
     NLA_HIP(hipGetLastError());
     P->ran[NLA_PHASE_PAIRS] = true;
@@ -661,3 +760,468 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     NLA_HIP(hipGetLastError());
     return NLA_OK;
 }
+
+// =====================================================================
+// Batches: many plans (meshes, horizons, kernels, balls) assembled together.
+// =====================================================================
+struct BatchInst {
+    // near pairs
+    int64_t n_near;
+    const int64_t *near_pair;
+    const int32_t *pair_k, *pair_kp, *tri;
+    ElemSoA E;
+    const RuleSet *R;
+    double delta, kc, ks;
+    float *near_blk;
+    // element blocks
+    int K;
+    const int64_t *tptr;
+    const int32_t *tperm;
+    const float *Cyy, *Cxx;
+    float *Ce;
+    // segmented sum
+    int64_t n_up;
+    const int64_t *up_ptr, *nup_ptr, *up_dst, *mirror;
+    const int32_t *codes, *ncodes;
+    const float *V;
+    float *val;
+    // A and the load vector
+    int64_t nnz_free;
+    const int64_t *a_src;
+    float *a_val;
+    const uint8_t *tin;
+    const double *f, *g;
+    double *Gk, *b;
+    int n_free;
+    const int32_t *free_nodes, *n2e_ptr, *n2e, *col, *n2f;
+    const int64_t *rowptr;
+    unsigned long long *counters;
+};
+
+// instance of global index i given the exclusive prefix offsets off[0..n]
+__device__ __forceinline__ int inst_of(const int64_t *off, int n, int64_t i)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_batch_zero(int n, const BatchInst *__restrict__ B, int *__restrict__ cursor)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *cursor = 0;
+    if (i < 6 * n) B[i / 6].counters[i % 6] = 0ull;
+}
+
+__global__ __launch_bounds__(64) void k_batch_near(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off)
+{
+    const int64_t g = blockIdx.x;
+    const int t = inst_of(off, n, g);
+    const BatchInst &I = B[t];
+    near_body<float>(g - off[t], I.near_pair, I.pair_k, I.pair_kp, I.tri, I.E, I.R, I.delta, I.kc, I.ks, I.near_blk);
+}
+
+__global__ __launch_bounds__(64) void k_batch_elem(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off)
+{
+    const int64_t g = blockIdx.x;
+    const int t = inst_of(off, n, g);
+    const BatchInst &I = B[t];
+    elem_blocks_body((int)(g - off[t]), I.tptr, I.tperm, I.Cyy, I.Cxx, I.Ce);
+}
+
+__global__ void k_batch_segsum(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off, int64_t total)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int t = inst_of(off, n, g);
+    const BatchInst &I = B[t];
+    segsum_body(g - off[t], I.up_ptr, I.codes, I.n_near > 0 ? I.nup_ptr : nullptr, I.ncodes, I.up_dst, I.mirror, I.V,
+                I.near_blk, I.val);
+}
+
+__global__ void k_batch_extract(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off, int64_t total)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int t = inst_of(off, n, g);
+    const BatchInst &I = B[t];
+    const int64_t i = g - off[t];
+    I.a_val[i] = I.val[I.a_src[i]];
+}
+
+__global__ void k_batch_load_elem(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off, int64_t total)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int t = inst_of(off, n, g);
+    const BatchInst &I = B[t];
+    if (!I.f) return;
+    const int k = (int)(g - off[t]);
+    double gk[3] = {0.0, 0.0, 0.0};
+    if (I.tin[k]) {
+        const int nq = I.R->n_out;
+        for (int q = 0; q < nq; q++) {
+            const double Wf = I.R->out_w[q] * I.E.a2[k] * I.f[(int64_t)k * nq + q];
+            for (int a = 0; a < 3; a++) gk[a] += Wf * I.R->out_lam[q][a];
+        }
+    }
+    for (int a = 0; a < 3; a++) I.Gk[3 * (int64_t)k + a] = gk[a];
+}
+
+__global__ __launch_bounds__(256) void k_batch_load_rhs(int n, const BatchInst *__restrict__ B,
+                                                        const int64_t *__restrict__ off, int64_t total)
+{
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= total) return;
+    const int t = inst_of(off, n, g);
+    const BatchInst &I = B[t];
+    if (!I.f) return;
+    const int i = (int)(g - off[t]);
+    const int j = I.free_nodes[i];
+    double s = 0.0;
+    for (int e = I.n2e_ptr[j] + lane; e < I.n2e_ptr[j + 1]; e += 64) s += I.Gk[I.n2e[e]];
+    for (int64_t q = I.rowptr[j] + lane; q < I.rowptr[j + 1]; q += 64) {
+        const int c = I.col[q];
+        if (I.n2f[c] < 0) s -= (double)I.val[q] * I.g[c];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) I.b[i] = s;
+}
+
+struct nla_batch {
+    std::vector<nla_plan *> plans;
+    int n = 0;
+    int device = 0, n_cu = 0;
+    DeviceArena arena;
+    PairArgs *d_args = nullptr;
+    BatchInst *d_inst = nullptr;
+    std::vector<BatchInst> h_inst;
+    int2 *d_work = nullptr;
+    int n_work = 0;
+    int *d_cursor = nullptr;
+    int64_t *d_off_near = nullptr, *d_off_k = nullptr, *d_off_up = nullptr, *d_off_a = nullptr, *d_off_free = nullptr;
+    int64_t tot_near = 0, tot_k = 0, tot_up = 0, tot_a = 0, tot_free = 0, tot_pairs = 0;
+    int max_cols = 0;
+    int chunk = 1, grid = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    bool graph_ok = false;
+    ~nla_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (stream) (void)hipStreamDestroy(stream);
+        for (nla_plan *p : plans) nla_plan_destroy(p);
+    }
+};
+
+static int batch_launch(nla_batch *B, hipStream_t s)
+{
+    const int n = B->n;
+    k_batch_zero<<<grid_for(6 * n + 1, 256), 256, 0, s>>>(n, B->d_inst, B->d_cursor);
+    const size_t lds = (size_t)B->max_cols * (6 * sizeof(float) + sizeof(int));
+    k_pairs_fp32_persistent<8, true><<<B->grid, 64, lds, s>>>(B->d_args, B->d_work, B->n_work, B->chunk, B->d_cursor);
+    if (B->tot_near > 0) k_batch_near<<<(unsigned)B->tot_near, 64, 0, s>>>(n, B->d_inst, B->d_off_near);
+    k_batch_elem<<<(unsigned)B->tot_k, 64, 0, s>>>(n, B->d_inst, B->d_off_k);
+    k_batch_segsum<<<grid_for(B->tot_up, 256), 256, 0, s>>>(n, B->d_inst, B->d_off_up, B->tot_up);
+    if (B->tot_a > 0) k_batch_extract<<<grid_for(B->tot_a, 256), 256, 0, s>>>(n, B->d_inst, B->d_off_a, B->tot_a);
+    k_batch_load_elem<<<grid_for(B->tot_k, 256), 256, 0, s>>>(n, B->d_inst, B->d_off_k, B->tot_k);
+    if (B->tot_free > 0)
+        k_batch_load_rhs<<<grid_for(B->tot_free, 4), 256, 0, s>>>(n, B->d_inst, B->d_off_free, B->tot_free);
+    NLA_HIP(hipGetLastError());
+    return NLA_OK;
+}
+
+static int batch_capture(nla_batch *B)
+{
+    if (B->exec) {
+        NLA_HIP(hipGraphExecDestroy(B->exec));
+        B->exec = nullptr;
+    }
+    if (B->graph) {
+        NLA_HIP(hipGraphDestroy(B->graph));
+        B->graph = nullptr;
+    }
+    NLA_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+    int st = batch_launch(B, B->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(B->stream, &g);
+    if (st != NLA_OK) return st;
+    if (e != hipSuccess) {
+        nla_set_error("graph capture failed: %s", hipGetErrorString(e));
+        return NLA_E_DEVICE;
+    }
+    B->graph = g;
+    NLA_HIP(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+    B->graph_ok = true;
+    return NLA_OK;
+}
+
+static int batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *probs, hipStream_t s, nla_batch *B)
+{
+    B->n = n;
+    NLA_HIP(hipGetDevice(&B->device));
+    NLA_HIP(hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, B->device));
+    for (int i = 0; i < n; i++) {
+        const nla_problem &p = probs[i];
+        if (p.precision != NLA_FP32 || p.outer.n > 8 || (p.ball == NLA_BALL_RETRI && (p.cap_edges & (p.cap_edges - 1)))) {
+            nla_set_error("batch instance %d: batches assemble in NLA_FP32 with <= 8 outer points and "
+                          "power-of-two cap counts", i);
+            return NLA_E_UNSUPPORTED;
+        }
+        nla_plan *P = nullptr;
+        int st = nla_plan_create(&meshes[i], &p, s, &P);
+        if (st != NLA_OK) {
+            std::string msg = nla_last_error();
+            nla_set_error("batch instance %d: %s", i, msg.c_str());
+            return st;
+        }
+        B->plans.push_back(P);
+        if (!P->rules.in_sym && p.kernel == NLA_KERNEL_CONSTANT) {
+            nla_set_error("batch instance %d: constant kernel needs a symmetric inner rule", i);
+            return NLA_E_UNSUPPORTED;
+        }
+        // per-plan value storage (FP32)
+        P->n_contrib = 6 * P->n_pairs + 12 * (int64_t)P->K + 3 * P->n_cols;
+        NLA_TRY(P->arena.alloc(&P->contrib, sizeof(float) * P->n_contrib));
+        NLA_TRY(P->arena.alloc(&P->val, sizeof(float) * P->nnz));
+        NLA_TRY(P->arena.alloc(&P->a_val, sizeof(float) * (P->nnz_free > 0 ? P->nnz_free : 1)));
+        NLA_TRY(P->arena.alloc(&P->near_blk, sizeof(float) * (P->n_near > 0 ? 21 * P->n_near : 1)));
+        NLA_TRY(P->arena.get(&P->Gk, 3 * (size_t)P->K));
+        NLA_TRY(P->arena.get(&P->b, P->n_free > 0 ? P->n_free : 1));
+        B->max_cols = std::max(B->max_cols, P->max_cols);
+        B->tot_pairs += P->n_pairs;
+    }
+    // argument tables
+    std::vector<PairArgs> args(n);
+    B->h_inst.resize(n);
+    std::vector<int64_t> on(n + 1, 0), ok(n + 1, 0), ou(n + 1, 0), oa(n + 1, 0), of(n + 1, 0);
+    std::vector<std::pair<double, int2>> work;
+    for (int i = 0; i < n; i++) {
+        nla_plan *P = B->plans[i];
+        args[i] = nla_pair_args(P);
+        BatchInst &I = B->h_inst[i];
+        memset(&I, 0, sizeof(I));
+        I.n_near = P->n_near; I.near_pair = P->near_pair; I.pair_k = P->pair_k; I.pair_kp = P->pair_kp; I.tri = P->tri;
+        I.E = P->E; I.R = P->d_rules; I.delta = P->prob.delta; I.kc = P->prob.kernel_c; I.ks = P->prob.kernel_s;
+        I.near_blk = (float *)P->near_blk;
+        I.K = P->K; I.tptr = P->tptr; I.tperm = P->tperm;
+        I.Cyy = args[i].Cyy; I.Cxx = args[i].Cxx; I.Ce = args[i].Rout + 3 * P->n_cols;
+        I.n_up = P->n_up; I.up_ptr = P->up_ptr; I.nup_ptr = P->nup_ptr; I.up_dst = P->up_dst; I.mirror = P->mirror;
+        I.codes = P->codes; I.ncodes = P->ncodes; I.V = args[i].Rout; I.val = (float *)P->val;
+        I.nnz_free = P->nnz_free; I.a_src = P->a_src; I.a_val = (float *)P->a_val;
+        I.tin = P->tin; I.Gk = P->Gk; I.b = P->b; I.n_free = P->n_free; I.free_nodes = P->free_nodes;
+        I.n2e_ptr = P->n2e_ptr; I.n2e = P->n2e; I.col = P->col; I.n2f = P->node_to_free; I.rowptr = P->rowptr;
+        I.counters = P->counters;
+        on[i + 1] = on[i] + P->n_near;
+        ok[i + 1] = ok[i] + P->K;
+        ou[i + 1] = ou[i] + P->n_up;
+        oa[i + 1] = oa[i] + P->nnz_free;
+        of[i + 1] = of[i] + P->n_free;
+        // cost of an outer element: its pairs, more with the retriangulated ball and the point-evaluated kernel
+        std::vector<int64_t> hp(P->K + 1);
+        NLA_HIP(hipMemcpy(hp.data(), P->pair_ptr, sizeof(int64_t) * (P->K + 1), hipMemcpyDeviceToHost));
+        const double wgt = (P->prob.ball == NLA_BALL_RETRI ? 3.0 : 1.0) * (P->prob.kernel == NLA_KERNEL_FRACTIONAL ? 4.0 : 1.0);
+        for (int k = 0; k < P->K; k++) work.push_back({wgt * (double)(hp[k + 1] - hp[k]), make_int2(i, k)});
+    }
+    std::stable_sort(work.begin(), work.end(), [](const std::pair<double, int2> &a, const std::pair<double, int2> &b) {
+        return a.first > b.first;
+    });
+    std::vector<int2> hw(work.size());
+    for (size_t j = 0; j < work.size(); j++) hw[j] = work[j].second;
+    B->n_work = (int)hw.size();
+    B->tot_near = on[n]; B->tot_k = ok[n]; B->tot_up = ou[n]; B->tot_a = oa[n]; B->tot_free = of[n];
+    NLA_TRY(B->arena.get(&B->d_args, n));
+    NLA_TRY(B->arena.get(&B->d_inst, n));
+    NLA_TRY(B->arena.get(&B->d_work, hw.size()));
+    NLA_TRY(B->arena.get(&B->d_cursor, 1));
+    NLA_TRY(B->arena.get(&B->d_off_near, n + 1));
+    NLA_TRY(B->arena.get(&B->d_off_k, n + 1));
+    NLA_TRY(B->arena.get(&B->d_off_up, n + 1));
+    NLA_TRY(B->arena.get(&B->d_off_a, n + 1));
+    NLA_TRY(B->arena.get(&B->d_off_free, n + 1));
+    NLA_HIP(hipMemcpy(B->d_args, args.data(), sizeof(PairArgs) * n, hipMemcpyHostToDevice));
+    NLA_HIP(hipMemcpy(B->d_inst, B->h_inst.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice));
+    NLA_HIP(hipMemcpy(B->d_work, hw.data(), sizeof(int2) * hw.size(), hipMemcpyHostToDevice));
+    NLA_HIP(hipMemcpy(B->d_off_near, on.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    NLA_HIP(hipMemcpy(B->d_off_k, ok.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    NLA_HIP(hipMemcpy(B->d_off_up, ou.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    NLA_HIP(hipMemcpy(B->d_off_a, oa.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    NLA_HIP(hipMemcpy(B->d_off_free, of.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice));
+    if (B->max_cols > 1536) { nla_set_error("batch column sets too large"); return NLA_E_UNSUPPORTED; }
+    B->chunk = 1;
+    B->grid = 8 * B->n_cu;
+    NLA_HIP(hipStreamCreate(&B->stream));
+    NLA_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+    NLA_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    return NLA_OK;
+}
+
+extern "C" int nla_batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *probs, void *stream,
+                                nla_batch **out)
+{
+    if (!out || n < 1 || !meshes || !probs) { nla_set_error("invalid batch arguments"); return NLA_E_INVALID; }
+    *out = nullptr;
+    nla_batch *B = new (std::nothrow) nla_batch();
+    if (!B) { nla_set_error("host allocation failed"); return NLA_E_NOMEM; }
+    int st;
+    try {
+        st = batch_create(n, meshes, probs, (hipStream_t)stream, B);
+    } catch (...) {
+        nla_set_error("unexpected exception in batch creation");
+        st = NLA_E_DEVICE;
+    }
+    if (st != NLA_OK) {
+        delete B;
+        return st;
+    }
+    *out = B;
+    return NLA_OK;
+}
+
+// point the per-instance load inputs at the caller's arrays (outside any graph)
+static int batch_set_inputs(nla_batch *B, const double *const *f, const double *const *g)
+{
+    bool changed = false;
+    for (int i = 0; i < B->n; i++) {
+        const double *fi = f ? f[i] : nullptr, *gi = g ? g[i] : nullptr;
+        if (B->h_inst[i].f != fi || B->h_inst[i].g != gi) changed = true;
+        B->h_inst[i].f = fi;
+        B->h_inst[i].g = gi;
+    }
+    if (changed) NLA_HIP(hipMemcpy(B->d_inst, B->h_inst.data(), sizeof(BatchInst) * B->n, hipMemcpyHostToDevice));
+    return NLA_OK;
+}
+
+extern "C" int nla_batch_assemble(nla_batch *B, int32_t mode, const double *const *f_outer,
+                                  const double *const *g_node, void *stream)
+{
+    if (!B) { nla_set_error("null batch"); return NLA_E_INVALID; }
+    if ((f_outer == nullptr) != (g_node == nullptr)) { nla_set_error("pass both f_outer and g_node, or neither"); return NLA_E_INVALID; }
+    hipStream_t s = (hipStream_t)stream;
+    if (mode == 0) {
+        // one plan after the other, each with its own launches
+        for (int i = 0; i < B->n; i++)
+            NLA_TRY(nla_numeric(B->plans[i], f_outer ? f_outer[i] : nullptr, g_node ? g_node[i] : nullptr, s));
+        return NLA_OK;
+    }
+    if (mode != 1) { nla_set_error("mode must be 0 (sequential) or 1 (persistent + graph)"); return NLA_E_INVALID; }
+    NLA_TRY(batch_set_inputs(B, f_outer, g_node));
+    if (!B->graph_ok) NLA_TRY(batch_capture(B));
+    NLA_HIP(hipEventRecord(B->ev_in, s));
+    NLA_HIP(hipStreamWaitEvent(B->stream, B->ev_in, 0));
+    NLA_HIP(hipGraphLaunch(B->exec, B->stream));
+    NLA_HIP(hipEventRecord(B->ev_out, B->stream));
+    NLA_HIP(hipStreamWaitEvent(s, B->ev_out, 0));
+    for (nla_plan *P : B->plans) {
+        P->assembled = true;
+        P->val_dtype = NLA_DTYPE_F32;
+        P->have_load = f_outer != nullptr;
+    }
+    return NLA_OK;
+}
+
+extern "C" int nla_batch_plan(const nla_batch *B, int32_t i, nla_plan **plan)
+{
+    if (!B || !plan || i < 0 || i >= B->n) { nla_set_error("invalid batch index"); return NLA_E_INVALID; }
+    *plan = B->plans[i];
+    return NLA_OK;
+}
+
+extern "C" int nla_batch_info(const nla_batch *B, nla_batch_summary *info)
+{
+    if (!B || !info) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    info->n = B->n;
+    info->total_pairs = B->tot_pairs;
+    info->total_elements = B->tot_k;
+    info->total_near = B->tot_near;
+    info->chunk = B->chunk;
+    info->grid = B->grid;
+    return NLA_OK;
+}
+
+// Times every (chunk, grid) candidate on the batch itself (graph replays,
+// median of 5 after 2 warm-ups) and keeps the fastest; with cache_path the
+// choice is read from / appended to a text file keyed by the batch shape.
+extern "C" int nla_batch_autotune(nla_batch *B, const char *cache_path, void *stream)
+{
+    if (!B) { nla_set_error("null batch"); return NLA_E_INVALID; }
+    (void)stream;
+    char key[128];
+    snprintf(key, sizeof(key), "n%d_pairs%lld_K%lld_near%lld_cu%d", B->n, (long long)B->tot_pairs, (long long)B->tot_k,
+             (long long)B->tot_near, B->n_cu);
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char k2[128];
+            int c, g;
+            while (fscanf(f, "%127s %d %d", k2, &c, &g) == 3)
+                if (strcmp(k2, key) == 0 && c > 0 && g > 0) {
+                    B->chunk = c;
+                    B->grid = g;
+                    B->graph_ok = false;
+                    fclose(f);
+                    return NLA_OK;
+                }
+            fclose(f);
+        }
+    }
+    const int chunks[4] = {1, 2, 4, 8};
+    const int mults[3] = {2, 4, 8};
+    hipEvent_t e0, e1;
+    NLA_HIP(hipEventCreate(&e0));
+    NLA_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bc = B->chunk, bg = B->grid;
+    for (int ci = 0; ci < 4; ci++)
+        for (int mi = 0; mi < 3; mi++) {
+            B->chunk = chunks[ci];
+            B->grid = mults[mi] * B->n_cu;
+            B->graph_ok = false;
+            int st = batch_capture(B);
+            if (st != NLA_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return st;
+            }
+            float ts[5];
+            for (int r = 0; r < 7; r++) {
+                NLA_HIP(hipEventRecord(e0, B->stream));
+                NLA_HIP(hipGraphLaunch(B->exec, B->stream));
+                NLA_HIP(hipEventRecord(e1, B->stream));
+                NLA_HIP(hipEventSynchronize(e1));
+                float t = 0.f;
+                NLA_HIP(hipEventElapsedTime(&t, e0, e1));
+                if (r >= 2) ts[r - 2] = t;
+            }
+            std::sort(ts, ts + 5);
+            if (ts[2] < best) {
+                best = ts[2];
+                bc = B->chunk;
+                bg = B->grid;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    B->chunk = bc;
+    B->grid = bg;
+    B->graph_ok = false;
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d\n", key, bc, bg);
+            fclose(f);
+        }
+    }
+    return NLA_OK;
+}
+
+extern "C" void nla_batch_destroy(nla_batch *B) { delete B; }

@@ -151,6 +151,25 @@ struct nla_plan {
     int val_dtype = NLA_DTYPE_F64;
 };
 
+// arguments of the FP32 pair kernel for one instance (plan)
+struct PairArgs {
+    const int64_t *pair_ptr;
+    const int32_t *pair_kp;
+    ElemSoA E;
+    const double *xq;
+    const RuleSet *R;
+    double dd;
+    float kc, ex;
+    int ball, ncap, frac, max_cols;
+    const uint8_t *near_flag;
+    const int64_t *col_off;
+    const int32_t *colent_ptr;
+    const uint16_t *colent;
+    float *Rout, *Cyy, *Cxx;
+    unsigned long long *counters;
+};
+PairArgs nla_pair_args(const nla_plan *P);
+
 // translation-unit entry points
 int nla_build_pairs(nla_plan *P, hipStream_t s);
 int nla_build_pattern(nla_plan *P, hipStream_t s);
