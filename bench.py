@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--duffy", type=int, default=0, help="override the singular-pair rule order")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="outer elements in the CPU-baseline sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy a MIB-MiB device buffer 3 times (reference kernel for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -236,6 +238,14 @@ def main():
            "roofline": roofline, "source_digest": digest}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, prob, args.cpu_sample)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = n
     print(json.dumps(out))
 
 
