@@ -17,7 +17,7 @@ _LIB = None
 
 def build(force=True):
     """Compile liboracle.so (gcc, FP64, no contraction, OpenMP for timing only)."""
-    srcs = [os.path.join(_DIR, f) for f in ("nlo.c", "nlo_duffy.c")]
+    srcs = [os.path.join(_DIR, f) for f in ("nlo.c", "nlo_duffy.c", "nlo_mlp.c")]
     if not force and os.path.exists(_SO) and all(os.path.getmtime(_SO) >= os.path.getmtime(s) for s in srcs):
         return _SO
     cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
@@ -39,7 +39,8 @@ class _Problem(C.Structure):
                 ("n_out2", C.c_int32), ("out2_lam", C.c_void_p), ("out2_w", C.c_void_p),
                 ("switch_dist", C.c_double),
                 ("duffy_n", C.c_int32), ("gl_x", C.c_void_p), ("gl_w", C.c_void_p),
-                ("skip_ixi", C.c_int32)]
+                ("skip_ixi", C.c_int32),
+                ("learned", C.c_int32), ("band", C.c_double), ("mlp_w", C.c_void_p), ("mlp_scale", C.c_double)]
 
 
 def _lib():
@@ -70,6 +71,16 @@ def _lib():
         L.nlo_blocks_range.restype = I64
         L.nlo_flops_census.argtypes = [P, P, I32, I32, P]
         L.nlo_flops_census.restype = I64
+        L.nlo_gelu.argtypes = [D]
+        L.nlo_gelu.restype = D
+        L.nlo_mlp_forward.argtypes = [P, P, I64, P]
+        L.nlo_mlp_backward.argtypes = [P, P, P, I64, P]
+        L.nlo_cap_moments.argtypes = [P, P, P, P]
+        L.nlo_cap_moments.restype = C.c_int
+        L.nlo_routed.argtypes = [D, D, P, P]
+        L.nlo_routed.restype = C.c_int
+        L.nlo_cap_candidate.argtypes = [P, D, D, D, I32, P, P]
+        L.nlo_cap_candidate.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -82,7 +93,7 @@ class OracleProblem:
     """Marshals a workloads.Problem (and a mesh) into the C structs; keeps the
     numpy buffers alive for the lifetime of this object."""
 
-    def __init__(self, mesh, prob):
+    def __init__(self, mesh, prob, mlp_w=None, mlp_scale=1.0):
         self.mesh = mesh
         self.prob = prob
         self._keep = []
@@ -130,6 +141,12 @@ class OracleProblem:
         else:
             p.duffy_n = 0
         p.skip_ixi = int(prob.skip_ixi)
+        if prob.precision == "learned":
+            if mlp_w is None:
+                raise ValueError("learned caps need the network weights (effective_weights(...))")
+            w = np.ascontiguousarray(mlp_w, dtype=np.float64)
+            self._keep.append(w)
+            p.learned, p.band, p.mlp_w, p.mlp_scale = 1, prob.fallback_band, _ptr(w), mlp_scale
         self.cprob = p
 
     @property
@@ -305,3 +322,81 @@ def solve_problem(mesh, prob, man, nthreads=0, dense=None):
     U = g.copy()
     U[fi] = Uf
     return dict(U=U, l2=l2_error(mesh, U, u), res=res, A=A, b=b, G=G, iters=its, op=op)
+
+
+# ------------------------------------------------------------ learned caps
+
+def bf16_round(a):
+    """float32 -> nearest bfloat16 (ties to even), returned as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def effective_weights(w32):
+    """The weights the network computes with: W2 and W3 rounded to bfloat16,
+    W1 and the biases in float32 (flat layout of workloads.learned)."""
+    from workloads.learned import OFFSETS
+    w = np.asarray(w32, dtype=np.float32).astype(np.float64)
+    for name in ("W2", "W3"):
+        off, shape = OFFSETS[name]
+        n = int(np.prod(shape))
+        w[off:off + n] = bf16_round(np.asarray(w32, dtype=np.float32)[off:off + n])
+    return w
+
+
+def gelu(z):
+    return _lib().nlo_gelu(float(z))
+
+
+def mlp_forward(w, feat):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.float64).reshape(-1, 6)
+    out = np.zeros((f.shape[0], 3))
+    _lib().nlo_mlp_forward(_ptr(w), _ptr(f), f.shape[0], _ptr(out))
+    return out
+
+
+def mlp_backward(w, feat, dout):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.float64).reshape(-1, 6)
+    d = np.ascontiguousarray(dout, dtype=np.float64).reshape(-1, 3)
+    dw = np.zeros(w.shape[0])
+    _lib().nlo_mlp_backward(_ptr(w), _ptr(f), _ptr(d), f.shape[0], _ptr(dw))
+    return dw
+
+
+def cap_moments(delta, x, tri_xy, cap_edges=8):
+    """(number of cap triangles, int over the caps of the three basis functions)."""
+    p = _Problem()
+    p.delta, p.kc, p.ball, p.cap_edges = delta, 1.0, 1, cap_edges
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    V = np.ascontiguousarray(tri_xy, dtype=np.float64).reshape(6)
+    m = np.zeros(3)
+    n = _lib().nlo_cap_moments(C.byref(p), _ptr(xx), _ptr(V), _ptr(m))
+    return n, m
+
+
+def routed(delta, band, x, tri_xy):
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    V = np.ascontiguousarray(tri_xy, dtype=np.float64).reshape(6)
+    return bool(_lib().nlo_routed(delta, band, _ptr(xx), _ptr(V)))
+
+
+def cap_candidates(U, L, jitter, band, cap_edges=8):
+    """Training candidates from uniforms U[n][10]: (valid[n], feat[n][6], label[n][3])."""
+    U = np.ascontiguousarray(U, dtype=np.float64).reshape(-1, 10)
+    n = U.shape[0]
+    valid = np.zeros(n, dtype=bool)
+    feat = np.zeros((n, 6))
+    lab = np.zeros((n, 3))
+    f6 = np.zeros(6)
+    l3 = np.zeros(3)
+    lib = _lib()
+    for i in range(n):
+        u = np.ascontiguousarray(U[i])
+        valid[i] = lib.nlo_cap_candidate(_ptr(u), L, jitter, band, cap_edges, _ptr(f6), _ptr(l3)) == 1
+        feat[i] = f6
+        lab[i] = l3
+    return valid, feat, lab

@@ -40,8 +40,6 @@
 #include <omp.h>
 #endif
 
-#define NLO_MAXCAP 256
-#define NLO_MAXSUB (4 + 3 * NLO_MAXCAP + 8)
 
 static const double NLO_PI = 3.14159265358979323846;
 
@@ -332,6 +330,7 @@ int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
     double sub[6 * NLO_MAXSUB];
     double cpt[2 * 8], cw[8];
     int ns = 0, nc = 0;
+    int use_mlp = 0;
     if (p->ball == 0) {
         double b[2];
         barycenter(V, b);
@@ -339,7 +338,27 @@ int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
         memcpy(sub, V, 6 * sizeof(double));
         ns = 1;
     } else {
-        ns = nlo_region(p, x, V, sub, NLO_MAXSUB, cpt, cw, &nc);
+        if (p->learned) {
+            /* a partial item (some vertex outside the ball, at least one cap)
+             * far from tangency takes the polygon and the learned caps */
+            int nin = 0;
+            for (int a = 0; a < 3; a++) {
+                double dx = V[2 * a] - x[0], dy = V[2 * a + 1] - x[1];
+                nin += dx * dx + dy * dy <= dd;
+            }
+            if (nin < 3 && nlo_routed(p->delta, p->band, x, V)) {
+                double mm[3];
+                int ncap = nlo_cap_moments(p, x, V, mm);
+                if (ncap < 0) return ncap;
+                use_mlp = ncap > 0;
+            }
+        }
+        nlo_problem p0 = *p;
+        if (use_mlp) {
+            p0.cap_edges = 0;
+            p0.cap_mode = 0;
+        }
+        ns = nlo_region(&p0, x, V, sub, NLO_MAXSUB, cpt, cw, &nc);
         if (ns < 0) return ns;
     }
     for (int t = 0; t < ns; t++) {
@@ -367,6 +386,7 @@ int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
             for (int e = 0; e < 3; e++) s2[3 * b + e] += wq * beta[b] * beta[e];
         }
     }
+    if (use_mlp) return nlo_learned_caps(p, x, V, s0, s1, s2);
     return 0;
 }
 

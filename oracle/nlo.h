@@ -34,7 +34,16 @@ typedef struct {
     int32_t n_out2; const double *out2_lam; const double *out2_w; double switch_dist;
     int32_t duffy_n; const double *gl_x; const double *gl_w;   /* Gauss-Legendre on [0,1] */
     int32_t skip_ixi;
+    /* learned caps (constant kernel, intersection ball): partial items with
+     * min_a | |v_a - x| - delta | >= band delta take the polygon plus the
+     * network's cap moments; the others keep the arc-subdivided caps */
+    int32_t learned; double band; const double *mlp_w; double mlp_scale;
 } nlo_problem;
+
+#define NLO_MLP_HIDDEN 128
+#define NLO_MLP_NW (128 * 6 + 128 + 128 * 128 + 128 + 3 * 128 + 3)
+#define NLO_MAXCAP 256
+#define NLO_MAXSUB (4 + 3 * NLO_MAXCAP + 8)
 
 typedef struct nlo_result nlo_result;
 
@@ -58,6 +67,15 @@ void nlo_load(const nlo_mesh *m, const nlo_problem *p, const double *f_outer, do
 void nlo_outer_points(const nlo_mesh *m, const nlo_problem *p, double *xq);
 int64_t nlo_blocks_range(const nlo_mesh *m, const nlo_problem *p, int32_t k0, int32_t k1, int32_t nthreads,
                          double *checksum);
+double nlo_gelu(double z);
+void nlo_mlp_forward(const double *w, const double *feat, int64_t n, double *out);
+void nlo_mlp_backward(const double *w, const double *feat, const double *dout, int64_t n, double *dw);
+int nlo_cap_moments(const nlo_problem *p, const double x[2], const double V[6], double m[3]);
+int nlo_routed(double delta, double band, const double x[2], const double V[6]);
+int nlo_learned_caps(const nlo_problem *p, const double x[2], const double V[6], double s0[1], double s1[3],
+                     double s2[9]);
+int nlo_cap_candidate(const double u[10], double L, double jitter, double band, int32_t cap_edges,
+                      double feat[6], double label[3]);
 int64_t nlo_flops_census(const nlo_mesh *m, const nlo_problem *p, int32_t k0, int32_t k1, int64_t out[8]);
 #ifdef __cplusplus
 }

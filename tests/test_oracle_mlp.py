@@ -1,0 +1,157 @@
+"""Pins of the learned-cap oracle (oracle/nlo_mlp.c) against facts that do
+not come from the oracle itself: the exact (erf) GELU, central finite
+differences of the forward pass, a matrix product where every activation is
+saturated, and the shoelace area/centroid of the 8-arc cap polygon."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.binding as ob
+from workloads.learned import N_WEIGHTS, OFFSETS, cap_uniforms, mlp_init
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+def test_gelu_tanh_form_close_to_exact_gelu():
+    # the tanh form differs from z*Phi(z) by at most 4.8e-4 (at |z| near 2.6;
+    # a constant off by 0.3% already exceeds it) and
+    # matches it in both limits
+    for z in np.linspace(-8, 8, 641):
+        exact = 0.5 * z * (1.0 + math.erf(z / math.sqrt(2.0)))
+        assert abs(ob.gelu(z) - exact) < 4.8e-4
+    assert ob.gelu(12.0) == 12.0
+    assert abs(ob.gelu(-12.0)) < 1e-30
+    assert ob.gelu(0.0) == 0.0
+
+
+def test_forward_saturated_is_affine():
+    """Pre-activations >= 8 everywhere: GELU is the identity to rounding and
+    the network is W3 (W2 (W1 f + b1) + b2) + b3."""
+    rng = np.random.default_rng(3)
+    w = np.zeros(N_WEIGHTS)
+    sl = {k: slice(o, o + int(np.prod(s))) for k, (o, s) in OFFSETS.items()}
+    W1 = rng.uniform(-0.1, 0.1, (128, 6)); b1 = np.full(128, 10.0)
+    W2 = rng.uniform(0.0, 0.01, (128, 128)); b2 = np.full(128, 8.0)
+    W3 = rng.uniform(-1, 1, (3, 128)); b3 = rng.uniform(-1, 1, 3)
+    for k, v in (("W1", W1), ("b1", b1), ("W2", W2), ("b2", b2), ("W3", W3), ("b3", b3)):
+        w[sl[k]] = v.ravel()
+    f = rng.uniform(-1.2, 1.2, (5, 6))
+    ref = ((f @ W1.T + b1) @ W2.T + b2) @ W3.T + b3
+    out = ob.mlp_forward(w, f)
+    assert np.max(np.abs(out - ref) / np.abs(ref).max()) < 1e-13
+
+
+def test_backward_matches_central_differences():
+    rng = np.random.default_rng(4)
+    w = ob.effective_weights(mlp_init(11, bias_scale=0.3))
+    f = rng.uniform(-1.2, 1.2, (3, 6))
+    dout = rng.normal(size=(3, 3))
+    g = ob.mlp_backward(w, f, dout)
+
+    def loss(wv):
+        return float(np.sum(ob.mlp_forward(wv, f) * dout))
+    idx = np.concatenate([rng.choice(np.arange(o, o + int(np.prod(s))), 12, replace=False)
+                          for o, s in OFFSETS.values() if int(np.prod(s)) >= 12] + [np.arange(17792, 17795)])
+    for i in idx:
+        e = 1e-5 * max(1.0, abs(w[i]))
+        wp = w.copy(); wp[i] += e
+        wm = w.copy(); wm[i] -= e
+        fd = (loss(wp) - loss(wm)) / (2 * e)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def _segment_polygon(x0, x1, y, n_arc):
+    """The 8-arc cap above the chord y = const of the unit circle, as a
+    polygon: exit point, arc points at equal angles, entry point."""
+    t0, t1 = math.atan2(y, x1), math.atan2(y, x0)
+    pts = [(math.cos(t0 + (t1 - t0) * j / n_arc), math.sin(t0 + (t1 - t0) * j / n_arc)) for j in range(n_arc + 1)]
+    return np.array(pts), t1 - t0
+
+
+def _shoelace(P):
+    x, y = P[:, 0], P[:, 1]
+    xs, ys = np.roll(x, -1), np.roll(y, -1)
+    cr = x * ys - xs * y
+    A = 0.5 * cr.sum()
+    return A, np.array([((x + xs) * cr).sum() / (6 * A), ((y + ys) * cr).sum() / (6 * A)])
+
+
+@pytest.mark.parametrize("c", [0.9, 0.97, 0.5])
+def test_cap_label_against_shoelace(c):
+    """A large triangle whose bottom edge is the chord line y = c: the caps
+    inside it are the one circular segment above the chord; its 8-arc
+    approximation is a polygon with a closed-form area and centroid, and a
+    linear basis function integrates to area * value at the centroid."""
+    V = np.array([[-3.0, c], [3.0, c], [0.0, 4.0]])
+    s = math.sqrt(1 - c * c)
+    P, D = _segment_polygon(-s, s, c, 8)
+    A, cen = _shoelace(P)
+    assert abs(A - 0.5 * (8 * math.sin(D / 8) - math.sin(D))) < 1e-14
+    M = np.vstack([V.T, np.ones(3)])
+    beta = np.linalg.solve(M, np.array([cen[0], cen[1], 1.0]))
+    n, m = ob.cap_moments(1.0, [0.0, 0.0], V, 8)
+    assert n == 8
+    assert np.allclose(m, A * beta, rtol=1e-12, atol=1e-16)
+
+
+def test_cap_label_two_caps_and_scaling():
+    """A triangle crossed by the circle twice (two caps): the labels scale
+    with delta^2 under x -> x0 + delta x, and sum to the sum of the two
+    8-arc segment areas."""
+    V = np.array([[-0.95, -0.6], [0.95, -0.6], [0.0, 1.6]])
+    n, m = ob.cap_moments(1.0, [0.0, 0.0], V, 8)
+    d, x0 = 0.037, np.array([0.3, -0.2])
+    n2, m2 = ob.cap_moments(d, x0, x0 + d * V, 8)
+    assert n == n2 and n % 8 == 0 and n >= 16
+    assert np.allclose(m2, m * d * d, rtol=1e-11)
+    # the polygon of E n B plus the caps covers E n B_8arc: compare with the
+    # difference of the regions' areas
+    op_area = []
+    for ce in (0, 8):
+        p = ob._Problem(); p.delta, p.kc, p.ball, p.cap_edges = 1.0, 1.0, 1, ce
+        sub = np.zeros(6 * 2048); cp = np.zeros(16); cw = np.zeros(8); nc = ob.C.c_int32()
+        ns = ob._lib().nlo_region(ob.C.byref(p), ob._ptr(np.zeros(2)), ob._ptr(V.ravel().copy()),
+                                  ob._ptr(sub), 2048, ob._ptr(cp), ob._ptr(cw), ob.C.byref(nc))
+        T = sub[:6 * ns].reshape(-1, 3, 2)
+        e1, e2 = T[:, 1] - T[:, 0], T[:, 2] - T[:, 0]
+        op_area.append(0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]).sum())
+    assert abs((op_area[1] - op_area[0]) - m.sum()) < 1e-14
+
+
+def test_candidates_are_partial_routed_items():
+    U = cap_uniforms(20052, 0, 400)
+    valid, feat, lab = ob.cap_candidates(U, 0.125, 0.1, 0.02)
+    assert 0.1 < valid.mean() < 0.4
+    for f, l in zip(feat[valid][:40], lab[valid][:40]):
+        V = f.reshape(3, 2)
+        r = np.hypot(V[:, 0], V[:, 1])
+        assert (r > 1).any()                 # not whole
+        assert np.min(np.abs(r - 1)) >= 0.02
+        n, m = ob.cap_moments(1.0, [0, 0], V, 8)
+        assert n > 0 and np.array_equal(m, l)
+        # counter-clockwise and legs of about L
+        cr = (V[1, 0] - V[0, 0]) * (V[2, 1] - V[0, 1]) - (V[1, 1] - V[0, 1]) * (V[2, 0] - V[0, 0])
+        assert 0.7 * 0.125 ** 2 < cr < 1.3 * 0.125 ** 2
+        assert np.all(l >= 0) and l.sum() > 0
+
+
+def test_learned_band_infinite_is_the_exact_path():
+    from workloads import make_config
+    from dataclasses import replace
+    from workloads import structured_mesh, Problem, constant_kernel_c
+    d = 0.1
+    mesh = structured_mesh(d, d / 4, jitter=0.1, seed=5)
+    p = Problem(delta=d, kernel_c=constant_kernel_c(d), ball="retri", cap_edges=8, outer="dunavant7",
+                inner="dunavant16")
+    w = ob.effective_weights(mlp_init(2, 0.1))
+    a = ob.assemble(ob.OracleProblem(mesh, p))
+    b = ob.assemble(ob.OracleProblem(mesh, replace(p, precision="learned", fallback_band=1e9), mlp_w=w))
+    assert np.array_equal(a["val"], b["val"])
+    # band 0 routes every partial item: the matrix changes
+    c = ob.assemble(ob.OracleProblem(mesh, replace(p, precision="learned", fallback_band=0.0), mlp_w=w))
+    assert np.array_equal(a["col"], c["col"]) and not np.array_equal(a["val"], c["val"])
