@@ -152,6 +152,103 @@ def bench_batch(args):
             "plan_ms": plan_ms}
 
 
+def _timed_assembly(plan, fo, g, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.assemble(fo, g)
+    plan.set_timing(steps)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.assemble(fo, g)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    phase, n = plan.timings()
+    plan.set_timing(0)
+    return e0.elapsed_time(e1) / steps, phase
+
+
+def _solve(plan, mesh, u):
+    U, its, rel = plan.cg(plan.load(), rtol=1e-12)
+    Ufull = u(mesh.xy[:, 0], mesh.xy[:, 1]).copy()
+    Ufull[plan.free_nodes().cpu().numpy()] = U.cpu().numpy()
+    return Ufull, its
+
+
+def _l2_diff(mesh, U1, U2):
+    return l2_error(mesh, U1 - U2, lambda x, y: 0.0 * x)
+
+
+def bench_learned(args):
+    """Learned caps on the c2 mesh: train the network on the GPU (outside the
+    timed region), then time the FP32 learned assembly against the FP64 and
+    FP32 exact-cap assemblies and the FP32 no-cap one, and compare solutions."""
+    import torch
+    from dataclasses import replace
+    from paper_2005_10775_amd import Mlp, Plan
+    from workloads import make_config, manufactured
+    from workloads.learned import TRAIN
+    mesh, p64, man = make_config("c2")
+    u, f = manufactured(man)
+    t0 = time.perf_counter()
+    feat, lab = Mlp.samples(int(TRAIN["samples"] / 0.17), TRAIN["seed"], L=TRAIN["L"], jitter=TRAIN["jitter"],
+                            band=TRAIN["band"], cap_edges=TRAIN["cap_edges"])
+    feat, lab = feat[:TRAIN["samples"]].contiguous(), lab[:TRAIN["samples"]].contiguous()
+    torch.cuda.synchronize()
+    t_samples = time.perf_counter() - t0
+    net = Mlp(seed=TRAIN["seed"])
+    t0 = time.perf_counter()
+    log = net.train(feat, lab, epochs=args.epochs, batch=TRAIN["batch"], lr=TRAIN["lr"], seed=TRAIN["seed"])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    fh, lh = Mlp.samples(400_000, TRAIN["seed"], first=10 ** 9)
+    w, sc = net.get_weights()
+    pred = net.forward(fh) * sc
+    held = float(torch.sqrt(torch.mean((pred - lh) ** 2)) / torch.sqrt(torch.mean(lh ** 2)))
+
+    variants = {"fp64_exactcap": p64, "fp32_exactcap": replace(p64, precision="fp32"),
+                "fp32_nocaps": replace(p64, precision="fp32", cap_edges=0),
+                "fp32_learned": replace(p64, precision="learned")}
+    res = {}
+    sols = {}
+    for name, prob in variants.items():
+        plan = Plan(mesh, prob, mlp=net if prob.precision == "learned" else None)
+        xq = plan.outer_points()
+        fo = f(xq[..., 0], xq[..., 1]).contiguous()
+        g = torch.tensor(u(mesh.xy[:, 0], mesh.xy[:, 1]), dtype=torch.float64, device="cuda")
+        ms, phase = _timed_assembly(plan, fo, g, args.steps, args.warmup)
+        info = plan.info()
+        U, its = _solve(plan, mesh, u)
+        sols[name] = U
+        res[name] = {"ms": ms, "pairs_per_s": info["n_pairs"] / (ms * 1e-3), "phase_ms": phase,
+                     "items": info["items"], "l2_err": l2_error(mesh, U, u), "cg_iters": its}
+        plan.close()
+    for name in res:
+        res[name]["l2_diff_vs_fp64_exactcap"] = _l2_diff(mesh, sols[name], sols["fp64_exactcap"])
+    L = res["fp32_learned"]
+    n_learned = L["items"]["learned"]
+    # the MLP phase: routing pass + network inference over the routed items
+    mfma_flops = n_learned * 2.0 * (128 * 128 + 3 * 128)
+    mlp_ms = L["phase_ms"]["mlp"]
+    out = {"metric": METRIC, "value": L["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": L["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+           "config": {"workload": "c5: c2 mesh (delta=0.1, h=delta/8 jittered, K=%d), 8-arc caps, 7x16 rules, "
+                                  "constant kernel; learned caps (6-128-128-3 tanh-GELU, bf16 MFMA) outside the "
+                                  "0.02 delta band, FP32 compensated sums" % mesh.n_triangles,
+                      "train_samples": int(feat.shape[0]), "epochs": args.epochs, "batch": TRAIN["batch"]},
+           "speedup_vs_fp64_exactcap": res["fp64_exactcap"]["ms"] / L["ms"],
+           "speedup_vs_fp32_exactcap": res["fp32_exactcap"]["ms"] / L["ms"],
+           "variants": res, "train": {"samples_s": t_samples, "train_s": t_train, "loss": log,
+                                      "heldout_rel_rms": held, "scale": sc},
+           "mlp_phase": {"routed_items": n_learned, "ms": mlp_ms,
+                         "mfma_tflops": mfma_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else None,
+                         "mfma_frac_of_bf16_dense_peak": mfma_flops / (mlp_ms * 1e-3) / 2.5e15 if mlp_ms > 0 else None}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +258,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--duffy", type=int, default=0, help="override the singular-pair rule order")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="outer elements in the CPU-baseline sample")
+    ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB device buffer 3 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -177,6 +275,9 @@ def main():
     torch.cuda.set_device(0)
     if args.config == "c4":
         print(json.dumps(bench_batch(args)))
+        return
+    if args.config == "c5":
+        print(json.dumps(bench_learned(args)))
         return
     mesh, prob, man = make_config(args.config)
     if args.duffy:

@@ -118,9 +118,10 @@ typedef struct {
     int64_t caps;                /* after nla_assemble: caps filled with triangles */
 } nla_info;
 
-/* phases timed by nla_last_timings */
-enum { NLA_PHASE_PAIRS = 0, NLA_PHASE_NEAR = 1, NLA_PHASE_SEGSUM = 2, NLA_PHASE_EXTRACT = 3, NLA_PHASE_LOAD = 4,
-       NLA_NPHASE = 5 };
+/* phases timed by nla_timings, in launch order (MLP: routing pass and network
+ * inference of the learned caps) */
+enum { NLA_PHASE_MLP = 0, NLA_PHASE_PAIRS = 1, NLA_PHASE_NEAR = 2, NLA_PHASE_SEGSUM = 3, NLA_PHASE_EXTRACT = 4,
+       NLA_PHASE_LOAD = 5, NLA_NPHASE = 6 };
 
 const char *nla_last_error(void);
 
@@ -228,6 +229,70 @@ int nla_batch_info(const nla_batch *batch, nla_batch_summary *info);
  * the batch shape, read first and appended to. */
 int nla_batch_autotune(nla_batch *batch, const char *cache_path, void *stream);
 void nla_batch_destroy(nla_batch *batch);
+
+/* ------------------------------------------------------------------------
+ * Learned cap corrector.  The caps that the inscribed polygon of the
+ * intersection ball leaves out (Sec. 4.2.1) are filled with triangles over
+ * equal arcs in Sec. 4.2.2; for partial items far from tangency
+ * (min_a | |v_a - x| - delta | >= fallback_band delta, FP64 test) the
+ * NLA_FP32_LEARNED path replaces them by a network that predicts
+ *     m_b = (1/delta^2) int_{caps in E_k'} phi_b dy,   b = 0, 1, 2,
+ * from the vertices of E_k' (mesh order) in a frame centred at x and rotated
+ * so that the triangle's centroid lies on the positive first axis (the cap
+ * integrals are invariant under it), shifted by the horizon and magnified by
+ * 8 (the element size of the h = delta/8 family):
+ *     f_a = 8 (R(-phi) (v_a - x)/delta - (1, 0)),  phi = angle of the centroid;
+ * the item then adds S0 += kc delta^2 sum m,
+ * S1_b += kc delta^2 m_b and the one-point centroid closure of Sec. 5.2,
+ * S2_bc += kc delta^2 m_b m_c / sum m (network outputs clamped at 0).
+ * Network: 6 -> 128 -> 128 -> 3 with g(z) = z/2 (1 + tanh(sqrt(2/pi)(z +
+ * 0.044715 z^3))); weights in one flat float array W1[128][6], b1[128],
+ * W2[128][128], b2[128], W3[3][128], b3[3] (row = output unit), 17795 floats;
+ * W2 and W3 are used rounded to bfloat16 (matrix cores, FP32 accumulation),
+ * W1 and the biases in FP32.  Outputs are in units of `scale` (m = scale *
+ * output).  An nla_mlp must outlive every plan that uses it; calls are
+ * stream-ordered on the caller's stream, and an nla_mlp is not thread-safe.
+ * ------------------------------------------------------------------------ */
+#define NLA_MLP_WEIGHTS 17795
+typedef struct nla_mlp nla_mlp;
+
+/* A network with seeded uniform initial weights (bound sqrt(6/fan_in), W3
+ * sqrt(1/fan_in), zero biases) and scale 0 (set by the first training call
+ * to the root mean square of its labels). */
+int nla_mlp_create(uint64_t seed, nla_mlp **out);
+/* Host weights in the flat layout (copied), output scale > 0; resets Adam. */
+int nla_mlp_set_weights(nla_mlp *mlp, const float *w, float scale);
+/* Master FP32 weights to host w[NLA_MLP_WEIGHTS], and the scale. */
+int nla_mlp_get_weights(const nla_mlp *mlp, float *w, float *scale);
+/* Training candidates first .. first+n_cand-1 in units of delta around x = 0,
+ * each from ten SplitMix64 outputs 10c .. 10c+9 of `seed`: a right triangle of
+ * legs L (= h/delta) from one of the four halves of a grid cell, its cell
+ * centre at distance 1 + (2u1 - 1) sqrt(2) L in direction 2 pi u2, each vertex
+ * coordinate jittered by jitter L (2u - 1) (u3..u8), vertex order rotated by
+ * floor(3 u9).  Kept when the ball cuts the triangle (at least one cap) and
+ * every vertex is at least `band` from the circle.  Writes the kept samples in
+ * candidate order to feat (device, [n_cand][6] floats of room: the network
+ * input above, with x = 0 and delta = 1) and label
+ * (device, [n_cand][3]: cap moments from the FP64 arc subdivision with
+ * cap_edges arcs) and their number to *n_valid (host; synchronises). */
+int nla_mlp_samples(int64_t n_cand, uint64_t seed, int64_t first, double L, double jitter, double band,
+                    int32_t cap_edges, float *feat, float *label, int64_t *n_valid, void *stream);
+/* Adam (beta 0.9, 0.999, eps 1e-8) on the mean squared error of the outputs
+ * against label/scale, cosine learning-rate decay from lr over the call,
+ * `epochs` passes over n device samples in seeded affine-permutation order,
+ * batch a multiple of 64 with n >= batch.  loss_log (host, may be NULL)
+ * receives the mean loss of each epoch.  Synchronises once per epoch. */
+int nla_mlp_train(nla_mlp *mlp, const float *feat, const float *label, int64_t n, int32_t epochs, int32_t batch,
+                  float lr, uint64_t seed, float *loss_log, void *stream);
+/* Network outputs (before scale) of n device samples into out [n][3]. */
+int nla_mlp_forward(const nla_mlp *mlp, const float *feat, int64_t n, float *out, void *stream);
+/* Gradient of sum_i sum_o dout[i][o] y[i][o] with respect to every weight
+ * (device dw[NLA_MLP_WEIGHTS], flat layout), on the weights as used. */
+int nla_mlp_backward(nla_mlp *mlp, const float *feat, const float *dout, int64_t n, float *dw, void *stream);
+/* Checkpoint (weights, scale, Adam state) to / from a file. */
+int nla_mlp_save(const nla_mlp *mlp, const char *path);
+int nla_mlp_load(const char *path, nla_mlp **out);
+void nla_mlp_destroy(nla_mlp *mlp);
 
 #ifdef __cplusplus
 }

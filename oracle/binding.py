@@ -79,7 +79,9 @@ def _lib():
         L.nlo_cap_moments.restype = C.c_int
         L.nlo_routed.argtypes = [D, D, P, P]
         L.nlo_routed.restype = C.c_int
-        L.nlo_cap_candidate.argtypes = [P, D, D, D, I32, P, P]
+        L.nlo_cap_candidate.argtypes = [P, D, D, D, I32, P, P, P]
+        L.nlo_mlp_features.argtypes = [P, P, D, P]
+        L.nlo_mlp_features.restype = None
         L.nlo_cap_candidate.restype = C.c_int
         _LIB = L
     return _LIB
@@ -302,11 +304,11 @@ def l2_error(mesh, U, u_exact, rule_name="dunavant7"):
     return float(np.sqrt(err))
 
 
-def solve_problem(mesh, prob, man, nthreads=0, dense=None):
+def solve_problem(mesh, prob, man, nthreads=0, dense=None, mlp_w=None, mlp_scale=1.0):
     """Assemble, build A and b, solve, and return the L2 error against u."""
     from workloads.problems import manufactured
     u, f = manufactured(man)
-    op = OracleProblem(mesh, prob)
+    op = OracleProblem(mesh, prob, mlp_w=mlp_w, mlp_scale=mlp_scale)
     res = assemble(op, nthreads)
     xq = outer_points(op)
     G = load_vector(op, f(xq[..., 0], xq[..., 1]))
@@ -384,19 +386,31 @@ def routed(delta, band, x, tri_xy):
     return bool(_lib().nlo_routed(delta, band, _ptr(xx), _ptr(V)))
 
 
+def mlp_features(x, tri_xy, delta):
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    V = np.ascontiguousarray(tri_xy, dtype=np.float64).reshape(6)
+    f = np.zeros(6)
+    _lib().nlo_mlp_features(_ptr(xx), _ptr(V), delta, _ptr(f))
+    return f
+
+
 def cap_candidates(U, L, jitter, band, cap_edges=8):
-    """Training candidates from uniforms U[n][10]: (valid[n], feat[n][6], label[n][3])."""
+    """Training candidates from uniforms U[n][10]:
+    (valid[n], feat[n][6] network inputs, label[n][3], verts[n][6])."""
     U = np.ascontiguousarray(U, dtype=np.float64).reshape(-1, 10)
     n = U.shape[0]
     valid = np.zeros(n, dtype=bool)
     feat = np.zeros((n, 6))
     lab = np.zeros((n, 3))
+    verts = np.zeros((n, 6))
+    v6 = np.zeros(6)
     f6 = np.zeros(6)
     l3 = np.zeros(3)
     lib = _lib()
     for i in range(n):
         u = np.ascontiguousarray(U[i])
-        valid[i] = lib.nlo_cap_candidate(_ptr(u), L, jitter, band, cap_edges, _ptr(f6), _ptr(l3)) == 1
+        valid[i] = lib.nlo_cap_candidate(_ptr(u), L, jitter, band, cap_edges, _ptr(v6), _ptr(f6), _ptr(l3)) == 1
         feat[i] = f6
         lab[i] = l3
-    return valid, feat, lab
+        verts[i] = v6
+    return valid, feat, lab, verts

@@ -74,8 +74,9 @@ int nlo_cap_moments(const nlo_problem *p, const double x[2], const double V[6], 
 int nlo_routed(double delta, double band, const double x[2], const double V[6]);
 int nlo_learned_caps(const nlo_problem *p, const double x[2], const double V[6], double s0[1], double s1[3],
                      double s2[9]);
+void nlo_mlp_features(const double x[2], const double V[6], double delta, double f[6]);
 int nlo_cap_candidate(const double u[10], double L, double jitter, double band, int32_t cap_edges,
-                      double feat[6], double label[3]);
+                      double verts[6], double feat[6], double label[3]);
 int64_t nlo_flops_census(const nlo_mesh *m, const nlo_problem *p, int32_t k0, int32_t k1, int64_t out[8]);
 #ifdef __cplusplus
 }

@@ -13,6 +13,11 @@
  *     S0 += kc sum(m),  S1_b += kc m_b,  S2_bc += kc m_b m_c / sum(m)
  * (times delta^2), which keeps each item's contribution positive semidefinite.
  *
+ * Network input: the vertices in a frame centred at x and rotated so that the
+ * triangle's centroid lies on the positive first axis (the cap integrals do
+ * not change under that rotation), shifted by the horizon and magnified by 8
+ * (the element size of the h = delta/8 family):
+ *     f_a = 8 (R(-phi) (v_a - x)/delta - (1, 0)),  phi = angle of the centroid.
  * Network (FP64 here): 6 -> 128 -> 128 -> 3 with the tanh form of GELU,
  *     g(z) = z/2 (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))),
  * weights in one flat array: W1[128][6], b1[128], W2[128][128], b2[128],
@@ -147,6 +152,19 @@ int nlo_cap_moments(const nlo_problem *p, const double x[2], const double V[6], 
     return ns - npoly;
 }
 
+/* the network input of (x, E_k') */
+void nlo_mlp_features(const double x[2], const double V[6], double delta, double f[6])
+{
+    double cx = ((V[0] + V[2]) + V[4]) / 3.0 - x[0], cy = ((V[1] + V[3]) + V[5]) / 3.0 - x[1];
+    double r = sqrt(cx * cx + cy * cy);
+    double c = r > 0.0 ? cx / r : 1.0, s = r > 0.0 ? cy / r : 0.0;
+    for (int a = 0; a < 3; a++) {
+        double dx = (V[2 * a] - x[0]) / delta, dy = (V[2 * a + 1] - x[1]) / delta;
+        f[2 * a] = 8.0 * ((dx * c + dy * s) - 1.0);
+        f[2 * a + 1] = 8.0 * (dy * c - dx * s);
+    }
+}
+
 /* learned routing: far enough from tangency, min_a | |v_a - x| - delta | >= band delta */
 int nlo_routed(double delta, double band, const double x[2], const double V[6])
 {
@@ -165,10 +183,7 @@ int nlo_learned_caps(const nlo_problem *p, const double x[2], const double V[6],
 {
     if (p->kernel != 0 || !p->mlp_w) return -4;
     double f[6], y[3];
-    for (int a = 0; a < 3; a++) {
-        f[2 * a] = (V[2 * a] - x[0]) / p->delta;
-        f[2 * a + 1] = (V[2 * a + 1] - x[1]) / p->delta;
-    }
+    nlo_mlp_features(x, V, p->delta, f);
     nlo_mlp_forward(p->mlp_w, f, 1, y);
     double m[3], sm = 0.0;
     for (int b = 0; b < 3; b++) {
@@ -190,9 +205,10 @@ int nlo_learned_caps(const nlo_problem *p, const double x[2], const double V[6],
  * in direction 2 pi u2, every vertex jittered by jitter*L*(2u - 1) per
  * coordinate, vertex order rotated cyclically by floor(3 u9).  Valid when the
  * ball cuts the triangle (at least one cap) and the item is routed.  Returns
- * 1 (valid) or 0; feat = the vertices, label = the cap moments (delta = 1). */
+ * 1 (valid) or 0; verts = the vertices, feat = the network input, label = the
+ * cap moments (delta = 1). */
 int nlo_cap_candidate(const double u[10], double L, double jitter, double band, int32_t cap_edges,
-                      double feat[6], double label[3])
+                      double verts[6], double feat[6], double label[3])
 {
     static const double shapes[4][6] = {{0, 0, 1, 0, 1, 1}, {0, 0, 1, 1, 0, 1}, {0, 0, 1, 0, 0, 1},
                                         {1, 0, 1, 1, 0, 1}};
@@ -210,17 +226,18 @@ int nlo_cap_candidate(const double u[10], double L, double jitter, double band, 
     if (rot > 2) rot = 2;
     for (int a = 0; a < 3; a++) {
         int b = (a + rot) % 3;
-        feat[2 * a] = V[2 * b];
-        feat[2 * a + 1] = V[2 * b + 1];
+        verts[2 * a] = V[2 * b];
+        verts[2 * a + 1] = V[2 * b + 1];
     }
+    const double x0[2] = {0.0, 0.0};
+    nlo_mlp_features(x0, verts, 1.0, feat);
     nlo_problem p;
     memset(&p, 0, sizeof p);
     p.delta = 1.0;
     p.kc = 1.0;
     p.ball = 1;
     p.cap_edges = cap_edges;
-    const double x[2] = {0.0, 0.0};
-    int nc = nlo_cap_moments(&p, x, feat, label);
+    int nc = nlo_cap_moments(&p, x0, verts, label);
     if (nc <= 0) return 0;
-    return nlo_routed(1.0, band, x, feat);
+    return nlo_routed(1.0, band, x0, verts);
 }

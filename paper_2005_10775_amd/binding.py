@@ -52,7 +52,8 @@ class nla_info(C.Structure):
                 ("caps", C.c_int64)]
 
 
-PHASES = ("pairs", "near", "segsum", "extract", "load")
+PHASES = ("mlp", "pairs", "near", "segsum", "extract", "load")
+MLP_WEIGHTS = 17795
 
 
 _LIB = None
@@ -91,10 +92,23 @@ def lib():
         L.nla_timings.argtypes = [P, P, C.POINTER(I32)]
         L.nla_plan_destroy.argtypes = [P]
         L.nla_plan_destroy.restype = None
+        L.nla_mlp_create.argtypes = [C.c_uint64, C.POINTER(P)]
+        L.nla_mlp_set_weights.argtypes = [P, P, C.c_float]
+        L.nla_mlp_get_weights.argtypes = [P, P, C.POINTER(C.c_float)]
+        L.nla_mlp_samples.argtypes = [I64, C.c_uint64, I64, D, D, D, I32, P, P, C.POINTER(I64), P]
+        L.nla_mlp_train.argtypes = [P, P, P, I64, I32, I32, C.c_float, C.c_uint64, P, P]
+        L.nla_mlp_forward.argtypes = [P, P, I64, P, P]
+        L.nla_mlp_backward.argtypes = [P, P, P, I64, P, P]
+        L.nla_mlp_save.argtypes = [P, C.c_char_p]
+        L.nla_mlp_load.argtypes = [C.c_char_p, C.POINTER(P)]
+        L.nla_mlp_destroy.argtypes = [P]
+        L.nla_mlp_destroy.restype = None
         for name in ("nla_plan_create", "nla_plan_info", "nla_pairs_view", "nla_outer_points", "nla_assemble",
                      "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg",
                      "nla_set_timing", "nla_timings", "nla_near_view", "nla_batch_create",
-                     "nla_batch_assemble", "nla_batch_plan", "nla_batch_info", "nla_batch_autotune"):
+                     "nla_batch_assemble", "nla_batch_plan", "nla_batch_info", "nla_batch_autotune",
+                     "nla_mlp_create", "nla_mlp_set_weights", "nla_mlp_get_weights", "nla_mlp_samples",
+                     "nla_mlp_train", "nla_mlp_forward", "nla_mlp_backward", "nla_mlp_save", "nla_mlp_load"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -138,9 +152,10 @@ def _rule(r, keep):
     return nla_rule(r.n, lam.ctypes.data, w.ctypes.data)
 
 
-def marshal(mesh, prob, keep):
+def marshal(mesh, prob, keep, mlp=None):
     """(nla_mesh, nla_problem) structs for a workloads mesh and problem; the
-    numpy buffers they point to are appended to `keep`."""
+    numpy buffers they point to are appended to `keep` (and the network of a
+    learned-caps problem, which must outlive the plan)."""
     from workloads.rules import get_rule, gauss_legendre01
     xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
     tri = np.ascontiguousarray(mesh.tri, dtype=np.int32)
@@ -166,6 +181,11 @@ def marshal(mesh, prob, keep):
     p.precision = PRECISIONS[prob.precision]
     p.fallback_band = prob.fallback_band
     p.flags = NLA_SKIP_IXI if prob.skip_ixi else 0
+    if prob.precision == "learned":
+        if mlp is None:
+            raise ValueError("a learned-caps problem needs a network (mlp=Mlp(...))")
+        p.mlp = mlp._h
+        keep.append(mlp)
     return m, p
 
 
@@ -177,7 +197,7 @@ class nla_batch_summary(C.Structure):
 class Plan:
     """A plan for one mesh and problem (nla_plan_create ... nla_plan_destroy)."""
 
-    def __init__(self, mesh, prob, stream=None, handle=None):
+    def __init__(self, mesh, prob, stream=None, handle=None, mlp=None):
         self.mesh = mesh
         self.problem = prob
         self.K = mesh.n_triangles
@@ -189,7 +209,8 @@ class Plan:
             self._h = handle
             return
         keep = []
-        m, p = marshal(mesh, prob, keep)
+        m, p = marshal(mesh, prob, keep, mlp)
+        self.mlp = mlp
         h = C.c_void_p()
         _check(lib().nla_plan_create(C.byref(m), C.byref(p), _stream(stream), C.byref(h)))
         self._h = h
@@ -354,3 +375,80 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Mlp:
+    """The learned cap corrector's network (nla_mlp_*): weights on the GPU,
+    training and inference in the library's kernels."""
+
+    def __init__(self, seed=0, handle=None):
+        if handle is None:
+            h = C.c_void_p()
+            _check(lib().nla_mlp_create(C.c_uint64(seed), C.byref(h)))
+            handle = h
+        self._h = handle
+
+    @classmethod
+    def load(cls, path):
+        h = C.c_void_p()
+        _check(lib().nla_mlp_load(path.encode(), C.byref(h)))
+        return cls(handle=h)
+
+    def save(self, path):
+        _check(lib().nla_mlp_save(self._h, path.encode()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nla_mlp_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_weights(self, w, scale):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.shape == (MLP_WEIGHTS,)
+        _check(lib().nla_mlp_set_weights(self._h, w.ctypes.data, C.c_float(scale)))
+
+    def get_weights(self):
+        w = np.empty(MLP_WEIGHTS, dtype=np.float32)
+        sc = C.c_float()
+        _check(lib().nla_mlp_get_weights(self._h, w.ctypes.data, C.byref(sc)))
+        return w, sc.value
+
+    @staticmethod
+    def samples(n_cand, seed, first=0, L=0.125, jitter=0.1, band=0.02, cap_edges=8, stream=None):
+        """Kept training samples (feat [n][6], label [n][3] float32 device tensors)."""
+        feat = torch.empty((max(n_cand, 1), 6), dtype=torch.float32, device="cuda")
+        lab = torch.empty((max(n_cand, 1), 3), dtype=torch.float32, device="cuda")
+        nv = C.c_int64()
+        _check(lib().nla_mlp_samples(n_cand, C.c_uint64(seed), first, L, jitter, band, cap_edges,
+                                     C.c_void_p(feat.data_ptr()), C.c_void_p(lab.data_ptr()), C.byref(nv),
+                                     _stream(stream)))
+        return feat[:nv.value], lab[:nv.value]
+
+    def train(self, feat, label, epochs, batch=4096, lr=1e-3, seed=0, stream=None):
+        """Mean loss per epoch (list)."""
+        assert feat.is_contiguous() and label.is_contiguous() and feat.dtype == torch.float32
+        log = (C.c_float * epochs)()
+        _check(lib().nla_mlp_train(self._h, C.c_void_p(feat.data_ptr()), C.c_void_p(label.data_ptr()),
+                                   feat.shape[0], epochs, batch, C.c_float(lr), C.c_uint64(seed), log,
+                                   _stream(stream)))
+        return list(log)
+
+    def forward(self, feat, stream=None):
+        feat = feat.contiguous()
+        out = torch.empty((feat.shape[0], 3), dtype=torch.float32, device="cuda")
+        _check(lib().nla_mlp_forward(self._h, C.c_void_p(feat.data_ptr()), feat.shape[0],
+                                     C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def backward(self, feat, dout, stream=None):
+        feat, dout = feat.contiguous(), dout.contiguous()
+        dw = torch.empty(MLP_WEIGHTS, dtype=torch.float32, device="cuda")
+        _check(lib().nla_mlp_backward(self._h, C.c_void_p(feat.data_ptr()), C.c_void_p(dout.data_ptr()),
+                                      feat.shape[0], C.c_void_p(dw.data_ptr()), _stream(stream)))
+        return dw

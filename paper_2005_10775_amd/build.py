@@ -22,6 +22,7 @@ UNITS = {
     "nla_numeric.hip": [],
     "nla_cg.hip": [],
     "nla_fp32.hip": [],
+    "nla_mlp.hip": [],
 }
 
 

@@ -281,3 +281,20 @@ __device__ __forceinline__ bool meets_edges(double xx, double xy, const double (
     return false;
 }
 
+
+// Input of the learned cap network for (x, E_k'): the vertices in a frame
+// centred at x, rotated so that the triangle's centroid lies on the positive
+// first axis, shifted by the horizon and magnified by 8 (the element size of
+// the h = delta/8 family): f_a = 8 (R(-phi)(v_a - x)/delta - (1, 0)).
+__device__ __forceinline__ void mlp_features(double xx, double xy, const double (&V)[6], double delta, float (&f)[6])
+{
+    const double cx = ((V[0] + V[2]) + V[4]) / 3.0 - xx, cy = ((V[1] + V[3]) + V[5]) / 3.0 - xy;
+    const double r = sqrt(cx * cx + cy * cy);
+    const double c = r > 0.0 ? cx / r : 1.0, s = r > 0.0 ? cy / r : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double dx = (V[2 * a] - xx) / delta, dy = (V[2 * a + 1] - xy) / delta;
+        f[2 * a] = (float)(8.0 * ((dx * c + dy * s) - 1.0));
+        f[2 * a + 1] = (float)(8.0 * (dy * c - dx * s));
+    }
+}

@@ -102,6 +102,58 @@ struct TriF32 {
     }
 };
 
+// Item class of (x, E_k') under the intersection ball: 1 whole (every vertex
+// in the closed ball), 2 partial (the ball meets the triangle otherwise), 0
+// empty.  Every product and sum is rounded on its own, so the routing pass of
+// the learned caps and the pair kernel take identical decisions.
+__device__ __forceinline__ int item_class(double xx, double xy, const double (&V)[6], double dd)
+{
+#pragma clang fp contract(off)
+    int nin = 0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
+        nin += dx * dx + dy * dy <= dd;
+    }
+    if (nin == 3) return 1;
+    if (nin > 0) return 2;
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        const double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        const double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        if (ex * py - ey * px < 0.0) inside = false;
+    }
+    if (inside) return 2;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        const double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        const double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        const double t = ex * px + ey * py, L = ex * ex + ey * ey;
+        if (t > 0.0 && t < L) {
+            const double c = ex * py - ey * px;
+            if (c * c <= dd * L) return 2;
+        }
+    }
+    return 0;
+}
+
+// learned caps: a partial item far from tangency, min_a | |v_a - x| - delta | >= band delta
+__device__ __forceinline__ bool item_routed(double xx, double xy, const double (&V)[6], double delta, double band)
+{
+#pragma clang fp contract(off)
+    double mn = 1e300;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
+        const double d = fabs(sqrt(dx * dx + dy * dy) - delta);
+        mn = d < mn ? d : mn;
+    }
+    return mn >= band * delta;
+}
+
 // One wavefront per outer element k, FP32 sums (structure as the FP64 kernel):
 // phase 1 classifies the items of each lane's pair and integrates whole items
 // in the lane, phase 2 retriangulates the queued partial items densely; the
@@ -121,6 +173,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
     const float kc = P.kc, ex = P.ex;
     const int ball = P.ball, ncap = P.ncap, max_cols = P.max_cols;
     const bool FRAC = FM == 2 ? P.frac != 0 : FM == 1;
+    constexpr bool LEARN = FM == 3;   // constant kernel with learned caps
     const uint8_t *__restrict__ near_flag = P.near_flag;
     const int64_t *__restrict__ col_off = P.col_off;
     const int32_t *__restrict__ colent_ptr = P.colent_ptr;
@@ -134,6 +187,8 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
     __shared__ double sV[64][7];
     __shared__ unsigned short queue[64 * NQ];
     __shared__ float res[64][10];
+    __shared__ int64_t rbase_l[LEARN ? 64 : 1];
+    __shared__ unsigned rmsk_l[LEARN ? 64 : 1];
     float(*mxy_l)[10] = res;
     const int lane = threadIdx.x;
     const int nq = R->n_out;
@@ -165,8 +220,9 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
     KahanF m0[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; q++) m0[q].zero();
-    unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
+    unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0, c_learn = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
+    int64_t rrun = LEARN ? P.route_off[k] : 0;   // routed items of k before this chunk
     for (int64_t base = p0; base < p1; base += 64) {
         const int64_t p = base + lane;
         const bool act = p < p1 && !(near_flag && near_flag[p]);
@@ -187,7 +243,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
 #pragma unroll
         for (int i = 0; i < 6; i++) ayy[i].zero();
         float ws = 0.f, aw[3] = {0.f, 0.f, 0.f};
-        unsigned pmask = 0;
+        unsigned pmask = 0, rmask = 0;
         if (act) {
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
@@ -198,14 +254,10 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
                     const double dx = xx - bxp, dy = xy - byp;
                     whole = dx * dx + dy * dy <= dd;
                 } else {
-                    int nin = 0;
-#pragma unroll
-                    for (int a = 0; a < 3; a++) {
-                        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
-                        nin += dx * dx + dy * dy <= dd;
-                    }
-                    whole = nin == 3;
-                    part = !whole && (nin > 0 || meets_edges(xx, xy, V, dd));
+                    const int cls = item_class(xx, xy, V, dd);
+                    whole = cls == 1;
+                    part = cls == 2;
+                    if (LEARN && part && item_routed(xx, xy, V, P.delta, P.band)) rmask |= 1u << q;
                 }
                 if (whole) {
                     c_whole++;
@@ -269,6 +321,20 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
                 queue[oo++] = (unsigned short)((lane << 8) | q);
             }
         }
+        if (LEARN) {
+            // routed items in (pair, q) order: the same order as the routing pass
+            const int rc = __popc(rmask);
+            int rp = rc;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(rp, off, 64);
+                if (lane >= off) rp += v;
+            }
+            const int rtot = __shfl(rp, 63, 64);
+            rbase_l[lane] = rrun + rp - rc;
+            rmsk_l[lane] = rmask;
+            rrun += rtot;
+        }
         __syncthreads();
         for (int ib = 0; ib < total; ib += 64) {
             const int i = ib + lane;
@@ -278,9 +344,30 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
                 A.zero();
                 TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC};
                 int ns = 0;
-                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns);
+                const bool routed = LEARN && P.n_routed > 0 && ((rmsk_l[owner] >> q) & 1u);
+                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, tri, ns);
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
+                if (routed) {
+                    // the polygon above plus the network's cap moments m_b (units of
+                    // kc delta^2 scale), second moments by the one-point centroid closure
+                    int64_t idx = rbase_l[owner] + __popc(rmsk_l[owner] & ((1u << q) - 1u));
+                    idx = idx < 0 ? 0 : (idx < P.n_routed ? idx : P.n_routed - 1);
+                    float mb[3];
+#pragma unroll
+                    for (int b = 0; b < 3; b++) mb[b] = fmaxf(P.mlp_y[3 * idx + b], 0.f) * P.mlp_k;
+                    const float sm = (mb[0] + mb[1]) + mb[2];
+                    A.s0.add(sm);
+#pragma unroll
+                    for (int b = 0; b < 3; b++) A.s1[b].add(mb[b]);
+                    if (sm > 0.f) {
+                        const float is = 1.f / sm;
+                        const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                        for (int e = 0; e < 6; e++) A.s2[e].add(mb[jj[e]] * mb[ll[e]] * is);
+                    }
+                    c_learn++;
+                }
                 res[lane][0] = A.s0.s;
 #pragma unroll
                 for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t].s;
@@ -363,9 +450,9 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
             if (q < nq) s.add(sW[q][1 + a] * (float)R->out_lam[q][c] * msum[q]);
         Cxx[6 * (int64_t)k + lane] = s.s;
     }
-    unsigned long long v[5] = {c_whole, c_part, c_empty, c_sub, c_cap};
+    unsigned long long v[6] = {c_whole, c_part, c_empty, c_sub, c_cap, c_learn};
 #pragma unroll
-    for (int i = 0; i < 5; i++) {
+    for (int i = 0; i < 6; i++) {
         unsigned long long x = v[i];
         for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
         v[i] = x;
@@ -376,8 +463,69 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
         atomicAdd(&counters[2], v[2]);
         atomicAdd(&counters[4], v[3]);
         atomicAdd(&counters[5], v[4]);
+        if (LEARN) atomicAdd(&counters[3], v[5]);
     }
     __syncthreads();
+}
+
+// Routing pass of the learned caps, one wavefront per outer element, with the
+// pair kernel's classification and item order (pair, then outer point):
+// FILL = false counts the routed items of k, FILL = true writes their
+// network inputs (mlp_features) at the element's offset.
+template <int NQ, bool FILL>
+__global__ __launch_bounds__(64) void k_route(PairArgs P, int64_t *__restrict__ count, float *__restrict__ feat)
+{
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const int nq = P.R->n_out;
+    __shared__ double sX[NQ][2];
+    if (lane < nq) {
+        sX[lane][0] = P.xq[2 * ((int64_t)k * nq + lane)];
+        sX[lane][1] = P.xq[2 * ((int64_t)k * nq + lane) + 1];
+    }
+    __syncthreads();
+    const int64_t p0 = P.pair_ptr[k], p1 = P.pair_ptr[k + 1];
+    int64_t run = FILL ? P.route_off[k] : 0;
+    for (int64_t base = p0; base < p1; base += 64) {
+        const int64_t p = base + lane;
+        const bool act = p < p1 && !(P.near_flag && P.near_flag[p]);
+        double V[6] = {0, 0, 0, 0, 0, 0};
+        unsigned rmask = 0;
+        if (act) {
+            const int kp = P.pair_kp[p];
+            V[0] = P.E.vx0[kp]; V[1] = P.E.vy0[kp]; V[2] = P.E.vx1[kp];
+            V[3] = P.E.vy1[kp]; V[4] = P.E.vx2[kp]; V[5] = P.E.vy2[kp];
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                if (q >= nq) break;
+                const double xx = sX[q][0], xy = sX[q][1];
+                if (item_class(xx, xy, V, P.dd) == 2 && item_routed(xx, xy, V, P.delta, P.band)) rmask |= 1u << q;
+            }
+        }
+        const int rc = __popc(rmask);
+        int rp = rc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(rp, off, 64);
+            if (lane >= off) rp += v;
+        }
+        const int rtot = __shfl(rp, 63, 64);
+        if (FILL) {
+            int64_t o = run + rp - rc;
+            const int64_t o_end = P.route_off[k + 1];
+            unsigned mm = o + rc <= o_end ? rmask : 0u;
+            while (mm) {
+                const int q = __ffs(mm) - 1;
+                mm &= mm - 1;
+                float fv[6];
+                mlp_features(sX[q][0], sX[q][1], V, P.delta, fv);
+#pragma unroll
+                for (int i = 0; i < 6; i++) feat[6 * o + i] = fv[i];
+                o++;
+            }
+        }
+        run += rtot;
+    }
+    if (!FILL && lane == 0) count[k] = run;
 }
 
 template <int NQ, int FM, bool POW2>
@@ -701,7 +849,38 @@ PairArgs nla_pair_args(const nla_plan *P)
     A.Cxx = Cxx;
     A.max_cols = P->max_cols;
     A.counters = P->counters;
+    A.delta = pr.delta;
+    A.band = pr.fallback_band;
+    A.route_off = P->route_off;
+    A.n_routed = P->n_routed;
+    A.mlp_y = P->route_y;
+    A.mlp_k = P->mlp ? (float)(pr.kernel_c * pr.delta * pr.delta * (double)nla_mlp_scale(P->mlp)) : 0.f;
     return A;
+}
+
+// learned caps: routed items per outer element (geometry only, fixed per plan)
+int nla_build_routes(nla_plan *P, hipStream_t s)
+{
+    const int K = P->K;
+    NLA_TRY(P->arena.get(&P->route_off, (size_t)K + 1));
+    DeviceArena tmp;
+    int64_t *cnt;
+    NLA_TRY(tmp.get(&cnt, (size_t)K));
+    PairArgs A = nla_pair_args(P);
+    k_route<8, false><<<K, 64, 0, s>>>(A, cnt, nullptr);
+    NLA_HIP(hipGetLastError());
+    std::vector<int64_t> c((size_t)K), off((size_t)K + 1, 0);
+    NLA_HIP(hipMemcpyAsync(c.data(), cnt, sizeof(int64_t) * K, hipMemcpyDeviceToHost, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < K; k++) off[k + 1] = off[k] + c[k];
+    P->n_routed = off[K];
+    NLA_HIP(hipMemcpyAsync(P->route_off, off.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, s));
+    NLA_HIP(hipStreamSynchronize(s));
+    if (P->n_routed > 0) {
+        NLA_TRY(P->arena.get(&P->route_feat, 6 * (size_t)P->n_routed));
+        NLA_TRY(P->arena.get(&P->route_y, 3 * (size_t)P->n_routed));
+    }
+    return NLA_OK;
 }
 
 int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, hipStream_t))
@@ -714,13 +893,19 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     float *V = Cxx + 6 * (int64_t)K;
     float *Ce = V + 3 * P->n_cols;
     const bool frac = pr.kernel == NLA_KERNEL_FRACTIONAL;
-    const float kc = (float)pr.kernel_c;
-    const float ex = frac ? (float)(-(1.0 + pr.kernel_s)) : 0.f;
     const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
     const bool pow2 = (ncap & (ncap - 1)) == 0;
     const size_t lds = (size_t)P->max_cols * (6 * sizeof(float) + sizeof(int));
-    mark(P, NLA_PHASE_PAIRS, s);
+    const bool learn = pr.precision == NLA_FP32_LEARNED;
     PairArgs A = nla_pair_args(P);
+    mark(P, NLA_PHASE_MLP, s);
+    if (learn && P->n_routed > 0) {
+        k_route<8, true><<<K, 64, 0, s>>>(A, nullptr, P->route_feat);
+        NLA_HIP(hipGetLastError());
+        NLA_TRY(nla_mlp_infer_launch(P->mlp, P->route_feat, P->n_routed, P->route_y, s));
+        P->ran[NLA_PHASE_MLP] = true;
+    }
+    mark(P, NLA_PHASE_PAIRS, s);
 #define NLA_LAUNCH32(NQ, FR, P2) k_pairs_fp32<NQ, FR, P2><<<K, 64, lds, s>>>(A)
     if (P->rules.n_out > 8) {
         nla_set_error("the FP32 path supports outer rules of at most 8 points");
@@ -730,7 +915,9 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
         nla_set_error("the FP32 constant-kernel path needs a symmetric inner rule");
         return NLA_E_UNSUPPORTED;
     }
-    if (frac && pow2) NLA_LAUNCH32(8, 1, true);
+    if (learn && pow2) NLA_LAUNCH32(8, 3, true);
+    else if (learn) NLA_LAUNCH32(8, 3, false);
+    else if (frac && pow2) NLA_LAUNCH32(8, 1, true);
     else if (frac) NLA_LAUNCH32(8, 1, false);
     else if (pow2) NLA_LAUNCH32(8, 0, true);
     else NLA_LAUNCH32(8, 0, false);

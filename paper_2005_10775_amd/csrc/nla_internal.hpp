@@ -134,6 +134,12 @@ struct nla_plan {
     int32_t *n2e = nullptr;
     double *Gk = nullptr;       // [K][3]
     double *b = nullptr;        // [n_free]
+    // learned caps: routed items per outer element, their features and outputs
+    const nla_mlp *mlp = nullptr;
+    int64_t *route_off = nullptr;   // [K+1]
+    int64_t n_routed = 0;
+    float *route_feat = nullptr;    // [n_routed][6]
+    float *route_y = nullptr;       // [n_routed][3]
     // counters: whole, partial, empty, learned, subtriangles, caps
     unsigned long long *counters = nullptr;
     // phase timing: (NLA_NPHASE + 1) events per timed assembly
@@ -167,8 +173,20 @@ struct PairArgs {
     const uint16_t *colent;
     float *Rout, *Cyy, *Cxx;
     unsigned long long *counters;
+    // learned caps: routed partial items take the network's cap moments
+    double delta, band;
+    const int64_t *route_off;   // [K+1] first routed item of each outer element
+    int64_t n_routed;
+    const float *mlp_y;         // [n_routed][3] network outputs
+    float mlp_k;                // kc delta^2 scale
 };
 PairArgs nla_pair_args(const nla_plan *P);
+
+// learned cap corrector (nla_mlp.hip)
+struct nla_mlp;
+int nla_mlp_infer_launch(const nla_mlp *M, const float *feat, int64_t n, float *out, hipStream_t s);
+float nla_mlp_scale(const nla_mlp *M);
+int nla_build_routes(nla_plan *P, hipStream_t s);
 
 // translation-unit entry points
 int nla_build_pairs(nla_plan *P, hipStream_t s);

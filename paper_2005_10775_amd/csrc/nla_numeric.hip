@@ -383,6 +383,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         double *Cxx = Cyy + 6 * NP;
         double *V = Cxx + 6 * (int64_t)K;          // [R (3 n_cols) | E (6K)]: the values the codes index
         double *Ce = V + 3 * P->n_cols;
+        nla_mark(P, NLA_PHASE_MLP, s);
         nla_mark(P, NLA_PHASE_PAIRS, s);
         const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
         const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;

@@ -110,8 +110,16 @@ static int validate(const nla_mesh *m, const nla_problem *p)
         return NLA_E_INVALID;
     }
     if (p->precision == NLA_FP32_LEARNED) {
-        nla_set_error("learned caps are not available in this build");
-        return NLA_E_UNSUPPORTED;
+        if (!p->mlp) { nla_set_error("learned caps need a network (nla_problem.mlp)"); return NLA_E_INVALID; }
+        if (!(p->fallback_band >= 0.0) || !std::isfinite(p->fallback_band)) {
+            nla_set_error("fallback_band must be finite and >= 0");
+            return NLA_E_INVALID;
+        }
+        if (p->kernel != NLA_KERNEL_CONSTANT || p->ball != NLA_BALL_RETRI || p->cap_edges < 2) {
+            nla_set_error("learned caps replace the arc-subdivided caps of the intersection ball under the constant "
+                          "kernel (kernel 0, ball 1, cap_edges >= 2)");
+            return NLA_E_UNSUPPORTED;
+        }
     }
     if (p->kernel == NLA_KERNEL_FRACTIONAL && p->precision == NLA_FP64) {
         nla_set_error("the fractional kernel is assembled in NLA_FP32 (FP64 geometry and near pairs)");
@@ -1173,6 +1181,10 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
     NLA_TRY(nla_build_pairs(P, s));
     NLA_TRY(nla_build_pattern(P, s));
     NLA_TRY(P->arena.get(&P->counters, 6));
+    if (p->precision == NLA_FP32_LEARNED) {
+        P->mlp = (const nla_mlp *)p->mlp;
+        NLA_TRY(nla_build_routes(P, s));
+    }
     return NLA_OK;
 }
 

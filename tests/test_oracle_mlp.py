@@ -125,10 +125,15 @@ def test_cap_label_two_caps_and_scaling():
 
 def test_candidates_are_partial_routed_items():
     U = cap_uniforms(20052, 0, 400)
-    valid, feat, lab = ob.cap_candidates(U, 0.125, 0.1, 0.02)
+    valid, feat, lab, verts = ob.cap_candidates(U, 0.125, 0.1, 0.02)
     assert 0.1 < valid.mean() < 0.4
-    for f, l in zip(feat[valid][:40], lab[valid][:40]):
-        V = f.reshape(3, 2)
+    for f, l, v in zip(feat[valid][:40], lab[valid][:40], verts[valid][:40]):
+        V = v.reshape(3, 2)
+        # the network input is the rotated, shifted, magnified frame: the
+        # centroid on the first axis, distances to x preserved
+        F = f.reshape(3, 2) / 8.0 + np.array([1.0, 0.0])
+        assert abs(F[:, 1].sum()) < 1e-12 and F[:, 0].sum() > 0
+        assert np.allclose(np.hypot(F[:, 0], F[:, 1]), np.hypot(V[:, 0], V[:, 1]), atol=1e-14)
         r = np.hypot(V[:, 0], V[:, 1])
         assert (r > 1).any()                 # not whole
         assert np.min(np.abs(r - 1)) >= 0.02
@@ -155,3 +160,21 @@ def test_learned_band_infinite_is_the_exact_path():
     # band 0 routes every partial item: the matrix changes
     c = ob.assemble(ob.OracleProblem(mesh, replace(p, precision="learned", fallback_band=0.0), mlp_w=w))
     assert np.array_equal(a["col"], c["col"]) and not np.array_equal(a["val"], c["val"])
+
+
+def test_features_rotation_invariant():
+    """Rotating and translating the configuration about x leaves the network
+    input unchanged; the cap labels are invariant too."""
+    rng = np.random.default_rng(8)
+    V = np.array([[0.93, 0.11], [1.05, 0.14], [0.97, 0.24]])
+    f0 = ob.mlp_features([0.0, 0.0], V, 1.0)
+    n0, m0 = ob.cap_moments(1.0, [0.0, 0.0], V, 8)
+    for _ in range(5):
+        t = rng.uniform(0, 2 * np.pi)
+        R = np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]])
+        x0 = rng.uniform(-1, 1, 2)
+        d = 0.05
+        W = x0 + d * V @ R.T
+        assert np.allclose(ob.mlp_features(x0, W, d), f0, atol=1e-11)
+        n1, m1 = ob.cap_moments(d, x0, W, 8)
+        assert n1 == n0 and np.allclose(m1 / d ** 2, m0, rtol=1e-9)
