@@ -24,9 +24,18 @@ struct KahanF {
     }
 };
 
-// item sums (S0, S1[3], S2[6]) in FP32, compensated over subtriangles
+// plain FP32 sum with the KahanF interface (short sums)
+struct PlainF {
+    float s;
+    __device__ __forceinline__ void zero() { s = 0.f; }
+    __device__ __forceinline__ void add(float v) { s += v; }
+};
+
+// item sums (S0, S1[3], S2[6]) in FP32 over the item's subtriangles (a dozen
+// terms at most, so plain: ~1e-6 relative); compensation starts at the sums
+// over items, pairs and matrix contributions, which run over thousands of terms
 struct AccF {
-    KahanF s0, s1[3], s2[6];
+    PlainF s0, s1[3], s2[6];
     __device__ __forceinline__ void zero()
     {
         s0.zero();
@@ -303,37 +312,50 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
 #pragma unroll
             for (int e = 0; e < 6; e++) ayy[e].add(ws * ka * (o + (jj[e] == ll[e] ? dm : 0.f)));
         }
-        const int cnt = __popc(pmask);
+        // queue: items with arc-subdivided caps first, then (learned) routed
+        // items, each in (pair, q) order, so that a batch of 64 is uniform
+        const unsigned emask = pmask & ~rmask;
+        const int cnt = __popc(emask);
         int pre = cnt;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int v = __shfl_up(pre, off, 64);
             if (lane >= off) pre += v;
         }
-        const int total = __shfl(pre, 63, 64);
+        const int totE = __shfl(pre, 63, 64);
         pre -= cnt;
-        {
-            int oo = pre;
-            unsigned mm = pmask;
-            while (mm) {
-                const int q = __ffs(mm) - 1;
-                mm &= mm - 1;
-                queue[oo++] = (unsigned short)((lane << 8) | q);
-            }
-        }
+        int cntR = 0, preR = 0, totR = 0;
         if (LEARN) {
             // routed items in (pair, q) order: the same order as the routing pass
-            const int rc = __popc(rmask);
-            int rp = rc;
+            cntR = __popc(rmask);
+            int rp = cntR;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const int v = __shfl_up(rp, off, 64);
                 if (lane >= off) rp += v;
             }
-            const int rtot = __shfl(rp, 63, 64);
-            rbase_l[lane] = rrun + rp - rc;
+            totR = __shfl(rp, 63, 64);
+            preR = rp - cntR;
+            rbase_l[lane] = rrun + preR;
             rmsk_l[lane] = rmask;
-            rrun += rtot;
+            rrun += totR;
+        }
+        const int total = totE + totR;
+        {
+            int oo = pre;
+            unsigned mm = emask;
+            while (mm) {
+                const int q = __ffs(mm) - 1;
+                mm &= mm - 1;
+                queue[oo++] = (unsigned short)((lane << 8) | q);
+            }
+            oo = totE + preR;
+            mm = LEARN ? rmask : 0u;
+            while (mm) {
+                const int q = __ffs(mm) - 1;
+                mm &= mm - 1;
+                queue[oo++] = (unsigned short)((lane << 8) | q);
+            }
         }
         __syncthreads();
         for (int ib = 0; ib < total; ib += 64) {
@@ -344,30 +366,12 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
                 A.zero();
                 TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC};
                 int ns = 0;
-                const bool routed = LEARN && P.n_routed > 0 && ((rmsk_l[owner] >> q) & 1u);
+                // routed items: the inscribed polygon only here; the owner adds the
+                // network's cap moments when it collects the result
+                const bool routed = LEARN && i >= totE;
                 partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, tri, ns);
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
-                if (routed) {
-                    // the polygon above plus the network's cap moments m_b (units of
-                    // kc delta^2 scale), second moments by the one-point centroid closure
-                    int64_t idx = rbase_l[owner] + __popc(rmsk_l[owner] & ((1u << q) - 1u));
-                    idx = idx < 0 ? 0 : (idx < P.n_routed ? idx : P.n_routed - 1);
-                    float mb[3];
-#pragma unroll
-                    for (int b = 0; b < 3; b++) mb[b] = fmaxf(P.mlp_y[3 * idx + b], 0.f) * P.mlp_k;
-                    const float sm = (mb[0] + mb[1]) + mb[2];
-                    A.s0.add(sm);
-#pragma unroll
-                    for (int b = 0; b < 3; b++) A.s1[b].add(mb[b]);
-                    if (sm > 0.f) {
-                        const float is = 1.f / sm;
-                        const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-                        for (int e = 0; e < 6; e++) A.s2[e].add(mb[jj[e]] * mb[ll[e]] * is);
-                    }
-                    c_learn++;
-                }
                 res[lane][0] = A.s0.s;
 #pragma unroll
                 for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t].s;
@@ -375,20 +379,47 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
                 for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t].s;
             }
             __syncthreads();
-            const int j0 = pre > ib ? pre : ib;
-            const int j1 = (pre + cnt) < (ib + 64) ? (pre + cnt) : (ib + 64);
-            for (int j = j0; j < j1; j++) {
-                const int q = queue[j] & 0xff;
-                const float *r = res[j - ib];
+            // each lane adds its own items of this batch: its cap segment, then its routed one
 #pragma unroll
-                for (int qq = 0; qq < NQ; qq++)
-                    if (qq == q) m0[qq].add(r[0]);
+            for (int seg = 0; seg < (LEARN ? 2 : 1); seg++) {
+                const int s0 = seg == 0 ? pre : totE + preR, s1 = s0 + (seg == 0 ? cnt : cntR);
+                const int j0 = s0 > ib ? s0 : ib;
+                const int j1 = s1 < (ib + 64) ? s1 : (ib + 64);
+                for (int j = j0; j < j1; j++) {
+                    const int q = queue[j] & 0xff;
+                    float r[10];
 #pragma unroll
-                for (int a = 0; a < 3; a++)
+                    for (int t = 0; t < 10; t++) r[t] = res[j - ib][t];
+                    if (LEARN && seg == 1) {
+                        // polygon sums plus the network's cap moments m_b (units of kc
+                        // delta^2 scale); second moments by the one-point centroid closure
+                        int64_t idx = rbase_l[lane] + __popc(rmask & ((1u << q) - 1u));
+                        idx = idx < 0 ? 0 : (idx < P.n_routed ? idx : P.n_routed - 1);
+                        float mb[3];
 #pragma unroll
-                    for (int b = 0; b < 3; b++) axy[3 * a + b].add(sW[q][1 + a] * r[1 + b]);
+                        for (int b = 0; b < 3; b++) mb[b] = fmaxf(P.mlp_y[3 * idx + b], 0.f) * P.mlp_k;
+                        const float sm = (mb[0] + mb[1]) + mb[2];
+                        r[0] += sm;
 #pragma unroll
-                for (int t = 0; t < 6; t++) ayy[t].add(sW[q][0] * r[4 + t]);
+                        for (int b = 0; b < 3; b++) r[1 + b] += mb[b];
+                        if (sm > 0.f) {
+                            const float is = 1.f / sm;
+                            const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                            for (int e = 0; e < 6; e++) r[4 + e] += mb[jj[e]] * mb[ll[e]] * is;
+                        }
+                        c_learn++;
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < NQ; qq++)
+                        if (qq == q) m0[qq].add(r[0]);
+#pragma unroll
+                    for (int a = 0; a < 3; a++)
+#pragma unroll
+                        for (int b = 0; b < 3; b++) axy[3 * a + b].add(sW[q][1 + a] * r[1 + b]);
+#pragma unroll
+                    for (int t = 0; t < 6; t++) ayy[t].add(sW[q][0] * r[4 + t]);
+                }
             }
             __syncthreads();
         }
@@ -557,7 +588,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
         const int end = base + chunk < n_work ? base + chunk : n_work;
         for (int j = base; j < end; j++) {
             const int2 w = work[j];
-            pairs_fp32_body<NQ, 2, POW2>(inst[w.x], w.y, dyn);
+            // the bodies of the single-plan kernels, so that both give the same bits
+            if (inst[w.x].frac) pairs_fp32_body<NQ, 1, POW2>(inst[w.x], w.y, dyn);
+            else pairs_fp32_body<NQ, 0, POW2>(inst[w.x], w.y, dyn);
         }
     }
 }
