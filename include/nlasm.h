@@ -176,7 +176,11 @@ int nla_blocks_view(const nla_plan *plan, const void **myy, const void **mxx, co
  * pair indices near_pair [n_near] (int64, ascending) and merged 6x6 blocks
  * blocks [n_near][21] (upper triangle, row-major over the slots a0,a1,a2,b0,b1,b2;
  * a slot of E_k' whose node is also a node of E_k is merged into E_k's slot and
- * holds zeros), dtype as in nla_csr_view; device views. */
+ * holds zeros), dtype as in nla_csr_view; device views.  The joint integrand
+ * of such a pair is symmetric under x <-> y, so a pair (k, k') with k > k'
+ * whose mirror (k', k) interacts is not integrated: the assembly reads the
+ * mirror's block with the nodes relabelled.  This call writes those relabelled
+ * blocks into the view (it synchronises the device). */
 int nla_near_view(const nla_plan *plan, int64_t *n_near, const int64_t **near_pair, const void **blocks,
                   int32_t *dtype);
 
@@ -211,7 +215,7 @@ void nla_plan_destroy(nla_plan *plan);
 typedef struct nla_batch nla_batch;
 typedef struct {
     int32_t n;                   /* instances */
-    int64_t total_pairs, total_elements, total_near;
+    int64_t total_pairs, total_elements, total_near;   /* total_near: singular-pair blocks integrated */
     int32_t chunk;               /* work items taken per cursor fetch */
     int32_t grid;                /* wavefronts of the persistent launch */
 } nla_batch_summary;

@@ -418,7 +418,34 @@ int nlo_pair_block(const nlo_mesh *m, const nlo_problem *p, int32_t k, int32_t k
     barycenter(Vkp, bkp);
     for (int i = 0; i < 9; i++) { mxy[i] = 0.0; myy[i] = 0.0; }
     for (int i = 0; i < 36; i++) blk[i] = 0.0;
-    if (p->kernel == 1 && shares_vertex(m, k, kp)) return nlo_duffy_block(m, p, k, kp, blk);
+    if (p->kernel == 1 && shares_vertex(m, k, kp)) {
+        /* The joint integrand (phi_n(x) - phi_n(y))(phi_m(x) - phi_m(y)) psi over
+         * {x in E_k, y in E_k', |x - y| <= delta} is symmetric under x <-> y, so
+         * the node-level block of (k', k) is that of (k, k').  It is computed for
+         * k <= k' (or when (k', k) is not an interacting pair) and relabelled. */
+        if (k > kp && pair_interacts(p, Vkp, bkp, Vk, bk)) {
+            double bt[36];
+            int st = nlo_duffy_block(m, p, kp, k, bt);
+            if (st < 0) return st;
+            int sl[6], slt[6];          /* slot of node n in (k, k') and in (k', k) order */
+            for (int i = 0; i < 6; i++) {
+                int n = i < 3 ? m->tri[3 * k + i] : m->tri[3 * kp + i - 3];
+                sl[i] = -1;
+                for (int a = 0; a < 3; a++)
+                    if (m->tri[3 * kp + a] == n) sl[i] = a;
+                if (sl[i] < 0)
+                    for (int a = 0; a < 3; a++)
+                        if (m->tri[3 * k + a] == n) sl[i] = 3 + a;
+                /* merged slot of (k, k'): a node of E_k' that is also in E_k */
+                slt[i] = i >= 3 && (m->tri[3 * k] == n || m->tri[3 * k + 1] == n || m->tri[3 * k + 2] == n);
+            }
+            for (int i = 0; i < 6; i++)
+                for (int j = 0; j < 6; j++)
+                    blk[6 * i + j] = (slt[i] || slt[j]) ? 0.0 : bt[6 * sl[i] + sl[j]];
+            return 0;
+        }
+        return nlo_duffy_block(m, p, k, kp, blk);
+    }
     int nq;
     const double *lam, *w;
     pair_rule(p, bk, bkp, &nq, &lam, &w);

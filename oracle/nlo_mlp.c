@@ -165,16 +165,19 @@ void nlo_mlp_features(const double x[2], const double V[6], double delta, double
     }
 }
 
-/* learned routing: far enough from tangency, min_a | |v_a - x| - delta | >= band delta */
+/* learned routing: far enough from tangency, | |v_a - x| - delta | >= band delta
+ * for every vertex, i.e. |v_a - x|^2 >= (delta (1 + band))^2 or
+ * |v_a - x|^2 <= (delta (1 - band))^2 (no square root) */
 int nlo_routed(double delta, double band, const double x[2], const double V[6])
 {
-    double mn = 1e300;
+    double hi = delta * (1.0 + band), lo = band < 1.0 ? delta * (1.0 - band) : 0.0;
+    double hi2 = hi * hi, lo2 = lo * lo;
     for (int a = 0; a < 3; a++) {
         double dx = V[2 * a] - x[0], dy = V[2 * a + 1] - x[1];
-        double d = fabs(sqrt(dx * dx + dy * dy) - delta);
-        if (d < mn) mn = d;
+        double d2 = dx * dx + dy * dy;
+        if (!(d2 >= hi2 || d2 <= lo2)) return 0;
     }
-    return mn >= band * delta;
+    return 1;
 }
 
 /* the learned cap contribution of a routed partial item (constant kernel) */

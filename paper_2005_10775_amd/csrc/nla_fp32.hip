@@ -149,18 +149,22 @@ __device__ __forceinline__ int item_class(double xx, double xy, const double (&V
     return 0;
 }
 
-// learned caps: a partial item far from tangency, min_a | |v_a - x| - delta | >= band delta
+// learned caps: a partial item far from tangency, | |v_a - x| - delta | >= band delta
+// for every vertex, tested as |v_a - x|^2 >= (delta (1 + band))^2 or
+// |v_a - x|^2 <= (delta (1 - band))^2
 __device__ __forceinline__ bool item_routed(double xx, double xy, const double (&V)[6], double delta, double band)
 {
 #pragma clang fp contract(off)
-    double mn = 1e300;
+    const double hi = delta * (1.0 + band), lo = band < 1.0 ? delta * (1.0 - band) : 0.0;
+    const double hi2 = hi * hi, lo2 = lo * lo;
+    bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
-        const double d = fabs(sqrt(dx * dx + dy * dy) - delta);
-        mn = d < mn ? d : mn;
+        const double d2 = dx * dx + dy * dy;
+        ok = ok && (d2 >= hi2 || d2 <= lo2);
     }
-    return mn >= band * delta;
+    return ok;
 }
 
 // One wavefront per outer element k, FP32 sums (structure as the FP64 kernel):
@@ -774,14 +778,16 @@ __device__ void near_body(const int64_t i, const int64_t *__restrict__ near_pair
     }
 }
 
+// one wavefront per computed near pair (the mirrored ones read their partner's block)
 template <class T>
-__global__ __launch_bounds__(64) void k_near(int64_t n_near, const int64_t *__restrict__ near_pair,
+__global__ __launch_bounds__(64) void k_near(int64_t n_comp, const int64_t *__restrict__ comp,
+                                             const int64_t *__restrict__ near_pair,
                                              const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp,
                                              const int32_t *__restrict__ tri, ElemSoA E, const RuleSet *__restrict__ R,
                                              double delta, double kc, double ks, T *__restrict__ out)
 {
-    if ((int64_t)blockIdx.x >= n_near) return;
-    near_body<T>(blockIdx.x, near_pair, pk, pkp, tri, E, R, delta, kc, ks, out);
+    if ((int64_t)blockIdx.x >= n_comp) return;
+    near_body<T>(comp[blockIdx.x], near_pair, pk, pkp, tri, E, R, delta, kc, ks, out);
 }
 
 // E(k') = Mxx(k') + sum_k Myy(k, k') in FP32 with compensation (lane-strided
@@ -958,10 +964,10 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     NLA_HIP(hipGetLastError());
     P->ran[NLA_PHASE_PAIRS] = true;
     mark(P, NLA_PHASE_NEAR, s);
-    if (P->n_near > 0) {
-        k_near<float><<<(unsigned)P->n_near, 64, 0, s>>>(P->n_near, P->near_pair, P->pair_k, P->pair_kp, P->tri, P->E,
-                                                         P->d_rules, pr.delta, pr.kernel_c, pr.kernel_s,
-                                                         (float *)P->near_blk);
+    if (P->n_near_comp > 0) {
+        k_near<float><<<(unsigned)P->n_near_comp, 64, 0, s>>>(P->n_near_comp, P->near_comp, P->near_pair, P->pair_k,
+                                                              P->pair_kp, P->tri, P->E, P->d_rules, pr.delta,
+                                                              pr.kernel_c, pr.kernel_s, (float *)P->near_blk);
         NLA_HIP(hipGetLastError());
         P->ran[NLA_PHASE_NEAR] = true;
     }
@@ -987,7 +993,7 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
 struct BatchInst {
     // near pairs
     int64_t n_near;
-    const int64_t *near_pair;
+    const int64_t *near_pair, *near_comp;
     const int32_t *pair_k, *pair_kp, *tri;
     ElemSoA E;
     const RuleSet *R;
@@ -1041,7 +1047,8 @@ __global__ __launch_bounds__(64) void k_batch_near(int n, const BatchInst *__res
     const int64_t g = blockIdx.x;
     const int t = inst_of(off, n, g);
     const BatchInst &I = B[t];
-    near_body<float>(g - off[t], I.near_pair, I.pair_k, I.pair_kp, I.tri, I.E, I.R, I.delta, I.kc, I.ks, I.near_blk);
+    near_body<float>(I.near_comp[g - off[t]], I.near_pair, I.pair_k, I.pair_kp, I.tri, I.E, I.R, I.delta, I.kc, I.ks,
+                     I.near_blk);
 }
 
 __global__ __launch_bounds__(64) void k_batch_elem(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off)
@@ -1230,7 +1237,7 @@ static int batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *pr
         args[i] = nla_pair_args(P);
         BatchInst &I = B->h_inst[i];
         memset(&I, 0, sizeof(I));
-        I.n_near = P->n_near; I.near_pair = P->near_pair; I.pair_k = P->pair_k; I.pair_kp = P->pair_kp; I.tri = P->tri;
+        I.n_near = P->n_near; I.near_pair = P->near_pair; I.near_comp = P->near_comp; I.pair_k = P->pair_k; I.pair_kp = P->pair_kp; I.tri = P->tri;
         I.E = P->E; I.R = P->d_rules; I.delta = P->prob.delta; I.kc = P->prob.kernel_c; I.ks = P->prob.kernel_s;
         I.near_blk = (float *)P->near_blk;
         I.K = P->K; I.tptr = P->tptr; I.tperm = P->tperm;
@@ -1241,7 +1248,7 @@ static int batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *pr
         I.tin = P->tin; I.Gk = P->Gk; I.b = P->b; I.n_free = P->n_free; I.free_nodes = P->free_nodes;
         I.n2e_ptr = P->n2e_ptr; I.n2e = P->n2e; I.col = P->col; I.n2f = P->node_to_free; I.rowptr = P->rowptr;
         I.counters = P->counters;
-        on[i + 1] = on[i] + P->n_near;
+        on[i + 1] = on[i] + P->n_near_comp;
         ok[i + 1] = ok[i] + P->K;
         ou[i + 1] = ou[i] + P->n_up;
         oa[i + 1] = oa[i] + P->nnz_free;

@@ -116,6 +116,9 @@ struct nla_plan {
     int64_t n_ncodes = 0;
     int64_t *nup_ptr = nullptr;     // [n_up+1]
     int32_t *ncodes = nullptr;      // [n_ncodes] indices into the near-block array
+    int64_t n_near_comp = 0;        // near pairs whose block is computed (the others mirror a partner)
+    int64_t *near_comp = nullptr;   // [n_near_comp] their near indices
+    int64_t *near_partner = nullptr;// [n_near] near index of the mirror partner, or -1
     void *near_blk = nullptr;       // [n_near][21]
     // contributions and values
     int64_t n_contrib = 0;      // 6P (Myy) + 6K (Mxx) + 6K (element blocks) + 3 n_cols (R) + 21 n_near

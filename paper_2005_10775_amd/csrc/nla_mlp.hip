@@ -90,6 +90,7 @@ struct TrainBuf {
     float *dz1;      // [Bp][128]
     float *dz2f;     // [Bp][128]
     __bf16 *dz2t;    // [128][Bp]
+    float *part;     // [Bp/64][1412] chunk sums of the reduction
 };
 
 __global__ void k_mlp_refresh(const float *__restrict__ w, __bf16 *__restrict__ w2, __bf16 *__restrict__ w2t,
@@ -323,37 +324,45 @@ __global__ __launch_bounds__(256) void k_mlp_dw2(TrainBuf T, float *__restrict__
     }
 }
 
-// the remaining gradients (dW1, b1, b2, dW3, b3) and the batch loss, one
-// thread per value, summed over the batch in position order
-__global__ void k_mlp_reduce(TrainBuf T, float *__restrict__ g, float *__restrict__ loss_out)
+// the remaining gradients (dW1, b1, b2, dW3, b3) and the batch loss: each
+// block sums a chunk of RCH batch positions for all 1412 values (threads over
+// values, so reads of a position's row are coalesced), then the chunks are
+// added in chunk order
+constexpr int RCH = 64, NRED = 1412;
+
+__device__ __forceinline__ float red_term(const TrainBuf &T, int r, int64_t p)
+{
+    if (r < 768) return T.dz1[p * H + r / 6] * T.fpos[p * 6 + r % 6];
+    if (r < 896) return T.dz1[p * H + (r - 768)];
+    if (r < 1024) return T.dz2f[p * H + (r - 896)];
+    if (r < 1408) return T.dy[p * 3 + (r - 1024) / H] * T.h2[p * H + (r - 1024) % H];
+    if (r < 1411) return T.dy[p * 3 + (r - 1408)];
+    return T.sq[p];
+}
+
+__global__ __launch_bounds__(256) void k_mlp_reduce_part(TrainBuf T, float *__restrict__ part)
+{
+    const int64_t p0 = (int64_t)blockIdx.x * RCH;
+    for (int r = threadIdx.x; r < NRED; r += blockDim.x) {
+        float s = 0.f;
+        for (int i = 0; i < RCH; i++) s += red_term(T, r, p0 + i);
+        part[(int64_t)blockIdx.x * NRED + r] = s;
+    }
+}
+
+__global__ void k_mlp_reduce_final(int nchunk, const float *__restrict__ part, float *__restrict__ g,
+                                   float *__restrict__ loss_out)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t Bp = T.Bp;
+    if (r >= NRED) return;
     float s = 0.f;
-    if (r < 768) {
-        const int h = r / 6, c = r % 6;
-        for (int64_t p = 0; p < Bp; p++) s += T.dz1[p * H + h] * T.fpos[p * 6 + c];
-        g[OW1 + r] = s;
-    } else if (r < 896) {
-        const int h = r - 768;
-        for (int64_t p = 0; p < Bp; p++) s += T.dz1[p * H + h];
-        g[OB1 + h] = s;
-    } else if (r < 1024) {
-        const int o = r - 896;
-        for (int64_t p = 0; p < Bp; p++) s += T.dz2f[p * H + o];
-        g[OB2 + o] = s;
-    } else if (r < 1408) {
-        const int c = (r - 1024) / H, k = (r - 1024) % H;
-        for (int64_t p = 0; p < Bp; p++) s += T.dy[p * 3 + c] * T.h2[p * H + k];
-        g[OW3 + c * H + k] = s;
-    } else if (r < 1411) {
-        const int c = r - 1408;
-        for (int64_t p = 0; p < Bp; p++) s += T.dy[p * 3 + c];
-        g[OB3 + c] = s;
-    } else if (r == 1411 && loss_out) {
-        for (int64_t p = 0; p < Bp; p++) s += T.sq[p];
-        *loss_out = s;
-    }
+    for (int c = 0; c < nchunk; c++) s += part[(int64_t)c * NRED + r];
+    if (r < 768) g[OW1 + r] = s;
+    else if (r < 896) g[OB1 + (r - 768)] = s;
+    else if (r < 1024) g[OB2 + (r - 896)] = s;
+    else if (r < 1408) g[OW3 + (r - 1024)] = s;
+    else if (r < 1411) g[OB3 + (r - 1408)] = s;
+    else if (loss_out) *loss_out = s;
 }
 
 __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
@@ -434,12 +443,14 @@ __global__ void k_cap_samples(int64_t n, uint64_t seed, int64_t first, double L,
     LabelF fa{mall}, fp{mpoly};
     partial_item<POW2>(0.0, 0.0, V, 1.0, ncap, fa, ns);
     partial_item<POW2>(0.0, 0.0, V, 1.0, 0, fp, ns0);
-    double mn = 1e300;
+    // every vertex at least band from the circle: |v|^2 >= (1 + band)^2 or |v|^2 <= (1 - band)^2
+    const double hi = 1.0 + band, lo = band < 1.0 ? 1.0 - band : 0.0;
+    bool far = true;
     for (int a = 0; a < 3; a++) {
-        const double d = fabs(sqrt(V[2 * a] * V[2 * a] + V[2 * a + 1] * V[2 * a + 1]) - 1.0);
-        mn = d < mn ? d : mn;
+        const double d2 = V[2 * a] * V[2 * a] + V[2 * a + 1] * V[2 * a + 1];
+        far = far && (d2 >= hi * hi || d2 <= lo * lo);
     }
-    const bool valid = (ns >> 16) > 0 && mn >= band;
+    const bool valid = (ns >> 16) > 0 && far;
     float fv[6];
     mlp_features(0.0, 0.0, V, 1.0, fv);
     for (int i = 0; i < 6; i++) feat[c * 6 + i] = fv[i];
@@ -498,6 +509,7 @@ static int mlp_scratch(nla_mlp *M, int64_t Bp, int64_t nloss)
     NLA_TRY(A.get(&T.dz1, H * Bp));
     NLA_TRY(A.get(&T.dz2f, H * Bp));
     NLA_TRY(A.get(&T.dz2t, H * Bp));
+    NLA_TRY(A.get(&T.part, (Bp / 64) * 1412));
     M->loss_cap = nloss > 1 ? nloss : 1;
     NLA_TRY(A.get(&M->lossb, M->loss_cap));
     return NLA_OK;
@@ -522,7 +534,9 @@ static int mlp_grad(nla_mlp *M, int mode, int64_t nB, const float *feat, const f
         k_mlp_fwd<2><<<fwd_grid(tiles), 256, 0, s>>>(nB, feat, label, dout, W, inv, gcoef, pa, pb, base, n_total, nullptr, M->T);
     k_mlp_bwd<<<fwd_grid(tiles), 256, 0, s>>>(W, M->T);
     k_mlp_dw2<<<16, 256, 0, s>>>(M->T, M->g);
-    k_mlp_reduce<<<grid_for(1412, 64), 64, 0, s>>>(M->T, M->g, loss_slot);
+    const int nchunk = (int)(M->T.Bp / RCH);
+    k_mlp_reduce_part<<<nchunk, 256, 0, s>>>(M->T, M->T.part);
+    k_mlp_reduce_final<<<grid_for(NRED, 256), 256, 0, s>>>(nchunk, M->T.part, M->g, loss_slot);
     NLA_HIP(hipGetLastError());
     return NLA_OK;
 }

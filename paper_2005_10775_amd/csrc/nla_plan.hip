@@ -650,19 +650,54 @@ __device__ __forceinline__ int upper_slot(int i, int j)
     return a * 6 - (a * (a - 1)) / 2 + (b - a);
 }
 
+// Mirror partner of a vertex-sharing pair (k, k') with k > k': the near index
+// of (k', k) when that pair interacts (its block is the same node-level
+// matrix: the joint integrand is symmetric under x <-> y), else -1 (computed).
+__global__ void k_near_partner(int64_t n_near, const int64_t *__restrict__ near_pair,
+                               const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp,
+                               const int64_t *__restrict__ pair_ptr, int64_t *__restrict__ partner)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_near) return;
+    const int64_t p = near_pair[i];
+    const int k = pk[p], kp = pkp[p];
+    int64_t res = -1;
+    if (k > kp) {
+        int64_t lo = pair_ptr[kp], hi = pair_ptr[kp + 1];     // k' row, k'' ascending
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (pkp[mid] < k) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < pair_ptr[kp + 1] && pkp[lo] == k) {
+            int64_t a = 0, b = n_near;                      // near_pair is ascending
+            while (a < b) {
+                const int64_t mid = (a + b) >> 1;
+                if (near_pair[mid] < lo) a = mid + 1;
+                else b = mid;
+            }
+            if (a < n_near && near_pair[a] == lo) res = a;
+        }
+    }
+    partner[i] = res;
+}
+
 // 36 slots per near pair: ordered slot pairs (I, J) whose nodes satisfy
 // node(I) <= node(J) (the mirror goes to the lower triangle), merged-away
 // slots (a node of E_k' that is also a node of E_k) excluded
 __global__ void k_near_codes(int64_t n_near, int J, const int64_t *__restrict__ near_pair,
                              const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
                              const int32_t *__restrict__ pkp, const uint64_t *__restrict__ uk, int64_t nnz,
-                             const int64_t *__restrict__ up_of, uint32_t sentinel, uint32_t *__restrict__ key,
-                             int32_t *__restrict__ code)
+                             const int64_t *__restrict__ up_of, uint32_t sentinel, const int64_t *__restrict__ partner,
+                             uint32_t *__restrict__ key, int32_t *__restrict__ code)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_near) return;
     const int64_t p = near_pair[i];
     const int k = pk[p], kp = pkp[p];
+    // a mirrored pair reads its partner's block: slot of each node in (k', k) order
+    const int64_t src = partner[i] >= 0 ? partner[i] : i;
+    int ps[6];
     int g[6];
     bool valid[6];
     for (int a = 0; a < 3; a++) {
@@ -675,12 +710,23 @@ __global__ void k_near_codes(int64_t n_near, int J, const int64_t *__restrict__ 
         for (int a = 0; a < 3; a++)
             if (g[3 + b] == g[a]) valid[3 + b] = false;
     }
+    for (int I = 0; I < 6; I++) {
+        ps[I] = I;
+        if (src != i) {
+            ps[I] = -1;
+            for (int a = 0; a < 3; a++)
+                if (tri[3 * kp + a] == g[I]) ps[I] = a;
+            if (ps[I] < 0)
+                for (int a = 0; a < 3; a++)
+                    if (tri[3 * k + a] == g[I]) ps[I] = 3 + a;
+        }
+    }
     for (int I = 0; I < 6; I++)
         for (int Jj = 0; Jj < 6; Jj++) {
             const int64_t s = 36 * i + 6 * I + Jj;
             if (valid[I] && valid[Jj] && g[I] <= g[Jj] && (g[I] < g[Jj] || I == Jj)) {
                 key[s] = upper_of(uk, nnz, up_of, J, g[I], g[Jj]);
-                code[s] = (int32_t)(21 * i + upper_slot(I, Jj));
+                code[s] = (int32_t)(21 * src + upper_slot(ps[I], ps[Jj]));
             } else {
                 key[s] = sentinel;
                 code[s] = -1;
@@ -1005,8 +1051,26 @@ int nla_build_pattern(nla_plan *P, hipStream_t s)
         NLA_TRY(S.get(&nv, ns));
         NLA_TRY(S.get(&snv, ns));
         const uint32_t nsent = (uint32_t)P->n_up;
+        int64_t *partner;
+        NLA_TRY(P->arena.get(&partner, P->n_near));
+        P->near_partner = partner;
+        k_near_partner<<<grid_for(P->n_near, 256), 256, 0, s>>>(P->n_near, P->near_pair, P->pair_k, P->pair_kp,
+                                                               P->pair_ptr, partner);
+        {
+            // the blocks computed: near pairs without a mirror partner
+            std::vector<int64_t> hp(P->n_near), cl;
+            NLA_HIP(hipMemcpyAsync(hp.data(), partner, sizeof(int64_t) * P->n_near, hipMemcpyDeviceToHost, s));
+            NLA_HIP(hipStreamSynchronize(s));
+            for (int64_t i = 0; i < P->n_near; i++)
+                if (hp[i] < 0) cl.push_back(i);
+            P->n_near_comp = (int64_t)cl.size();
+            NLA_TRY(P->arena.get(&P->near_comp, cl.size() > 0 ? cl.size() : 1));
+            if (!cl.empty())
+                NLA_HIP(hipMemcpyAsync(P->near_comp, cl.data(), sizeof(int64_t) * cl.size(), hipMemcpyHostToDevice, s));
+            NLA_HIP(hipStreamSynchronize(s));
+        }
         k_near_codes<<<grid_for(P->n_near, 256), 256, 0, s>>>(P->n_near, J, P->near_pair, P->tri, P->pair_k, P->pair_kp,
-                                                             ukeys, nnz, up_of, nsent, nk, nv);
+                                                             ukeys, nnz, up_of, nsent, partner, nk, nv);
         size_t t5 = 0;
         const int nb = bits_for((uint64_t)nsent);
         NLA_HIP(rocprim::radix_sort_pairs(nullptr, t5, nk, snk, nv, snv, (size_t)ns, 0, nb, s));
@@ -1292,11 +1356,51 @@ extern "C" int nla_blocks_view(const nla_plan *P, const void **myy, const void *
     return NLA_OK;
 }
 
+// the blocks of mirrored near pairs, relabelled from their partners' (view only;
+// the assembly reads the partner's block through the codes)
+template <class T>
+__global__ void k_near_mirror_fill(int64_t n_near, const int64_t *__restrict__ near_pair,
+                                   const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
+                                   const int32_t *__restrict__ pkp, const int64_t *__restrict__ partner,
+                                   T *__restrict__ blk)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_near || partner[i] < 0) return;
+    const int64_t j = partner[i], p = near_pair[i];
+    const int k = pk[p], kp = pkp[p];
+    int ps[6];
+    bool merged[6];
+    for (int I = 0; I < 6; I++) {
+        const int g = I < 3 ? tri[3 * k + I] : tri[3 * kp + I - 3];
+        ps[I] = -1;
+        for (int a = 0; a < 3; a++)
+            if (tri[3 * kp + a] == g) ps[I] = a;
+        if (ps[I] < 0)
+            for (int a = 0; a < 3; a++)
+                if (tri[3 * k + a] == g) ps[I] = 3 + a;
+        merged[I] = I >= 3 && (tri[3 * k] == g || tri[3 * k + 1] == g || tri[3 * k + 2] == g);
+    }
+    for (int I = 0; I < 6; I++)
+        for (int Jj = I; Jj < 6; Jj++)
+            blk[21 * i + upper_slot(I, Jj)] = (merged[I] || merged[Jj]) ? (T)0 : blk[21 * j + upper_slot(ps[I], ps[Jj])];
+}
+
 extern "C" int nla_near_view(const nla_plan *P, int64_t *n_near, const int64_t **near_pair, const void **blocks,
                              int32_t *dtype)
 {
     if (!P || !n_near || !near_pair || !blocks || !dtype) { nla_set_error("null argument"); return NLA_E_INVALID; }
     if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
+    if (P->n_near > 0 && P->n_near_comp < P->n_near) {
+        NLA_HIP(hipDeviceSynchronize());
+        if (P->val_dtype == NLA_DTYPE_F32)
+            k_near_mirror_fill<float><<<grid_for(P->n_near, 256), 256>>>(P->n_near, P->near_pair, P->tri, P->pair_k,
+                                                                        P->pair_kp, P->near_partner, (float *)P->near_blk);
+        else
+            k_near_mirror_fill<double><<<grid_for(P->n_near, 256), 256>>>(P->n_near, P->near_pair, P->tri, P->pair_k,
+                                                                         P->pair_kp, P->near_partner, (double *)P->near_blk);
+        NLA_HIP(hipGetLastError());
+        NLA_HIP(hipDeviceSynchronize());
+    }
     *n_near = P->n_near;
     *near_pair = P->near_pair;
     *blocks = P->near_blk;
