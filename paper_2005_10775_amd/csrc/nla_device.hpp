@@ -97,20 +97,25 @@ __device__ __forceinline__ void set5(double (&d)[5], double x, double y, double 
     d[0] = x; d[1] = y; d[2] = b0; d[3] = b1; d[4] = b2;
 }
 
-// E' n B_delta(x) retriangulated (Sec. 4.2.1-4.2.2 and Sec. 7.1 tasks 3-6),
-// written as one generator loop so that a single copy of the subtriangle
-// quadrature is inlined.  The edges are walked v0->v1->v2: vertices inside
-// the closed ball and the roots lambda in (0,1) of |v_a + lambda e - x|^2 =
-// delta^2 (smaller root entry, larger exit) arrive in order; every new point
-// closes the fan triangle (first, previous, new), and every exit followed by
-// an entry (cyclically) opens a cap: the arc from exit X counter-clockwise to
-// entry N split into ncap equal arcs fanned from the chord midpoint.  A cap
-// span not in (0, pi] only arises from rounding when X and N coincide and is
-// dropped (cross product <= 0).  Each subtriangle goes to tri(t).  POW2: ncap is a power of two and the
-// rotation comes from half-angle steps instead of atan2/sincos.  Vl: E' in absolute coordinates (6 values); coordinates below are
-// relative to the outer point.
+// E' n B_delta(x) retriangulated (Sec. 4.2.1-4.2.2 and Sec. 7.1 tasks 3-6) in
+// two loops, each with one inlined copy of the subtriangle quadrature tri(t):
+//  1. the edges are walked v0->v1->v2: vertices inside the closed ball and the
+//     roots lambda in (0,1) of |v_a + lambda e - x|^2 = delta^2 (smaller root
+//     entry, larger exit) arrive in order; every new point closes the fan
+//     triangle (first, previous, new); every exit followed by an entry
+//     (cyclically) is a cap, recorded in cb (at most three: one per exit);
+//  2. each cap, the arc from exit X counter-clockwise to entry N, is split into
+//     ncap equal arcs fanned from the chord midpoint.
+// Separating the loops keeps a wavefront's lanes on the same code path (walk or
+// fan) instead of paying both per step.  A cap span not in (0, pi] only arises
+// from rounding when X and N coincide and is dropped (cross product <= 0).
+// POW2: ncap is a power of two and the rotation comes from half-angle steps
+// instead of atan2/sincos.  Vl: E' in absolute coordinates (6 values); all
+// coordinates below are relative to the outer point.  cb: 12 doubles of
+// scratch per call (cap endpoints).  nsub counts triangles, plus 2^16 per cap.
 template <bool POW2, class TriF>
-__device__ void partial_item(double xx, double xy, const double *Vl, double dd, int ncap, TriF &tri, int &nsub)
+__device__ void partial_item(double xx, double xy, const double *Vl, double dd, int ncap, TriF &tri, int &nsub,
+                             double *cb)
 {
     Basis B;
     {
@@ -123,20 +128,103 @@ __device__ void partial_item(double xx, double xy, const double *Vl, double dd, 
         B.i21 = -e1y * id;
         B.i22 = e1x * id;
     }
-    int ev = 0, cnt = 0, ft = 0, pt = 0, ea = 0, eb = 0;
+    int ev = 0, cnt = 0, ft = 0, pt = 0, ea = 0, eb = 0, ncp = 0;
     double f[5] = {0, 0, 0, 0, 0}, q[5] = {0, 0, 0, 0, 0};
     double epx = 0, epy = 0, eex = 0, eey = 0, el1 = 2.0, el2 = 2.0;
-    int cj = 0;
-    bool wrapped = false;
-    double Mc[5] = {0, 0, 0, 0, 0}, u[5] = {0, 0, 0, 0, 0}, N[5] = {0, 0, 0, 0, 0};
-    double cc = 1.0, ss = 0.0;
-    auto start_cap = [&](const double (&X)[5], const double (&Y)[5]) {
-        const double cr = X[0] * Y[1] - X[1] * Y[0], dt = X[0] * Y[0] + X[1] * Y[1];
-        if (!(cr > 0.0) || ncap < 2) return;      // span in (0, pi): counter-clockwise from X to N
+    auto record_cap = [&](double x0, double y0, double x1, double y1) {
+        // span in (0, pi): counter-clockwise from X to N
+        if (ncap < 2 || !(x0 * y1 - y0 * x1 > 0.0)) return;
+        cb[4 * ncp] = x0;
+        cb[4 * ncp + 1] = y0;
+        cb[4 * ncp + 2] = x1;
+        cb[4 * ncp + 3] = y1;
+        ncp++;
+    };
+    while (true) {
+        bool got = false;
+        double n[5];
+        int nt = 0;
+        while (ev < 9 && !got) {
+            const int a = ev / 3, kind = ev - 3 * (ev / 3);
+            ev++;
+            if (kind == 0) {
+                const int b = a == 2 ? 0 : a + 1;
+                const double ax = Vl[2 * a], ay = Vl[2 * a + 1];
+                epx = ax - xx;
+                epy = ay - xy;
+                eex = Vl[2 * b] - ax;
+                eey = Vl[2 * b + 1] - ay;
+                ea = a;
+                eb = b;
+                const double r2 = epx * epx + epy * epy;
+                const double L = eex * eex + eey * eey;
+                const double Bq = eex * epx + eey * epy;
+                const double disc = Bq * Bq - L * (r2 - dd);
+                el1 = 2.0;
+                el2 = 2.0;
+                if (disc > 0.0) {
+                    const double sq = sqrt(disc);
+                    const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
+                    if (l1 > 0.0 && l1 < 1.0) el1 = l1;
+                    if (l2 > 0.0 && l2 < 1.0) el2 = l2;
+                }
+                if (r2 <= dd) {
+                    set5(n, epx, epy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0);
+                    nt = 0;
+                    got = true;
+                }
+            } else {
+                const double l = kind == 1 ? el1 : el2;
+                if (l < 1.5) {
+                    const double w1 = 1.0 - l;
+                    set5(n, epx + l * eex, epy + l * eey, ea == 0 ? w1 : (eb == 0 ? l : 0.0),
+                         ea == 1 ? w1 : (eb == 1 ? l : 0.0), ea == 2 ? w1 : (eb == 2 ? l : 0.0));
+                    nt = kind;
+                    got = true;
+                }
+            }
+        }
+        if (!got) {
+            // the cap from the last exit back to the first entry
+            if (cnt >= 2 && pt == 2 && ft == 1) record_cap(q[0], q[1], f[0], f[1]);
+            break;
+        }
+        if (cnt >= 1 && pt == 2 && nt == 1) record_cap(q[0], q[1], n[0], n[1]);
+        if (cnt >= 2) {
+            double t[3][5];
+#pragma unroll
+            for (int i = 0; i < 5; i++) {
+                t[0][i] = f[i];
+                t[1][i] = q[i];
+                t[2][i] = n[i];
+            }
+            tri(t);
+            nsub++;
+        }
+        if (cnt == 0) {
+#pragma unroll
+            for (int i = 0; i < 5; i++) f[i] = n[i];
+            ft = nt;
+        }
+#pragma unroll
+        for (int i = 0; i < 5; i++) q[i] = n[i];
+        pt = nt;
+        cnt++;
+    }
+    for (int c = 0; c < ncp; c++) {
+        double X[5], N[5], Mc[5], u[5];
+        X[0] = cb[4 * c];
+        X[1] = cb[4 * c + 1];
+        N[0] = cb[4 * c + 2];
+        N[1] = cb[4 * c + 3];
+        basis_at(B, X[0], X[1], X[2], X[3], X[4]);
+        basis_at(B, N[0], N[1], N[2], N[3], N[4]);
+        const double cr = X[0] * N[1] - X[1] * N[0], dt = X[0] * N[0] + X[1] * N[1];
+        double cc, ss;
         if (POW2) {
             // rotation by D/ncap from cos D, sin D by repeated half angles:
             // cos(t/2) = sqrt((1 + cos t)/2), sin(t/2) = sin t / (2 cos(t/2))
-            const double r = 1.0 / sqrt((X[0] * X[0] + X[1] * X[1]) * (Y[0] * Y[0] + Y[1] * Y[1]));
+            const double r = 1.0 / sqrt((X[0] * X[0] + X[1] * X[1]) * (N[0] * N[0] + N[1] * N[1]));
             cc = dt * r;
             ss = cr * r;
             for (int m = ncap; m > 1; m >>= 1) {
@@ -150,27 +238,21 @@ __device__ void partial_item(double xx, double xy, const double *Vl, double dd, 
         }
 #pragma unroll
         for (int i = 0; i < 5; i++) {
-            Mc[i] = 0.5 * (X[i] + Y[i]);
+            Mc[i] = 0.5 * (X[i] + N[i]);
             u[i] = X[i];
-            N[i] = Y[i];
         }
-        cj = 1;
         nsub += 1 << 16;
-    };
-    while (true) {
-        double t[3][5];
-        if (cj > 0) {
+        for (int j = 1; j <= ncap; j++) {
             double v[5];
-            if (cj == ncap) {
+            if (j == ncap) {
 #pragma unroll
                 for (int i = 0; i < 5; i++) v[i] = N[i];
-                cj = 0;
             } else {
                 v[0] = cc * u[0] - ss * u[1];
                 v[1] = ss * u[0] + cc * u[1];
                 basis_at(B, v[0], v[1], v[2], v[3], v[4]);
-                cj++;
             }
+            double t[3][5];
 #pragma unroll
             for (int i = 0; i < 5; i++) {
                 t[0][i] = Mc[i];
@@ -178,81 +260,9 @@ __device__ void partial_item(double xx, double xy, const double *Vl, double dd, 
                 t[2][i] = v[i];
                 u[i] = v[i];
             }
-        } else {
-            bool got = false;
-            double n[5];
-            int nt = 0;
-            while (ev < 9 && !got) {
-                const int a = ev / 3, kind = ev - 3 * (ev / 3);
-                ev++;
-                if (kind == 0) {
-                    const int b = a == 2 ? 0 : a + 1;
-                    const double ax = Vl[2 * a], ay = Vl[2 * a + 1];
-                    epx = ax - xx;
-                    epy = ay - xy;
-                    eex = Vl[2 * b] - ax;
-                    eey = Vl[2 * b + 1] - ay;
-                    ea = a;
-                    eb = b;
-                    const double r2 = epx * epx + epy * epy;
-                    const double L = eex * eex + eey * eey;
-                    const double Bq = eex * epx + eey * epy;
-                    const double disc = Bq * Bq - L * (r2 - dd);
-                    el1 = 2.0;
-                    el2 = 2.0;
-                    if (disc > 0.0) {
-                        const double sq = sqrt(disc);
-                        const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
-                        if (l1 > 0.0 && l1 < 1.0) el1 = l1;
-                        if (l2 > 0.0 && l2 < 1.0) el2 = l2;
-                    }
-                    if (r2 <= dd) {
-                        set5(n, epx, epy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0);
-                        nt = 0;
-                        got = true;
-                    }
-                } else {
-                    const double l = kind == 1 ? el1 : el2;
-                    if (l < 1.5) {
-                        const double w1 = 1.0 - l;
-                        set5(n, epx + l * eex, epy + l * eey, ea == 0 ? w1 : (eb == 0 ? l : 0.0),
-                             ea == 1 ? w1 : (eb == 1 ? l : 0.0), ea == 2 ? w1 : (eb == 2 ? l : 0.0));
-                        nt = kind;
-                        got = true;
-                    }
-                }
-            }
-            if (!got) {
-                if (!wrapped && cnt >= 2 && pt == 2 && ft == 1) {
-                    wrapped = true;
-                    start_cap(q, f);
-                    continue;
-                }
-                break;
-            }
-            const bool fan = cnt >= 2;
-            if (fan) {
-#pragma unroll
-                for (int i = 0; i < 5; i++) {
-                    t[0][i] = f[i];
-                    t[1][i] = q[i];
-                    t[2][i] = n[i];
-                }
-            }
-            if (cnt >= 1 && pt == 2 && nt == 1) start_cap(q, n);
-            if (cnt == 0) {
-#pragma unroll
-                for (int i = 0; i < 5; i++) f[i] = n[i];
-                ft = nt;
-            }
-#pragma unroll
-            for (int i = 0; i < 5; i++) q[i] = n[i];
-            pt = nt;
-            cnt++;
-            if (!fan) continue;
+            tri(t);
+            nsub++;
         }
-        tri(t);
-        nsub++;
     }
 }
 

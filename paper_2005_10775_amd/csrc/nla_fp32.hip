@@ -200,6 +200,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
     __shared__ double sV[64][7];
     __shared__ unsigned short queue[64 * NQ];
     __shared__ float res[64][10];
+    __shared__ double capbuf[64][12];
     __shared__ int64_t rbase_l[LEARN ? 64 : 1];
     __shared__ unsigned rmsk_l[LEARN ? 64 : 1];
     float(*mxy_l)[10] = res;
@@ -373,7 +374,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
                 // routed items: the inscribed polygon only here; the owner adds the
                 // network's cap moments when it collects the result
                 const bool routed = LEARN && i >= totE;
-                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, tri, ns);
+                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, tri, ns, &capbuf[lane][0]);
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
                 res[lane][0] = A.s0.s;

@@ -441,8 +441,9 @@ __global__ void k_cap_samples(int64_t n, uint64_t seed, int64_t first, double L,
     double mall[3] = {0, 0, 0}, mpoly[3] = {0, 0, 0};
     int ns = 0, ns0 = 0;
     LabelF fa{mall}, fp{mpoly};
-    partial_item<POW2>(0.0, 0.0, V, 1.0, ncap, fa, ns);
-    partial_item<POW2>(0.0, 0.0, V, 1.0, 0, fp, ns0);
+    double cb[12];
+    partial_item<POW2>(0.0, 0.0, V, 1.0, ncap, fa, ns, cb);
+    partial_item<POW2>(0.0, 0.0, V, 1.0, 0, fp, ns0, cb);
     // every vertex at least band from the circle: |v|^2 >= (1 + band)^2 or |v|^2 <= (1 - band)^2
     const double hi = 1.0 + band, lo = band < 1.0 ? 1.0 - band : 0.0;
     bool far = true;

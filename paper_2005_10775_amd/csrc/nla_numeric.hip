@@ -36,8 +36,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     __shared__ double sV[64][7];
     __shared__ unsigned short queue[64 * NQ];
     // item results of a phase-2 round, later the chunk's -Mxy (never live together)
-    __shared__ double res[64][10];
-    double (*mxy_l)[10] = res;
+    __shared__ double res[64][12];
+    double (*mxy_l)[12] = res;
     const int k = blockIdx.x, lane = threadIdx.x;
     const int nq = R->n_out;
     const double a2k = E.a2[k];
@@ -159,7 +159,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 for (int t = 0; t < 6; t++) A.s2[t] = 0.0;
                 int ns = 0;
                 auto tri = [&](const double (&t)[3][5]) { tri_accum<SYM>(t, M, A); };
-                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns);
+                // the cap endpoints live in this lane's row of res until the sums are written
+                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns, &res[lane][0]);
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
                 res[lane][0] = A.a2 * M.wsum;
