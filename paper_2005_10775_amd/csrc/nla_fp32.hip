@@ -111,6 +111,20 @@ struct TriF32 {
     }
 };
 
+// LDS of one pair-kernel wavefront (declared by the kernels, so that the
+// persistent kernel's two bodies share it)
+template <int NQ>
+struct PairLDS {
+    double sX[NQ][2];
+    float sW[NQ][4];
+    double sV[64][7];
+    unsigned short queue[64 * NQ];
+    float res[64][10];
+    double capbuf[64][12];
+    int64_t rbase_l[64];
+    unsigned rmsk_l[64];
+};
+
 // Item class of (x, E_k') under the intersection ball: 1 whole (every vertex
 // in the closed ball), 2 partial (the ball meets the triangle otherwise), 0
 // empty.  Every product and sum is rounded on its own, so the routing pass of
@@ -175,7 +189,7 @@ __device__ __forceinline__ bool item_routed(double xx, double xy, const double (
 // pair and Mxx per element are written.  Pairs flagged near (vertex-sharing,
 // singular kernel) are skipped here.
 template <int NQ, int FM, bool POW2>
-__device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
+__device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, PairLDS<NQ> &S)
 {
     const int64_t *__restrict__ pair_ptr = P.pair_ptr;
     const int32_t *__restrict__ pair_kp = P.pair_kp;
@@ -195,14 +209,14 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn)
     float *__restrict__ Cyy = P.Cyy;
     float *__restrict__ Cxx = P.Cxx;
     unsigned long long *__restrict__ counters = P.counters;
-    __shared__ double sX[NQ][2];
-    __shared__ float sW[NQ][4];
-    __shared__ double sV[64][7];
-    __shared__ unsigned short queue[64 * NQ];
-    __shared__ float res[64][10];
-    __shared__ double capbuf[64][12];
-    __shared__ int64_t rbase_l[LEARN ? 64 : 1];
-    __shared__ unsigned rmsk_l[LEARN ? 64 : 1];
+    auto &sX = S.sX;
+    auto &sW = S.sW;
+    auto &sV = S.sV;
+    auto &queue = S.queue;
+    auto &res = S.res;
+    auto &capbuf = S.capbuf;
+    auto &rbase_l = S.rbase_l;
+    auto &rmsk_l = S.rmsk_l;
     float(*mxy_l)[10] = res;
     const int lane = threadIdx.x;
     const int nq = R->n_out;
@@ -568,7 +582,8 @@ template <int NQ, int FM, bool POW2>
 __global__ __launch_bounds__(64, 2) void k_pairs_fp32(PairArgs P)
 {
     extern __shared__ double dyn[];
-    pairs_fp32_body<NQ, FM, POW2>(P, blockIdx.x, dyn);
+    __shared__ PairLDS<NQ> S;
+    pairs_fp32_body<NQ, FM, POW2>(P, blockIdx.x, dyn, S);
 }
 
 // Persistent form for a batch of instances: a fixed grid of wavefronts takes
@@ -584,6 +599,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
 {
     extern __shared__ double dyn[];
     __shared__ int base_s;
+    __shared__ PairLDS<NQ> S;
     while (true) {
         if (threadIdx.x == 0) base_s = atomicAdd(cursor, chunk);
         __syncthreads();
@@ -594,8 +610,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
         for (int j = base; j < end; j++) {
             const int2 w = work[j];
             // the bodies of the single-plan kernels, so that both give the same bits
-            if (inst[w.x].frac) pairs_fp32_body<NQ, 1, POW2>(inst[w.x], w.y, dyn);
-            else pairs_fp32_body<NQ, 0, POW2>(inst[w.x], w.y, dyn);
+            if (inst[w.x].frac) pairs_fp32_body<NQ, 1, POW2>(inst[w.x], w.y, dyn, S);
+            else pairs_fp32_body<NQ, 0, POW2>(inst[w.x], w.y, dyn, S);
         }
     }
 }
@@ -823,7 +839,9 @@ __global__ __launch_bounds__(64) void k_elem_blocks_f32(int K, const int64_t *__
                                                         const int32_t *__restrict__ tperm, const float *__restrict__ Cyy,
                                                         const float *__restrict__ Cxx, float *__restrict__ Ce)
 {
-    elem_blocks_body(blockIdx.x, tptr, tperm, Cyy, Cxx, Ce);
+    const int64_t kb = xcd_block(blockIdx.x, gridDim.x);
+    if (kb >= K) return;
+    elem_blocks_body((int)kb, tptr, tperm, Cyy, Cxx, Ce);
 }
 
 // compensated FP32 sum of every upper entry: its [R | E] codes, then its
@@ -849,7 +867,7 @@ __global__ void k_segsum_f32(int64_t n_up, const int64_t *__restrict__ up_ptr, c
                              const int64_t *__restrict__ up_dst, const int64_t *__restrict__ mirror,
                              const float *__restrict__ V, const float *__restrict__ N, float *__restrict__ val)
 {
-    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t u = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (u >= n_up) return;
     segsum_body(u, up_ptr, codes, nup_ptr, ncodes, up_dst, mirror, V, N, val);
 }
@@ -973,9 +991,9 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
         P->ran[NLA_PHASE_NEAR] = true;
     }
     mark(P, NLA_PHASE_SEGSUM, s);
-    k_elem_blocks_f32<<<K, 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
+    k_elem_blocks_f32<<<(unsigned)xcd_grid(K), 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
     if (P->n_up > 0)
-        k_segsum_f32<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes,
+        k_segsum_f32<<<(unsigned)xcd_grid(grid_for(P->n_up, 256)), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes,
                                                            P->n_near > 0 ? P->nup_ptr : nullptr, P->ncodes, P->up_dst,
                                                            P->mirror, V, (const float *)P->near_blk, (float *)P->val);
     P->ran[NLA_PHASE_SEGSUM] = true;

@@ -185,6 +185,16 @@ struct PairArgs {
 };
 PairArgs nla_pair_args(const nla_plan *P);
 
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2: the
+// work index of workgroup b (of nb) such that each XCD takes one contiguous
+// range, so neighbouring work items (sharing cache lines) meet in one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t chunk = (nb + 7) / 8;
+    return (b % 8) * chunk + b / 8;
+}
+inline int64_t xcd_grid(int64_t nb) { return (nb + 7) / 8 * 8; }
+
 // learned cap corrector (nla_mlp.hip)
 struct nla_mlp;
 int nla_mlp_infer_launch(const nla_mlp *M, const float *feat, int64_t n, float *out, hipStream_t s);

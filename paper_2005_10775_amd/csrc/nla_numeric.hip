@@ -265,7 +265,9 @@ __global__ __launch_bounds__(64) void k_elem_blocks(int K, const int64_t *__rest
                                                     const int32_t *__restrict__ tperm, const T *__restrict__ Cyy,
                                                     const T *__restrict__ Cxx, T *__restrict__ Ce)
 {
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int64_t kb = xcd_block(blockIdx.x, gridDim.x);
+    if (kb >= K) return;
+    const int k = (int)kb, lane = threadIdx.x;
     double y[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t t = tptr[k] + lane; t < tptr[k + 1]; t += 64) {
         const int64_t p = tperm[t];
@@ -294,7 +296,7 @@ __global__ void k_segsum_f64(int64_t n_up, const int64_t *__restrict__ up_ptr, c
                              const int64_t *__restrict__ up_dst, const int64_t *__restrict__ mirror,
                              const double *__restrict__ C, double *__restrict__ val)
 {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t u = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (u >= n_up) return;
     double s = 0.0;
     for (int64_t t = up_ptr[u]; t < up_ptr[u + 1]; t++) s += C[codes[t]];
@@ -404,10 +406,11 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         P->ran[NLA_PHASE_PAIRS] = true;
         nla_mark(P, NLA_PHASE_NEAR, s);
         nla_mark(P, NLA_PHASE_SEGSUM, s);
-        k_elem_blocks<double><<<K, 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
+        k_elem_blocks<double><<<(unsigned)xcd_grid(K), 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
         if (P->n_up > 0)
-            k_segsum_f64<<<grid_for(P->n_up, 256), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes, P->up_dst, P->mirror, V,
-                                                               (double *)P->val);
+            k_segsum_f64<<<(unsigned)xcd_grid(grid_for(P->n_up, 256)), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes,
+                                                                                   P->up_dst, P->mirror, V,
+                                                                                   (double *)P->val);
         P->ran[NLA_PHASE_SEGSUM] = true;
         nla_mark(P, NLA_PHASE_EXTRACT, s);
         if (P->nnz_free > 0)
