@@ -308,3 +308,140 @@ __device__ __forceinline__ void mlp_features(double xx, double xy, const double 
         f[2 * a + 1] = (float)(8.0 * (dy * c - dx * s));
     }
 }
+
+// Boundary sums of a polygon's area and first and second moments (Green's
+// theorem, counter-clockwise boundary, coordinates z about a local origin):
+//   c = sum cr, mx = sum cr (ax + bx), my = sum cr (ay + by),
+//   qxx = sum cr (ax^2 + ax bx + bx^2), qyy = likewise, qxy = sum cr (2 ax ay + ax by + bx ay + 2 bx by),
+// cr = ax by - ay bx, so that A = c/2, int z = m/6, int zx^2 = qxx/12, int zx zy = qxy/24.
+struct RegionMom {
+    double c, mx, my, qxx, qxy, qyy;
+};
+
+__device__ __forceinline__ void edge_mom(RegionMom &R, double ax, double ay, double bx, double by)
+{
+    const double cr = ax * by - ay * bx;
+    R.c += cr;
+    R.mx += cr * (ax + bx);
+    R.my += cr * (ay + by);
+    R.qxx += cr * (ax * ax + ax * bx + bx * bx);
+    R.qyy += cr * (ay * ay + ay * by + by * by);
+    R.qxy += cr * (ax * (2.0 * ay + by) + bx * (ay + 2.0 * by));
+}
+
+// The same region E' n B_delta,h(x) as partial_item (inscribed polygon of
+// Sec. 4.2.1 plus ncap equal-arc caps of Sec. 4.2.2), integrated through its
+// boundary: walking the edges v0->v1->v2 gives the polygon's points in order
+// (vertices in the closed ball, entry and exit roots); consecutive points are
+// joined along an edge of E' except from an exit to the next entry, where the
+// cap's arc chords X = P_0, P_1, ..., P_ncap = N replace the chord X N.  With
+// psi constant and an inner rule exact for quadratics, the composite rule over
+// the fan of the region gives exactly these moments.  Coordinates about
+// vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.
+template <bool POW2>
+__device__ void partial_boundary(double xx, double xy, const double *Vl, double dd, int ncap, RegionMom &R, int &nseg)
+{
+    const double ox = Vl[0] - xx, oy = Vl[1] - xy;      // local origin (vertex 0) relative to x
+    int cnt = 0, ft = 0, pt = 0;
+    double fx = 0.0, fy = 0.0, qx = 0.0, qy = 0.0;
+    auto connect = [&](double ax, double ay, int at, double bx, double by, int bt) {
+        if (at == 2 && bt == 1 && ncap >= 2 && ax * by - ay * bx > 0.0) {
+            // the cap: arc from X counter-clockwise to N in ncap equal pieces
+            const double cr = ax * by - ay * bx, dt = ax * bx + ay * by;
+            double cc, ss;
+            if (POW2) {
+                const double r = 1.0 / sqrt((ax * ax + ay * ay) * (bx * bx + by * by));
+                cc = dt * r;
+                ss = cr * r;
+                for (int m = ncap; m > 1; m >>= 1) {
+                    const double ch = sqrt(0.5 * (1.0 + cc));
+                    ss = ss / (2.0 * ch);
+                    cc = ch;
+                }
+            } else {
+                const double D = atan2(cr, dt);
+                sincos(D / (double)ncap, &ss, &cc);
+            }
+            double ux = ax, uy = ay;
+            for (int j = 1; j <= ncap; j++) {
+                double vx, vy;
+                if (j == ncap) {
+                    vx = bx;
+                    vy = by;
+                } else {
+                    vx = cc * ux - ss * uy;
+                    vy = ss * ux + cc * uy;
+                }
+                edge_mom(R, ux - ox, uy - oy, vx - ox, vy - oy);
+                ux = vx;
+                uy = vy;
+            }
+            nseg += (1 << 16) + ncap;
+        } else {
+            edge_mom(R, ax - ox, ay - oy, bx - ox, by - oy);
+            nseg++;
+        }
+    };
+    auto emit = [&](double nx, double ny, int nt) {
+        if (cnt == 0) {
+            fx = nx;
+            fy = ny;
+            ft = nt;
+        } else {
+            connect(qx, qy, pt, nx, ny, nt);
+        }
+        qx = nx;
+        qy = ny;
+        pt = nt;
+        cnt++;
+    };
+    for (int a = 0; a < 3; a++) {
+        const int b = a == 2 ? 0 : a + 1;
+        const double epx = Vl[2 * a] - xx, epy = Vl[2 * a + 1] - xy;
+        const double eex = Vl[2 * b] - Vl[2 * a], eey = Vl[2 * b + 1] - Vl[2 * a + 1];
+        const double r2 = epx * epx + epy * epy;
+        const double L = eex * eex + eey * eey;
+        const double Bq = eex * epx + eey * epy;
+        const double disc = Bq * Bq - L * (r2 - dd);
+        double el1 = 2.0, el2 = 2.0;
+        if (disc > 0.0) {
+            const double sq = sqrt(disc);
+            const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
+            if (l1 > 0.0 && l1 < 1.0) el1 = l1;
+            if (l2 > 0.0 && l2 < 1.0) el2 = l2;
+        }
+        if (r2 <= dd) emit(epx, epy, 0);
+        if (el1 < 1.5) emit(epx + el1 * eex, epy + el1 * eey, 1);
+        if (el2 < 1.5) emit(epx + el2 * eex, epy + el2 * eey, 2);
+    }
+    if (cnt >= 2) connect(qx, qy, pt, fx, fy, ft);
+}
+
+// S0 = int 1, S1_b = int beta_b, S2 = int beta_b beta_b' (upper 00,01,02,11,12,22)
+// over the region from its boundary sums; beta1 = g1 . z, beta2 = g2 . z,
+// beta0 = 1 - beta1 - beta2 with z about vertex 0 and g the rows of the
+// inverse edge matrix of E'.
+__device__ __forceinline__ void region_sums(const RegionMom &R, const double *Vl, double &s0, double (&s1)[3],
+                                            double (&s2)[6])
+{
+    const double e1x = Vl[2] - Vl[0], e1y = Vl[3] - Vl[1], e2x = Vl[4] - Vl[0], e2y = Vl[5] - Vl[1];
+    const double id = 1.0 / (e1x * e2y - e1y * e2x);
+    const double g11 = e2y * id, g12 = -e2x * id, g21 = -e1y * id, g22 = e1x * id;
+    const double A = 0.5 * R.c;
+    const double mx = R.mx * (1.0 / 6.0), my = R.my * (1.0 / 6.0);
+    const double Qxx = R.qxx * (1.0 / 12.0), Qyy = R.qyy * (1.0 / 12.0), Qxy = R.qxy * (1.0 / 24.0);
+    const double I1 = g11 * mx + g12 * my, I2 = g21 * mx + g22 * my;
+    const double Q11 = g11 * (g11 * Qxx + g12 * Qxy) + g12 * (g11 * Qxy + g12 * Qyy);
+    const double Q22 = g21 * (g21 * Qxx + g22 * Qxy) + g22 * (g21 * Qxy + g22 * Qyy);
+    const double Q12 = g11 * (g21 * Qxx + g22 * Qxy) + g12 * (g21 * Qxy + g22 * Qyy);
+    s0 = A;
+    s1[0] = A - I1 - I2;
+    s1[1] = I1;
+    s1[2] = I2;
+    s2[0] = A - 2.0 * (I1 + I2) + Q11 + 2.0 * Q12 + Q22;
+    s2[1] = I1 - Q11 - Q12;
+    s2[2] = I2 - Q12 - Q22;
+    s2[3] = Q11;
+    s2[4] = Q12;
+    s2[5] = Q22;
+}

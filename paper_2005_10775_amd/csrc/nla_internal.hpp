@@ -38,6 +38,7 @@ void nla_set_error(const char *fmt, ...);
 // with its sums reordered, not a different rule).
 struct RuleSet {
     int32_t n_out, n_in, duffy_n, in_sym;   // in_sym: inner rule symmetric under vertex permutations
+    int32_t in_q2exact, pad_;               // inner rule integrates quadratics exactly
     double out_lam[NLA_MAX_OUTER][3];
     double out_w[NLA_MAX_OUTER];
     double in_lam[NLA_MAX_INNER][3];

@@ -19,7 +19,7 @@ static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs -
 // reduction of sum_k' S0(x_q), and the row block R_k[a][c] = sum of -Mxy_ab
 // over the pairs whose inner slot b is node C_k[c], reduced in LDS column by
 // column in pair order (each column owned by one lane).
-template <int NQ, bool SYM, bool POW2>
+template <int NQ, bool SYM, bool POW2, bool BND>
 __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
                                                          const int32_t *__restrict__ pair_kp, ElemSoA E,
                                                          const double *__restrict__ xq, const RuleSet *__restrict__ R,
@@ -158,16 +158,29 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
 #pragma unroll
                 for (int t = 0; t < 6; t++) A.s2[t] = 0.0;
                 int ns = 0;
-                auto tri = [&](const double (&t)[3][5]) { tri_accum<SYM>(t, M, A); };
-                // the cap endpoints live in this lane's row of res until the sums are written
-                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns, &res[lane][0]);
+                if (BND) {
+                    // the rule is exact for quadratics: the region's moments from its boundary
+                    RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, Rm, ns);
+                    double s0, s1[3], s2[6];
+                    region_sums(Rm, &sV[owner][0], s0, s1, s2);
+                    res[lane][0] = s0;
+#pragma unroll
+                    for (int t = 0; t < 3; t++) res[lane][1 + t] = s1[t];
+#pragma unroll
+                    for (int t = 0; t < 6; t++) res[lane][4 + t] = s2[t];
+                } else {
+                    auto tri = [&](const double (&t)[3][5]) { tri_accum<SYM>(t, M, A); };
+                    // the cap endpoints live in this lane's row of res until the sums are written
+                    partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns, &res[lane][0]);
+                    res[lane][0] = A.a2 * M.wsum;
+#pragma unroll
+                    for (int t = 0; t < 3; t++) res[lane][1 + t] = SYM ? A.s1[t] * M.m1c : A.s1[t];
+#pragma unroll
+                    for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t];
+                }
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
-                res[lane][0] = A.a2 * M.wsum;
-#pragma unroll
-                for (int t = 0; t < 3; t++) res[lane][1 + t] = SYM ? A.s1[t] * M.m1c : A.s1[t];
-#pragma unroll
-                for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t];
             }
             __syncthreads();
             const int j0 = pre > ib ? pre : ib;
@@ -390,17 +403,21 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         nla_mark(P, NLA_PHASE_PAIRS, s);
         const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
         const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
-#define NLA_LAUNCH_PAIRS(NQ, SYM, POW2)                                                                            \
-    k_pairs_const_fp64<NQ, SYM, POW2><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules,          \
+#define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND)                                                                       \
+    k_pairs_const_fp64<NQ, SYM, POW2, BND><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules,          \
                                                          pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap, P->col_off, \
                                                          P->colent_ptr, P->colent, V, Cyy, Cxx, P->max_cols,          \
                                                          P->counters)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
-        if (P->rules.n_out <= 8 && sym && pow2) NLA_LAUNCH_PAIRS(8, true, true);
-        else if (P->rules.n_out <= 8 && sym) NLA_LAUNCH_PAIRS(8, true, false);
-        else if (P->rules.n_out <= 8) NLA_LAUNCH_PAIRS(8, false, false);
-        else NLA_LAUNCH_PAIRS(16, false, false);
+        const bool bnd = P->rules.in_q2exact != 0 && pr.ball == NLA_BALL_RETRI;
+        if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true);
+        else if (P->rules.n_out <= 8 && bnd) NLA_LAUNCH_PAIRS(8, true, false, true);
+        else if (P->rules.n_out <= 8 && sym && pow2) NLA_LAUNCH_PAIRS(8, true, true, false);
+        else if (P->rules.n_out <= 8 && sym) NLA_LAUNCH_PAIRS(8, true, false, false);
+        else if (P->rules.n_out <= 8) NLA_LAUNCH_PAIRS(8, false, false, false);
+        else if (bnd) NLA_LAUNCH_PAIRS(16, false, false, true);
+        else NLA_LAUNCH_PAIRS(16, false, false, false);
 #undef NLA_LAUNCH_PAIRS
         NLA_HIP(hipGetLastError());
         P->ran[NLA_PHASE_PAIRS] = true;

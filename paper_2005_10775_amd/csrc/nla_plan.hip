@@ -1162,6 +1162,14 @@ static void fill_rules(const nla_problem *p, RuleSet *R)
             for (int j = 0; j < 3; j++)
                 sym = sym && std::fabs(R->in_m2[i][j] - (i == j ? R->in_m2[0][0] : R->in_m2[0][1])) <= tol;
         R->in_sym = sym ? 1 : 0;
+        // exact for quadratics on the reference triangle (weights summing to 1/2):
+        // sum w lambda_i = 1/6, sum w lambda_i lambda_j = (1 + [i == j]) / 24
+        bool q2 = std::fabs(R->in_wsum - 0.5) <= 1e-14;
+        for (int i = 0; i < 3; i++) {
+            q2 = q2 && std::fabs(R->in_m1[i] - 1.0 / 6.0) <= 1e-14;
+            for (int j = 0; j < 3; j++) q2 = q2 && std::fabs(R->in_m2[i][j] - (i == j ? 1.0 / 12.0 : 1.0 / 24.0)) <= 1e-14;
+        }
+        R->in_q2exact = q2 ? 1 : 0;
     }
     if (p->kernel == NLA_KERNEL_FRACTIONAL) {
         R->duffy_n = p->duffy_n;
