@@ -26,23 +26,31 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
 
 # Algorithmic FP64 operations of the pair kernel per unit of work (counted
 # from the arithmetic the method needs per unit; an FMA counts 2, sqrt, div
-# and transcendental calls count 1).
+# and transcendental calls count 1).  With an inner rule exact for quadratics
+# (constant kernel) a partial item is integrated through its boundary: the
+# counter "subtriangles" then counts boundary segments.
 COST = dict(item=15,           # classification: 3 squared vertex distances
             whole=6,           # whole item: outer-weight sums and S0
-            partial=114,       # polygon walk (3 edge quadratics, basis map, roots) + owner accumulation
+            partial=114,       # polygon walk (3 edge quadratics, roots) + owner accumulation
             subtriangle=81,    # inner rule on one subtriangle from its vertex basis values (area, S1, S2),
                                # symmetric-rule form
             cap=30,            # arc span, chord midpoint, rotation by half angles
             arc_point=16,      # one rotated arc point and its basis values
             pair=45)           # per-pair accumulator set-up and output
+COST_BOUNDARY = dict(item=15, whole=6,
+                     partial=114 + 60,   # walk + owner accumulation + moments to S0, S1, S2
+                     subtriangle=26,     # one boundary segment: cross product, first and second moment terms
+                     cap=30,             # arc span, rotation by half angles
+                     arc_point=6,        # one rotated arc point
+                     pair=45)
 
 
-def algorithmic_flops(info, n_pairs, ncap):
+def algorithmic_flops(info, n_pairs, ncap, cost=COST):
     it = info["items"]
     items = it["whole"] + it["partial"] + it["empty"]
-    return (COST["item"] * items + COST["whole"] * it["whole"] + COST["partial"] * it["partial"] +
-            COST["subtriangle"] * info["subtriangles"] + COST["cap"] * info["caps"] +
-            COST["arc_point"] * info["caps"] * max(ncap - 1, 0) + COST["pair"] * n_pairs)
+    return (cost["item"] * items + cost["whole"] * it["whole"] + cost["partial"] * it["partial"] +
+            cost["subtriangle"] * info["subtriangles"] + cost["cap"] * info["caps"] +
+            cost["arc_point"] * info["caps"] * max(ncap - 1, 0) + cost["pair"] * n_pairs)
 
 
 def l2_error(mesh, U, u_exact):
@@ -310,7 +318,12 @@ def main():
     value = n_pairs / (ms * 1e-3)
 
     # roofline of the dominant kernel (pair quadrature): algorithmic FP64 work per launch
-    flops = algorithmic_flops(info, n_pairs, prob.cap_edges if prob.ball == "retri" else 0)
+    from workloads import get_rule
+    ri = get_rule(prob.inner)
+    q2 = abs(ri.w.sum() - 0.5) < 1e-14 and all(abs((ri.w * ri.lam[:, i]).sum() - 1 / 6) < 1e-14 for i in range(3))
+    boundary = prob.precision == "fp64" and prob.ball == "retri" and q2
+    flops = algorithmic_flops(info, n_pairs, prob.cap_edges if prob.ball == "retri" else 0,
+                              COST_BOUNDARY if boundary else COST)
     t_pair = phase["pairs"] * 1e-3
     achieved = flops / t_pair / 1e12
     digest = source_digest()

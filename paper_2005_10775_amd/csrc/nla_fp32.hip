@@ -388,14 +388,30 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 // routed items: the inscribed polygon only here; the owner adds the
                 // network's cap moments when it collects the result
                 const bool routed = LEARN && i >= totE;
-                partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, tri, ns, &capbuf[lane][0]);
+                if (!FRAC && P.bnd) {
+                    // constant kernel, rule exact for quadratics: moments of the region from its
+                    // boundary (FP64 geometry), item sums rounded to FP32
+                    RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, Rm, ns);
+                    double s0, s1[3], s2[6];
+                    region_sums(Rm, &sV[owner][0], s0, s1, s2);
+                    const double kd = (double)kc;
+                    res[lane][0] = (float)(kd * s0);
+#pragma unroll
+                    for (int t = 0; t < 3; t++) res[lane][1 + t] = (float)(kd * s1[t]);
+#pragma unroll
+                    for (int t = 0; t < 6; t++) res[lane][4 + t] = (float)(kd * s2[t]);
+                } else {
+                    partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, tri, ns,
+                                       &capbuf[lane][0]);
+                    res[lane][0] = A.s0.s;
+#pragma unroll
+                    for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t].s;
+#pragma unroll
+                    for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t].s;
+                }
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
-                res[lane][0] = A.s0.s;
-#pragma unroll
-                for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t].s;
-#pragma unroll
-                for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t].s;
             }
             __syncthreads();
             // each lane adds its own items of this batch: its cap segment, then its routed one
@@ -907,6 +923,7 @@ PairArgs nla_pair_args(const nla_plan *P)
     A.Cxx = Cxx;
     A.max_cols = P->max_cols;
     A.counters = P->counters;
+    A.bnd = (!A.frac && pr.ball == NLA_BALL_RETRI && P->rules.in_q2exact) ? 1 : 0;
     A.delta = pr.delta;
     A.band = pr.fallback_band;
     A.route_off = P->route_off;

@@ -171,6 +171,7 @@ struct PairArgs {
     double dd;
     float kc, ex;
     int ball, ncap, frac, max_cols;
+    int bnd;                    // constant kernel, rule exact for quadratics: partial items by boundary moments
     const uint8_t *near_flag;
     const int64_t *col_off;
     const int32_t *colent_ptr;
