@@ -337,52 +337,31 @@ __device__ __forceinline__ void edge_mom(RegionMom &R, double ax, double ay, dou
 // cap's arc chords X = P_0, P_1, ..., P_ncap = N replace the chord X N.  With
 // psi constant and an inner rule exact for quadratics, the composite rule over
 // the fan of the region gives exactly these moments.  Coordinates about
-// vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.
+// vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.  cb: 12
+// doubles of scratch per call.
 template <bool POW2>
-__device__ void partial_boundary(double xx, double xy, const double *Vl, double dd, int ncap, RegionMom &R, int &nseg)
+__device__ void partial_boundary(double xx, double xy, const double *Vl, double dd, int ncap, RegionMom &R, int &nseg,
+                                 double *cb)
 {
     const double ox = Vl[0] - xx, oy = Vl[1] - xy;      // local origin (vertex 0) relative to x
-    int cnt = 0, ft = 0, pt = 0;
+    int cnt = 0, ft = 0, pt = 0, ncp = 0;
     double fx = 0.0, fy = 0.0, qx = 0.0, qy = 0.0;
-    auto connect = [&](double ax, double ay, int at, double bx, double by, int bt) {
+    // caps found on the walk (at most three, one per exit) are kept in cb (12
+    // doubles) and integrated after it, so that the lanes of a wavefront fan
+    // their caps together
+    auto connect = [&](double ax, double ay, int at, double bx, double by, int bt) __attribute__((always_inline)) {
         if (at == 2 && bt == 1 && ncap >= 2 && ax * by - ay * bx > 0.0) {
-            // the cap: arc from X counter-clockwise to N in ncap equal pieces
-            const double cr = ax * by - ay * bx, dt = ax * bx + ay * by;
-            double cc, ss;
-            if (POW2) {
-                const double r = 1.0 / sqrt((ax * ax + ay * ay) * (bx * bx + by * by));
-                cc = dt * r;
-                ss = cr * r;
-                for (int m = ncap; m > 1; m >>= 1) {
-                    const double ch = sqrt(0.5 * (1.0 + cc));
-                    ss = ss / (2.0 * ch);
-                    cc = ch;
-                }
-            } else {
-                const double D = atan2(cr, dt);
-                sincos(D / (double)ncap, &ss, &cc);
-            }
-            double ux = ax, uy = ay;
-            for (int j = 1; j <= ncap; j++) {
-                double vx, vy;
-                if (j == ncap) {
-                    vx = bx;
-                    vy = by;
-                } else {
-                    vx = cc * ux - ss * uy;
-                    vy = ss * ux + cc * uy;
-                }
-                edge_mom(R, ux - ox, uy - oy, vx - ox, vy - oy);
-                ux = vx;
-                uy = vy;
-            }
-            nseg += (1 << 16) + ncap;
+            cb[4 * ncp] = ax;
+            cb[4 * ncp + 1] = ay;
+            cb[4 * ncp + 2] = bx;
+            cb[4 * ncp + 3] = by;
+            ncp++;
         } else {
             edge_mom(R, ax - ox, ay - oy, bx - ox, by - oy);
             nseg++;
         }
     };
-    auto emit = [&](double nx, double ny, int nt) {
+    auto emit = [&](double nx, double ny, int nt) __attribute__((always_inline)) {
         if (cnt == 0) {
             fx = nx;
             fy = ny;
@@ -415,6 +394,40 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
         if (el2 < 1.5) emit(epx + el2 * eex, epy + el2 * eey, 2);
     }
     if (cnt >= 2) connect(qx, qy, pt, fx, fy, ft);
+    // each cap: the arc from X counter-clockwise to N in ncap equal pieces
+    for (int ci = 0; ci < ncp; ci++) {
+        const double ax = cb[4 * ci], ay = cb[4 * ci + 1], bx = cb[4 * ci + 2], by = cb[4 * ci + 3];
+        const double cr = ax * by - ay * bx, dt = ax * bx + ay * by;
+        double cc, ss;
+        if (POW2) {
+            const double r = 1.0 / sqrt((ax * ax + ay * ay) * (bx * bx + by * by));
+            cc = dt * r;
+            ss = cr * r;
+            for (int m = ncap; m > 1; m >>= 1) {
+                const double ch = sqrt(0.5 * (1.0 + cc));
+                ss = ss / (2.0 * ch);
+                cc = ch;
+            }
+        } else {
+            const double D = atan2(cr, dt);
+            sincos(D / (double)ncap, &ss, &cc);
+        }
+        double ux = ax, uy = ay;
+        for (int j = 1; j <= ncap; j++) {
+            double vx, vy;
+            if (j == ncap) {
+                vx = bx;
+                vy = by;
+            } else {
+                vx = cc * ux - ss * uy;
+                vy = ss * ux + cc * uy;
+            }
+            edge_mom(R, ux - ox, uy - oy, vx - ox, vy - oy);
+            ux = vx;
+            uy = vy;
+        }
+        nseg += (1 << 16) + ncap;
+    }
 }
 
 // S0 = int 1, S1_b = int beta_b, S2 = int beta_b beta_b' (upper 00,01,02,11,12,22)

@@ -392,7 +392,8 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                     // constant kernel, rule exact for quadratics: moments of the region from its
                     // boundary (FP64 geometry), item sums rounded to FP32
                     RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, Rm, ns);
+                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, Rm, ns,
+                                           &capbuf[lane][0]);
                     double s0, s1[3], s2[6];
                     region_sums(Rm, &sV[owner][0], s0, s1, s2);
                     const double kd = (double)kc;

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 if (BND) {
                     // the rule is exact for quadratics: the region's moments from its boundary
                     RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, Rm, ns);
+                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, Rm, ns, &res[lane][0]);
                     double s0, s1[3], s2[6];
                     region_sums(Rm, &sV[owner][0], s0, s1, s2);
                     res[lane][0] = s0;
