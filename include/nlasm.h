@@ -101,7 +101,18 @@ typedef struct {
     double fallback_band;        /* learned caps: exact path when min_a | |v_a - x| - delta | <
                                     fallback_band * delta */
     uint32_t flags;              /* NLA_SKIP_IXI */
+    nla_rule outer2;             /* optional second outer rule (n = 0: none), used for the pairs
+                                    with |b_k - b_k'| < switch_dist (Sec. 8: a lower-order rule
+                                    for pairs well inside each other's ball), decided in FP64 with
+                                    every operation rounded on its own */
+    double switch_dist;
+    int32_t cap_mode;            /* retri caps: NLA_CAPS_ARCS (cap_edges equal arcs, Sec. 4.2.2) or
+                                    NLA_CAPS_CENTROID (exact caps, one-point rule at the cap
+                                    centroid with the cap area as weight, Sec. 5.2; FP64, constant
+                                    kernel, inner rule exact for quadratics) */
 } nla_problem;
+
+enum { NLA_CAPS_ARCS = 0, NLA_CAPS_CENTROID = 1 };
 
 typedef struct nla_plan nla_plan;
 

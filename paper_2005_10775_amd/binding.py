@@ -42,7 +42,8 @@ class nla_problem(C.Structure):
                 ("kernel_s", C.c_double), ("outer", nla_rule), ("inner", nla_rule),
                 ("duffy_n", C.c_int32), ("duffy_x", C.c_void_p), ("duffy_w", C.c_void_p),
                 ("ball", C.c_int32), ("cap_edges", C.c_int32), ("precision", C.c_int32),
-                ("mlp", C.c_void_p), ("fallback_band", C.c_double), ("flags", C.c_uint32)]
+                ("mlp", C.c_void_p), ("fallback_band", C.c_double), ("flags", C.c_uint32),
+                ("outer2", nla_rule), ("switch_dist", C.c_double), ("cap_mode", C.c_int32)]
 
 
 class nla_info(C.Structure):
@@ -175,9 +176,11 @@ def marshal(mesh, prob, keep, mlp=None):
         keep += [gx, gw]
         p.duffy_n, p.duffy_x, p.duffy_w = prob.duffy_order, gx.ctypes.data, gw.ctypes.data
     p.ball = BALLS[prob.ball]
-    if prob.cap_mode != "poly":
-        raise ValueError("the GPU path fills caps with equal-arc triangles (cap_mode='poly')")
+    p.cap_mode = {"poly": 0, "centroid": 1}[prob.cap_mode]
     p.cap_edges = prob.cap_edges
+    if prob.outer2:
+        p.outer2 = _rule(get_rule(prob.outer2), keep)
+        p.switch_dist = prob.switch_dist
     p.precision = PRECISIONS[prob.precision]
     p.fallback_band = prob.fallback_band
     p.flags = NLA_SKIP_IXI if prob.skip_ixi else 0

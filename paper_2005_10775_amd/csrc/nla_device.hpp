@@ -97,6 +97,31 @@ __device__ __forceinline__ void set5(double (&d)[5], double x, double y, double 
     d[0] = x; d[1] = y; d[2] = b0; d[3] = b1; d[4] = b2;
 }
 
+// Edge a->b of E' relative to the outer point (start p, direction e): whether
+// p lies in the closed ball |z| <= delta, and the roots lambda in (0,1) of
+// |p + lambda e|^2 = delta^2 (entry el1 < exit el2; 2 when absent).  Every
+// product and sum is rounded on its own, so that vertices exactly on the circle
+// (uniform grids put many there) are decided as the pair predicate and the
+// oracle decide them.
+__device__ __forceinline__ bool edge_roots(double epx, double epy, double eex, double eey, double dd, double &el1,
+                                           double &el2)
+{
+#pragma clang fp contract(off)
+    const double r2 = epx * epx + epy * epy;
+    const double L = eex * eex + eey * eey;
+    const double Bq = eex * epx + eey * epy;
+    const double disc = Bq * Bq - L * (r2 - dd);
+    el1 = 2.0;
+    el2 = 2.0;
+    if (disc > 0.0) {
+        const double sq = sqrt(disc);
+        const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
+        if (l1 > 0.0 && l1 < 1.0) el1 = l1;
+        if (l2 > 0.0 && l2 < 1.0) el2 = l2;
+    }
+    return r2 <= dd;
+}
+
 // E' n B_delta(x) retriangulated (Sec. 4.2.1-4.2.2 and Sec. 7.1 tasks 3-6) in
 // two loops, each with one inlined copy of the subtriangle quadrature tri(t):
 //  1. the edges are walked v0->v1->v2: vertices inside the closed ball and the
@@ -156,19 +181,7 @@ __device__ void partial_item(double xx, double xy, const double *Vl, double dd, 
                 eey = Vl[2 * b + 1] - ay;
                 ea = a;
                 eb = b;
-                const double r2 = epx * epx + epy * epy;
-                const double L = eex * eex + eey * eey;
-                const double Bq = eex * epx + eey * epy;
-                const double disc = Bq * Bq - L * (r2 - dd);
-                el1 = 2.0;
-                el2 = 2.0;
-                if (disc > 0.0) {
-                    const double sq = sqrt(disc);
-                    const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
-                    if (l1 > 0.0 && l1 < 1.0) el1 = l1;
-                    if (l2 > 0.0 && l2 < 1.0) el2 = l2;
-                }
-                if (r2 <= dd) {
+                if (edge_roots(epx, epy, eex, eey, dd, el1, el2)) {
                     set5(n, epx, epy, a == 0 ? 1.0 : 0.0, a == 1 ? 1.0 : 0.0, a == 2 ? 1.0 : 0.0);
                     nt = 0;
                     got = true;
@@ -266,29 +279,68 @@ __device__ void partial_item(double xx, double xy, const double *Vl, double dd, 
     }
 }
 
-__device__ __forceinline__ bool meets_edges(double xx, double xy, const double (&V)[6], double dd)
+// Barycenter ball: b_k' in the closed ball around x, rounded as the pair predicate.
+__device__ __forceinline__ bool bary_in(double xx, double xy, double bx, double by, double dd)
 {
+#pragma clang fp contract(off)
+    const double dx = xx - bx, dy = xy - by;
+    return dx * dx + dy * dy <= dd;
+}
+
+// Item class of (x, E_k') under the intersection ball: 1 whole (every vertex
+// in the closed ball), 2 partial (the ball meets the triangle otherwise), 0
+// empty.  Every product and sum is rounded on its own, so the routing pass of
+// the learned caps, the pair kernels and the oracle take identical decisions.
+__device__ __forceinline__ int item_class(double xx, double xy, const double (&V)[6], double dd)
+{
+#pragma clang fp contract(off)
+    int nin = 0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
+        nin += dx * dx + dy * dy <= dd;
+    }
+    if (nin == 3) return 1;
+    if (nin > 0) return 2;
     bool inside = true;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const int b = (a + 1) % 3;
-        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
-        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        const double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        const double px = xx - V[2 * a], py = xy - V[2 * a + 1];
         if (ex * py - ey * px < 0.0) inside = false;
     }
-    if (inside) return true;
+    if (inside) return 2;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const int b = (a + 1) % 3;
-        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
-        double px = xx - V[2 * a], py = xy - V[2 * a + 1];
-        double t = ex * px + ey * py, L = ex * ex + ey * ey;
+        const double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        const double px = xx - V[2 * a], py = xy - V[2 * a + 1];
+        const double t = ex * px + ey * py, L = ex * ex + ey * ey;
         if (t > 0.0 && t < L) {
-            double c = ex * py - ey * px;
-            if (c * c <= dd * L) return true;
+            const double c = ex * py - ey * px;
+            if (c * c <= dd * L) return 2;
         }
     }
-    return false;
+    return 0;
+}
+
+// learned caps: a partial item far from tangency, | |v_a - x| - delta | >= band delta
+// for every vertex, tested as |v_a - x|^2 >= (delta (1 + band))^2 or
+// |v_a - x|^2 <= (delta (1 - band))^2
+__device__ __forceinline__ bool item_routed(double xx, double xy, const double (&V)[6], double delta, double band)
+{
+#pragma clang fp contract(off)
+    const double hi = delta * (1.0 + band), lo = band < 1.0 ? delta * (1.0 - band) : 0.0;
+    const double hi2 = hi * hi, lo2 = lo * lo;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
+        const double d2 = dx * dx + dy * dy;
+        ok = ok && (d2 >= hi2 || d2 <= lo2);
+    }
+    return ok;
 }
 
 
@@ -339,10 +391,12 @@ __device__ __forceinline__ void edge_mom(RegionMom &R, double ax, double ay, dou
 // the fan of the region gives exactly these moments.  Coordinates about
 // vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.  cb: 12
 // doubles of scratch per call.
-template <bool POW2>
+template <bool POW2, bool CEN = false>
 __device__ void partial_boundary(double xx, double xy, const double *Vl, double dd, int ncap, RegionMom &R, int &nseg,
-                                 double *cb)
+                                 double *cb, int centroid_rt = 0, double delta = 0.0)
 {
+    // CEN: the instantiation that can take exact caps (centroid_rt selects them at run time)
+    const bool centroid = CEN && centroid_rt != 0;
     const double ox = Vl[0] - xx, oy = Vl[1] - xy;      // local origin (vertex 0) relative to x
     int cnt = 0, ft = 0, pt = 0, ncp = 0;
     double fx = 0.0, fy = 0.0, qx = 0.0, qy = 0.0;
@@ -350,7 +404,8 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
     // doubles) and integrated after it, so that the lanes of a wavefront fan
     // their caps together
     auto connect = [&](double ax, double ay, int at, double bx, double by, int bt) __attribute__((always_inline)) {
-        if (at == 2 && bt == 1 && ncap >= 2 && ax * by - ay * bx > 0.0) {
+        if (at == 2 && bt == 1 && (ncap >= 2 || centroid) && ax * by - ay * bx > 0.0) {
+            if (centroid) edge_mom(R, ax - ox, ay - oy, bx - ox, by - oy);   // the chord stays
             cb[4 * ncp] = ax;
             cb[4 * ncp + 1] = ay;
             cb[4 * ncp + 2] = bx;
@@ -378,18 +433,8 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
         const int b = a == 2 ? 0 : a + 1;
         const double epx = Vl[2 * a] - xx, epy = Vl[2 * a + 1] - xy;
         const double eex = Vl[2 * b] - Vl[2 * a], eey = Vl[2 * b + 1] - Vl[2 * a + 1];
-        const double r2 = epx * epx + epy * epy;
-        const double L = eex * eex + eey * eey;
-        const double Bq = eex * epx + eey * epy;
-        const double disc = Bq * Bq - L * (r2 - dd);
-        double el1 = 2.0, el2 = 2.0;
-        if (disc > 0.0) {
-            const double sq = sqrt(disc);
-            const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
-            if (l1 > 0.0 && l1 < 1.0) el1 = l1;
-            if (l2 > 0.0 && l2 < 1.0) el2 = l2;
-        }
-        if (r2 <= dd) emit(epx, epy, 0);
+        double el1, el2;
+        if (edge_roots(epx, epy, eex, eey, dd, el1, el2)) emit(epx, epy, 0);
         if (el1 < 1.5) emit(epx + el1 * eex, epy + el1 * eey, 1);
         if (el2 < 1.5) emit(epx + el2 * eex, epy + el2 * eey, 2);
     }
@@ -398,6 +443,31 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
     for (int ci = 0; ci < ncp; ci++) {
         const double ax = cb[4 * ci], ay = cb[4 * ci + 1], bx = cb[4 * ci + 2], by = cb[4 * ci + 3];
         const double cr = ax * by - ay * bx, dt = ax * bx + ay * by;
+        if (centroid) {
+            // exact cap by the one-point rule of Sec. 5.2: weight = cap area
+            // (delta^2/2)(2t - sin 2t), point on the bisector at 4 delta sin^3 t / (3 (2t - sin 2t)),
+            // t = half the span; a point mass adds (w, w z, w z z^T) to the moments
+            const double th = 0.5 * atan2(cr, dt);
+            double seg = 2.0 * th - sin(2.0 * th);
+            if (th < 1e-2) {                        // series of 2t - sin 2t, free of cancellation
+                const double u = 2.0 * th, u2 = u * u;
+                seg = u * u2 / 6.0 * (1.0 - u2 / 20.0 * (1.0 - u2 / 42.0 * (1.0 - u2 / 72.0)));
+            }
+            if (!(seg > 0.0)) continue;
+            const double s3 = sin(th);
+            const double dist = 4.0 * delta * s3 * s3 * s3 / (3.0 * seg);
+            const double ang = atan2(ay, ax) + th;
+            const double w = 0.5 * dd * seg;
+            const double zx = dist * cos(ang) - ox, zy = dist * sin(ang) - oy;
+            R.c += 2.0 * w;
+            R.mx += 6.0 * w * zx;
+            R.my += 6.0 * w * zy;
+            R.qxx += 12.0 * w * zx * zx;
+            R.qyy += 12.0 * w * zy * zy;
+            R.qxy += 24.0 * w * zx * zy;
+            nseg += 1 << 16;
+            continue;
+        }
         double cc, ss;
         if (POW2) {
             const double r = 1.0 / sqrt((ax * ax + ay * ay) * (bx * bx + by * by));

@@ -125,62 +125,6 @@ struct PairLDS {
     unsigned rmsk_l[64];
 };
 
-// Item class of (x, E_k') under the intersection ball: 1 whole (every vertex
-// in the closed ball), 2 partial (the ball meets the triangle otherwise), 0
-// empty.  Every product and sum is rounded on its own, so the routing pass of
-// the learned caps and the pair kernel take identical decisions.
-__device__ __forceinline__ int item_class(double xx, double xy, const double (&V)[6], double dd)
-{
-#pragma clang fp contract(off)
-    int nin = 0;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
-        nin += dx * dx + dy * dy <= dd;
-    }
-    if (nin == 3) return 1;
-    if (nin > 0) return 2;
-    bool inside = true;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const int b = (a + 1) % 3;
-        const double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
-        const double px = xx - V[2 * a], py = xy - V[2 * a + 1];
-        if (ex * py - ey * px < 0.0) inside = false;
-    }
-    if (inside) return 2;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const int b = (a + 1) % 3;
-        const double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
-        const double px = xx - V[2 * a], py = xy - V[2 * a + 1];
-        const double t = ex * px + ey * py, L = ex * ex + ey * ey;
-        if (t > 0.0 && t < L) {
-            const double c = ex * py - ey * px;
-            if (c * c <= dd * L) return 2;
-        }
-    }
-    return 0;
-}
-
-// learned caps: a partial item far from tangency, | |v_a - x| - delta | >= band delta
-// for every vertex, tested as |v_a - x|^2 >= (delta (1 + band))^2 or
-// |v_a - x|^2 <= (delta (1 - band))^2
-__device__ __forceinline__ bool item_routed(double xx, double xy, const double (&V)[6], double delta, double band)
-{
-#pragma clang fp contract(off)
-    const double hi = delta * (1.0 + band), lo = band < 1.0 ? delta * (1.0 - band) : 0.0;
-    const double hi2 = hi * hi, lo2 = lo * lo;
-    bool ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
-        const double d2 = dx * dx + dy * dy;
-        ok = ok && (d2 >= hi2 || d2 <= lo2);
-    }
-    return ok;
-}
-
 // One wavefront per outer element k, FP32 sums (structure as the FP64 kernel):
 // phase 1 classifies the items of each lane's pair and integrates whole items
 // in the lane, phase 2 retriangulates the queued partial items densely; the
@@ -279,8 +223,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 const double xx = sX[q][0], xy = sX[q][1];
                 bool whole = false, part = false;
                 if (ball == NLA_BALL_BARYCENTER) {
-                    const double dx = xx - bxp, dy = xy - byp;
-                    whole = dx * dx + dy * dy <= dd;
+                    whole = bary_in(xx, xy, bxp, byp, dd);
                 } else {
                     const int cls = item_class(xx, xy, V, dd);
                     whole = cls == 1;

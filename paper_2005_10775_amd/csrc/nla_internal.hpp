@@ -41,6 +41,10 @@ struct RuleSet {
     int32_t in_q2exact, pad_;               // inner rule integrates quadratics exactly
     double out_lam[NLA_MAX_OUTER][3];
     double out_w[NLA_MAX_OUTER];
+    int32_t n_out2, pad2_;                  // second outer rule (0: none) for pairs closer than switch_dist
+    double out2_lam[NLA_MAX_OUTER][3];
+    double out2_w[NLA_MAX_OUTER];
+    double switch_dist;
     double in_lam[NLA_MAX_INNER][3];
     double in_w[NLA_MAX_INNER];
     double in_wsum;
@@ -81,6 +85,8 @@ struct nla_plan {
     uint8_t *tin = nullptr, *nfree = nullptr;
     ElemSoA E{};
     double *xq = nullptr;      // [K][n_out][2]
+    double *xq2 = nullptr;     // [K][n_out2][2] (second outer rule)
+    uint8_t *pair_r2 = nullptr;// [n_pairs] 1: the pair takes the second outer rule
     // pairs
     int64_t n_pairs = 0;
     int64_t *pair_ptr = nullptr;

@@ -19,11 +19,13 @@ static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs -
 // reduction of sum_k' S0(x_q), and the row block R_k[a][c] = sum of -Mxy_ab
 // over the pairs whose inner slot b is node C_k[c], reduced in LDS column by
 // column in pair order (each column owned by one lane).
-template <int NQ, bool SYM, bool POW2, bool BND>
+template <int NQ, bool SYM, bool POW2, bool BND, bool SW>
 __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
                                                          const int32_t *__restrict__ pair_kp, ElemSoA E,
                                                          const double *__restrict__ xq, const RuleSet *__restrict__ R,
-                                                         double dd, double psi, int ball, int ncap,
+                                                         double dd, double psi, int ball, int ncap, int centroid,
+                                                         double delta, const double *__restrict__ xq2,
+                                                         const uint8_t *__restrict__ pair_r2,
                                                          const int64_t *__restrict__ col_off,
                                                          const int32_t *__restrict__ colent_ptr,
                                                          const uint16_t *__restrict__ colent, double *__restrict__ Rout,
@@ -33,6 +35,10 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     extern __shared__ double dyn[];
     __shared__ double sW[NQ][4];
     __shared__ double sX[NQ][2];
+    // SW: the second outer rule's weights and points (pairs with pair_r2 set); this
+// variant also integrates exact caps by the centroid rule when asked
+    __shared__ double sW2[SW ? NQ : 1][4];
+    __shared__ double sX2[SW ? NQ : 1][2];
     __shared__ double sV[64][7];
     __shared__ unsigned short queue[64 * NQ];
     // item results of a phase-2 round, later the chunk's -Mxy (never live together)
@@ -50,6 +56,16 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         sX[lane][0] = xq[2 * ((int64_t)k * nq + lane)];
         sX[lane][1] = xq[2 * ((int64_t)k * nq + lane) + 1];
     }
+    const int nq2 = SW ? R->n_out2 : 0;
+    if (SW && lane < nq2) {
+        double W = R->out2_w[lane] * a2k;
+        sW2[lane][0] = W;
+        sW2[lane][1] = W * R->out2_lam[lane][0];
+        sW2[lane][2] = W * R->out2_lam[lane][1];
+        sW2[lane][3] = W * R->out2_lam[lane][2];
+        sX2[lane][0] = xq2[2 * ((int64_t)k * nq2 + lane)];
+        sX2[lane][1] = xq2[2 * ((int64_t)k * nq2 + lane) + 1];
+    }
     __syncthreads();
     const RuleMom M = load_moments(R);
     const int64_t coff = col_off[k];
@@ -62,9 +78,11 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         R_l[2 * nC + c] = 0.0;
         cur_l[c] = colent_ptr[coff + c];
     }
-    double m0[NQ];
+    double m0[NQ], m0b[SW ? NQ : 1];
 #pragma unroll
     for (int q = 0; q < NQ; q++) m0[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < (SW ? NQ : 1); q++) m0b[q] = 0.0;
     unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
     for (int64_t base = p0; base < p1; base += 64) {
@@ -83,31 +101,29 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         for (int i = 0; i < 6; i++) sV[lane][i] = V[i];
         double ws = 0.0, aw[3] = {0.0, 0.0, 0.0};
         unsigned pmask = 0;
+        const bool r2 = SW && nq2 > 0 && act && pair_r2[p];
+        const int nqp = r2 ? nq2 : nq;
         if (act) {
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
-                if (q >= nq) break;
-                const double xx = sX[q][0], xy = sX[q][1];
+                if (q >= nqp) break;
+                const double xx = r2 ? sX2[q][0] : sX[q][0], xy = r2 ? sX2[q][1] : sX[q][1];
                 bool whole = false, part = false;
                 if (ball == NLA_BALL_BARYCENTER) {
-                    double dx = xx - bxp, dy = xy - byp;
-                    whole = dx * dx + dy * dy <= dd;
+                    whole = bary_in(xx, xy, bxp, byp, dd);
                 } else {
-                    int nin = 0;
-#pragma unroll
-                    for (int a = 0; a < 3; a++) {
-                        double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
-                        nin += dx * dx + dy * dy <= dd;
-                    }
-                    whole = nin == 3;
-                    part = !whole && (nin > 0 || meets_edges(xx, xy, V, dd));
+                    const int cls = item_class(xx, xy, V, dd);
+                    whole = cls == 1;
+                    part = cls == 2;
                 }
                 if (whole) {
-                    ws += sW[q][0];
-                    aw[0] += sW[q][1];
-                    aw[1] += sW[q][2];
-                    aw[2] += sW[q][3];
-                    m0[q] += a2p * M.wsum;
+                    const double *w4 = r2 ? sW2[q] : sW[q];
+                    ws += w4[0];
+                    aw[0] += w4[1];
+                    aw[1] += w4[2];
+                    aw[2] += w4[3];
+                    if (r2) m0b[q] += a2p * M.wsum;
+                    else m0[q] += a2p * M.wsum;
                     c_whole++;
                 } else if (part) {
                     pmask |= 1u << q;
@@ -143,14 +159,16 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             while (mm) {
                 int q = __ffs(mm) - 1;
                 mm &= mm - 1;
-                queue[o++] = (unsigned short)((lane << 8) | q);
+                queue[o++] = (unsigned short)((lane << 8) | (r2 ? 0x80 : 0) | q);
             }
         }
         __syncthreads();
         for (int ib = 0; ib < total; ib += 64) {
             const int i = ib + lane;
             if (i < total) {
-                const int e = queue[i], owner = e >> 8, q = e & 0xff;
+                const int e = queue[i], owner = e >> 8, q = e & 0x0f;
+                const bool rr = SW && (e & 0x80);
+                const double qx = rr ? sX2[q][0] : sX[q][0], qy = rr ? sX2[q][1] : sX[q][1];
                 Acc A;
                 A.a2 = 0.0;
 #pragma unroll
@@ -161,7 +179,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 if (BND) {
                     // the rule is exact for quadratics: the region's moments from its boundary
                     RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, Rm, ns, &res[lane][0]);
+                    partial_boundary<POW2, SW>(qx, qy, &sV[owner][0], dd, ncap, Rm, ns, &res[lane][0], centroid, delta);
                     double s0, s1[3], s2[6];
                     region_sums(Rm, &sV[owner][0], s0, s1, s2);
                     res[lane][0] = s0;
@@ -172,7 +190,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 } else {
                     auto tri = [&](const double (&t)[3][5]) { tri_accum<SYM>(t, M, A); };
                     // the cap endpoints live in this lane's row of res until the sums are written
-                    partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, ncap, tri, ns, &res[lane][0]);
+                    partial_item<POW2>(qx, qy, &sV[owner][0], dd, ncap, tri, ns, &res[lane][0]);
                     res[lane][0] = A.a2 * M.wsum;
 #pragma unroll
                     for (int t = 0; t < 3; t++) res[lane][1 + t] = SYM ? A.s1[t] * M.m1c : A.s1[t];
@@ -186,16 +204,21 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             const int j0 = pre > ib ? pre : ib;
             const int j1 = (pre + cnt) < (ib + 64) ? (pre + cnt) : (ib + 64);
             for (int j = j0; j < j1; j++) {
-                const int q = queue[j] & 0xff;
+                const int q = queue[j] & 0x0f;
+                const bool rr = SW && (queue[j] & 0x80);
                 const double *r = res[j - ib];
 #pragma unroll
                 for (int qq = 0; qq < NQ; qq++)
-                    if (qq == q) m0[qq] += r[0];
-                const double W = sW[q][0];
+                    if (qq == q) {
+                        if (rr) m0b[qq] += r[0];
+                        else m0[qq] += r[0];
+                    }
+                const double *w4 = rr ? sW2[q] : sW[q];
+                const double W = w4[0];
 #pragma unroll
                 for (int a = 0; a < 3; a++)
 #pragma unroll
-                    for (int b = 0; b < 3; b++) axy[a][b] += sW[q][1 + a] * r[1 + b];
+                    for (int b = 0; b < 3; b++) axy[a][b] += w4[1 + a] * r[1 + b];
 #pragma unroll
                 for (int t = 0; t < 6; t++) ayy[t] += W * r[4 + t];
             }
@@ -244,6 +267,12 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
         m0[q] = __shfl(x, 0, 64);
     }
+#pragma unroll
+    for (int q = 0; q < (SW ? NQ : 0); q++) {
+        double x = m0b[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        m0b[q] = __shfl(x, 0, 64);
+    }
     if (lane < 6) {
         const int aa[6] = {0, 0, 0, 1, 1, 2}, cc[6] = {0, 1, 2, 1, 2, 2};
         const int a = aa[lane], c = cc[lane];
@@ -251,6 +280,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
 #pragma unroll
         for (int q = 0; q < NQ; q++)
             if (q < nq) s += sW[q][1 + a] * R->out_lam[q][c] * m0[q];
+#pragma unroll
+        for (int q = 0; q < (SW ? NQ : 0); q++)
+            if (q < nq2) s += sW2[q][1 + a] * R->out2_lam[q][c] * m0b[q];
         Cxx[6 * (int64_t)k + lane] = psi * s;
     }
     // work counters
@@ -403,21 +435,30 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         nla_mark(P, NLA_PHASE_PAIRS, s);
         const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
         const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
-#define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND)                                                                       \
-    k_pairs_const_fp64<NQ, SYM, POW2, BND><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules,          \
-                                                         pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap, P->col_off, \
-                                                         P->colent_ptr, P->colent, V, Cyy, Cxx, P->max_cols,          \
-                                                         P->counters)
+#define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND, SW)                                                                   \
+    k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, lds, s>>>(                                                  \
+        P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,           \
+        pr.cap_mode == NLA_CAPS_CENTROID ? 1 : 0, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr,            \
+        P->colent, V, Cyy, Cxx, P->max_cols, P->counters)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
         const bool bnd = P->rules.in_q2exact != 0 && pr.ball == NLA_BALL_RETRI;
-        if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true);
-        else if (P->rules.n_out <= 8 && bnd) NLA_LAUNCH_PAIRS(8, true, false, true);
-        else if (P->rules.n_out <= 8 && sym && pow2) NLA_LAUNCH_PAIRS(8, true, true, false);
-        else if (P->rules.n_out <= 8 && sym) NLA_LAUNCH_PAIRS(8, true, false, false);
-        else if (P->rules.n_out <= 8) NLA_LAUNCH_PAIRS(8, false, false, false);
-        else if (bnd) NLA_LAUNCH_PAIRS(16, false, false, true);
-        else NLA_LAUNCH_PAIRS(16, false, false, false);
+        // the variant with the second outer rule also carries the exact (centroid) caps
+        const bool sw = P->rules.n_out2 > 0 || pr.cap_mode == NLA_CAPS_CENTROID;
+        if (sw && !(sym && pow2 && P->rules.n_out <= 8)) {
+            nla_set_error("a second outer rule needs outer rules of at most 8 points, a symmetric inner rule and "
+                          "2^m arcs per cap");
+            return NLA_E_UNSUPPORTED;
+        }
+        if (sw && bnd) NLA_LAUNCH_PAIRS(8, true, true, true, true);
+        else if (sw) NLA_LAUNCH_PAIRS(8, true, true, false, true);
+        else if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true, false);
+        else if (P->rules.n_out <= 8 && bnd) NLA_LAUNCH_PAIRS(8, true, false, true, false);
+        else if (P->rules.n_out <= 8 && sym && pow2) NLA_LAUNCH_PAIRS(8, true, true, false, false);
+        else if (P->rules.n_out <= 8 && sym) NLA_LAUNCH_PAIRS(8, true, false, false, false);
+        else if (P->rules.n_out <= 8) NLA_LAUNCH_PAIRS(8, false, false, false, false);
+        else if (bnd) NLA_LAUNCH_PAIRS(16, false, false, true, false);
+        else NLA_LAUNCH_PAIRS(16, false, false, false, false);
 #undef NLA_LAUNCH_PAIRS
         NLA_HIP(hipGetLastError());
         P->ran[NLA_PHASE_PAIRS] = true;

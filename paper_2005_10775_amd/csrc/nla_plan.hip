@@ -151,6 +151,52 @@ static int validate(const nla_mesh *m, const nla_problem *p)
         if (std::fabs(ws - 0.5) > 1e-12) { nla_set_error("rule weights must sum to 1/2"); return NLA_E_INVALID; }
     }
     if (p->flags & ~(uint32_t)NLA_SKIP_IXI) { nla_set_error("unknown flags"); return NLA_E_INVALID; }
+    if (p->outer2.n != 0) {
+        if (p->outer2.n < 0 || p->outer2.n > NLA_MAX_OUTER || !p->outer2.lambda || !p->outer2.w) {
+            nla_set_error("second outer rule must have 1..%d points", NLA_MAX_OUTER);
+            return NLA_E_INVALID;
+        }
+        double ws = 0;
+        for (int q = 0; q < p->outer2.n; q++) {
+            const double *l = p->outer2.lambda + 3 * q;
+            if (!(l[0] >= 0 && l[1] >= 0 && l[2] >= 0) || std::fabs(l[0] + l[1] + l[2] - 1.0) > 1e-12) {
+                nla_set_error("second outer rule point %d is not barycentric", q);
+                return NLA_E_INVALID;
+            }
+            ws += p->outer2.w[q];
+        }
+        if (std::fabs(ws - 0.5) > 1e-12) { nla_set_error("rule weights must sum to 1/2"); return NLA_E_INVALID; }
+        if (!(p->switch_dist >= 0.0) || !std::isfinite(p->switch_dist)) {
+            nla_set_error("switch_dist must be finite and >= 0");
+            return NLA_E_INVALID;
+        }
+        if (p->precision != NLA_FP64) {
+            nla_set_error("the second outer rule is supported in NLA_FP64");
+            return NLA_E_UNSUPPORTED;
+        }
+    }
+    if (p->cap_mode != NLA_CAPS_ARCS && p->cap_mode != NLA_CAPS_CENTROID) {
+        nla_set_error("unknown cap_mode %d", p->cap_mode);
+        return NLA_E_INVALID;
+    }
+    if (p->cap_mode == NLA_CAPS_CENTROID) {
+        // exact caps by the one-point centroid rule ride on the boundary-moment integration
+        double m1 = 0, m11 = 0, m12 = 0, ws = 0;
+        for (int q = 0; q < p->inner.n; q++) {
+            const double *l = p->inner.lambda + 3 * q;
+            ws += p->inner.w[q];
+            m1 += p->inner.w[q] * l[0];
+            m11 += p->inner.w[q] * l[0] * l[0];
+            m12 += p->inner.w[q] * l[0] * l[1];
+        }
+        const bool q2 = std::fabs(ws - 0.5) <= 1e-14 && std::fabs(m1 - 1.0 / 6.0) <= 1e-14 &&
+                        std::fabs(m11 - 1.0 / 12.0) <= 1e-14 && std::fabs(m12 - 1.0 / 24.0) <= 1e-14;
+        if (p->ball != NLA_BALL_RETRI || p->kernel != NLA_KERNEL_CONSTANT || p->precision != NLA_FP64 || !q2) {
+            nla_set_error("centroid caps need the intersection ball, the constant kernel, NLA_FP64 and an inner rule "
+                          "exact for quadratics");
+            return NLA_E_UNSUPPORTED;
+        }
+    }
     // mesh rules of Sec. 3.1
     const int J = m->n_vertices, K = m->n_triangles;
     for (int i = 0; i < 2 * J; i++)
@@ -190,7 +236,7 @@ static int validate(const nla_mesh *m, const nla_problem *p)
 
 // ---------------------------------------------------------------- kernels
 __global__ void k_elem(int K, const double *__restrict__ xy, const int32_t *__restrict__ tri, ElemSoA E,
-                       const RuleSet *__restrict__ R, double *__restrict__ xq)
+                       const RuleSet *__restrict__ R, double *__restrict__ xq, double *__restrict__ xq2)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
@@ -218,6 +264,28 @@ __global__ void k_elem(int K, const double *__restrict__ xy, const int32_t *__re
         xq[2 * ((int64_t)k * nq + q)] = (l0 * x0 + l1 * x1) + l2 * x2;
         xq[2 * ((int64_t)k * nq + q) + 1] = (l0 * y0 + l1 * y1) + l2 * y2;
     }
+    const int nq2 = R->n_out2;
+    for (int q = 0; q < nq2; q++) {
+        const double l0 = R->out2_lam[q][0], l1 = R->out2_lam[q][1], l2 = R->out2_lam[q][2];
+        xq2[2 * ((int64_t)k * nq2 + q)] = (l0 * x0 + l1 * x1) + l2 * x2;
+        xq2[2 * ((int64_t)k * nq2 + q) + 1] = (l0 * y0 + l1 * y1) + l2 * y2;
+    }
+}
+
+// the pair takes the second outer rule when |b_k - b_k'| < switch_dist
+__device__ __forceinline__ bool use_rule2(double bkx, double bky, double bpx, double bpy, double sd)
+{
+    const double dx = bkx - bpx, dy = bky - bpy;
+    return dx * dx + dy * dy < sd * sd;
+}
+
+__global__ void k_pair_rule2(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, ElemSoA E,
+                             double sd, uint8_t *__restrict__ r2)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int k = pk[p], kp = pkp[p];
+    r2[p] = use_rule2(E.bx[k], E.by[k], E.bx[kp], E.by[kp], sd) ? 1 : 0;
 }
 
 struct Grid {
@@ -300,9 +368,9 @@ struct PairQuery {
     const int32_t *cell_start;   // [ncell+1]
     const int32_t *cell_elems;
     const uint8_t *tin;
-    const double *xq;
-    double delta, dd;
-    int nq, ball, skip_ixi;
+    const double *xq, *xq2;     // outer points of the first and the second rule
+    double delta, dd, sd;       // sd: switch distance of the second rule
+    int nq, nq2, ball, skip_ixi;
 };
 
 // candidate ranges of the 3x3 cells around element k
@@ -338,7 +406,7 @@ __device__ __forceinline__ int candidate_at(const PairQuery &Q, const int (&lo)[
 }
 
 __device__ __forceinline__ bool pair_test(const PairQuery &Q, const ElemSoA &E, int k, int kp, double bk_x, double bk_y,
-                                          double rk, const double *xs)
+                                          double rk, const double *xs, const double *xs2)
 {
     if (Q.skip_ixi && !Q.tin[k] && !Q.tin[kp]) return false;
     double bx = E.bx[kp], by = E.by[kp];
@@ -346,23 +414,28 @@ __device__ __forceinline__ bool pair_test(const PairQuery &Q, const ElemSoA &E, 
     reach = reach * (1.0 + 1e-9) + 1e-14;
     double ddx = bk_x - bx, ddy = bk_y - by;
     if (!(ddx * ddx + ddy * ddy <= reach * reach)) return false;
+    // the outer points of the pair's rule
+    const bool r2 = Q.nq2 > 0 && use_rule2(bk_x, bk_y, bx, by, Q.sd);
+    const double *pts = r2 ? xs2 : xs;
+    const int nq = r2 ? Q.nq2 : Q.nq;
     if (Q.ball == NLA_BALL_BARYCENTER) {
-        for (int q = 0; q < Q.nq; q++)
-            if (bary_in(xs[2 * q], xs[2 * q + 1], bx, by, Q.dd)) return true;
+        for (int q = 0; q < nq; q++)
+            if (bary_in(pts[2 * q], pts[2 * q + 1], bx, by, Q.dd)) return true;
         return false;
     }
     double V[6] = {E.vx0[kp], E.vy0[kp], E.vx1[kp], E.vy1[kp], E.vx2[kp], E.vy2[kp]};
-    for (int q = 0; q < Q.nq; q++)
-        if (ball_meets(xs[2 * q], xs[2 * q + 1], V, Q.dd)) return true;
+    for (int q = 0; q < nq; q++)
+        if (ball_meets(pts[2 * q], pts[2 * q + 1], V, Q.dd)) return true;
     return false;
 }
 
 __global__ __launch_bounds__(256) void k_pair_count(int K, PairQuery Q, ElemSoA E, int32_t *__restrict__ cnt)
 {
-    __shared__ double xs[2 * NLA_MAX_OUTER];
+    __shared__ double xs[2 * NLA_MAX_OUTER], xs2[2 * NLA_MAX_OUTER];
     __shared__ int red[256 / 64];
     const int k = blockIdx.x, tid = threadIdx.x;
     if (tid < 2 * Q.nq) xs[tid] = Q.xq[2 * (int64_t)k * Q.nq + tid];
+    if (tid < 2 * Q.nq2) xs2[tid] = Q.xq2[2 * (int64_t)k * Q.nq2 + tid];
     __syncthreads();
     const double bx = E.bx[k], by = E.by[k], rk = E.r[k];
     int lo[9], n[9];
@@ -370,7 +443,7 @@ __global__ __launch_bounds__(256) void k_pair_count(int K, PairQuery Q, ElemSoA 
     int c = 0;
     for (int i = tid; i < tot; i += blockDim.x) {
         int kp = candidate_at(Q, lo, n, i);
-        c += pair_test(Q, E, k, kp, bx, by, rk, xs) ? 1 : 0;
+        c += pair_test(Q, E, k, kp, bx, by, rk, xs, xs2) ? 1 : 0;
     }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
     if ((tid & 63) == 0) red[tid >> 6] = c;
@@ -388,11 +461,12 @@ __global__ __launch_bounds__(256) void k_pair_count(int K, PairQuery Q, ElemSoA 
 __global__ __launch_bounds__(256) void k_pair_emit(int K, PairQuery Q, ElemSoA E, const int64_t *__restrict__ ptr,
                                                    int32_t *__restrict__ out)
 {
-    __shared__ double xs[2 * NLA_MAX_OUTER];
+    __shared__ double xs[2 * NLA_MAX_OUTER], xs2[2 * NLA_MAX_OUTER];
     __shared__ int hits[NLA_MAX_PAIRS_PER_K];
     __shared__ int nh;
     const int k = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     if (tid < 2 * Q.nq) xs[tid] = Q.xq[2 * (int64_t)k * Q.nq + tid];
+    if (tid < 2 * Q.nq2) xs2[tid] = Q.xq2[2 * (int64_t)k * Q.nq2 + tid];
     if (tid == 0) nh = 0;
     __syncthreads();
     const double bx = E.bx[k], by = E.by[k], rk = E.r[k];
@@ -405,7 +479,7 @@ __global__ __launch_bounds__(256) void k_pair_emit(int K, PairQuery Q, ElemSoA E
         bool hit = false;
         if (i < tot) {
             kp = candidate_at(Q, lo, n, i);
-            hit = pair_test(Q, E, k, kp, bx, by, rk, xs);
+            hit = pair_test(Q, E, k, kp, bx, by, rk, xs, xs2);
         }
         unsigned long long mask = __ballot(hit);
         int wcnt = __popcll(mask);
@@ -842,9 +916,12 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
     Q.cell_elems = elems;
     Q.tin = P->tin;
     Q.xq = P->xq;
+    Q.xq2 = P->xq2;
     Q.delta = pr.delta;
     Q.dd = pr.delta * pr.delta;
+    Q.sd = P->rules.switch_dist;
     Q.nq = P->rules.n_out;
+    Q.nq2 = P->rules.n_out2;
     Q.ball = pr.ball;
     Q.skip_ixi = (pr.flags & NLA_SKIP_IXI) ? 1 : 0;
     k_pair_count<<<K, 256, 0, s>>>(K, Q, P->E, pcnt);
@@ -873,6 +950,11 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
     NLA_HIP(hipMemcpyAsync(P->pair_ptr, hptr.data(), sizeof(int64_t) * (K + 1), hipMemcpyHostToDevice, s));
     k_pair_emit<<<K, 256, 0, s>>>(K, Q, P->E, P->pair_ptr, P->pair_kp);
     k_pair_k<<<K, 256, 0, s>>>(K, P->pair_ptr, P->pair_k);
+    if (P->rules.n_out2 > 0 && P->n_pairs > 0) {
+        NLA_TRY(P->arena.get(&P->pair_r2, P->n_pairs));
+        k_pair_rule2<<<grid_for(P->n_pairs, 256), 256, 0, s>>>(P->n_pairs, P->pair_k, P->pair_kp, P->E,
+                                                              P->rules.switch_dist, P->pair_r2);
+    }
     NLA_HIP(hipGetLastError());
     NLA_HIP(hipStreamSynchronize(s));
     return NLA_OK;
@@ -1141,6 +1223,12 @@ static void fill_rules(const nla_problem *p, RuleSet *R)
         for (int a = 0; a < 3; a++) R->out_lam[q][a] = p->outer.lambda[3 * q + a];
         R->out_w[q] = p->outer.w[q];
     }
+    R->n_out2 = p->outer2.n > 0 ? p->outer2.n : 0;
+    for (int q = 0; q < R->n_out2; q++) {
+        for (int a = 0; a < 3; a++) R->out2_lam[q][a] = p->outer2.lambda[3 * q + a];
+        R->out2_w[q] = p->outer2.w[q];
+    }
+    R->switch_dist = R->n_out2 > 0 ? p->switch_dist : 0.0;
     for (int q = 0; q < p->inner.n; q++) {
         for (int a = 0; a < 3; a++) {
             R->in_lam[q][a] = p->inner.lambda[3 * q + a];
@@ -1189,6 +1277,7 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
     P->prob.duffy_x = nullptr;
     P->prob.duffy_w = nullptr;
     P->prob.outer.lambda = P->prob.outer.w = nullptr;
+    P->prob.outer2.lambda = P->prob.outer2.w = nullptr;
     P->prob.inner.lambda = P->prob.inner.w = nullptr;
     fill_rules(p, &P->rules);
     const int K = P->K, J = P->J;
@@ -1203,6 +1292,7 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
                       &P->E.bx, &P->E.by, &P->E.a2, &P->E.r};
     for (int i = 0; i < 10; i++) *f[i] = eb + (size_t)i * K;
     NLA_TRY(P->arena.get(&P->xq, 2 * (size_t)K * P->rules.n_out));
+    if (P->rules.n_out2 > 0) NLA_TRY(P->arena.get(&P->xq2, 2 * (size_t)K * P->rules.n_out2));
     NLA_HIP(hipMemcpyAsync(P->d_rules, &P->rules, sizeof(RuleSet), hipMemcpyHostToDevice, s));
     NLA_HIP(hipMemcpyAsync(P->xy, m->xy, sizeof(double) * 2 * J, hipMemcpyHostToDevice, s));
     NLA_HIP(hipMemcpyAsync(P->tri, m->tri, sizeof(int32_t) * 3 * K, hipMemcpyHostToDevice, s));
@@ -1248,7 +1338,7 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
     NLA_HIP(hipMemcpyAsync(P->node_to_free, n2f.data(), sizeof(int32_t) * J, hipMemcpyHostToDevice, s));
     NLA_HIP(hipMemcpyAsync(P->n2e_ptr, n2e_ptr.data(), sizeof(int32_t) * (J + 1), hipMemcpyHostToDevice, s));
     if (!n2e.empty()) NLA_HIP(hipMemcpyAsync(P->n2e, n2e.data(), sizeof(int32_t) * n2e.size(), hipMemcpyHostToDevice, s));
-    k_elem<<<grid_for(K, 128), 128, 0, s>>>(K, P->xy, P->tri, P->E, P->d_rules, P->xq);
+    k_elem<<<grid_for(K, 128), 128, 0, s>>>(K, P->xy, P->tri, P->E, P->d_rules, P->xq, P->xq2);
     NLA_HIP(hipGetLastError());
     NLA_TRY(nla_build_pairs(P, s));
     NLA_TRY(nla_build_pattern(P, s));

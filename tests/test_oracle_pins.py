@@ -380,11 +380,8 @@ def test_load_vector_constant_source():
 
 # ----------------------------------------------------- paper's worked example
 def _paper_problem(h, ball):
-    d = 0.1
-    kw = {"approxcaps": dict(ball="retri", cap_edges=2), "nocaps": dict(ball="retri", cap_edges=0),
-          "exactcaps": dict(ball="retri", cap_mode="centroid"), "barycenter": dict(ball="barycenter")}[ball]
-    return Problem(delta=d, kernel_c=constant_kernel_c(d), outer="vertex7", inner="gauss3",
-                   outer2="strang4", switch_dist=d - math.sqrt(2) * h, **kw)
+    from workloads import paper_workload
+    return paper_workload(h, ball)[1]
 
 
 @pytest.mark.parametrize("ball", ["approxcaps", "nocaps"])

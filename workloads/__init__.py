@@ -8,8 +8,8 @@ volume-constraint data, and counter-based random numbers).
 from .mesh import Mesh, structured_mesh, splitmix64_uniform
 from .rules import Rule, get_rule, RULE_NAMES
 from .problems import (Problem, constant_kernel_c, fractional_kernel_c,
-                       CONFIGS, make_config, manufactured, batch_instances)
+                       CONFIGS, make_config, manufactured, batch_instances, paper_workload)
 
 __all__ = ["Mesh", "structured_mesh", "splitmix64_uniform", "Rule", "get_rule",
            "RULE_NAMES", "Problem", "constant_kernel_c", "fractional_kernel_c",
-           "CONFIGS", "make_config", "manufactured", "batch_instances"]
+           "CONFIGS", "make_config", "manufactured", "batch_instances", "paper_workload"]

@@ -53,6 +53,21 @@ def manufactured(name):
     raise KeyError(name)
 
 
+def paper_workload(h, ball, delta=0.1):
+    """The workload of Sec. 8: uniform grid (a) with spacing h, delta = 0.1, the
+    constant kernel, u = x1^2 x2 + x2^2 with f = -2(x2 + 1); the 7-point
+    vertex/mid-side/centroid outer rule, switched to the 4-point rule for pairs
+    with |b_k - b_k'| < delta - h_max (h_max = sqrt(2) h, the element diameter);
+    the 3-point inner rule; balls: "approxcaps" (one triangle per cap: two arcs
+    fanned from the chord midpoint), "nocaps", "exactcaps" (one-point centroid
+    rule on the true caps) and "barycenter"."""
+    kw = {"approxcaps": dict(ball="retri", cap_edges=2), "nocaps": dict(ball="retri", cap_edges=0),
+          "exactcaps": dict(ball="retri", cap_mode="centroid"), "barycenter": dict(ball="barycenter")}[ball]
+    p = Problem(delta=delta, kernel_c=constant_kernel_c(delta), outer="vertex7", inner="gauss3",
+                outer2="strang4", switch_dist=delta - math.sqrt(2) * h, **kw)
+    return structured_mesh(delta, h), p, "paper"
+
+
 def _c1():
     d = 0.1
     p = Problem(delta=d, kernel="constant", kernel_c=constant_kernel_c(d), ball="barycenter",
