@@ -113,7 +113,9 @@ class OracleProblem:
         p.kernel = {"constant": 0, "fractional": 1}[prob.kernel]
         p.kc = prob.kernel_c
         p.ks = prob.kernel_s
-        p.ball = {"barycenter": 0, "retri": 1}[prob.ball]
+        p.ball = {"barycenter": 0, "retri": 1, "overlap": 2, "shifted": 3, "barysupport": 4}[prob.ball]
+        if p.ball >= 2 and p.kernel != 0:
+            raise ValueError("the overlap, shifted and barysupport balls take the constant kernel")
         p.cap_mode = {"poly": 0, "centroid": 1}[prob.cap_mode]
         p.cap_edges = prob.cap_edges
         ro = get_rule(prob.outer)

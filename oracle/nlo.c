@@ -17,7 +17,12 @@
  *     triangles over equal arcs (Sec. 4.2.2) or integrated by the one-point
  *     centroid rule of Sec. 5.2 (the cap weight is the cap area of
  *     Eq. (areacap); the factor 1/4 printed next to the centroid formula is
- *     read as 1/2, which is what Eq. (areacap) gives);
+ *     read as 1/2, which is what Eq. (areacap) gives); the overlap ball (Eq.
+ *     (overlap): whole elements meeting B_delta(x)); the shifted ball of
+ *     Sec. 4.3 (the intersection ball about b_k for every point of E_k); and the
+ *     barycenter ball with its outer support resolved (Sec. 6, case 2: the outer
+ *     rule over the nocaps / approxcaps region of E_k n B_delta(b_k'), the inner
+ *     integral over the whole E_k'); the last three for the constant kernel;
  *   - the geometric tasks 1-6 of Sec. 7.1 (vertex test, edge-circle quadratic,
  *     counter-clockwise ordering and fan triangulation from the first point);
  *   - composite inner rules of Eq. (cqr1), outer rule of Sec. 6 (optionally
@@ -30,7 +35,11 @@
  * Parity pins: see tests/test_oracle_pins.py (rule moments, kernel
  * normalisation, closed-form whole pairs, exact ball area/second moment with
  * analytic caps, brute-force region moments, matrix invariants, load vector,
- * the paper's printed L2 errors of Sec. 8).
+ * the paper's printed L2 errors of Sec. 8 for the nocaps, approxcaps, overlap,
+ * shifted and barycenter-support balls, the x <-> y identity between the
+ * shifted and barycenter-support matrices, grid (b)'s printed element sizes).
+ * Parity unpinned: the printed barycenter column of Sec. 8.1 and the grid (b)
+ * columns are not reproduced (lattice ties; the unstated diagonal direction).
  */
 #include "nlo.h"
 #include <math.h>
@@ -164,6 +173,11 @@ static int pair_interacts(const nlo_problem *p, const double Vk[6], const double
                           const double Vkp[6], const double bkp[2])
 {
     double dd = p->delta * p->delta;
+    /* shifted (Sec. 4.3): every point of E_k uses the ball about b_k */
+    if (p->ball == 3) return ball_meets_triangle(bk, Vkp, dd);
+    /* barycenter, outer support (Sec. 6, case 2): some x in E_k has b_k' in
+     * B_delta(x), i.e. E_k meets the ball about b_k' */
+    if (p->ball == 4) return ball_meets_triangle(bkp, Vk, dd);
     int nq;
     const double *lam, *w;
     pair_rule(p, bk, bkp, &nq, &lam, &w);
@@ -173,6 +187,7 @@ static int pair_interacts(const nlo_problem *p, const double Vk[6], const double
         if (p->ball == 0) {
             if (bary_in(x, bkp, dd)) return 1;
         } else {
+            /* intersection and overlap balls: E_k' meets B_delta(x) */
             if (ball_meets_triangle(x, Vkp, dd)) return 1;
         }
     }
@@ -337,6 +352,16 @@ int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
         if (!bary_in(x, b, dd)) return 0;
         memcpy(sub, V, 6 * sizeof(double));
         ns = 1;
+    } else if (p->ball == 2) {
+        /* overlap ball, Eq. (overlap): the whole element when it meets B_delta(x) */
+        if (!ball_meets_triangle(x, V, dd)) return 0;
+        memcpy(sub, V, 6 * sizeof(double));
+        ns = 1;
+    } else if (p->ball == 4) {
+        /* barycenter ball with the outer support resolved: x lies in the
+         * support, so the whole inner element */
+        memcpy(sub, V, 6 * sizeof(double));
+        ns = 1;
     } else {
         if (p->learned) {
             /* a partial item (some vertex outside the ball, at least one cap)
@@ -451,10 +476,56 @@ int nlo_pair_block(const nlo_mesh *m, const nlo_problem *p, int32_t k, int32_t k
     pair_rule(p, bk, bkp, &nq, &lam, &w);
     double ak2 = twice_area(Vk);
     double mxx[9] = {0};
+    if (p->ball == 4) {
+        /* Sec. 6, case 2 for the barycenter ball: the outer integrand vanishes
+         * outside S = E_k n B_delta(b_k'), so the outer rule is applied to the
+         * triangles of S's nocaps / approxcaps region (and exact caps by their
+         * one-point centroid rule); at each such x the inner integral runs over
+         * the whole E_k'. */
+        double sub[6 * NLO_MAXSUB], cpt[2 * 8], cw[8];
+        int nc = 0;
+        nlo_problem pr = *p;
+        pr.ball = 1;
+        int ns = nlo_region(&pr, bkp, Vk, sub, NLO_MAXSUB, cpt, cw, &nc);
+        if (ns < 0) return ns;
+        for (int q = 0; q < 64; q++) s0q[q] = 0.0;
+        for (int t = 0; t < ns + nc; t++) {
+            int npt = t < ns ? nq : 1;
+            for (int q = 0; q < npt; q++) {
+                double x[2], al[3], Wq, S0, S1[3], S2[9];
+                if (t < ns) {
+                    map_point(sub + 6 * t, lam + 3 * q, x);
+                    Wq = w[q] * twice_area(sub + 6 * t);
+                } else {
+                    x[0] = cpt[2 * (t - ns)];
+                    x[1] = cpt[2 * (t - ns) + 1];
+                    Wq = cw[t - ns];
+                }
+                basis_at(Vk, x, al);
+                int st = nlo_inner_sums(p, x, Vkp, &S0, S1, S2);
+                if (st < 0) return st;
+                for (int a = 0; a < 3; a++) {
+                    for (int c = 0; c < 3; c++) mxx[3 * a + c] += Wq * al[a] * al[c] * S0;
+                    for (int b = 0; b < 3; b++) mxy[3 * a + b] += Wq * al[a] * S1[b];
+                }
+                for (int i = 0; i < 9; i++) myy[i] += Wq * S2[i];
+            }
+        }
+        nq = 0;
+    }
     for (int q = 0; q < nq; q++) {
         double x[2], S0, S1[3], S2[9];
         map_point(Vk, lam + 3 * q, x);
-        int st = nlo_inner_sums(p, x, Vkp, &S0, S1, S2);
+        int st;
+        if (p->ball == 3) {
+            /* shifted ball (Sec. 4.3): the inner region is E_k' n B_delta(b_k)
+             * for every outer point (constant kernel) */
+            nlo_problem pr = *p;
+            pr.ball = 1;
+            st = nlo_inner_sums(&pr, bk, Vkp, &S0, S1, S2);
+        } else {
+            st = nlo_inner_sums(p, x, Vkp, &S0, S1, S2);
+        }
         if (st < 0) return st;
         double Wq = w[q] * ak2;
         const double *al = lam + 3 * q;
@@ -772,6 +843,7 @@ int64_t nlo_flops_census(const nlo_mesh *m, const nlo_problem *p, int32_t k0, in
     for (int k = k0; k < k1; k++) {
         int n = pairs_of(m, p, &e, k, kp, m->nt);
         out[0] += n;
+        if (p->ball >= 2) continue;     /* item counts for the barycenter and intersection balls only */
         for (int t = 0; t < n; t++) {
             const double *Vk = e.V + 6 * k, *Vj = e.V + 6 * kp[t];
             for (int q = 0; q < p->n_out; q++) {

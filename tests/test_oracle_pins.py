@@ -401,3 +401,82 @@ def test_paper_table_l2_errors(ball):
     rate = math.log(got[0] / got[1], 2)
     ref_rate = math.log(tab["l2"][ball][1] / tab["l2"][ball][2], 2)
     assert abs(rate - ref_rate) < 0.2
+
+
+# ------------------------------------------- the other balls of Sec. 8 (NEXT)
+def _other_table():
+    with open(os.path.join(HERE, "golden", "paper_sec8_other_balls.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("ball", ["overlap", "shifted", "barynocaps", "baryapproxcaps"])
+def test_paper_other_balls_l2_errors(ball):
+    """Sec. 8.1, columns (5)-(8): overlap (whole elements touching the ball),
+    shifted + nocaps, and the barycenter ball with the outer integral over
+    E_k n B_delta(b_k') (nocaps / approxcaps): the printed L2 errors at
+    h = 0.05, 0.025 within 12% and the observed rate within 0.2."""
+    from workloads import paper_workload
+    tab = _other_table()
+    got = []
+    for i, h in enumerate(tab["h"][1:3], start=1):
+        mesh, p, man = paper_workload(h, ball)
+        r = oracle.solve_problem(mesh, p, man)
+        ref = tab["l2"][ball][i]
+        assert abs(r["l2"] - ref) < 0.12 * ref, (ball, h, r["l2"], ref)
+        got.append(r["l2"])
+    rate = math.log(got[0] / got[1], 2)
+    ref_rate = math.log(tab["l2"][ball][1] / tab["l2"][ball][2], 2)
+    assert abs(rate - ref_rate) < 0.2
+
+
+def test_shifted_is_barycenter_support_transposed():
+    """The bilinear form is symmetric under x <-> y.  The shifted pair (k, k')
+    integrates x over E_k and y over E_k' n B_delta(b_k); the barycenter-support
+    pair (k', k) integrates x over E_k' n B_delta(b_k) and y over E_k.  With
+    both rules exact for the quadratic integrand the two assembled matrices are
+    the same; they come from different code paths (inner region vs outer
+    region) and different rules on the region (3-point vs 4-point)."""
+    from workloads import paper_workload
+    mesh = structured_mesh(0.1, 0.05, jitter=0.2, seed=7)
+    for cap in (0, 2):
+        out = []
+        for ball in ("shifted", "barynocaps"):
+            p = paper_workload(0.05, ball)[1]
+            from dataclasses import replace
+            p = replace(p, cap_edges=cap, inner="gauss3", outer="strang4")
+            out.append(oracle.assemble(oracle.OracleProblem(mesh, p)))
+        a, b = out
+        assert np.array_equal(a["rowptr"], b["rowptr"]) and np.array_equal(a["col"], b["col"])
+        scale = np.abs(a["val"]).max()
+        assert np.max(np.abs(a["val"] - b["val"])) < 1e-12 * scale, cap
+
+
+def test_overlap_pairs_are_intersection_pairs():
+    """Eq. (overlap): the elements of the overlap ball are those meeting
+    B_delta(x), the same interaction set as the intersection ball; and every
+    whole-element inner integral is at least the intersected one, so the
+    overlap matrix's diagonal dominates the intersection ball's."""
+    from workloads import paper_workload
+    mesh = structured_mesh(0.1, 0.05, jitter=0.2, seed=8)
+    ro = oracle.assemble(oracle.OracleProblem(mesh, paper_workload(0.05, "overlap")[1]))
+    ri = oracle.assemble(oracle.OracleProblem(mesh, paper_workload(0.05, "nocaps")[1]))
+    assert np.array_equal(ro["pair_ptr"], ri["pair_ptr"]) and np.array_equal(ro["pair_kp"], ri["pair_kp"])
+    assert np.array_equal(ro["col"], ri["col"])
+    rows = np.repeat(np.arange(len(ro["rowptr"]) - 1), np.diff(ro["rowptr"]))
+    diag = rows == ro["col"]
+    assert np.all(ro["val"][diag] >= ri["val"][diag] * (1 - 1e-12))
+
+
+def test_grid_b_element_sizes():
+    """Sec. 8.2, Table num:bary (b): interior node counts and the smallest and
+    largest element diameters of grid (b), printed truncated to four decimals,
+    fix the reading of the mapping (every grid line 0 < x2 < 1 moved)."""
+    tab = _other_table()["grid_b"]
+    for h, J, hmin, hmax in zip(_other_table()["h"], tab["J_omega"], tab["h_min"], tab["h_max"]):
+        m = structured_mesh(0.1, h, grid="b")
+        assert int(m.node_free.sum()) == J
+        V = m.xy[m.tri]
+        d = np.max(np.stack([np.linalg.norm(V[:, a] - V[:, (a + 1) % 3], axis=1) for a in range(3)]), axis=0)
+        inside = m.tri_in_omega.astype(bool)
+        assert math.floor(d[inside].min() * 1e4) / 1e4 == pytest.approx(hmin, abs=1e-12)
+        assert math.floor(d[inside].max() * 1e4) / 1e4 == pytest.approx(hmax, abs=1e-12)

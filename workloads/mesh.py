@@ -54,7 +54,7 @@ class Mesh:
         return int(self.node_free.sum())
 
 
-def structured_mesh(delta, h, jitter=0.0, seed=20050, grid="a"):
+def structured_mesh(delta, h, jitter=0.0, seed=20050, grid="a", diagonal="/"):
     """Uniform mesh with cells of side h = 1/n_omega and a layer of
     n_layer = delta/h cells.  Vertex (i, j) sits at ((i-n_layer)/n_omega,
     (j-n_layer)/n_omega), so the boundary of Omega lies exactly on 0 and 1.
@@ -63,8 +63,12 @@ def structured_mesh(delta, h, jitter=0.0, seed=20050, grid="a"):
     uniform offsets in (-jitter*h, jitter*h) per coordinate (SplitMix64 from
     ``seed``, x then y per vertex in index order); boundary and layer
     vertices stay fixed, which keeps the interface and the corners.
-    grid="b" maps interior vertices by (x1, x2) -> (x1, x2^2) (the non-uniform
-    Cartesian grid (b) of Sec. 8.2).
+    grid="b" is the non-uniform Cartesian grid (b) of Sec. 8.2: every grid
+    line x2 = c with 0 < c < 1 moves to x2 = c^2, across the whole width, so
+    that the grid stays a tensor product (mapping only the vertices inside
+    Omega would kink each line at x1 = 0 and 1 and leave elements there of
+    diameter near 1/4, against the printed h_max).
+    diagonal: "/" splits each cell along sw-ne, "\\" along se-nw.
     """
     n_omega = int(round(1.0 / h))
     n_layer = int(round(delta / h))
@@ -79,7 +83,7 @@ def structured_mesh(delta, h, jitter=0.0, seed=20050, grid="a"):
     free = ((ii > n_layer) & (ii < n_layer + n_omega) &
             (jj > n_layer) & (jj < n_layer + n_omega))
     if grid == "b":
-        y = np.where(free, y * y, y)
+        y = np.where((y > 0.0) & (y < 1.0), y * y, y)
     elif grid != "a":
         raise ValueError("grid must be 'a' or 'b'")
     if jitter > 0.0:
@@ -96,8 +100,14 @@ def structured_mesh(delta, h, jitter=0.0, seed=20050, grid="a"):
     ci = ci.ravel()
     cj = cj.ravel()
     sw, se, ne, nw = vid(ci, cj), vid(ci + 1, cj), vid(ci + 1, cj + 1), vid(ci, cj + 1)
-    t1 = np.stack([sw, se, ne], axis=1)
-    t2 = np.stack([sw, ne, nw], axis=1)
+    if diagonal == "/":
+        t1 = np.stack([sw, se, ne], axis=1)
+        t2 = np.stack([sw, ne, nw], axis=1)
+    elif diagonal == "\\":
+        t1 = np.stack([sw, se, nw], axis=1)
+        t2 = np.stack([se, ne, nw], axis=1)
+    else:
+        raise ValueError("diagonal must be '/' or '\\\\'")
     tri = np.empty((2 * n * n, 3), dtype=np.int32)
     tri[0::2] = t1
     tri[1::2] = t2
@@ -107,4 +117,4 @@ def structured_mesh(delta, h, jitter=0.0, seed=20050, grid="a"):
     return Mesh(xy=np.ascontiguousarray(xy), tri=tri, tri_in_omega=tin,
                 node_free=free.astype(np.uint8), delta=float(n_layer) / n_omega,
                 h=1.0 / n_omega, n_layer=n_layer, n_omega=n_omega,
-                meta={"jitter": jitter, "seed": seed, "grid": grid})
+                meta={"jitter": jitter, "seed": seed, "grid": grid, "diagonal": diagonal})

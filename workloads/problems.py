@@ -27,7 +27,7 @@ class Problem:
     kernel: str = "constant"          # "constant" | "fractional"
     kernel_c: float = 0.0
     kernel_s: float = 0.0
-    ball: str = "barycenter"          # "barycenter" | "retri"
+    ball: str = "barycenter"          # "barycenter" | "retri" | "overlap" | "shifted" | "barysupport"
     cap_mode: str = "poly"            # "poly": caps by cap_edges equal arcs ; "centroid": exact caps, 1-pt rule
     cap_edges: int = 0                # 0 = the paper's nocaps polygon
     outer: str = "dunavant7"
@@ -53,19 +53,31 @@ def manufactured(name):
     raise KeyError(name)
 
 
-def paper_workload(h, ball, delta=0.1):
-    """The workload of Sec. 8: uniform grid (a) with spacing h, delta = 0.1, the
-    constant kernel, u = x1^2 x2 + x2^2 with f = -2(x2 + 1); the 7-point
-    vertex/mid-side/centroid outer rule, switched to the 4-point rule for pairs
-    with |b_k - b_k'| < delta - h_max (h_max = sqrt(2) h, the element diameter);
-    the 3-point inner rule; balls: "approxcaps" (one triangle per cap: two arcs
-    fanned from the chord midpoint), "nocaps", "exactcaps" (one-point centroid
-    rule on the true caps) and "barycenter"."""
-    kw = {"approxcaps": dict(ball="retri", cap_edges=2), "nocaps": dict(ball="retri", cap_edges=0),
-          "exactcaps": dict(ball="retri", cap_mode="centroid"), "barycenter": dict(ball="barycenter")}[ball]
-    p = Problem(delta=delta, kernel_c=constant_kernel_c(delta), outer="vertex7", inner="gauss3",
-                outer2="strang4", switch_dist=delta - math.sqrt(2) * h, **kw)
-    return structured_mesh(delta, h), p, "paper"
+def paper_workload(h, ball, delta=0.1, grid="a"):
+    """The workloads of Sec. 8 on grid (a) (or grid (b), the interior vertices
+    mapped by (x1, x2) -> (x1, x2^2)) with spacing h, delta = 0.1, the constant
+    kernel, u = x1^2 x2 + x2^2 with f = -2(x2 + 1), and the 3-point inner rule.
+    Experiments (1)-(5) use the 7-point vertex/mid-side/centroid outer rule,
+    switched to the 4-point rule for pairs with |b_k - b_k'| < delta - h_max
+    (h_max = sqrt(2) h, the element diameter), with the balls "exactcaps"
+    (one-point centroid rule on the true caps), "approxcaps" (one triangle per
+    cap: two arcs fanned from the chord midpoint), "nocaps", "barycenter" and
+    "overlap".  Experiments (6)-(10) use the 4-point outer rule throughout:
+    "shifted" (the nocaps ball about b_k) and "barynocaps" / "baryapproxcaps"
+    (barycenter ball with the outer integral over E_k n B_delta(b_k'),
+    approximated by nocaps / approxcaps)."""
+    first = {"approxcaps": dict(ball="retri", cap_edges=2), "nocaps": dict(ball="retri", cap_edges=0),
+             "exactcaps": dict(ball="retri", cap_mode="centroid"), "barycenter": dict(ball="barycenter"),
+             "overlap": dict(ball="overlap")}
+    second = {"shifted": dict(ball="shifted", cap_edges=0), "barynocaps": dict(ball="barysupport", cap_edges=0),
+              "baryapproxcaps": dict(ball="barysupport", cap_edges=2)}
+    if ball in first:
+        p = Problem(delta=delta, kernel_c=constant_kernel_c(delta), outer="vertex7", inner="gauss3",
+                    outer2="strang4", switch_dist=delta - math.sqrt(2) * h, **first[ball])
+    else:
+        p = Problem(delta=delta, kernel_c=constant_kernel_c(delta), outer="strang4", inner="gauss3",
+                    **second[ball])
+    return structured_mesh(delta, h, grid=grid), p, "paper"
 
 
 def _c1():
