@@ -57,7 +57,14 @@ enum {
 };
 
 enum { NLA_KERNEL_CONSTANT = 0, NLA_KERNEL_FRACTIONAL = 1 };
-enum { NLA_BALL_BARYCENTER = 0, NLA_BALL_RETRI = 1 };
+/* balls (Sec. 4): barycenter (Eq. (baryball)); intersection ball, retriangulated
+ * (Sec. 4.2); overlap (Eq. (overlap): every element meeting B_delta(x), whole);
+ * shifted (Sec. 4.3: the intersection ball about b_k for every point of E_k);
+ * barycenter ball with the outer integral restricted to its support
+ * E_k n B_delta(b_k') (Sec. 6, case 2), approximated by the intersection-ball
+ * region of that set.  The last three: constant kernel, NLA_FP64. */
+enum { NLA_BALL_BARYCENTER = 0, NLA_BALL_RETRI = 1, NLA_BALL_OVERLAP = 2, NLA_BALL_SHIFTED = 3,
+       NLA_BALL_BARYSUPPORT = 4 };
 enum { NLA_FP64 = 0, NLA_FP32 = 1, NLA_FP32_LEARNED = 2 };
 enum { NLA_DTYPE_F64 = 0, NLA_DTYPE_F32 = 1 };
 enum { NLA_SKIP_IXI = 1u };     /* flags: drop Omega_I x Omega_I pairs (A and b unchanged) */
@@ -94,8 +101,9 @@ typedef struct {
                                     element pairs sharing a vertex (0 = not used) */
     const double *duffy_x;       /* [duffy_n] host, nodes on [0,1] */
     const double *duffy_w;       /* [duffy_n] host, weights summing to 1 */
-    int32_t ball;                /* NLA_BALL_BARYCENTER | NLA_BALL_RETRI */
-    int32_t cap_edges;           /* retri: equal arcs per cap, 0 (= inscribed polygon) or 2..64 */
+    int32_t ball;                /* NLA_BALL_* */
+    int32_t cap_edges;           /* retri, shifted, barysupport: equal arcs per cap, 0 (= inscribed
+                                    polygon) or 2..64 */
     int32_t precision;           /* NLA_FP64 | NLA_FP32 (compensated) | NLA_FP32_LEARNED */
     const void *mlp;             /* NLA_FP32_LEARNED: an nla_mlp* ; else NULL */
     double fallback_band;        /* learned caps: exact path when min_a | |v_a - x| - delta | <
@@ -139,9 +147,14 @@ const char *nla_last_error(void);
 /* Builds the plan: element data, the canonical pair list (k ascending, k'
  * ascending within k) of pairs with at least one outer point x_{k,q} whose
  * approximate ball reaches E_k' (Sec. 7.1 tasks 1-4; barycenter ball:
- * |x - b_k'| <= delta; retri: the closed ball meets E_k'), and the CSR
- * pattern of D.  Retri needs every element diameter <= delta
- * (NLA_E_UNSUPPORTED otherwise: a ball inside a triangle is not retriangulated).
+ * |x - b_k'| <= delta; retri and overlap: the closed ball meets E_k'; shifted:
+ * the closed ball about b_k meets E_k'; barysupport: the closed ball about b_k'
+ * meets E_k), and the CSR pattern of D.  The balls that cut elements (retri,
+ * shifted, barysupport) need every element's inradius < delta/2 (the fractional
+ * kernel: every diameter <= delta), so that no ball lies inside an element and
+ * every cap spans less than a half circle; NLA_E_UNSUPPORTED otherwise.
+ * Shifted needs an inner rule exact for quadratics, barysupport an outer rule
+ * exact for quadratics (their regions are integrated through their moments).
  * *out receives a new plan; destroy it with nla_plan_destroy. */
 int nla_plan_create(const nla_mesh *mesh, const nla_problem *prob, void *stream, nla_plan **out);
 int nla_plan_info(const nla_plan *plan, nla_info *info);

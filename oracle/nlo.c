@@ -159,7 +159,8 @@ static void pair_rule(const nlo_problem *p, const double bk[2], const double bkp
     *nq = p->n_out;
     *lam = p->out_lam;
     *w = p->out_w;
-    if (p->n_out2 > 0) {
+    /* |b_k - b_k'| < switch_dist, compared in squares: never when switch_dist <= 0 */
+    if (p->n_out2 > 0 && p->switch_dist > 0.0) {
         double dx = bk[0] - bkp[0], dy = bk[1] - bkp[1];
         if (dx * dx + dy * dy < p->switch_dist * p->switch_dist) {
             *nq = p->n_out2;

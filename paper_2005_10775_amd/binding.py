@@ -17,7 +17,7 @@ NLA_OK = 0
 ERRORS = {-1: "NLA_E_INVALID", -2: "NLA_E_MESH", -3: "NLA_E_NOMEM", -4: "NLA_E_DEVICE",
           -5: "NLA_E_UNSUPPORTED", -6: "NLA_E_NOT_CONVERGED", -7: "NLA_E_STATE"}
 KERNELS = {"constant": 0, "fractional": 1}
-BALLS = {"barycenter": 0, "retri": 1}
+BALLS = {"barycenter": 0, "retri": 1, "overlap": 2, "shifted": 3, "barysupport": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "learned": 2}
 NLA_SKIP_IXI = 1
 

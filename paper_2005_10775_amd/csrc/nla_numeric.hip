@@ -7,6 +7,37 @@ static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs -
 
 #include "nla_device.hpp"
 
+// Adds a chunk's -Mxy (pairs lo..lo+63 of element k, one row of 9 per pair in
+// mxy_l) into the row block R_k[a][c], column by column: each column is owned
+// by one lane, which takes its contributions in pair order (colent: pair index
+// << 2 | inner slot, sorted by pair; cur_l: the column's next entry).
+__device__ __forceinline__ void fold_row_block(double *R_l, int *cur_l, int nC, const int32_t *__restrict__ cptr,
+                                               const uint16_t *__restrict__ colent, const double (*mxy_l)[12], int lo,
+                                               int lane)
+{
+    const int hi = lo + 64;
+    for (int c = lane; c < nC; c += 64) {
+        int cur = cur_l[c];
+        const int end = cptr[c + 1];
+        double r0 = R_l[c], r1 = R_l[nC + c], r2 = R_l[2 * nC + c];
+        while (cur < end) {
+            const int e = colent[cur];
+            const int pl = e >> 2;
+            if (pl >= hi) break;
+            const int b = e & 3;
+            const double *mm = mxy_l[pl - lo];
+            r0 += mm[b];
+            r1 += mm[3 + b];
+            r2 += mm[6 + b];
+            cur++;
+        }
+        R_l[c] = r0;
+        R_l[nC + c] = r1;
+        R_l[2 * nC + c] = r2;
+        cur_l[c] = cur;
+    }
+}
+
 // One wavefront per outer element k (Eq. (bformhj) restricted to the pairs
 // of k).  Phase 1: every lane takes one pair (k, k'), classifies its items
 // (x_{k,q}, E_k') as whole / partial / empty; whole items (all of E_k' in the
@@ -112,9 +143,10 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 if (ball == NLA_BALL_BARYCENTER) {
                     whole = bary_in(xx, xy, bxp, byp, dd);
                 } else {
+                    // overlap ball: every element meeting the ball counts whole
                     const int cls = item_class(xx, xy, V, dd);
-                    whole = cls == 1;
-                    part = cls == 2;
+                    whole = cls == 1 || (ball == NLA_BALL_OVERLAP && cls == 2);
+                    part = cls == 2 && ball != NLA_BALL_OVERLAP;
                 }
                 if (whole) {
                     const double *w4 = r2 ? sW2[q] : sW[q];
@@ -233,29 +265,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * ayy[t];
         }
         __syncthreads();
-        {
-            const int lo = (int)(base - p0), hi = lo + 64;
-            for (int c = lane; c < nC; c += 64) {
-                int cur = cur_l[c];
-                const int end = colent_ptr[coff + c + 1];
-                double r0 = R_l[c], r1 = R_l[nC + c], r2 = R_l[2 * nC + c];
-                while (cur < end) {
-                    const int e = colent[cur];
-                    const int pl = e >> 2;
-                    if (pl >= hi) break;
-                    const int b = e & 3;
-                    const double *mm = mxy_l[pl - lo];
-                    r0 += mm[b];
-                    r1 += mm[3 + b];
-                    r2 += mm[6 + b];
-                    cur++;
-                }
-                R_l[c] = r0;
-                R_l[nC + c] = r1;
-                R_l[2 * nC + c] = r2;
-                cur_l[c] = cur;
-            }
-        }
+        fold_row_block(R_l, cur_l, nC, colent_ptr + coff, colent, mxy_l, (int)(base - p0), lane);
         __syncthreads();
     }
     for (int i = lane; i < 3 * nC; i += 64) Rout[3 * coff + i] = R_l[i];
@@ -286,6 +296,179 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         Cxx[6 * (int64_t)k + lane] = psi * s;
     }
     // work counters
+    unsigned long long v[5] = {c_whole, c_part, c_empty, c_sub, c_cap};
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        unsigned long long x = v[i];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        v[i] = x;
+    }
+    if (lane == 0) {
+        atomicAdd(&counters[0], v[0]);
+        atomicAdd(&counters[1], v[1]);
+        atomicAdd(&counters[2], v[2]);
+        atomicAdd(&counters[4], v[3]);
+        atomicAdd(&counters[5], v[4]);
+    }
+}
+
+// The shifted ball (Sec. 4.3) and the barycenter ball with its outer support
+// resolved (Sec. 6, case 2) integrate one region per pair instead of one per
+// (pair, outer point).  One wavefront per outer element k, one lane per pair:
+//  * shifted: R = E_k' n B_delta,h(b_k) serves every x in E_k; its inner sums
+//    S0, S1_b, S2_bb' (moments through the boundary, the inner rule being exact
+//    for quadratics) meet the outer rule over the whole E_k:
+//    Mxx = (sum_q W_q alpha alpha^T) S0, Mxy_ab = (sum_q W_q alpha_a) S1_b,
+//    Myy = (sum_q W_q) S2;
+//  * barycenter support: the inner integrand is non-zero for x in
+//    S = E_k n B_delta,h(b_k'), where it runs over the whole E_k' (rule
+//    constants T0, T1_b, T2_bb'); the outer rule over the triangles of S is
+//    exact for alpha alpha^T, so S's moments a0, a1_a, a2_aa' give
+//    Mxx = a2 T0, Mxy_ab = a1_a T1_b, Myy = a0 T2.
+// A region is whole (every vertex in the ball), empty, or cut (moments from
+// its boundary, caps over ncap equal arcs).  Outputs as k_pairs_const_fp64.
+template <bool POW2>
+__global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__restrict__ pair_ptr,
+                                                        const int32_t *__restrict__ pair_kp, ElemSoA E,
+                                                        const RuleSet *__restrict__ R, double dd, double psi,
+                                                        int ball, int ncap, const int64_t *__restrict__ col_off,
+                                                        const int32_t *__restrict__ colent_ptr,
+                                                        const uint16_t *__restrict__ colent, double *__restrict__ Rout,
+                                                        double *__restrict__ Cyy, double *__restrict__ Cxx,
+                                                        int max_cols, unsigned long long *__restrict__ counters)
+{
+    extern __shared__ double dyn[];
+    __shared__ double sQ[10];           // the outer rule over E_k: sum W, sum W alpha_a, sum W alpha_a alpha_c
+    __shared__ double res[64][12];      // a lane's cap endpoints, then its pair's -Mxy
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const double a2k = E.a2[k];
+    const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+    if (lane < 10) {
+        double v = 0.0;
+        for (int q = 0; q < R->n_out; q++) {
+            const double W = R->out_w[q] * a2k;
+            if (lane == 0) v += W;
+            else if (lane < 4) v += W * R->out_lam[q][lane - 1];
+            else v += W * R->out_lam[q][jj[lane - 4]] * R->out_lam[q][ll[lane - 4]];
+        }
+        sQ[lane] = v;
+    }
+    __syncthreads();
+    const RuleMom M = load_moments(R);
+    const double bkx = E.bx[k], bky = E.by[k];
+    const double Vk[6] = {E.vx0[k], E.vy0[k], E.vx1[k], E.vy1[k], E.vx2[k], E.vy2[k]};
+    const int64_t coff = col_off[k];
+    const int nC = (int)(col_off[k + 1] - coff);
+    double *R_l = dyn;                                  // [3][nC]
+    int *cur_l = (int *)(dyn + 3 * (size_t)max_cols);   // [nC]
+    for (int c = lane; c < nC; c += 64) {
+        R_l[c] = 0.0;
+        R_l[nC + c] = 0.0;
+        R_l[2 * nC + c] = 0.0;
+        cur_l[c] = colent_ptr[coff + c];
+    }
+    double s0sum = 0.0, mxx[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
+    const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
+    for (int64_t base = p0; base < p1; base += 64) {
+        const int64_t p = base + lane;
+        const bool act = p < p1;
+        double mxy[9], myy[6];
+#pragma unroll
+        for (int i = 0; i < 9; i++) mxy[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; i++) myy[i] = 0.0;
+        if (act) {
+            const int kp = pair_kp[p];
+            const double V[6] = {E.vx0[kp], E.vy0[kp], E.vx1[kp], E.vy1[kp], E.vx2[kp], E.vy2[kp]};
+            const double a2p = E.a2[kp];
+            const bool shifted = ball == NLA_BALL_SHIFTED;
+            // the cut element (selected by value, so that both stay in registers)
+            // and the centre of the ball that cuts it
+            const double cx = shifted ? bkx : E.bx[kp], cy = shifted ? bky : E.by[kp];
+            double Vc[6];
+#pragma unroll
+            for (int i = 0; i < 6; i++) Vc[i] = shifted ? V[i] : Vk[i];
+            const double ac = shifted ? a2p : a2k;
+            const int cls = item_class(cx, cy, Vc, dd);
+            double g0 = 0.0, g1[3] = {0, 0, 0}, g2[6] = {0, 0, 0, 0, 0, 0};   // the region's moments
+            if (cls == 1) {
+                // whole element: the rule's constants (inner rule on E_k', or the outer rule on E_k)
+                if (shifted) {
+                    g0 = ac * M.wsum;
+#pragma unroll
+                    for (int b = 0; b < 3; b++) g1[b] = ac * M.m1[b];
+#pragma unroll
+                    for (int t = 0; t < 6; t++) g2[t] = ac * M.m2[jj[t]][ll[t]];
+                } else {
+                    g0 = sQ[0];
+#pragma unroll
+                    for (int b = 0; b < 3; b++) g1[b] = sQ[1 + b];
+#pragma unroll
+                    for (int t = 0; t < 6; t++) g2[t] = sQ[4 + t];
+                }
+                c_whole++;
+            } else if (cls == 2) {
+                RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int ns = 0;
+                partial_boundary<POW2>(cx, cy, Vc, dd, ncap, Rm, ns, &res[lane][0]);
+                region_sums(Rm, Vc, g0, g1, g2);
+                c_sub += ns & 0xffff;
+                c_cap += ns >> 16;
+                c_part++;
+            } else {
+                c_empty++;
+            }
+            if (shifted) {
+                s0sum += g0;
+#pragma unroll
+                for (int a = 0; a < 3; a++)
+#pragma unroll
+                    for (int b = 0; b < 3; b++) mxy[3 * a + b] = sQ[1 + a] * g1[b];
+#pragma unroll
+                for (int t = 0; t < 6; t++) myy[t] = sQ[0] * g2[t];
+            } else {
+                const double t0 = a2p * M.wsum;
+#pragma unroll
+                for (int t = 0; t < 6; t++) mxx[t] += g2[t] * t0;
+#pragma unroll
+                for (int a = 0; a < 3; a++)
+#pragma unroll
+                    for (int b = 0; b < 3; b++) mxy[3 * a + b] = g1[a] * (a2p * M.m1[b]);
+#pragma unroll
+                for (int t = 0; t < 6; t++) myy[t] = g0 * (a2p * M.m2[jj[t]][ll[t]]);
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < 9; i++) res[lane][i] = -psi * mxy[i];
+#pragma unroll
+            for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * myy[t];
+        }
+        __syncthreads();
+        fold_row_block(R_l, cur_l, nC, colent_ptr + coff, colent, res, (int)(base - p0), lane);
+        __syncthreads();
+    }
+    for (int i = lane; i < 3 * nC; i += 64) Rout[3 * coff + i] = R_l[i];
+    // Mxx(k): a fixed butterfly over the lanes, lane 0's sum broadcast
+    {
+        double x = s0sum;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        s0sum = __shfl(x, 0, 64);
+    }
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+        double x = mxx[t];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        mxx[t] = __shfl(x, 0, 64);
+    }
+    if (lane < 6) {
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < 6; t++)
+            if (t == lane) v = ball == NLA_BALL_SHIFTED ? sQ[4 + t] * s0sum : mxx[t];
+        Cxx[6 * (int64_t)k + lane] = psi * v;
+    }
     unsigned long long v[5] = {c_whole, c_part, c_empty, c_sub, c_cap};
 #pragma unroll
     for (int i = 0; i < 5; i++) {
@@ -434,7 +617,8 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         nla_mark(P, NLA_PHASE_MLP, s);
         nla_mark(P, NLA_PHASE_PAIRS, s);
         const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
-        const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
+        const bool cuts = pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT;
+        const int ncap = cuts ? pr.cap_edges : 0;
 #define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND, SW)                                                                   \
     k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, lds, s>>>(                                                  \
         P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,           \
@@ -450,7 +634,18 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
                           "2^m arcs per cap");
             return NLA_E_UNSUPPORTED;
         }
-        if (sw && bnd) NLA_LAUNCH_PAIRS(8, true, true, true, true);
+        if (pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT) {
+            if (pow2)
+                k_pairs_support_fp64<true><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
+                                                               pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
+                                                               P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
+                                                               P->max_cols, P->counters);
+            else
+                k_pairs_support_fp64<false><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
+                                                                pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
+                                                                P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
+                                                                P->max_cols, P->counters);
+        } else if (sw && bnd) NLA_LAUNCH_PAIRS(8, true, true, true, true);
         else if (sw) NLA_LAUNCH_PAIRS(8, true, true, false, true);
         else if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true, false);
         else if (P->rules.n_out <= 8 && bnd) NLA_LAUNCH_PAIRS(8, true, false, true, false);

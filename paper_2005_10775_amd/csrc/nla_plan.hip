@@ -87,6 +87,29 @@ struct Scratch {
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // ------------------------------------------------------------- validation
+
+// the rule integrates quadratics exactly on the reference triangle (weights
+// summing to 1/2, first moments 1/6, second moments 1/12 and 1/24)
+static bool rule_q2exact(const nla_rule &r)
+{
+    if (r.n < 1 || !r.lambda || !r.w) return false;
+    double ws = 0, m1[3] = {0, 0, 0}, m2[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int q = 0; q < r.n; q++) {
+        const double *l = r.lambda + 3 * q;
+        ws += r.w[q];
+        for (int a = 0; a < 3; a++) {
+            m1[a] += r.w[q] * l[a];
+            for (int b = 0; b < 3; b++) m2[a][b] += r.w[q] * l[a] * l[b];
+        }
+    }
+    bool ok = std::fabs(ws - 0.5) <= 1e-14;
+    for (int a = 0; a < 3; a++) {
+        ok = ok && std::fabs(m1[a] - 1.0 / 6.0) <= 1e-14;
+        for (int b = 0; b < 3; b++) ok = ok && std::fabs(m2[a][b] - (a == b ? 1.0 / 12.0 : 1.0 / 24.0)) <= 1e-14;
+    }
+    return ok;
+}
+
 static int validate(const nla_mesh *m, const nla_problem *p)
 {
     if (!m || !p) { nla_set_error("null mesh or problem"); return NLA_E_INVALID; }
@@ -100,7 +123,15 @@ static int validate(const nla_mesh *m, const nla_problem *p)
         return NLA_E_INVALID;
     }
     if (!std::isfinite(p->kernel_c) || p->kernel_c <= 0.0) { nla_set_error("kernel_c must be > 0"); return NLA_E_INVALID; }
-    if (p->ball != NLA_BALL_BARYCENTER && p->ball != NLA_BALL_RETRI) { nla_set_error("unknown ball %d", p->ball); return NLA_E_INVALID; }
+    if (p->ball < NLA_BALL_BARYCENTER || p->ball > NLA_BALL_BARYSUPPORT) {
+        nla_set_error("unknown ball %d", p->ball);
+        return NLA_E_INVALID;
+    }
+    if (p->ball >= NLA_BALL_OVERLAP && (p->kernel != NLA_KERNEL_CONSTANT || p->precision != NLA_FP64)) {
+        nla_set_error("the overlap, shifted and barycenter-support balls are assembled for the constant kernel in "
+                      "NLA_FP64");
+        return NLA_E_UNSUPPORTED;
+    }
     if (p->cap_edges < 0 || p->cap_edges == 1 || p->cap_edges > NLA_MAX_CAP) {
         nla_set_error("cap_edges must be 0 or 2..%d", NLA_MAX_CAP);
         return NLA_E_INVALID;
@@ -179,18 +210,22 @@ static int validate(const nla_mesh *m, const nla_problem *p)
         nla_set_error("unknown cap_mode %d", p->cap_mode);
         return NLA_E_INVALID;
     }
+    if ((p->ball == NLA_BALL_SHIFTED || p->ball == NLA_BALL_BARYSUPPORT) &&
+        (p->outer2.n != 0 || p->cap_mode != NLA_CAPS_ARCS)) {
+        nla_set_error("the shifted and barycenter-support balls take one outer rule and arc caps");
+        return NLA_E_UNSUPPORTED;
+    }
+    if (p->ball == NLA_BALL_SHIFTED && !rule_q2exact(p->inner)) {
+        nla_set_error("the shifted ball needs an inner rule exact for quadratics");
+        return NLA_E_UNSUPPORTED;
+    }
+    if (p->ball == NLA_BALL_BARYSUPPORT && !rule_q2exact(p->outer)) {
+        nla_set_error("the barycenter-support ball needs an outer rule exact for quadratics");
+        return NLA_E_UNSUPPORTED;
+    }
     if (p->cap_mode == NLA_CAPS_CENTROID) {
         // exact caps by the one-point centroid rule ride on the boundary-moment integration
-        double m1 = 0, m11 = 0, m12 = 0, ws = 0;
-        for (int q = 0; q < p->inner.n; q++) {
-            const double *l = p->inner.lambda + 3 * q;
-            ws += p->inner.w[q];
-            m1 += p->inner.w[q] * l[0];
-            m11 += p->inner.w[q] * l[0] * l[0];
-            m12 += p->inner.w[q] * l[0] * l[1];
-        }
-        const bool q2 = std::fabs(ws - 0.5) <= 1e-14 && std::fabs(m1 - 1.0 / 6.0) <= 1e-14 &&
-                        std::fabs(m11 - 1.0 / 12.0) <= 1e-14 && std::fabs(m12 - 1.0 / 24.0) <= 1e-14;
+        const bool q2 = rule_q2exact(p->inner);
         if (p->ball != NLA_BALL_RETRI || p->kernel != NLA_KERNEL_CONSTANT || p->precision != NLA_FP64 || !q2) {
             nla_set_error("centroid caps need the intersection ball, the constant kernel, NLA_FP64 and an inner rule "
                           "exact for quadratics");
@@ -201,7 +236,7 @@ static int validate(const nla_mesh *m, const nla_problem *p)
     const int J = m->n_vertices, K = m->n_triangles;
     for (int i = 0; i < 2 * J; i++)
         if (!std::isfinite(m->xy[i])) { nla_set_error("vertex %d not finite", i / 2); return NLA_E_MESH; }
-    double dmax = 0.0;
+    double dmax = 0.0, inr = 0.0;
     for (int k = 0; k < K; k++) {
         const int32_t *t = m->tri + 3 * k;
         for (int a = 0; a < 3; a++)
@@ -212,10 +247,14 @@ static int validate(const nla_mesh *m, const nla_problem *p)
         if (!(cr > 0.0)) { nla_set_error("triangle %d is not counter-clockwise", k); return NLA_E_MESH; }
         if (m->tri_in_omega[k] > 1) { nla_set_error("tri_in_omega[%d] not 0/1", k); return NLA_E_MESH; }
         const double *V[3] = {A, B, Cc};
+        double per = 0.0;
         for (int a = 0; a < 3; a++) {
             double dx = V[a][0] - V[(a + 1) % 3][0], dy = V[a][1] - V[(a + 1) % 3][1];
-            dmax = std::max(dmax, std::sqrt(dx * dx + dy * dy));
+            const double l = std::sqrt(dx * dx + dy * dy);
+            dmax = std::max(dmax, l);
+            per += l;
         }
+        inr = std::max(inr, cr / per);      // inradius = area / semi-perimeter
     }
     for (int j = 0; j < J; j++)
         if (m->node_free[j] > 1) { nla_set_error("node_free[%d] not 0/1", j); return NLA_E_MESH; }
@@ -227,8 +266,17 @@ static int validate(const nla_mesh *m, const nla_problem *p)
                     nla_set_error("free node %d belongs to Omega_I element %d", m->tri[3 * k + a], k);
                     return NLA_E_MESH;
                 }
-    if (p->ball == NLA_BALL_RETRI && dmax > p->delta) {
-        nla_set_error("retriangulated ball needs element diameter (%g) <= delta (%g)", dmax, p->delta);
+    // a ball inside an element is not seen by the region walk, and a cap of a
+    // half circle or more is not a cap; an element holding neither has inradius
+    // < delta/2 (a half disk of radius delta has inradius delta/2)
+    const bool cuts = p->ball == NLA_BALL_RETRI || p->ball == NLA_BALL_SHIFTED || p->ball == NLA_BALL_BARYSUPPORT;
+    if (cuts && p->kernel == NLA_KERNEL_FRACTIONAL && dmax > p->delta) {
+        nla_set_error("the fractional kernel with the retriangulated ball needs element diameter (%g) <= delta (%g)",
+                      dmax, p->delta);
+        return NLA_E_UNSUPPORTED;
+    }
+    if (cuts && !(inr < 0.5 * p->delta)) {
+        nla_set_error("the ball needs every element inradius (largest %g) < delta/2 (%g)", inr, 0.5 * p->delta);
         return NLA_E_UNSUPPORTED;
     }
     return NLA_OK;
@@ -414,6 +462,16 @@ __device__ __forceinline__ bool pair_test(const PairQuery &Q, const ElemSoA &E, 
     reach = reach * (1.0 + 1e-9) + 1e-14;
     double ddx = bk_x - bx, ddy = bk_y - by;
     if (!(ddx * ddx + ddy * ddy <= reach * reach)) return false;
+    if (Q.ball == NLA_BALL_SHIFTED) {
+        // every point of E_k uses the ball about b_k (Sec. 4.3)
+        const double V[6] = {E.vx0[kp], E.vy0[kp], E.vx1[kp], E.vy1[kp], E.vx2[kp], E.vy2[kp]};
+        return ball_meets(bk_x, bk_y, V, Q.dd);
+    }
+    if (Q.ball == NLA_BALL_BARYSUPPORT) {
+        // some x in E_k has b_k' in its ball: E_k meets the ball about b_k'
+        const double V[6] = {E.vx0[k], E.vy0[k], E.vx1[k], E.vy1[k], E.vx2[k], E.vy2[k]};
+        return ball_meets(bx, by, V, Q.dd);
+    }
     // the outer points of the pair's rule
     const bool r2 = Q.nq2 > 0 && use_rule2(bk_x, bk_y, bx, by, Q.sd);
     const double *pts = r2 ? xs2 : xs;

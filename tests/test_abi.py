@@ -97,10 +97,16 @@ def test_invalid_problem_fields(L, small):
 
 
 def test_ball_inside_triangle_unsupported(L):
-    """The retriangulated ball needs element diameters <= delta."""
-    d = 0.05
-    code, msg = _create(L, structured_mesh(0.1, 0.05), Problem(delta=d, kernel_c=1.0, ball="retri"))
-    # delta is snapped to the mesh layer (0.1); use a coarse mesh instead
+    """The balls that cut elements need every element's inradius < delta/2 (no
+    ball inside an element, every cap less than a half circle): a mesh scaled
+    by 4 has inradius 0.29 * 2 > 0.25 and is refused before any device work;
+    the unscaled one (inradius 0.15) passes validation."""
     mesh = structured_mesh(0.5, 0.5)
-    code, msg = _create(L, mesh, Problem(delta=0.5, kernel_c=1.0, ball="retri", cap_edges=8))
-    assert code == -5 and "diameter" in msg
+    prob = Problem(delta=0.5, kernel_c=1.0, ball="retri", cap_edges=8)
+    for ball in ("retri", "shifted", "barysupport"):
+        from dataclasses import replace
+        pb = replace(prob, ball=ball, outer="strang4", inner="gauss3")
+        code, msg = _create(L, mesh, pb, mutate_mesh=lambda xy, tri, tin, nfr: (xy * 4.0, tri, tin, nfr))
+        assert code == -5 and "inradius" in msg, (ball, code, msg)
+        code, msg = _create(L, mesh, pb)
+        assert code != -5, (ball, msg)

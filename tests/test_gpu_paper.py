@@ -41,10 +41,20 @@ def _gpu_l2(mesh, prob, man):
     return plan, oracle.l2_error(mesh, Uf, u)
 
 
-@pytest.mark.parametrize("ball", ["approxcaps", "nocaps", "exactcaps", "barycenter"])
-def test_paper_workload_parity(ball):
-    mesh, prob, man = paper_workload(0.05, ball)
-    _say("case paper", ball, "K", mesh.n_triangles)
+PARITY_CASES = [("approxcaps", 0.05, "a"), ("nocaps", 0.05, "a"), ("exactcaps", 0.05, "a"),
+                ("barycenter", 0.05, "a"), ("approxcaps", 0.1, "a"), ("overlap", 0.05, "a"),
+                ("shifted", 0.05, "a"), ("barynocaps", 0.05, "a"), ("baryapproxcaps", 0.05, "a"),
+                ("barynocaps", 0.05, "b"), ("baryapproxcaps", 0.1, "b")]
+
+
+@pytest.mark.parametrize("ball,h,grid", PARITY_CASES)
+def test_paper_workload_parity(ball, h, grid):
+    """Columns (1)-(10) of Sec. 8: the intersection balls (switched outer
+    rule), barycenter, overlap, shifted + nocaps, barycenter + nocaps /
+    approxcaps over the outer support, on grid (a) and grid (b); h = 0.1 has
+    elements of diameter above delta (inradius below delta/2)."""
+    mesh, prob, man = paper_workload(h, ball, grid=grid)
+    _say("case paper", ball, "h", h, "grid", grid, "K", mesh.n_triangles)
     plan = gpu_assemble(mesh, prob, man)
     ref = oracle.solve_problem(mesh, prob, man)
     rr = ref["res"]
@@ -64,6 +74,45 @@ def test_paper_table_on_gpu(ball):
     """Printed L2 errors at h = 0.05, 0.025, 0.0125 within 12%, and the observed
     rates within 0.2 (the grid's diagonal direction is not stated)."""
     with open(os.path.join(HERE, "golden", "paper_sec8_table.json")) as f:
+        tab = json.load(f)
+    got = []
+    for i, h in enumerate(tab["h"][1:4], start=1):
+        mesh, prob, man = paper_workload(h, ball)
+        _, l2 = _gpu_l2(mesh, prob, man)
+        ref = tab["l2"][ball][i]
+        _say("paper", ball, "h", h, "L2 %.3e (printed %.3e)" % (l2, ref))
+        assert abs(l2 - ref) < 0.12 * ref
+        got.append(l2)
+    for i in range(2):
+        rate = math.log(got[i] / got[i + 1], 2)
+        ref_rate = math.log(tab["l2"][ball][i + 1] / tab["l2"][ball][i + 2], 2)
+        assert abs(rate - ref_rate) < 0.2
+
+
+def test_shifted_equals_barycenter_support_on_gpu():
+    """x <-> y symmetry of the bilinear form: the shifted matrix equals the
+    barycenter-support matrix (same pattern, entries to rounding), from two
+    different kernels' code paths (inner region vs outer region), at a size
+    the oracle is not run on."""
+    vals = []
+    for ball in ("shifted", "barynocaps"):
+        mesh, prob, man = paper_workload(0.0125, ball)
+        plan = gpu_assemble(mesh, prob, man, with_load=False)
+        rowptr, col, val = (host(t) for t in plan.csr(0))
+        vals.append((rowptr, col, val))
+        _say("paper", ball, "h 0.0125 pairs", int(host(plan.pairs()[0])[-1]))
+    (ra, ca, va), (rb, cb, vb) = vals
+    assert np.array_equal(ra, rb) and np.array_equal(ca, cb)
+    err = row_scaled_error(ra, vb, va)
+    _say("shifted vs barycenter support, row-scaled %.3e" % err)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("ball", ["overlap", "shifted", "barynocaps", "baryapproxcaps"])
+def test_paper_other_balls_table_on_gpu(ball):
+    """Columns (5)-(8) of Sec. 8.1 computed on the GPU: the printed L2 errors at
+    h = 0.05, 0.025, 0.0125 within 12%, the rates within 0.2."""
+    with open(os.path.join(HERE, "golden", "paper_sec8_other_balls.json")) as f:
         tab = json.load(f)
     got = []
     for i, h in enumerate(tab["h"][1:4], start=1):

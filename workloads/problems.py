@@ -59,7 +59,8 @@ def paper_workload(h, ball, delta=0.1, grid="a"):
     kernel, u = x1^2 x2 + x2^2 with f = -2(x2 + 1), and the 3-point inner rule.
     Experiments (1)-(5) use the 7-point vertex/mid-side/centroid outer rule,
     switched to the 4-point rule for pairs with |b_k - b_k'| < delta - h_max
-    (h_max = sqrt(2) h, the element diameter), with the balls "exactcaps"
+    (h_max = sqrt(2) h, the element diameter; no pair when h_max >= delta),
+    with the balls "exactcaps"
     (one-point centroid rule on the true caps), "approxcaps" (one triangle per
     cap: two arcs fanned from the chord midpoint), "nocaps", "barycenter" and
     "overlap".  Experiments (6)-(10) use the 4-point outer rule throughout:
@@ -73,7 +74,7 @@ def paper_workload(h, ball, delta=0.1, grid="a"):
               "baryapproxcaps": dict(ball="barysupport", cap_edges=2)}
     if ball in first:
         p = Problem(delta=delta, kernel_c=constant_kernel_c(delta), outer="vertex7", inner="gauss3",
-                    outer2="strang4", switch_dist=delta - math.sqrt(2) * h, **first[ball])
+                    outer2="strang4", switch_dist=max(0.0, delta - math.sqrt(2) * h), **first[ball])
     else:
         p = Problem(delta=delta, kernel_c=constant_kernel_c(delta), outer="strang4", inner="gauss3",
                     **second[ball])
