@@ -257,6 +257,64 @@ def bench_learned(args):
     return out
 
 
+PAPER_BALLS = ("exactcaps", "approxcaps", "nocaps", "barycenter", "overlap", "shifted", "barynocaps",
+               "baryapproxcaps")
+
+
+def bench_paper(args):
+    """The workloads of Sec. 8 (grid (a), delta = 0.1, u = x1^2 x2 + x2^2, the
+    paper's rules and outer-rule switch) at the paper's finest grid
+    h = 0.00625 (K = 73,728): per ball, the FP64 assembly time, pairs, solution
+    L2 error next to the printed one, and the time relative to the slowest ball
+    (the paper's 'time [%]' column is relative to its slowest run, exactcaps at
+    this h)."""
+    import torch
+    from paper_2005_10775_amd import Plan
+    from workloads import manufactured, paper_workload
+    here = os.path.dirname(os.path.abspath(__file__))
+    printed = {}
+    for name in ("paper_sec8_table.json", "paper_sec8_other_balls.json"):
+        with open(os.path.join(here, "tests", "golden", name)) as fh:
+            tab = json.load(fh)
+        for ball, vals in tab["l2"].items():
+            printed[ball] = dict(zip(tab["h"], vals))
+    h = args.paper_h
+    rows = {}
+    for ball in PAPER_BALLS:
+        mesh, prob, man = paper_workload(h, ball)
+        u, f = manufactured(man)
+        t0 = time.perf_counter()
+        plan = Plan(mesh, prob)
+        torch.cuda.synchronize()
+        plan_ms = (time.perf_counter() - t0) * 1e3
+        xq = plan.outer_points()
+        fo = f(xq[..., 0], xq[..., 1]).contiguous()
+        g = torch.tensor(u(mesh.xy[:, 0], mesh.xy[:, 1]), dtype=torch.float64, device="cuda")
+        ms, phase = _timed_assembly(plan, fo, g, args.steps, args.warmup)
+        info = plan.info()
+        U, its = _solve(plan, mesh, u)
+        l2 = l2_error(mesh, U, u)
+        rows[ball] = {"assembly_ms": ms, "pairs_ms": phase["pairs"], "plan_ms": plan_ms,
+                      "n_pairs": info["n_pairs"], "pairs_per_s": info["n_pairs"] / (ms * 1e-3),
+                      "items": info["items"], "l2": l2, "l2_printed": printed.get(ball, {}).get(h), "cg_iters": its}
+        print("paper %-15s h=%g K=%d pairs=%d assembly %.3f ms L2 %.3e (printed %s)" % (
+            ball, h, mesh.n_triangles, info["n_pairs"], ms, l2, rows[ball]["l2_printed"]), file=sys.stderr,
+            flush=True)
+        del plan
+        torch.cuda.empty_cache()
+    slow = max(r["assembly_ms"] for r in rows.values())
+    for r in rows.values():
+        r["time_pct"] = 100.0 * r["assembly_ms"] / slow
+    ms = sum(r["assembly_ms"] for r in rows.values())
+    n = sum(r["n_pairs"] for r in rows.values())
+    return {"metric": "paper Sec. 8 workloads: FP64 assembly time per ball", "value": n / (ms * 1e-3),
+            "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "Sec. 8 grid (a): delta=0.1 h=%g K=%d, eight balls, 7/4-pt outer with switch "
+                                   "(4-pt for shifted, barycenter support), 3-pt inner" % (h, mesh.n_triangles)},
+            "balls": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +325,7 @@ def main():
     ap.add_argument("--duffy", type=int, default=0, help="override the singular-pair rule order")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="outer elements in the CPU-baseline sample")
     ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs")
+    ap.add_argument("--paper-h", type=float, default=0.00625, help="paper: grid spacing of the Sec. 8 workloads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB device buffer 3 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -286,6 +345,9 @@ def main():
         return
     if args.config == "c5":
         print(json.dumps(bench_learned(args)))
+        return
+    if args.config == "paper":
+        print(json.dumps(bench_paper(args)))
         return
     mesh, prob, man = make_config(args.config)
     if args.duffy:

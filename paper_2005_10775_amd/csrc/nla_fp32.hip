@@ -178,14 +178,20 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
     const int nC = (int)(col_off[k + 1] - coff);
     float *R_s = (float *)dyn;                                // [3][nC] sums
     float *R_c = R_s + 3 * (size_t)max_cols;                 // [3][nC] compensations
-    int *cur_l = (int *)(R_c + 3 * (size_t)max_cols);        // [nC]
+    // per column: offset of the next entry from cbase (low 16 bits) and its pair
+    // index (high 16 bits, 0xffff when done), so that the fold skips a column
+    // with nothing in a chunk on one LDS read
+    unsigned *cn_l = (unsigned *)(R_c + 3 * (size_t)max_cols);   // [nC]
+    const int cbase = colent_ptr[coff];
     for (int c = lane; c < nC; c += 64) {
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             R_s[a * nC + c] = 0.f;
             R_c[a * nC + c] = 0.f;
         }
-        cur_l[c] = colent_ptr[coff + c];
+        const int e0 = colent_ptr[coff + c];
+        const unsigned nx = e0 < colent_ptr[coff + c + 1] ? (unsigned)(colent[e0] >> 2) : 0xffffu;
+        cn_l[c] = (nx << 16) | (unsigned)(e0 - cbase);
     }
     __syncthreads();
     const float m1c = (float)R->in_m1[0], o = (float)R->in_m2[0][1], dm = (float)(R->in_m2[0][0] - R->in_m2[0][1]);
@@ -412,7 +418,10 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         {
             const int lo = (int)(base - p0), hi = lo + 64;
             for (int c = lane; c < nC; c += 64) {
-                int cur = cur_l[c];
+                // a column's entries fall in one or two chunks: skip it on one LDS read otherwise
+                const unsigned w = cn_l[c];
+                if ((int)(w >> 16) >= hi) continue;
+                int cur = cbase + (int)(w & 0xffffu);
                 const int end = colent_ptr[coff + c + 1];
                 KahanF r[3];
 #pragma unroll
@@ -420,23 +429,27 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                     r[a].s = R_s[a * nC + c];
                     r[a].c = R_c[a * nC + c];
                 }
-                while (cur < end) {
+                int pl;
+                while (true) {
                     const int e = colent[cur];
-                    const int pl = e >> 2;
+                    pl = e >> 2;
                     if (pl >= hi) break;
                     const int b = e & 3;
                     const float *mm = mxy_l[pl - lo];
                     r[0].add(mm[b]);
                     r[1].add(mm[3 + b]);
                     r[2].add(mm[6 + b]);
-                    cur++;
+                    if (++cur == end) {
+                        pl = 0xffff;
+                        break;
+                    }
                 }
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
                     R_s[a * nC + c] = r[a].s;
                     R_c[a * nC + c] = r[a].c;
                 }
-                cur_l[c] = cur;
+                cn_l[c] = ((unsigned)pl << 16) | (unsigned)(cur - cbase);
             }
         }
         __syncthreads();
@@ -914,7 +927,7 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     const bool frac = pr.kernel == NLA_KERNEL_FRACTIONAL;
     const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
     const bool pow2 = (ncap & (ncap - 1)) == 0;
-    const size_t lds = (size_t)P->max_cols * (6 * sizeof(float) + sizeof(int));
+    const size_t lds = (size_t)P->max_cols * (6 * sizeof(float) + sizeof(unsigned));
     const bool learn = pr.precision == NLA_FP32_LEARNED;
     PairArgs A = nla_pair_args(P);
     mark(P, NLA_PHASE_MLP, s);
@@ -1134,7 +1147,7 @@ static int batch_launch(nla_batch *B, hipStream_t s)
 {
     const int n = B->n;
     k_batch_zero<<<grid_for(6 * n + 1, 256), 256, 0, s>>>(n, B->d_inst, B->d_cursor);
-    const size_t lds = (size_t)B->max_cols * (6 * sizeof(float) + sizeof(int));
+    const size_t lds = (size_t)B->max_cols * (6 * sizeof(float) + sizeof(unsigned));
     k_pairs_fp32_persistent<8, true><<<B->grid, 64, lds, s>>>(B->d_args, B->d_work, B->n_work, B->chunk, B->d_cursor);
     if (B->tot_near > 0) k_batch_near<<<(unsigned)B->tot_near, 64, 0, s>>>(n, B->d_inst, B->d_off_near);
     k_batch_elem<<<(unsigned)B->tot_k, 64, 0, s>>>(n, B->d_inst, B->d_off_k);

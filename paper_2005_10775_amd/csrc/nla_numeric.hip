@@ -10,32 +10,60 @@ static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs -
 // Adds a chunk's -Mxy (pairs lo..lo+63 of element k, one row of 9 per pair in
 // mxy_l) into the row block R_k[a][c], column by column: each column is owned
 // by one lane, which takes its contributions in pair order (colent: pair index
-// << 2 | inner slot, sorted by pair; cur_l: the column's next entry).
-__device__ __forceinline__ void fold_row_block(double *R_l, int *cur_l, int nC, const int32_t *__restrict__ cptr,
-                                               const uint16_t *__restrict__ colent, const double (*mxy_l)[12], int lo,
-                                               int lane)
+// << 2 | inner slot, sorted by pair, from cbase on for this element).  cn_l
+// packs per column the offset of its next entry (low 16 bits: at most
+// 3 * 4096 entries per element) and that entry's pair index (high 16 bits,
+// 0xffff when done), so that a column with nothing in this chunk costs one
+// LDS read: a column's entries fall in one or two of the element's chunks.
+__device__ __forceinline__ void fold_row_block(double *R_l, unsigned *cn_l, int nC, const int32_t *__restrict__ cptr,
+                                               int cbase, const uint16_t *__restrict__ colent,
+                                               const double (*mxy_l)[12], int lo, int lane)
 {
     const int hi = lo + 64;
     for (int c = lane; c < nC; c += 64) {
-        int cur = cur_l[c];
+        const unsigned w = cn_l[c];
+        if ((int)(w >> 16) >= hi) continue;
+        int cur = cbase + (int)(w & 0xffffu);
         const int end = cptr[c + 1];
         double r0 = R_l[c], r1 = R_l[nC + c], r2 = R_l[2 * nC + c];
-        while (cur < end) {
+        int pl;
+        while (true) {
             const int e = colent[cur];
-            const int pl = e >> 2;
+            pl = e >> 2;
             if (pl >= hi) break;
             const int b = e & 3;
             const double *mm = mxy_l[pl - lo];
             r0 += mm[b];
             r1 += mm[3 + b];
             r2 += mm[6 + b];
-            cur++;
+            if (++cur == end) {
+                pl = 0xffff;
+                break;
+            }
         }
         R_l[c] = r0;
         R_l[nC + c] = r1;
         R_l[2 * nC + c] = r2;
-        cur_l[c] = cur;
+        cn_l[c] = ((unsigned)pl << 16) | (unsigned)(cur - cbase);
     }
+}
+
+// Row-block LDS of one element: R [3][nC] doubles, then the packed fold
+// cursors [nC] (see fold_row_block); returns the cursors.
+__device__ __forceinline__ unsigned *init_row_block(double *dyn, int max_cols, int nC,
+                                                    const int32_t *__restrict__ cptr, int cbase,
+                                                    const uint16_t *__restrict__ colent, int lane)
+{
+    unsigned *cn_l = (unsigned *)(dyn + 3 * (size_t)max_cols);
+    for (int c = lane; c < nC; c += 64) {
+        dyn[c] = 0.0;
+        dyn[nC + c] = 0.0;
+        dyn[2 * nC + c] = 0.0;
+        const int e0 = cptr[c];
+        const unsigned nx = e0 < cptr[c + 1] ? (unsigned)(colent[e0] >> 2) : 0xffffu;
+        cn_l[c] = (nx << 16) | (unsigned)(e0 - cbase);
+    }
+    return cn_l;
 }
 
 // One wavefront per outer element k (Eq. (bformhj) restricted to the pairs
@@ -102,13 +130,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     const int64_t coff = col_off[k];
     const int nC = (int)(col_off[k + 1] - coff);
     double *R_l = dyn;                                  // [3][nC]
-    int *cur_l = (int *)(dyn + 3 * (size_t)max_cols);   // [nC]
-    for (int c = lane; c < nC; c += 64) {
-        R_l[c] = 0.0;
-        R_l[nC + c] = 0.0;
-        R_l[2 * nC + c] = 0.0;
-        cur_l[c] = colent_ptr[coff + c];
-    }
+    const int cbase = colent_ptr[coff];
+    unsigned *cn_l = init_row_block(dyn, max_cols, nC, colent_ptr + coff, cbase, colent, lane);
     double m0[NQ], m0b[SW ? NQ : 1];
 #pragma unroll
     for (int q = 0; q < NQ; q++) m0[q] = 0.0;
@@ -265,7 +288,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * ayy[t];
         }
         __syncthreads();
-        fold_row_block(R_l, cur_l, nC, colent_ptr + coff, colent, mxy_l, (int)(base - p0), lane);
+        fold_row_block(R_l, cn_l, nC, colent_ptr + coff, cbase, colent, mxy_l, (int)(base - p0), lane);
         __syncthreads();
     }
     for (int i = lane; i < 3 * nC; i += 64) Rout[3 * coff + i] = R_l[i];
@@ -360,13 +383,8 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
     const int64_t coff = col_off[k];
     const int nC = (int)(col_off[k + 1] - coff);
     double *R_l = dyn;                                  // [3][nC]
-    int *cur_l = (int *)(dyn + 3 * (size_t)max_cols);   // [nC]
-    for (int c = lane; c < nC; c += 64) {
-        R_l[c] = 0.0;
-        R_l[nC + c] = 0.0;
-        R_l[2 * nC + c] = 0.0;
-        cur_l[c] = colent_ptr[coff + c];
-    }
+    const int cbase = colent_ptr[coff];
+    unsigned *cn_l = init_row_block(dyn, max_cols, nC, colent_ptr + coff, cbase, colent, lane);
     double s0sum = 0.0, mxx[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
@@ -446,7 +464,7 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
             for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * myy[t];
         }
         __syncthreads();
-        fold_row_block(R_l, cur_l, nC, colent_ptr + coff, colent, res, (int)(base - p0), lane);
+        fold_row_block(R_l, cn_l, nC, colent_ptr + coff, cbase, colent, res, (int)(base - p0), lane);
         __syncthreads();
     }
     for (int i = lane; i < 3 * nC; i += 64) Rout[3 * coff + i] = R_l[i];
@@ -616,7 +634,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         double *Ce = V + 3 * P->n_cols;
         nla_mark(P, NLA_PHASE_MLP, s);
         nla_mark(P, NLA_PHASE_PAIRS, s);
-        const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(int));
+        const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(unsigned));
         const bool cuts = pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT;
         const int ncap = cuts ? pr.cap_edges : 0;
 #define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND, SW)                                                                   \
