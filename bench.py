@@ -258,7 +258,7 @@ def bench_learned(args):
 
 
 PAPER_BALLS = ("exactcaps", "approxcaps", "nocaps", "barycenter", "overlap", "shifted", "barynocaps",
-               "baryapproxcaps")
+               "baryapproxcaps", "analyticcaps")
 
 
 def bench_paper(args):
@@ -267,7 +267,8 @@ def bench_paper(args):
     h = 0.00625 (K = 73,728): per ball, the FP64 assembly time, pairs, solution
     L2 error next to the printed one, and the time relative to the slowest ball
     (the paper's 'time [%]' column is relative to its slowest run, exactcaps at
-    this h)."""
+    this h).  "analyticcaps" is the exact ball (caps in closed form), which the
+    paper recommends without running it."""
     import torch
     from paper_2005_10775_amd import Plan
     from workloads import manufactured, paper_workload
@@ -310,7 +311,7 @@ def bench_paper(args):
     return {"metric": "paper Sec. 8 workloads: FP64 assembly time per ball", "value": n / (ms * 1e-3),
             "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "Sec. 8 grid (a): delta=0.1 h=%g K=%d, eight balls, 7/4-pt outer with switch "
+            "config": {"workload": "Sec. 8 grid (a): delta=0.1 h=%g K=%d, nine balls, 7/4-pt outer with switch "
                                    "(4-pt for shifted, barycenter support), 3-pt inner" % (h, mesh.n_triangles)},
             "balls": rows}
 

@@ -114,13 +114,16 @@ typedef struct {
                                     for pairs well inside each other's ball), decided in FP64 with
                                     every operation rounded on its own */
     double switch_dist;
-    int32_t cap_mode;            /* retri caps: NLA_CAPS_ARCS (cap_edges equal arcs, Sec. 4.2.2) or
+    int32_t cap_mode;            /* retri caps: NLA_CAPS_ARCS (cap_edges equal arcs, Sec. 4.2.2),
                                     NLA_CAPS_CENTROID (exact caps, one-point rule at the cap
-                                    centroid with the cap area as weight, Sec. 5.2; FP64, constant
-                                    kernel, inner rule exact for quadratics) */
+                                    centroid with the cap area as weight, Sec. 5.2) or
+                                    NLA_CAPS_ANALYTIC (exact caps integrated in closed form from the
+                                    circular segment's area and first and second moments: the exact
+                                    ball, no geometric error, the route Sec. 9 points to); the last
+                                    two: FP64, constant kernel, inner rule exact for quadratics */
 } nla_problem;
 
-enum { NLA_CAPS_ARCS = 0, NLA_CAPS_CENTROID = 1 };
+enum { NLA_CAPS_ARCS = 0, NLA_CAPS_CENTROID = 1, NLA_CAPS_ANALYTIC = 2 };
 
 typedef struct nla_plan nla_plan;
 

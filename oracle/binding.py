@@ -116,7 +116,9 @@ class OracleProblem:
         p.ball = {"barycenter": 0, "retri": 1, "overlap": 2, "shifted": 3, "barysupport": 4}[prob.ball]
         if p.ball >= 2 and p.kernel != 0:
             raise ValueError("the overlap, shifted and barysupport balls take the constant kernel")
-        p.cap_mode = {"poly": 0, "centroid": 1}[prob.cap_mode]
+        p.cap_mode = {"poly": 0, "centroid": 1, "analytic": 2}[prob.cap_mode]
+        if p.cap_mode == 2 and (p.kernel != 0 or p.ball not in (1, 3)):
+            raise ValueError("analytic caps integrate the constant kernel over the intersection or shifted ball")
         p.cap_edges = prob.cap_edges
         ro = get_rule(prob.outer)
         ri = get_rule(prob.inner)
@@ -238,11 +240,12 @@ def region(op, x, tri_xy, cap=2048):
     x = np.ascontiguousarray(x, dtype=np.float64)
     V = np.ascontiguousarray(np.asarray(tri_xy, dtype=np.float64).reshape(6))
     sub = np.empty(6 * cap)
-    cp, cw, nc = np.empty(16), np.empty(8), C.c_int32()
+    cp, cw, nc = np.empty(32), np.empty(8), C.c_int32()
     n = L.nlo_region(C.byref(op.cprob), _ptr(x), _ptr(V), _ptr(sub), cap, _ptr(cp), _ptr(cw), C.byref(nc))
     if n < 0:
         raise RuntimeError("region status %d" % n)
-    return sub[:6 * n].reshape(n, 3, 2).copy(), cp[:2 * nc.value].reshape(-1, 2).copy(), cw[:nc.value].copy()
+    per = 4 if op.prob.cap_mode == "analytic" else 2   # chord ends, or centroid points
+    return sub[:6 * n].reshape(n, 3, 2).copy(), cp[:per * nc.value].reshape(-1, 2).copy(), cw[:nc.value].copy()
 
 
 def blocks_range(op, k0, k1, nthreads=0):

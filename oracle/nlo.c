@@ -294,7 +294,15 @@ int nlo_region(const nlo_problem *p, const double x[2], const double V[6],
         /* a cap inside a triangle of diameter <= delta spans less than pi; a
          * larger span only arises from rounding when X and N coincide */
         if (!(D > 0.0) || D > NLO_PI) continue;
-        if (p->cap_mode == 1) {
+        if (p->cap_mode == 2) {
+            /* analytic caps: the chord ends and the span, integrated in closed form by the caller */
+            cap_pts[4 * (*n_cap)] = X->x;
+            cap_pts[4 * (*n_cap) + 1] = X->y;
+            cap_pts[4 * (*n_cap) + 2] = N->x;
+            cap_pts[4 * (*n_cap) + 3] = N->y;
+            cap_w[*n_cap] = D;
+            (*n_cap)++;
+        } else if (p->cap_mode == 1) {
             double th = 0.5 * D;
             double seg = 2.0 * th - sin(2.0 * th);
             if (th < 1e-2) {                        /* series of 2t - sin 2t, cancellation-free */
@@ -332,6 +340,61 @@ int nlo_region(const nlo_problem *p, const double x[2], const double V[6],
     return ns;
 }
 
+/* t - sin t, by its series where the difference cancels */
+static double t_minus_sin(double t)
+{
+    if (t < 1e-1) {
+        double t2 = t * t;
+        return t * t2 / 6.0 * (1.0 - t2 / 20.0 * (1.0 - t2 / 42.0 * (1.0 - t2 / 72.0 * (1.0 - t2 / 110.0))));
+    }
+    return t - sin(t);
+}
+
+/* t/8 - sin(t)/6 + sin(2t)/48 = sum_{k>=2} (-1)^k t^(2k+1) (2^(2k+1) - 8) / (48 (2k+1)!),
+ * by the series where the direct form cancels (it is t^5/240 + O(t^7)) */
+static double cap_v2_factor(double t)
+{
+    if (t < 0.5) {
+        double sum = 0.0, pw = t, fact = 1.0, two = 2.0;
+        for (int k = 1; k <= 13; k++) {
+            pw *= t * t;
+            fact *= (2.0 * k) * (2.0 * k + 1.0);
+            two *= 4.0;
+            if (k >= 2) sum += ((k & 1) ? -1.0 : 1.0) * pw / fact * (two - 8.0) / 48.0;
+        }
+        return sum;
+    }
+    return t / 8.0 - sin(t) / 6.0 + sin(2.0 * t) / 48.0;
+}
+
+/* Area, first and second moments about the centre x of the circular segment
+ * of the ball B_delta(x) cut off by the chord X N, the arc running
+ * counter-clockwise from X to N over the span D < pi (the caps of Sec. 4.2.2
+ * taken exactly; cf. Eq. (areacap)).  In the frame of the span's bisector
+ * (u along it, v across) with t = D:
+ *   A = delta^2 (t - sin t) / 2,  int u = 2/3 delta^3 sin^3(t/2),  int v = 0,
+ *   int u^2 = delta^4 (2t - sin 2t) / 16,
+ *   int v^2 = delta^4 (t/8 - sin(t)/6 + sin(2t)/48),  int uv = 0
+ * (sector minus triangle); rotated to the axes: M1 = (int y - x),
+ * M2 = (int (y-x)_1^2, int (y-x)_1 (y-x)_2, int (y-x)_2^2). */
+static void cap_segment_moments(double delta, const double x[2], const double X[2], double D,
+                                double *A, double M1[2], double M2[3])
+{
+    double d2 = delta * delta, d4 = d2 * d2;
+    double phi = atan2(X[1] - x[1], X[0] - x[0]) + 0.5 * D;
+    double c = cos(phi), sn = sin(phi);
+    double s3 = sin(0.5 * D);
+    double iu = 2.0 / 3.0 * delta * d2 * s3 * s3 * s3;
+    double iuu = d4 * t_minus_sin(2.0 * D) / 16.0;
+    double ivv = d4 * cap_v2_factor(D);
+    *A = 0.5 * d2 * t_minus_sin(D);
+    M1[0] = iu * c;
+    M1[1] = iu * sn;
+    M2[0] = iuu * c * c + ivv * sn * sn;
+    M2[1] = (iuu - ivv) * c * sn;
+    M2[2] = iuu * sn * sn + ivv * c * c;
+}
+
 /* composite inner rule (Eq. (cqr1)) of psi, psi*beta_b, psi*beta_b*beta_b'
  * over the region of (x, E_k').  Returns 0, or a negative status. */
 int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
@@ -344,7 +407,7 @@ int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
     for (int b = 0; b < 9; b++) s2[b] = 0.0;
     double dd = p->delta * p->delta;
     double sub[6 * NLO_MAXSUB];
-    double cpt[2 * 8], cw[8];
+    double cpt[4 * 8], cw[8];
     int ns = 0, nc = 0;
     int use_mlp = 0;
     if (p->ball == 0) {
@@ -401,6 +464,38 @@ int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
                 for (int c = 0; c < 3; c++) s2[3 * b + c] += wq * beta[b] * beta[c];
             }
         }
+    }
+    if (p->ball != 0 && p->cap_mode == 2 && !use_mlp) {
+        /* analytic caps (constant kernel): beta_b(y) = a_b + g_b . (y - x) is
+         * affine, so its integrals over a segment follow from the segment's
+         * moments: int beta_b = a_b A + g_b . M1,
+         * int beta_b beta_c = a_b a_c A + a_b g_c . M1 + a_c g_b . M1 + g_b^T M2 g_c */
+        double a[3], g[3][2];
+        double det = (V[2] - V[0]) * (V[5] - V[1]) - (V[3] - V[1]) * (V[4] - V[0]);
+        basis_at(V, x, a);
+        g[1][0] = (V[5] - V[1]) / det;
+        g[1][1] = -(V[4] - V[0]) / det;
+        g[2][0] = -(V[3] - V[1]) / det;
+        g[2][1] = (V[2] - V[0]) / det;
+        g[0][0] = -g[1][0] - g[2][0];
+        g[0][1] = -g[1][1] - g[2][1];
+        double psi = kernel_psi(p, x, x);
+        for (int c = 0; c < nc; c++) {
+            double A, M1[2], M2[3];
+            cap_segment_moments(p->delta, x, cpt + 4 * c, cw[c], &A, M1, M2);
+            s0[0] += psi * A;
+            for (int b = 0; b < 3; b++) {
+                double gm_b = g[b][0] * M1[0] + g[b][1] * M1[1];
+                s1[b] += psi * (a[b] * A + gm_b);
+                for (int e = 0; e < 3; e++) {
+                    double gm_e = g[e][0] * M1[0] + g[e][1] * M1[1];
+                    double q = g[b][0] * (M2[0] * g[e][0] + M2[1] * g[e][1]) +
+                               g[b][1] * (M2[1] * g[e][0] + M2[2] * g[e][1]);
+                    s2[3 * b + e] += psi * (a[b] * a[e] * A + a[b] * gm_e + a[e] * gm_b + q);
+                }
+            }
+        }
+        nc = 0;
     }
     for (int c = 0; c < nc; c++) {
         double y[2] = {cpt[2 * c], cpt[2 * c + 1]}, beta[3];
@@ -483,7 +578,7 @@ int nlo_pair_block(const nlo_mesh *m, const nlo_problem *p, int32_t k, int32_t k
          * triangles of S's nocaps / approxcaps region (and exact caps by their
          * one-point centroid rule); at each such x the inner integral runs over
          * the whole E_k'. */
-        double sub[6 * NLO_MAXSUB], cpt[2 * 8], cw[8];
+        double sub[6 * NLO_MAXSUB], cpt[4 * 8], cw[8];
         int nc = 0;
         nlo_problem pr = *p;
         pr.ball = 1;

@@ -29,7 +29,8 @@ typedef struct {
     int32_t ball;                /* 0: barycenter ; 1: intersection (retriangulated) ball ;
                                   * 2: overlap ; 3: shifted (intersection ball about b_k) ;
                                   * 4: barycenter with the outer integral over E_k n B(b_k') */
-    int32_t cap_mode;            /* 0: caps by cap_edges equal arcs ; 1: exact caps, 1-pt centroid rule */
+    int32_t cap_mode;            /* 0: caps by cap_edges equal arcs ; 1: exact caps, 1-pt centroid rule ;
+                                  * 2: exact caps integrated in closed form (constant kernel) */
     int32_t cap_edges;           /* 0 = inscribed polygon only */
     int32_t n_out; const double *out_lam; const double *out_w;
     int32_t n_in;  const double *in_lam;  const double *in_w;

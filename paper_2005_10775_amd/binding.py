@@ -176,7 +176,7 @@ def marshal(mesh, prob, keep, mlp=None):
         keep += [gx, gw]
         p.duffy_n, p.duffy_x, p.duffy_w = prob.duffy_order, gx.ctypes.data, gw.ctypes.data
     p.ball = BALLS[prob.ball]
-    p.cap_mode = {"poly": 0, "centroid": 1}[prob.cap_mode]
+    p.cap_mode = {"poly": 0, "centroid": 1, "analytic": 2}[prob.cap_mode]
     p.cap_edges = prob.cap_edges
     if prob.outer2:
         p.outer2 = _rule(get_rule(prob.outer2), keep)

@@ -391,11 +391,73 @@ __device__ __forceinline__ void edge_mom(RegionMom &R, double ax, double ay, dou
 // the fan of the region gives exactly these moments.  Coordinates about
 // vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.  cb: 12
 // doubles of scratch per call.
+// t - sin t, by its series where the difference cancels
+__device__ __forceinline__ double t_sin_diff(double t)
+{
+    if (t < 0.1) {
+        const double t2 = t * t;
+        return t * t2 / 6.0 * (1.0 - t2 / 20.0 * (1.0 - t2 / 42.0 * (1.0 - t2 / 72.0 * (1.0 - t2 / 110.0))));
+    }
+    return t - sin(t);
+}
+
+// t/8 - sin(t)/6 + sin(2t)/48 = t^5/240 + O(t^7): for t < 1/2 by its series
+// sum_{k>=2} (-1)^k t^(2k+1) (2^(2k+1) - 8) / (48 (2k+1)!)
+__device__ __forceinline__ double segment_v2(double t)
+{
+    if (t < 0.5) {
+        const double t2 = t * t;
+        double pw = t * t2 * t2, fact = 120.0, two = 32.0, sum = 0.0;
+        for (int k = 2; k <= 13; k++) {
+            sum += ((k & 1) ? -1.0 : 1.0) * pw / fact * (two - 8.0) * (1.0 / 48.0);
+            pw *= t2;
+            fact *= (2.0 * k + 2.0) * (2.0 * k + 3.0);
+            two *= 4.0;
+        }
+        return sum;
+    }
+    return t * (1.0 / 8.0) - sin(t) * (1.0 / 6.0) + sin(2.0 * t) * (1.0 / 48.0);
+}
+
+// The boundary-sum increments (RegionMom convention) of an exact cap in closed
+// form: the circular segment from X = (ax, ay) counter-clockwise to N (cr, dt:
+// cross and dot products of X and N, all relative to the centre) has, in the
+// frame of the span's bisector (u along it, v across, t = the span),
+// A = delta^2 (t - sin t)/2, int u = 2/3 delta^3 sin^3(t/2), int v = int uv = 0,
+// int u^2 = delta^4 (2t - sin 2t)/16, int v^2 = delta^4 (t/8 - sin t/6 + sin 2t/48);
+// rotated, and moved to the local origin o: int z = M1 - A o,
+// int z z^T = M2 - M1 o^T - o M1^T + A o o^T.  Kept out of line: a rare path in
+// kernels whose registers are spoken for.
+__device__ __attribute__((noinline)) RegionMom analytic_cap(double ax, double ay, double cr, double dt, double ox,
+                                                             double oy, double dd, double delta)
+{
+    RegionMom m = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double t = atan2(cr, dt);
+    const double A = 0.5 * dd * t_sin_diff(t);
+    if (!(A > 0.0)) return m;
+    const double sh = sin(0.5 * t);
+    const double iu = (2.0 / 3.0) * delta * dd * sh * sh * sh;
+    const double iuu = dd * dd * t_sin_diff(2.0 * t) * (1.0 / 16.0), ivv = dd * dd * segment_v2(t);
+    double sa, ca;
+    sincos(atan2(ay, ax) + 0.5 * t, &sa, &ca);
+    const double m1x = iu * ca, m1y = iu * sa;
+    const double m2xx = iuu * ca * ca + ivv * sa * sa, m2yy = iuu * sa * sa + ivv * ca * ca;
+    const double m2xy = (iuu - ivv) * ca * sa;
+    m.c = 2.0 * A;
+    m.mx = 6.0 * (m1x - A * ox);
+    m.my = 6.0 * (m1y - A * oy);
+    m.qxx = 12.0 * (m2xx - 2.0 * m1x * ox + A * ox * ox);
+    m.qyy = 12.0 * (m2yy - 2.0 * m1y * oy + A * oy * oy);
+    m.qxy = 24.0 * (m2xy - m1x * oy - m1y * ox + A * ox * oy);
+    return m;
+}
+
 template <bool POW2, bool CEN = false>
 __device__ void partial_boundary(double xx, double xy, const double *Vl, double dd, int ncap, RegionMom &R, int &nseg,
                                  double *cb, int centroid_rt = 0, double delta = 0.0)
 {
-    // CEN: the instantiation that can take exact caps (centroid_rt selects them at run time)
+    // CEN: the instantiation that can take exact caps (centroid_rt selects them at run
+    // time: 1 the one-point centroid rule, 2 closed-form segment moments)
     const bool centroid = CEN && centroid_rt != 0;
     const double ox = Vl[0] - xx, oy = Vl[1] - xy;      // local origin (vertex 0) relative to x
     int cnt = 0, ft = 0, pt = 0, ncp = 0;
@@ -443,6 +505,17 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
     for (int ci = 0; ci < ncp; ci++) {
         const double ax = cb[4 * ci], ay = cb[4 * ci + 1], bx = cb[4 * ci + 2], by = cb[4 * ci + 3];
         const double cr = ax * by - ay * bx, dt = ax * bx + ay * by;
+        if (centroid && centroid_rt == 2) {
+            const RegionMom m = analytic_cap(ax, ay, cr, dt, ox, oy, dd, delta);
+            R.c += m.c;
+            R.mx += m.mx;
+            R.my += m.my;
+            R.qxx += m.qxx;
+            R.qyy += m.qyy;
+            R.qxy += m.qxy;
+            nseg += 1 << 16;
+            continue;
+        }
         if (centroid) {
             // exact cap by the one-point rule of Sec. 5.2: weight = cap area
             // (delta^2/2)(2t - sin 2t), point on the bisector at 4 delta sin^3 t / (3 (2t - sin 2t)),

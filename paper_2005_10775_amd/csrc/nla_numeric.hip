@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     __shared__ double sW[NQ][4];
     __shared__ double sX[NQ][2];
     // SW: the second outer rule's weights and points (pairs with pair_r2 set); this
-// variant also integrates exact caps by the centroid rule when asked
+// variant also integrates exact caps (centroid rule or closed form) when asked
     __shared__ double sW2[SW ? NQ : 1][4];
     __shared__ double sX2[SW ? NQ : 1][2];
     __shared__ double sV[64][7];
@@ -640,13 +640,13 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
 #define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND, SW)                                                                   \
     k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, lds, s>>>(                                                  \
         P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,           \
-        pr.cap_mode == NLA_CAPS_CENTROID ? 1 : 0, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr,            \
+        pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr,                                         \
         P->colent, V, Cyy, Cxx, P->max_cols, P->counters)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
         const bool bnd = P->rules.in_q2exact != 0 && pr.ball == NLA_BALL_RETRI;
-        // the variant with the second outer rule also carries the exact (centroid) caps
-        const bool sw = P->rules.n_out2 > 0 || pr.cap_mode == NLA_CAPS_CENTROID;
+        // the variant with the second outer rule also carries the exact caps
+        const bool sw = P->rules.n_out2 > 0 || pr.cap_mode != NLA_CAPS_ARCS;
         if (sw && !(sym && pow2 && P->rules.n_out <= 8)) {
             nla_set_error("a second outer rule needs outer rules of at most 8 points, a symmetric inner rule and "
                           "2^m arcs per cap");

@@ -206,7 +206,7 @@ static int validate(const nla_mesh *m, const nla_problem *p)
             return NLA_E_UNSUPPORTED;
         }
     }
-    if (p->cap_mode != NLA_CAPS_ARCS && p->cap_mode != NLA_CAPS_CENTROID) {
+    if (p->cap_mode != NLA_CAPS_ARCS && p->cap_mode != NLA_CAPS_CENTROID && p->cap_mode != NLA_CAPS_ANALYTIC) {
         nla_set_error("unknown cap_mode %d", p->cap_mode);
         return NLA_E_INVALID;
     }
@@ -223,11 +223,11 @@ static int validate(const nla_mesh *m, const nla_problem *p)
         nla_set_error("the barycenter-support ball needs an outer rule exact for quadratics");
         return NLA_E_UNSUPPORTED;
     }
-    if (p->cap_mode == NLA_CAPS_CENTROID) {
-        // exact caps by the one-point centroid rule ride on the boundary-moment integration
+    if (p->cap_mode != NLA_CAPS_ARCS) {
+        // exact caps (centroid rule or closed form) ride on the boundary-moment integration
         const bool q2 = rule_q2exact(p->inner);
         if (p->ball != NLA_BALL_RETRI || p->kernel != NLA_KERNEL_CONSTANT || p->precision != NLA_FP64 || !q2) {
-            nla_set_error("centroid caps need the intersection ball, the constant kernel, NLA_FP64 and an inner rule "
+            nla_set_error("exact caps need the intersection ball, the constant kernel, NLA_FP64 and an inner rule "
                           "exact for quadratics");
             return NLA_E_UNSUPPORTED;
         }

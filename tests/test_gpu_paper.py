@@ -44,7 +44,8 @@ def _gpu_l2(mesh, prob, man):
 PARITY_CASES = [("approxcaps", 0.05, "a"), ("nocaps", 0.05, "a"), ("exactcaps", 0.05, "a"),
                 ("barycenter", 0.05, "a"), ("approxcaps", 0.1, "a"), ("overlap", 0.05, "a"),
                 ("shifted", 0.05, "a"), ("barynocaps", 0.05, "a"), ("baryapproxcaps", 0.05, "a"),
-                ("barynocaps", 0.05, "b"), ("baryapproxcaps", 0.1, "b")]
+                ("barynocaps", 0.05, "b"), ("baryapproxcaps", 0.1, "b"), ("analyticcaps", 0.05, "a"),
+                ("analyticcaps", 0.1, "a")]
 
 
 @pytest.mark.parametrize("ball,h,grid", PARITY_CASES)

@@ -480,3 +480,68 @@ def test_grid_b_element_sizes():
         inside = m.tri_in_omega.astype(bool)
         assert math.floor(d[inside].min() * 1e4) / 1e4 == pytest.approx(hmin, abs=1e-12)
         assert math.floor(d[inside].max() * 1e4) / 1e4 == pytest.approx(hmax, abs=1e-12)
+
+
+# ------------------------------------------- analytic caps (NEXT: exact caps)
+@pytest.mark.parametrize("seed", [11, 12])
+def test_analytic_caps_are_the_exact_intersection(seed):
+    """Exact caps in closed form (segment area, first and second moments) make
+    the region E' n B(x) exact: S0, S1, S2 equal the moments of the exact
+    intersection computed independently by Green's theorem, to rounding (not
+    just in the limit of many arcs), on the scale of the element's area.
+    Shape-regular triangles only: for slivers the reference's conversion of
+    region moments into basis integrals is itself ill-conditioned."""
+    d = 0.1
+    rng = np.random.default_rng(seed)
+    op = oracle.OracleProblem(structured_mesh(d, 0.05),
+                              Problem(delta=d, kernel_c=1.0, ball="retri", cap_mode="analytic",
+                                      outer="dunavant7", inner="gauss3"))
+    tested = 0
+    while tested < 60:
+        V = rng.uniform(-0.004, 0.004, size=(3, 2)) + np.array([[0, 0], [0.0125, 0], [0.0125, 0.0125]])
+        a2 = (V[1, 0] - V[0, 0]) * (V[2, 1] - V[0, 1]) - (V[1, 1] - V[0, 1]) * (V[2, 0] - V[0, 0])
+        lmax = max(np.linalg.norm(V[a] - V[(a + 1) % 3]) for a in range(3))
+        if a2 <= 0.4 * lmax * lmax:
+            continue
+        x = rng.uniform(-0.12, 0.13, size=2)
+        dv = np.linalg.norm(V - x, axis=1)
+        if np.all(dv < d) or np.min(np.abs(dv - d)) < 1e-6:
+            continue
+        mom = _green_moments(x, V, d)
+        if mom[0] < 1e-12:
+            continue
+        ex0, ex1, ex2 = _beta_moments(x, V, mom)
+        s0, s1, s2 = oracle.inner_sums(op, x, V)
+        err = max(abs(s0 - ex0), np.max(np.abs(s1 - ex1)), np.max(np.abs(s2 - ex2))) / (0.5 * a2)
+        # rounding: both sides expand quadratics about a centre ~delta/h elements away (64 arcs: >= 1e-9)
+        assert err < 2e-11, (err, x, V)
+        tested += 1
+
+
+def test_analytic_caps_whole_ball():
+    """Summed over the elements around an interior point, analytic caps give the
+    disk itself: area pi delta^2, first moment 0 and polar second moment
+    pi delta^4 / 2 about x, to rounding; hence -L u = -4 for u = |x|^2 with no
+    geometric error."""
+    d = 0.1
+    m = structured_mesh(d, 0.025, jitter=0.1, seed=5)
+    op = oracle.OracleProblem(m, Problem(delta=d, kernel_c=1.0, ball="retri", cap_mode="analytic",
+                                         outer="dunavant7", inner="gauss3"))
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        x = rng.uniform(0.3, 0.7, size=2)
+        area, m1, m2 = 0.0, np.zeros(2), 0.0
+        for k in range(m.n_triangles):
+            V = m.xy[m.tri[k]]
+            if np.min(np.linalg.norm(V - x, axis=1)) > d + 0.04:
+                continue
+            s0, s1, s2 = oracle.inner_sums(op, x, V)
+            R = V - x
+            area += s0
+            m1 += s1 @ R
+            m2 += np.sum(s2 * (R @ R.T))
+        assert abs(area - math.pi * d * d) < 1e-13 * area
+        assert np.max(np.abs(m1)) < 1e-13 * d * area
+        assert abs(m2 - math.pi * d ** 4 / 2) < 1e-13 * m2
+        psi = constant_kernel_c(d)
+        assert abs(-2 * psi * m2 - 4 * psi * (x @ m1) + 4.0) < 1e-11

@@ -28,7 +28,8 @@ class Problem:
     kernel_c: float = 0.0
     kernel_s: float = 0.0
     ball: str = "barycenter"          # "barycenter" | "retri" | "overlap" | "shifted" | "barysupport"
-    cap_mode: str = "poly"            # "poly": caps by cap_edges equal arcs ; "centroid": exact caps, 1-pt rule
+    cap_mode: str = "poly"            # "poly": caps by cap_edges equal arcs ; "centroid": exact caps, 1-pt rule ;
+                                      # "analytic": exact caps in closed form (constant kernel)
     cap_edges: int = 0                # 0 = the paper's nocaps polygon
     outer: str = "dunavant7"
     inner: str = "dunavant16"
@@ -63,12 +64,14 @@ def paper_workload(h, ball, delta=0.1, grid="a"):
     with the balls "exactcaps"
     (one-point centroid rule on the true caps), "approxcaps" (one triangle per
     cap: two arcs fanned from the chord midpoint), "nocaps", "barycenter" and
-    "overlap".  Experiments (6)-(10) use the 4-point outer rule throughout:
+    "overlap"; and "analyticcaps", the exact ball (caps integrated in closed
+    form), which the paper recommends but does not run.  Experiments (6)-(10) use the 4-point outer rule throughout:
     "shifted" (the nocaps ball about b_k) and "barynocaps" / "baryapproxcaps"
     (barycenter ball with the outer integral over E_k n B_delta(b_k'),
     approximated by nocaps / approxcaps)."""
     first = {"approxcaps": dict(ball="retri", cap_edges=2), "nocaps": dict(ball="retri", cap_edges=0),
              "exactcaps": dict(ball="retri", cap_mode="centroid"), "barycenter": dict(ball="barycenter"),
+             "analyticcaps": dict(ball="retri", cap_mode="analytic"),
              "overlap": dict(ball="overlap")}
     second = {"shifted": dict(ball="shifted", cap_edges=0), "barynocaps": dict(ball="barysupport", cap_edges=0),
               "baryapproxcaps": dict(ball="barysupport", cap_edges=2)}
