@@ -429,19 +429,29 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                     r[a].s = R_s[a * nC + c];
                     r[a].c = R_c[a * nC + c];
                 }
-                int pl;
-                while (true) {
-                    const int e = colent[cur];
-                    pl = e >> 2;
-                    if (pl >= hi) break;
-                    const int b = e & 3;
-                    const float *mm = mxy_l[pl - lo];
-                    r[0].add(mm[b]);
-                    r[1].add(mm[3 + b]);
-                    r[2].add(mm[6 + b]);
-                    if (++cur == end) {
-                        pl = 0xffff;
-                        break;
+                // the column's end and next four entries in one round trip (colent is padded by four)
+                int pl = 0;
+                bool more = true;
+                while (more) {
+                    int e[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) e[j] = colent[cur + j];
+                    more = false;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        if (cur == end) {
+                            pl = 0xffff;
+                            break;
+                        }
+                        pl = e[j] >> 2;
+                        if (pl >= hi) break;
+                        const int b = e[j] & 3;
+                        const float *mm = mxy_l[pl - lo];
+                        r[0].add(mm[b]);
+                        r[1].add(mm[3 + b]);
+                        r[2].add(mm[6 + b]);
+                        cur++;
+                        more = j == 3;
                     }
                 }
 #pragma unroll

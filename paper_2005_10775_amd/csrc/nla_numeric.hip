@@ -10,11 +10,13 @@ static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs -
 // Adds a chunk's -Mxy (pairs lo..lo+63 of element k, one row of 9 per pair in
 // mxy_l) into the row block R_k[a][c], column by column: each column is owned
 // by one lane, which takes its contributions in pair order (colent: pair index
-// << 2 | inner slot, sorted by pair, from cbase on for this element).  cn_l
-// packs per column the offset of its next entry (low 16 bits: at most
-// 3 * 4096 entries per element) and that entry's pair index (high 16 bits,
-// 0xffff when done), so that a column with nothing in this chunk costs one
-// LDS read: a column's entries fall in one or two of the element's chunks.
+// << 2 | inner slot, sorted by pair, from cbase on for this element; padded by
+// four entries).  cn_l packs per column the offset of its next entry (low 16
+// bits: at most 3 * 4096 entries per element) and that entry's pair index
+// (high 16 bits, 0xffff when done), so that a column with nothing in this
+// chunk costs one LDS read (a column's entries fall in one or two of the
+// element's chunks).  An active column's end and next four entries are loaded
+// together, so the walk costs one memory round trip, not one per entry.
 __device__ __forceinline__ void fold_row_block(double *R_l, unsigned *cn_l, int nC, const int32_t *__restrict__ cptr,
                                                int cbase, const uint16_t *__restrict__ colent,
                                                const double (*mxy_l)[12], int lo, int lane)
@@ -26,19 +28,28 @@ __device__ __forceinline__ void fold_row_block(double *R_l, unsigned *cn_l, int 
         int cur = cbase + (int)(w & 0xffffu);
         const int end = cptr[c + 1];
         double r0 = R_l[c], r1 = R_l[nC + c], r2 = R_l[2 * nC + c];
-        int pl;
-        while (true) {
-            const int e = colent[cur];
-            pl = e >> 2;
-            if (pl >= hi) break;
-            const int b = e & 3;
-            const double *mm = mxy_l[pl - lo];
-            r0 += mm[b];
-            r1 += mm[3 + b];
-            r2 += mm[6 + b];
-            if (++cur == end) {
-                pl = 0xffff;
-                break;
+        int pl = 0;
+        bool more = true;
+        while (more) {
+            int e[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) e[j] = colent[cur + j];
+            more = false;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (cur == end) {
+                    pl = 0xffff;
+                    break;
+                }
+                pl = e[j] >> 2;
+                if (pl >= hi) break;
+                const int b = e[j] & 3;
+                const double *mm = mxy_l[pl - lo];
+                r0 += mm[b];
+                r1 += mm[3 + b];
+                r2 += mm[6 + b];
+                cur++;
+                more = j == 3;
             }
         }
         R_l[c] = r0;

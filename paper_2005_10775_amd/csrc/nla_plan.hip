@@ -1113,7 +1113,9 @@ int nla_build_pattern(nla_plan *P, hipStream_t s)
     NLA_TRY(P->arena.get(&P->col_off, K + 1));
     NLA_TRY(P->arena.get(&P->colset, nu));
     NLA_TRY(P->arena.get(&P->colent_ptr, nu + 1));
-    NLA_TRY(P->arena.get(&P->colent, n3));
+    // four entries of padding: the fold reads a column's next four entries at once
+    NLA_TRY(P->arena.get(&P->colent, n3 + 4));
+    NLA_HIP(hipMemsetAsync(P->colent + n3, 0, 4 * sizeof(uint16_t), s));
     k_col_off<<<grid_for(K + 1, 256), 256, 0, s>>>(K, U, nu, P->col_off);
     if (nu > 0) k_colset<<<grid_for(nu, 256), 256, 0, s>>>(nu, U, P->colset);
     {
