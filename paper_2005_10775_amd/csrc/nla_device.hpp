@@ -391,6 +391,16 @@ __device__ __forceinline__ void edge_mom(RegionMom &R, double ax, double ay, dou
 // the fan of the region gives exactly these moments.  Coordinates about
 // vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.  cb: 12
 // doubles of scratch per call.
+// 1/sqrt(v) to about an ulp: the hardware estimate and two Newton steps (for
+// values that decide nothing: the exact decisions use the rounded sqrt)
+__device__ __forceinline__ double rsqrt_nr(double v)
+{
+    double y = __builtin_amdgcn_rsq(v);
+    y = y * (1.5 - 0.5 * v * y * y);
+    y = y * (1.5 - 0.5 * v * y * y);
+    return y;
+}
+
 // t - sin t, by its series where the difference cancels
 __device__ __forceinline__ double t_sin_diff(double t)
 {
@@ -541,15 +551,19 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
             nseg += 1 << 16;
             continue;
         }
+        // rotation by phi = span / ncap
         double cc, ss;
         if (POW2) {
-            const double r = 1.0 / sqrt((ax * ax + ay * ay) * (bx * bx + by * by));
+            // half angles: cos(t/2) = sqrt((1 + cos t)/2), sin(t/2) = sin t / (2 cos(t/2)),
+            // both from one reciprocal square root
+            const double r = rsqrt_nr((ax * ax + ay * ay) * (bx * bx + by * by));
             cc = dt * r;
             ss = cr * r;
             for (int m = ncap; m > 1; m >>= 1) {
-                const double ch = sqrt(0.5 * (1.0 + cc));
-                ss = ss / (2.0 * ch);
-                cc = ch;
+                const double h = 0.5 * (1.0 + cc);
+                const double rh = rsqrt_nr(h);
+                ss = 0.5 * ss * rh;
+                cc = h * rh;
             }
         } else {
             const double D = atan2(cr, dt);
