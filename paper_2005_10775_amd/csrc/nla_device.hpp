@@ -475,18 +475,19 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
     // caps found on the walk (at most three, one per exit) are kept in cb (12
     // doubles) and integrated after it, so that the lanes of a wavefront fan
     // their caps together
+    // (the counters move by arithmetic, not in the branches: an increment in
+    // both arms is merged through a selected address, which puts them in memory)
     auto connect = [&](double ax, double ay, int at, double bx, double by, int bt) __attribute__((always_inline)) {
-        if (at == 2 && bt == 1 && (ncap >= 2 || centroid) && ax * by - ay * bx > 0.0) {
-            if (centroid) edge_mom(R, ax - ox, ay - oy, bx - ox, by - oy);   // the chord stays
+        const bool cap = at == 2 && bt == 1 && (ncap >= 2 || centroid) && ax * by - ay * bx > 0.0;
+        if (cap) {
             cb[4 * ncp] = ax;
             cb[4 * ncp + 1] = ay;
             cb[4 * ncp + 2] = bx;
             cb[4 * ncp + 3] = by;
-            ncp++;
-        } else {
-            edge_mom(R, ax - ox, ay - oy, bx - ox, by - oy);
-            nseg++;
         }
+        if (!cap || centroid) edge_mom(R, ax - ox, ay - oy, bx - ox, by - oy);   // exact caps keep the chord
+        ncp += cap ? 1 : 0;
+        nseg += cap ? 0 : 1;
     };
     auto emit = [&](double nx, double ny, int nt) __attribute__((always_inline)) {
         if (cnt == 0) {
