@@ -610,7 +610,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
 // capped at delta).  Per outer point the ray sums reduce to six angular
 // moments, then to the 21 upper entries of the block.  One wavefront per pair.
 template <class T>
-__device__ void near_body(const int64_t i, const int64_t *__restrict__ near_pair, const int32_t *__restrict__ pk,
+__device__ __forceinline__ void near_body(const int64_t i, const int64_t *__restrict__ near_pair, const int32_t *__restrict__ pk,
                           const int32_t *__restrict__ pkp, const int32_t *__restrict__ tri, const ElemSoA &E,
                           const RuleSet *__restrict__ R, double delta, double kc, double ks, T *__restrict__ out)
 {
