@@ -114,10 +114,19 @@ __device__ __forceinline__ bool edge_roots(double epx, double epy, double eex, d
     el1 = 2.0;
     el2 = 2.0;
     if (disc > 0.0) {
+        // the roots n / L; whether the rounded quotient lies in (0, 1) is decided
+        // without dividing: fl(n/L) > 0 iff n > 0, and fl(n/L) < 1 iff
+        // n/L < 1 - 2^-54 (the midpoint rounds to 1) iff n - L < -L 2^-54, where
+        // n - L is exact whenever n is within a factor two of L (Sterbenz) and
+        // its sign settles the test otherwise.  The root's value decides nothing.
         const double sq = sqrt(disc);
-        const double l1 = (-Bq - sq) / L, l2 = (-Bq + sq) / L;
-        if (l1 > 0.0 && l1 < 1.0) el1 = l1;
-        if (l2 > 0.0 && l2 < 1.0) el2 = l2;
+        const double n1 = -Bq - sq, n2 = -Bq + sq, tiny = L * 0x1p-54;
+        const bool in1 = n1 > 0.0 && n1 - L < -tiny, in2 = n2 > 0.0 && n2 - L < -tiny;
+        if (in1 || in2) {
+            const double iL = 1.0 / L;
+            if (in1) el1 = n1 * iL;
+            if (in2) el2 = n2 * iL;
+        }
     }
     return r2 <= dd;
 }
