@@ -664,6 +664,10 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
     const int n = R->duffy_n;
     const double pi2 = 6.283185307179586476925286766559;
     const double e0 = -2.0 * ks;                    // exponent of r^(m-2s) at m = 0
+    // kc / (m + e0) for m = 0, 1, 2 (0 where the exponent vanishes: the log form is used)
+    double kce[3];
+#pragma unroll
+    for (int m = 0; m < 3; m++) kce[m] = fabs(m + e0) < 1e-14 ? 0.0 : kc / (m + e0);
     double L[21];
 #pragma unroll
     for (int t = 0; t < 21; t++) L[t] = 0.0;
@@ -741,8 +745,8 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
                 for (int m = 0; m < 3; m++) {
                     const double ex = m + e0;
                     if (fabs(ex) < 1e-14) J[m] = rin > 0.0 ? kc * log(rout / rin) : 0.0;
-                    else if (rin > 0.0) J[m] = kc * (ro * po - ri * pi) / ex;
-                    else J[m] = ex > 0.0 ? kc * ro * po / ex : 0.0;
+                    else if (rin > 0.0) J[m] = kce[m] * (ro * po - ri * pi);
+                    else J[m] = ex > 0.0 ? kce[m] * ro * po : 0.0;
                     ro *= rout;
                     ri *= rin;
                 }
@@ -780,7 +784,7 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
 
 // one wavefront per computed near pair (the mirrored ones read their partner's block)
 template <class T>
-__global__ __launch_bounds__(64) void k_near(int64_t n_comp, const int64_t *__restrict__ comp,
+__global__ __launch_bounds__(64, 2) void k_near(int64_t n_comp, const int64_t *__restrict__ comp,
                                              const int64_t *__restrict__ near_pair,
                                              const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp,
                                              const int32_t *__restrict__ tri, ElemSoA E, const RuleSet *__restrict__ R,
@@ -1045,7 +1049,7 @@ __global__ void k_batch_zero(int n, const BatchInst *__restrict__ B, int *__rest
     if (i < 6 * n) B[i / 6].counters[i % 6] = 0ull;
 }
 
-__global__ __launch_bounds__(64) void k_batch_near(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off)
+__global__ __launch_bounds__(64, 2) void k_batch_near(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off)
 {
     const int64_t g = blockIdx.x;
     const int t = inst_of(off, n, g);
