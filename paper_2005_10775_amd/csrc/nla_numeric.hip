@@ -109,7 +109,11 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
 // variant also integrates exact caps (centroid rule or closed form) when asked
     __shared__ double sW2[SW ? NQ : 1][4];
     __shared__ double sX2[SW ? NQ : 1][2];
-    __shared__ double sV[64][7];
+    // each lane's inner element for phase 2: its vertices re-read from memory,
+    // which keeps LDS (and so occupancy) down; the SW variant, bound by its
+    // registers instead, keeps them in LDS
+    __shared__ int skp[64];
+    __shared__ double sV[SW ? 64 : 1][7];
     __shared__ unsigned short queue[64 * NQ];
     // item results of a phase-2 round, later the chunk's -Mxy (never live together)
     __shared__ double res[64][12];
@@ -155,15 +159,19 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         const bool act = p < p1;
         double V[6] = {0, 0, 0, 0, 0, 0};
         double a2p = 0.0, bxp = 0.0, byp = 0.0;
+        const int kp = act ? pair_kp[p] : 0;
         if (act) {
-            int kp = pair_kp[p];
             V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
             a2p = E.a2[kp];
             bxp = E.bx[kp];
             byp = E.by[kp];
         }
+        skp[lane] = kp;
+        if (SW) {
 #pragma unroll
-        for (int i = 0; i < 6; i++) sV[lane][i] = V[i];
+            for (int i = 0; i < 6; i++) sV[SW ? lane : 0][i] = V[i];
+        }
+
         double ws = 0.0, aw[3] = {0.0, 0.0, 0.0};
         unsigned pmask = 0;
         const bool r2 = SW && nq2 > 0 && act && pair_r2[p];
@@ -235,6 +243,15 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 const int e = queue[i], owner = e >> 8, q = e & 0x0f;
                 const bool rr = SW && (e & 0x80);
                 const double qx = rr ? sX2[q][0] : sX[q][0], qy = rr ? sX2[q][1] : sX[q][1];
+                double Vo[6];
+                if (SW) {
+#pragma unroll
+                    for (int i = 0; i < 6; i++) Vo[i] = sV[SW ? owner : 0][i];
+                } else {
+                    const int kq = skp[owner];
+                    Vo[0] = E.vx0[kq]; Vo[1] = E.vy0[kq]; Vo[2] = E.vx1[kq]; Vo[3] = E.vy1[kq]; Vo[4] = E.vx2[kq];
+                    Vo[5] = E.vy2[kq];
+                }
                 Acc A;
                 A.a2 = 0.0;
 #pragma unroll
@@ -245,9 +262,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 if (BND) {
                     // the rule is exact for quadratics: the region's moments from its boundary
                     RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    partial_boundary<POW2, SW>(qx, qy, &sV[owner][0], dd, ncap, Rm, ns, &res[lane][0], centroid, delta);
+                    partial_boundary<POW2, SW>(qx, qy, Vo, dd, ncap, Rm, ns, &res[lane][0], centroid, delta);
                     double s0, s1[3], s2[6];
-                    region_sums(Rm, &sV[owner][0], s0, s1, s2);
+                    region_sums(Rm, Vo, s0, s1, s2);
                     res[lane][0] = s0;
 #pragma unroll
                     for (int t = 0; t < 3; t++) res[lane][1 + t] = s1[t];
@@ -256,7 +273,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 } else {
                     auto tri = [&](const double (&t)[3][5]) { tri_accum<SYM>(t, M, A); };
                     // the cap endpoints live in this lane's row of res until the sums are written
-                    partial_item<POW2>(qx, qy, &sV[owner][0], dd, ncap, tri, ns, &res[lane][0]);
+                    partial_item<POW2>(qx, qy, Vo, dd, ncap, tri, ns, &res[lane][0]);
                     res[lane][0] = A.a2 * M.wsum;
 #pragma unroll
                     for (int t = 0; t < 3; t++) res[lane][1 + t] = SYM ? A.s1[t] * M.m1c : A.s1[t];
