@@ -183,11 +183,15 @@ __device__ void partial_item(double xx, double xy, const double *Vl, double dd, 
             ev++;
             if (kind == 0) {
                 const int b = a == 2 ? 0 : a + 1;
-                const double ax = Vl[2 * a], ay = Vl[2 * a + 1];
+                // vertices picked by value (constant indices), so that Vl may point at registers
+                const double ax = a == 0 ? Vl[0] : (a == 1 ? Vl[2] : Vl[4]);
+                const double ay = a == 0 ? Vl[1] : (a == 1 ? Vl[3] : Vl[5]);
+                const double bx = b == 0 ? Vl[0] : (b == 1 ? Vl[2] : Vl[4]);
+                const double by = b == 0 ? Vl[1] : (b == 1 ? Vl[3] : Vl[5]);
                 epx = ax - xx;
                 epy = ay - xy;
-                eex = Vl[2 * b] - ax;
-                eey = Vl[2 * b + 1] - ay;
+                eex = bx - ax;
+                eey = by - ay;
                 ea = a;
                 eb = b;
                 if (edge_roots(epx, epy, eex, eey, dd, el1, el2)) {
@@ -511,6 +515,7 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
         pt = nt;
         cnt++;
     };
+#pragma unroll
     for (int a = 0; a < 3; a++) {
         const int b = a == 2 ? 0 : a + 1;
         const double epx = Vl[2 * a] - xx, epy = Vl[2 * a + 1] - xy;

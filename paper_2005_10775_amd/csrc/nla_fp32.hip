@@ -117,7 +117,7 @@ template <int NQ>
 struct PairLDS {
     double sX[NQ][2];
     float sW[NQ][4];
-    double sV[64][7];
+    int skp[64];                // each lane's inner element (phase 2 re-reads its vertices)
     unsigned short queue[64 * NQ];
     float res[64][10];
     double capbuf[64][12];
@@ -155,7 +155,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
     unsigned long long *__restrict__ counters = P.counters;
     auto &sX = S.sX;
     auto &sW = S.sW;
-    auto &sV = S.sV;
+    auto &skp = S.skp;
     auto &queue = S.queue;
     auto &res = S.res;
     auto &capbuf = S.capbuf;
@@ -206,15 +206,14 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         const bool act = p < p1 && !(near_flag && near_flag[p]);
         double V[6] = {0, 0, 0, 0, 0, 0};
         double bxp = 0.0, byp = 0.0, a2p = 0.0;
+        const int kp = act ? pair_kp[p] : 0;
         if (act) {
-            const int kp = pair_kp[p];
             V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
             bxp = E.bx[kp];
             byp = E.by[kp];
             a2p = E.a2[kp];
         }
-#pragma unroll
-        for (int i = 0; i < 6; i++) sV[lane][i] = V[i];
+        skp[lane] = kp;
         KahanF axy[9], ayy[6];
 #pragma unroll
         for (int i = 0; i < 9; i++) axy[i].zero();
@@ -330,6 +329,8 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
             const int i = ib + lane;
             if (i < total) {
                 const int e = queue[i], owner = e >> 8, q = e & 0xff;
+                const int kq = skp[owner];
+                const double Vo[6] = {E.vx0[kq], E.vy0[kq], E.vx1[kq], E.vy1[kq], E.vx2[kq], E.vy2[kq]};
                 AccF A;
                 A.zero();
                 TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC};
@@ -341,10 +342,10 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                     // constant kernel, rule exact for quadratics: moments of the region from its
                     // boundary (FP64 geometry), item sums rounded to FP32
                     RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    partial_boundary<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, Rm, ns,
+                    partial_boundary<POW2>(sX[q][0], sX[q][1], Vo, dd, routed ? 0 : ncap, Rm, ns,
                                            &capbuf[lane][0]);
                     double s0, s1[3], s2[6];
-                    region_sums(Rm, &sV[owner][0], s0, s1, s2);
+                    region_sums(Rm, Vo, s0, s1, s2);
                     const double kd = (double)kc;
                     res[lane][0] = (float)(kd * s0);
 #pragma unroll
@@ -352,7 +353,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
 #pragma unroll
                     for (int t = 0; t < 6; t++) res[lane][4 + t] = (float)(kd * s2[t]);
                 } else {
-                    partial_item<POW2>(sX[q][0], sX[q][1], &sV[owner][0], dd, routed ? 0 : ncap, tri, ns,
+                    partial_item<POW2>(sX[q][0], sX[q][1], Vo, dd, routed ? 0 : ncap, tri, ns,
                                        &capbuf[lane][0]);
                     res[lane][0] = A.s0.s;
 #pragma unroll
