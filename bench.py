@@ -68,8 +68,13 @@ def l2_error(mesh, U, u_exact):
 
 
 def source_digest():
+    """Digest of every source the FP64 pair kernel is compiled from: counters
+    taken on other source are not reported."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2005_10775_amd", "csrc", "nla_numeric.hip"), "rb") as f:
+    for name in ("nla_numeric.hip", "nla_device.hpp", "nla_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2005_10775_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    with open(os.path.join(ROOT, "include", "nlasm.h"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
