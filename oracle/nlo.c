@@ -851,16 +851,20 @@ int nlo_row(const nlo_mesh *m, const nlo_problem *p, int32_t j, int32_t *cols, d
     double *cmp = (double *)calloc(J, sizeof(double));
     uint8_t *hit = (uint8_t *)calloc(J, 1);
     int32_t *kp = (int32_t *)malloc(sizeof(int32_t) * K);
+    /* the elements with node j, ascending (listed once: the same order as a scan) */
+    int32_t *jel = (int32_t *)malloc(sizeof(int32_t) * K);
+    int nj = 0;
+    for (int kk = 0; kk < K; kk++)
+        for (int a = 0; a < 3; a++)
+            if (m->tri[3 * kk + a] == j) { jel[nj++] = kk; break; }
     int status = 0;
     for (int k = 0; k < K && status == 0; k++) {
         int kin = 0;
         for (int a = 0; a < 3; a++) kin |= m->tri[3 * k + a] == j;
         if (!kin) {
             /* pairs (k, k') with j a node of E_k' only */
-            for (int kk = 0; kk < K; kk++) {
-                int jin = 0;
-                for (int a = 0; a < 3; a++) jin |= m->tri[3 * kk + a] == j;
-                if (!jin) continue;
+            for (int ij = 0; ij < nj; ij++) {
+                const int kk = jel[ij];
                 if (p->skip_ixi && !m->tri_in_omega[k] && !m->tri_in_omega[kk]) continue;
                 if (!maybe_pair(p, e.b + 2 * k, e.r[k], e.b + 2 * kk, e.r[kk])) continue;
                 if (!pair_interacts(p, e.V + 6 * k, e.b + 2 * k, e.V + 6 * kk, e.b + 2 * kk)) continue;
@@ -895,7 +899,7 @@ int nlo_row(const nlo_mesh *m, const nlo_problem *p, int32_t j, int32_t *cols, d
             if (nc < cap) { cols[nc] = c; vals[nc] = sum[c] + cmp[c]; }
             nc++;
         }
-    free(sum); free(cmp); free(hit); free(kp);
+    free(sum); free(cmp); free(hit); free(kp); free(jel);
     elem_free(&e);
     return status < 0 ? status : nc;
 }
