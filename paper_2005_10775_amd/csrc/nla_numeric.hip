@@ -7,6 +7,12 @@ static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs -
 
 #include "nla_device.hpp"
 
+// the fold's 16-bit entry offsets (3 per pair) and pair indices, and the 16-bit
+// (pair << 2 | slot) entries, hold for every element the plan admits
+static_assert(3 * NLA_MAX_PAIRS_PER_K + 4 <= 0xffff && NLA_MAX_PAIRS_PER_K + 64 < 0xffff &&
+                  NLA_MAX_PAIRS_PER_K <= (1 << 14),
+              "fold cursors and column entries are 16-bit");
+
 // Adds a chunk's -Mxy (pairs lo..lo+63 of element k, one row of 9 per pair in
 // mxy_l) into the row block R_k[a][c], column by column: each column is owned
 // by one lane, which takes its contributions in pair order (colent: pair index

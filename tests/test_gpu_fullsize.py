@@ -6,13 +6,16 @@ times (one plan, nla_assemble with f at the outer points and g at the nodes):
   * the fractional workload (delta = 0.05, h = delta/4, s = 0.4, FP32 with the
     vertex-sharing pairs in FP64);
   * the paper's finest grid (Sec. 8, h = 0.00625, K = 73,728, approxcaps, the
-    switched outer rule, 124M pairs).
+    switched outer rule, 124M pairs);
+  * the learned-cap workload on the headline mesh (FP32, a seeded network: the
+    path, not the training, is under test).
 
 The oracle cannot assemble these whole, so it builds sampled rows of D one at
 a time (nodes in the interior, next to the boundary of Omega, at a corner and
 in Omega_I): columns bitwise, values within the path's bar row-scaled (FP64
-1e-12, FP32 2e-5); the pair lists of sampled outer elements bitwise; the load
-vector b = G - D[free, Dirichlet] g at the sampled free nodes."""
+1e-12, FP32 2e-5, learned 5e-5); the pair lists of sampled outer elements
+bitwise; the load vector b = G - D[free, Dirichlet] g at the sampled free
+nodes."""
 import sys
 
 import numpy as np
@@ -20,8 +23,11 @@ import pytest
 import torch
 
 import oracle
+import oracle.binding as ob
 from gpu_util import gpu_assemble, host
+from paper_2005_10775_amd import Mlp, Plan
 from workloads import make_config, manufactured, paper_workload
+from workloads.learned import mlp_init
 
 pytestmark = pytest.mark.gpu
 
@@ -50,13 +56,22 @@ def _sample_nodes(mesh, rng, n_free=8, n_dir=2):
     return sorted(pick)
 
 
-def _check_full(mesh, prob, man, tol, seed):
+def _check_full(mesh, prob, man, tol, seed, mlp=None, mlp_w=None, mlp_scale=1.0):
     u, f = manufactured(man)
     _say("full size: K", mesh.n_triangles, "J", mesh.n_vertices)
-    plan = gpu_assemble(mesh, prob, man)
+    if mlp is None:
+        plan = gpu_assemble(mesh, prob, man)
+    else:
+        plan = Plan(mesh, prob, mlp=mlp)
+        xq = plan.outer_points()
+        plan.assemble(f(xq[..., 0], xq[..., 1]).contiguous(),
+                      torch.tensor(u(mesh.xy[:, 0], mesh.xy[:, 1]), dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+        _say("learned items", plan.info()["items"]["learned"])
+        assert plan.info()["items"]["learned"] > 0
     rowptr, col, val = (host(t) for t in plan.csr(0))
     val = val.astype(np.float64)
-    op = oracle.OracleProblem(mesh, prob)
+    op = oracle.OracleProblem(mesh, prob, mlp_w=mlp_w, mlp_scale=mlp_scale)
     rng = np.random.default_rng(seed)
     worst = 0.0
     for j in _sample_nodes(mesh, rng):
@@ -100,3 +115,12 @@ def test_fractional_fp32_full_size():
 def test_paper_finest_grid_full_size():
     mesh, prob, man = paper_workload(0.00625, "approxcaps")
     _check_full(mesh, prob, man, 1e-12, seed=3)
+
+
+def test_learned_full_size():
+    mesh, prob, man = make_config("c5")
+    scale = 1e-5
+    w = mlp_init(12, bias_scale=0.3)
+    m = Mlp()
+    m.set_weights(w, scale)
+    _check_full(mesh, prob, man, 5e-5, seed=4, mlp=m, mlp_w=ob.effective_weights(w), mlp_scale=scale)
