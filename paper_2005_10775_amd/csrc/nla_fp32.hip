@@ -669,12 +669,35 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
     double kce[3];
 #pragma unroll
     for (int m = 0; m < 3; m++) kce[m] = fabs(m + e0) < 1e-14 ? 0.0 : kc / (m + e0);
-    double L[21];
+    // The 21 upper entries are formed after the rays, cooperatively: each outer
+    // point leaves its weight, six angular moments and six basis offsets in
+    // LDS, and lane l < 63 sums entry l % 21 over a third of the points (the
+    // thirds are added in a fixed order at the end).  Keeping one accumulator
+    // per lane instead of 21 leaves the ray loop room for three waves per SIMD.
+    __shared__ double sg[12];                  // basis gradients of the six slots: x, then y
+    __shared__ double spt[64][14];             // per point: W, A0, A1x, A1y, Axx, Axy, Ayy, c0[6]
 #pragma unroll
-    for (int t = 0; t < 21; t++) L[t] = 0.0;
-    for (int oi = lane; oi < n * n; oi += 64) {
-        const double sv = R->duffy_x[oi / n], wv = R->duffy_x[oi % n];
-        const double Wx = R->duffy_w[oi / n] * R->duffy_w[oi % n] * a2k * sv;
+    for (int a = 0; a < 6; a++)
+        if (lane == a) {
+            sg[a] = gxs[a];
+            sg[6 + a] = gys[a];
+        }
+    const int tt = lane % 21, part = lane / 21;
+    int ti = 0, tj = 0;
+    for (int ii = 0, t = 0; ii < 6; ii++)
+        for (int jj = ii; jj < 6; jj++, t++)
+            if (t == tt) {
+                ti = ii;
+                tj = jj;
+            }
+    const int pb = part == 0 ? 0 : (part == 1 ? 22 : 43), pe = part == 0 ? 22 : (part == 1 ? 43 : 64);
+    double Lt = 0.0;
+    for (int ob = 0; ob < n * n; ob += 64) {
+        const int oi = ob + lane;
+        const bool pact = oi < n * n;
+        const int oq = pact ? oi : 0;
+        const double sv = R->duffy_x[oq / n], wv = R->duffy_x[oq % n];
+        const double Wx = pact ? R->duffy_w[oq / n] * R->duffy_w[oq % n] * a2k * sv : 0.0;
         double x[2];
         for (int d = 0; d < 2; d++)
             x[d] = Vk[2 * c + d] + sv * ((1.0 - wv) * (Vk[2 * c1 + d] - Vk[2 * c + d]) + wv * (Vk[2 * c2 + d] - Vk[2 * c + d]));
@@ -719,7 +742,7 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
         }
         // angular moments: A0 = sum w J0, A1 = sum w J1 e, A2 = sum w J2 e e^T
         double A0 = 0, A1x = 0, A1y = 0, Axx = 0, Axy = 0, Ayy = 0;
-        for (int pc = 0; pc < npc; pc++)
+        for (int pc = 0; pc < (pact ? npc : 0); pc++)
             for (int it = 0; it < n; it++) {
                 const double u = R->duffy_x[it];
                 const double th = lo[pc] + (hi[pc] - lo[pc]) * (u * u * (3.0 - 2.0 * u));
@@ -758,34 +781,36 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
                 Axy += wt * J[2] * cs * sn;
                 Ayy += wt * J[2] * sn * sn;
             }
-        int t = 0;
-        for (int ii = 0; ii < 6; ii++) {
-            const double gi1 = gxs[ii] * A1x + gys[ii] * A1y;
-            for (int jj = ii; jj < 6; jj++, t++) {
-                const double gj1 = gxs[jj] * A1x + gys[jj] * A1y;
-                const double g2 = gxs[ii] * (Axx * gxs[jj] + Axy * gys[jj]) + gys[ii] * (Axy * gxs[jj] + Ayy * gys[jj]);
-                L[t] += Wx * (c0[ii] * c0[jj] * A0 + c0[ii] * gj1 + gi1 * c0[jj] + g2);
+        spt[lane][0] = Wx;
+        spt[lane][1] = pact ? A0 : 0.0;
+        spt[lane][2] = pact ? A1x : 0.0;
+        spt[lane][3] = pact ? A1y : 0.0;
+        spt[lane][4] = pact ? Axx : 0.0;
+        spt[lane][5] = pact ? Axy : 0.0;
+        spt[lane][6] = pact ? Ayy : 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; a++) spt[lane][7 + a] = pact ? c0[a] : 0.0;
+        __syncthreads();
+        if (lane < 63) {
+            const double gix = sg[ti], giy = sg[6 + ti], gjx = sg[tj], gjy = sg[6 + tj];
+            for (int q = pb; q < pe; q++) {
+                const double *r = spt[q];
+                const double a1x = r[2], a1y = r[3], axx = r[4], axy = r[5], ayy = r[6];
+                const double ci = r[7 + ti], cj = r[7 + tj];
+                const double gi1 = gix * a1x + giy * a1y, gj1 = gjx * a1x + gjy * a1y;
+                const double g2 = gix * (axx * gjx + axy * gjy) + giy * (axy * gjx + ayy * gjy);
+                Lt += r[0] * (ci * cj * r[1] + ci * gj1 + gi1 * cj + g2);
             }
         }
+        __syncthreads();
     }
-#pragma unroll
-    for (int t = 0; t < 21; t++) {
-        double v = L[t];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        L[t] = v;
-    }
-    if (lane < 21) {
-        double v = 0.0;
-#pragma unroll
-        for (int t = 0; t < 21; t++)
-            if (t == lane) v = L[t];
-        out[21 * i + lane] = (T)v;
-    }
+    const double v1 = __shfl(Lt, (lane + 21) & 63, 64), v2 = __shfl(Lt, (lane + 42) & 63, 64);
+    if (lane < 21) out[21 * i + lane] = (T)((Lt + v1) + v2);
 }
 
 // one wavefront per computed near pair (the mirrored ones read their partner's block)
 template <class T>
-__global__ __launch_bounds__(64, 2) void k_near(int64_t n_comp, const int64_t *__restrict__ comp,
+__global__ __launch_bounds__(64, 3) void k_near(int64_t n_comp, const int64_t *__restrict__ comp,
                                              const int64_t *__restrict__ near_pair,
                                              const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp,
                                              const int32_t *__restrict__ tri, ElemSoA E, const RuleSet *__restrict__ R,

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     __shared__ double sW[NQ][4];
     __shared__ double sX[NQ][2];
     // SW: the second outer rule's weights and points (pairs with pair_r2 set); this
-// variant also integrates exact caps (centroid rule or closed form) when asked
+    // variant also integrates exact caps (centroid rule or closed form) when asked
     __shared__ double sW2[SW ? NQ : 1][4];
     __shared__ double sX2[SW ? NQ : 1][2];
     // each lane's inner element for phase 2: its vertices re-read from memory,
