@@ -110,3 +110,70 @@ def test_ball_inside_triangle_unsupported(L):
         assert code == -5 and "inradius" in msg, (ball, code, msg)
         code, msg = _create(L, mesh, pb)
         assert code != -5, (ball, msg)
+
+
+def _create_prob(L, mesh, prob):
+    """nla_plan_create through the binding's marshalling (every problem field)."""
+    keep = []
+    m, p = B.marshal(mesh, prob, keep)
+    h = C.c_void_p()
+    L.nla_last_error.restype = C.c_char_p
+    code = L.nla_plan_create(C.byref(m), C.byref(p), None, C.byref(h))
+    return code, L.nla_last_error().decode()
+
+
+def test_paper_workloads_pass_validation(L):
+    """Every workload of Sec. 8 is accepted: on this host the first device call
+    then fails (NLA_E_DEVICE), after validation."""
+    from workloads import paper_workload
+    for ball in ("exactcaps", "approxcaps", "nocaps", "barycenter", "overlap", "shifted", "barynocaps",
+                 "baryapproxcaps", "analyticcaps"):
+        for h, grid in ((0.1, "a"), (0.05, "b")):
+            mesh, prob, _ = paper_workload(h, ball, grid=grid)
+            code, msg = _create_prob(L, mesh, prob)
+            assert code == -4, (ball, h, grid, code, msg)
+
+
+def test_ball_and_cap_rules_unsupported(L):
+    """The balls and cap modes that need the constant kernel, FP64, one outer
+    rule, arc caps or rules exact for quadratics are refused with
+    NLA_E_UNSUPPORTED and a message naming the requirement."""
+    from dataclasses import replace
+    from workloads import paper_workload
+    mesh = structured_mesh(0.1, 0.05)
+    shifted = paper_workload(0.05, "shifted")[1]
+    bary = paper_workload(0.05, "barynocaps")[1]
+    overlap = paper_workload(0.05, "overlap")[1]
+    analytic = paper_workload(0.05, "analyticcaps")[1]
+    cases = [
+        (replace(shifted, kernel="fractional", kernel_s=0.4, duffy_order=8), "constant kernel"),
+        (replace(overlap, precision="fp32", outer2="", switch_dist=0.0), "NLA_FP64"),
+        (replace(shifted, outer2="vertex7", switch_dist=0.01), "one outer rule"),
+        (replace(bary, cap_mode="centroid"), "arc caps"),
+        (replace(shifted, inner="centroid1"), "inner rule exact for quadratics"),
+        (replace(bary, outer="centroid1"), "outer rule exact for quadratics"),
+        (replace(analytic, precision="fp32", outer2="", switch_dist=0.0), "exact caps"),
+        (replace(analytic, inner="centroid1"), "exact caps"),
+        (replace(analytic, ball="barycenter"), "exact caps"),
+    ]
+    for prob, need in cases:
+        code, msg = _create_prob(L, mesh, prob)
+        assert code == -5 and need in msg, (prob, code, msg)
+
+
+def test_invalid_ball_fields(L):
+    from dataclasses import replace
+    from workloads import paper_workload
+    mesh = structured_mesh(0.1, 0.05)
+    prob = paper_workload(0.05, "approxcaps")[1]
+    code, msg = _create_prob(L, mesh, replace(prob, switch_dist=-1.0))
+    assert code == -1 and "switch_dist" in msg
+    keep = []
+    m, p = B.marshal(mesh, prob, keep)
+    h = C.c_void_p()
+    for field, bad in (("ball", 5), ("cap_mode", 3)):
+        saved = getattr(p, field)
+        setattr(p, field, bad)
+        assert L.nla_plan_create(C.byref(m), C.byref(p), None, C.byref(h)) == -1, field
+        assert field.split("_")[-1] in L.nla_last_error().decode()
+        setattr(p, field, saved)
