@@ -562,8 +562,10 @@ __global__ __launch_bounds__(64) void k_route(PairArgs P, int64_t *__restrict__ 
     if (!FILL && lane == 0) count[k] = run;
 }
 
+// the fractional kernel with 2^m-arc caps fits three waves per SIMD (a 44-byte
+// spill); the other variants spill heavily below their natural two
 template <int NQ, int FM, bool POW2>
-__global__ __launch_bounds__(64, 2) void k_pairs_fp32(PairArgs P)
+__global__ __launch_bounds__(64, (FM == 1 && POW2) ? 3 : 2) void k_pairs_fp32(PairArgs P)
 {
     extern __shared__ double dyn[];
     __shared__ PairLDS<NQ> S;
