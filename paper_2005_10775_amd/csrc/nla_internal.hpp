@@ -92,6 +92,12 @@ struct nla_plan {
     int64_t *pair_ptr = nullptr;
     int32_t *pair_kp = nullptr;
     int32_t *pair_k = nullptr;
+    // processing order of the FP64 constant-kernel pair kernel (nullptr: canonical):
+    // within each element the pairs that can have partial items first, then the
+    // deep pairs (every item whole), each in canonical order
+    int32_t *proc_p = nullptr;  // [n_pairs] canonical pair index of processing slot i
+    int32_t *proc_kp = nullptr; // [n_pairs] k' of processing slot i
+    int32_t *nband = nullptr;   // [K] pairs of k before its deep ones
     // pattern of D
     int64_t nnz = 0;
     int64_t *rowptr = nullptr;

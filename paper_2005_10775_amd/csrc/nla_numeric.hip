@@ -106,7 +106,10 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                                                          const int32_t *__restrict__ colent_ptr,
                                                          const uint16_t *__restrict__ colent, double *__restrict__ Rout,
                                                          double *__restrict__ Cyy, double *__restrict__ Cxx,
-                                                         int max_cols, unsigned long long *__restrict__ counters)
+                                                         int max_cols, const int32_t *__restrict__ proc_p,
+                                                         const int32_t *__restrict__ proc_kp,
+                                                         const int32_t *__restrict__ nband,
+                                                         unsigned long long *__restrict__ counters)
 {
     extern __shared__ double dyn[];
     __shared__ double sW[NQ][4];
@@ -160,12 +163,18 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     for (int q = 0; q < (SW ? NQ : 1); q++) m0b[q] = 0.0;
     unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
+    // pairs are visited in the plan's processing order when it has one: those
+    // that can have partial items first, then the deep ones, whose items are
+    // all whole (chunks of deep pairs skip the classification)
+    const int64_t nb = nband ? (int64_t)nband[k] : p1 - p0;
     for (int64_t base = p0; base < p1; base += 64) {
-        const int64_t p = base + lane;
-        const bool act = p < p1;
+        const int64_t pi = base + lane;                                   // processing slot
+        const bool act = pi < p1;
+        const int64_t p = (proc_p && act) ? (int64_t)proc_p[pi] : pi;    // the pair's canonical index
+        const bool deep = act && pi - p0 >= nb;
         double V[6] = {0, 0, 0, 0, 0, 0};
         double a2p = 0.0, bxp = 0.0, byp = 0.0;
-        const int kp = act ? pair_kp[p] : 0;
+        const int kp = act ? (proc_kp ? proc_kp[pi] : pair_kp[pi]) : 0;
         if (act) {
             V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
             a2p = E.a2[kp];
@@ -188,7 +197,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 if (q >= nqp) break;
                 const double xx = r2 ? sX2[q][0] : sX[q][0], xy = r2 ? sX2[q][1] : sX[q][1];
                 bool whole = false, part = false;
-                if (ball == NLA_BALL_BARYCENTER) {
+                if (deep) {
+                    whole = true;
+                } else if (ball == NLA_BALL_BARYCENTER) {
                     whole = bary_in(xx, xy, bxp, byp, dd);
                 } else {
                     // overlap ball: every element meeting the ball counts whole
@@ -675,7 +686,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
     k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, lds, s>>>(                                                  \
         P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,           \
         pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr,                                         \
-        P->colent, V, Cyy, Cxx, P->max_cols, P->counters)
+        P->colent, V, Cyy, Cxx, P->max_cols, P->proc_p, P->proc_kp, P->nband, P->counters)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
         const bool bnd = P->rules.in_q2exact != 0 && pr.ball == NLA_BALL_RETRI;

@@ -686,19 +686,58 @@ __global__ void k_colset(int64_t nu, const uint64_t *__restrict__ U, int32_t *__
 }
 
 // slot key (global column slot) and value (p_local << 2 | b) of every (pair, b)
+// A pair is deep when every outer point of E_k is within delta of every vertex
+// of E_k' with room to spare: outer points lie within r_k of b_k and vertices
+// within r_k' of b_k', so |b_k - b_k'| + r_k + r_k' <= delta (1 - 1e-9) makes
+// every item whole under each ball (the relative margin covers the rounding of
+// these sums and of the outer points).  Key 2 k + deep orders each element's
+// pairs band first, deep after.
+__global__ void k_deep_keys(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, ElemSoA E,
+                            double delta, uint32_t *__restrict__ key, int32_t *__restrict__ val)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int k = pk[p], kp = pkp[p];
+    const double dx = E.bx[k] - E.bx[kp], dy = E.by[k] - E.by[kp];
+    const bool deep = sqrt(dx * dx + dy * dy) + E.r[k] + E.r[kp] <= delta * (1.0 - 1e-9);
+    key[p] = 2u * (uint32_t)k + (deep ? 1u : 0u);
+    val[p] = (int32_t)p;
+}
+
+__global__ void k_proc_kp(int64_t P, const int32_t *__restrict__ proc_p, const int32_t *__restrict__ pkp,
+                          int32_t *__restrict__ proc_kp)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    proc_kp[i] = pkp[proc_p[i]];
+}
+
+__global__ void k_nband(int K, const int64_t *__restrict__ ptr, const uint32_t *__restrict__ skey,
+                        int32_t *__restrict__ nband)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const int64_t lo = ptr[k];
+    nband[k] = (int32_t)lower_bound_u32(skey + lo, ptr[k + 1] - lo, 2u * (uint32_t)k + 1u);
+}
+
+// Column entries in processing order (slot i of pair proc_p[i], or the pairs
+// themselves when proc_p is null), so that the stable sort by column keeps each
+// column's entries in the order the pair kernel visits them.
 __global__ void k_colent_keys(int64_t P, const int32_t *__restrict__ tri, const int32_t *__restrict__ pk,
                               const int32_t *__restrict__ pkp, const int64_t *__restrict__ pair_ptr,
-                              const uint64_t *__restrict__ U, int64_t nu, uint32_t *__restrict__ key,
-                              uint16_t *__restrict__ val)
+                              const int32_t *__restrict__ proc_p, const uint64_t *__restrict__ U, int64_t nu,
+                              uint32_t *__restrict__ key, uint16_t *__restrict__ val)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const int64_t p = proc_p ? (int64_t)proc_p[i] : i;
     const uint64_t k = (uint64_t)pk[p];
-    const int pl = (int)(p - pair_ptr[k]);
+    const int pl = (int)(i - pair_ptr[k]);
     for (int b = 0; b < 3; b++) {
         int64_t slot = lower_bound_u64(U, nu, (k << 32) | (uint64_t)tri[3 * pkp[p] + b]);
-        key[3 * p + b] = (uint32_t)slot;
-        val[3 * p + b] = (uint16_t)((pl << 2) | b);
+        key[3 * i + b] = (uint32_t)slot;
+        val[3 * i + b] = (uint16_t)((pl << 2) | b);
     }
 }
 
@@ -1013,6 +1052,35 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         k_pair_rule2<<<grid_for(P->n_pairs, 256), 256, 0, s>>>(P->n_pairs, P->pair_k, P->pair_kp, P->E,
                                                               P->rules.switch_dist, P->pair_r2);
     }
+    // processing order of the FP64 constant-kernel pair kernel: band pairs first,
+    // then the deep ones (a stable sort of the keys 2 k + deep)
+    const bool ordered = pr.precision == NLA_FP64 && pr.kernel == NLA_KERNEL_CONSTANT &&
+                         (pr.ball == NLA_BALL_BARYCENTER || pr.ball == NLA_BALL_RETRI ||
+                          pr.ball == NLA_BALL_OVERLAP) &&
+                         P->n_pairs > 0 && 2 * (int64_t)K < (int64_t)UINT32_MAX;
+    if (ordered) {
+        const int64_t NP = P->n_pairs;
+        Scratch S;
+        uint32_t *key, *skey;
+        int32_t *val;
+        NLA_TRY(S.get(&key, NP));
+        NLA_TRY(S.get(&skey, NP));
+        NLA_TRY(S.get(&val, NP));
+        NLA_TRY(P->arena.get(&P->proc_p, NP));
+        NLA_TRY(P->arena.get(&P->proc_kp, NP));
+        NLA_TRY(P->arena.get(&P->nband, K));
+        k_deep_keys<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->pair_k, P->pair_kp, P->E, pr.delta, key, val);
+        const int kb = bits_for(2 * (uint64_t)K);
+        size_t tb = 0;
+        NLA_HIP(rocprim::radix_sort_pairs(nullptr, tb, key, skey, val, P->proc_p, (size_t)NP, 0, kb, s));
+        void *tmp;
+        NLA_TRY(S.get((char **)&tmp, tb));
+        NLA_HIP(rocprim::radix_sort_pairs(tmp, tb, key, skey, val, P->proc_p, (size_t)NP, 0, kb, s));
+        k_proc_kp<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->proc_p, P->pair_kp, P->proc_kp);
+        k_nband<<<grid_for(K, 256), 256, 0, s>>>(K, P->pair_ptr, skey, P->nband);
+        NLA_HIP(hipGetLastError());
+        NLA_HIP(hipStreamSynchronize(s));
+    }
     NLA_HIP(hipGetLastError());
     NLA_HIP(hipStreamSynchronize(s));
     return NLA_OK;
@@ -1137,7 +1205,8 @@ int nla_build_pattern(nla_plan *P, hipStream_t s)
         NLA_TRY(S.get(&sk, n3));
         NLA_TRY(S.get(&skk, n3));
         NLA_TRY(S.get(&sv, n3));
-        k_colent_keys<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->tri, P->pair_k, P->pair_kp, P->pair_ptr, U, nu, sk, sv);
+        k_colent_keys<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->tri, P->pair_k, P->pair_kp, P->pair_ptr, P->proc_p,
+                                                        U, nu, sk, sv);
         const int sb = bits_for((uint64_t)nu);
         size_t t3 = 0;
         NLA_HIP(rocprim::radix_sort_pairs(nullptr, t3, sk, skk, sv, P->colent, (size_t)n3, 0, sb, s));
