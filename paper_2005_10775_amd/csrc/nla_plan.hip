@@ -1053,10 +1053,11 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
                                                               P->rules.switch_dist, P->pair_r2);
     }
     // processing order of the FP64 constant-kernel pair kernel: band pairs first,
-    // then the deep ones (a stable sort of the keys 2 k + deep)
+    // then the deep ones (a stable sort of the keys 2 k + deep); the barycenter
+    // ball, whose items cost one distance test and are never partial, keeps the
+    // canonical order
     const bool ordered = pr.precision == NLA_FP64 && pr.kernel == NLA_KERNEL_CONSTANT &&
-                         (pr.ball == NLA_BALL_BARYCENTER || pr.ball == NLA_BALL_RETRI ||
-                          pr.ball == NLA_BALL_OVERLAP) &&
+                         (pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_OVERLAP) &&
                          P->n_pairs > 0 && 2 * (int64_t)K < (int64_t)UINT32_MAX;
     if (ordered) {
         const int64_t NP = P->n_pairs;
