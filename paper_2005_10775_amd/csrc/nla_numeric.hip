@@ -560,7 +560,24 @@ __global__ __launch_bounds__(64) void k_elem_blocks(int K, const int64_t *__rest
     if (kb >= K) return;
     const int k = (int)kb, lane = threadIdx.x;
     double y[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t t = tptr[k] + lane; t < tptr[k + 1]; t += 64) {
+    // two pairs' loads in flight per step (the additions keep the lane's order)
+    const int64_t te = tptr[k + 1];
+    int64_t t = tptr[k] + lane;
+    for (; t + 64 < te; t += 128) {
+        const int64_t pa = tperm[t], pb = tperm[t + 64];
+        T a[6], b[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            a[i] = Cyy[6 * pa + i];
+            b[i] = Cyy[6 * pb + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            y[i] += (double)a[i];
+            y[i] += (double)b[i];
+        }
+    }
+    if (t < te) {
         const int64_t p = tperm[t];
 #pragma unroll
         for (int i = 0; i < 6; i++) y[i] += (double)Cyy[6 * p + i];
@@ -590,7 +607,18 @@ __global__ void k_segsum_f64(int64_t n_up, const int64_t *__restrict__ up_ptr, c
     int64_t u = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (u >= n_up) return;
     double s = 0.0;
-    for (int64_t t = up_ptr[u]; t < up_ptr[u + 1]; t++) s += C[codes[t]];
+    // four codes' loads in flight per step (the additions keep the code order)
+    const int64_t te = up_ptr[u + 1];
+    int64_t t = up_ptr[u];
+    for (; t + 4 <= te; t += 4) {
+        const int c0 = codes[t], c1 = codes[t + 1], c2 = codes[t + 2], c3 = codes[t + 3];
+        const double v0 = C[c0], v1 = C[c1], v2 = C[c2], v3 = C[c3];
+        s += v0;
+        s += v1;
+        s += v2;
+        s += v3;
+    }
+    for (; t < te; t++) s += C[codes[t]];
     int64_t d = up_dst[u];
     val[d] = s;
     val[mirror[d]] = s;
