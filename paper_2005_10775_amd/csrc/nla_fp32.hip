@@ -832,7 +832,24 @@ __device__ void elem_blocks_body(const int k, const int64_t *__restrict__ tptr, 
     KahanF y[6];
 #pragma unroll
     for (int i = 0; i < 6; i++) y[i].zero();
-    for (int64_t t = tptr[k] + lane; t < tptr[k + 1]; t += 64) {
+    // two pairs' loads in flight per step (the additions keep the lane's order)
+    const int64_t te = tptr[k + 1];
+    int64_t t = tptr[k] + lane;
+    for (; t + 64 < te; t += 128) {
+        const int64_t pa = tperm[t], pb = tperm[t + 64];
+        float a[6], b[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            a[i] = Cyy[6 * pa + i];
+            b[i] = Cyy[6 * pb + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            y[i].add(a[i]);
+            y[i].add(b[i]);
+        }
+    }
+    if (t < te) {
         const int64_t p = tperm[t];
 #pragma unroll
         for (int i = 0; i < 6; i++) y[i].add(Cyy[6 * p + i]);
@@ -869,7 +886,18 @@ __device__ __forceinline__ void segsum_body(const int64_t u, const int64_t *__re
 {
     KahanF s;
     s.zero();
-    for (int64_t t = up_ptr[u]; t < up_ptr[u + 1]; t++) s.add(V[codes[t]]);
+    // four codes' loads in flight per step (the additions keep the code order)
+    const int64_t te = up_ptr[u + 1];
+    int64_t t = up_ptr[u];
+    for (; t + 4 <= te; t += 4) {
+        const int c0 = codes[t], c1 = codes[t + 1], c2 = codes[t + 2], c3 = codes[t + 3];
+        const float v0 = V[c0], v1 = V[c1], v2 = V[c2], v3 = V[c3];
+        s.add(v0);
+        s.add(v1);
+        s.add(v2);
+        s.add(v3);
+    }
+    for (; t < te; t++) s.add(V[codes[t]]);
     if (nup_ptr)
         for (int64_t t = nup_ptr[u]; t < nup_ptr[u + 1]; t++) s.add(N[ncodes[t]]);
     const int64_t d = up_dst[u];
