@@ -286,7 +286,10 @@ def bench_paper(args):
             printed[ball] = dict(zip(tab["h"], vals))
     h = args.paper_h
     rows = {}
-    for ball in PAPER_BALLS:
+    balls = args.paper_balls.split(",") if args.paper_balls else PAPER_BALLS
+    for ball in balls:
+        if ball not in PAPER_BALLS:
+            raise SystemExit("unknown ball %r: choose from %s" % (ball, ", ".join(PAPER_BALLS)))
         mesh, prob, man = paper_workload(h, ball)
         u, f = manufactured(man)
         t0 = time.perf_counter()
@@ -316,8 +319,9 @@ def bench_paper(args):
     return {"metric": "paper Sec. 8 workloads: FP64 assembly time per ball", "value": n / (ms * 1e-3),
             "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "Sec. 8 grid (a): delta=0.1 h=%g K=%d, nine balls, 7/4-pt outer with switch "
-                                   "(4-pt for shifted, barycenter support), 3-pt inner" % (h, mesh.n_triangles)},
+            "config": {"workload": "Sec. 8 grid (a): delta=0.1 h=%g K=%d, balls %s, 7/4-pt outer with switch "
+                                   "(4-pt for shifted, barycenter support), 3-pt inner" % (
+                                       h, mesh.n_triangles, ",".join(balls))},
             "balls": rows}
 
 
@@ -332,6 +336,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096, help="outer elements in the CPU-baseline sample")
     ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs")
     ap.add_argument("--paper-h", type=float, default=0.00625, help="paper: grid spacing of the Sec. 8 workloads")
+    ap.add_argument("--paper-balls", default="", help="paper: comma-separated subset of the balls (default: all)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB device buffer 3 times (reference kernel for HBM counters)")
     args = ap.parse_args()

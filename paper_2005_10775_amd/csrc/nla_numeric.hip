@@ -3,84 +3,151 @@
 #include "nla_internal.hpp"
 #include <cmath>
 
+// workgroups per CU of the FP64 pair kernels (see lds_for_occupancy)
+#define NLA_PAIRS_WG_PER_CU 10
+#define NLA_SUPPORT_WG_PER_CU 0
+
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 #include "nla_device.hpp"
 
-// the fold's 16-bit entry offsets (3 per pair) and pair indices, and the 16-bit
-// (pair << 2 | slot) entries, hold for every element the plan admits
-static_assert(3 * NLA_MAX_PAIRS_PER_K + 4 <= 0xffff && NLA_MAX_PAIRS_PER_K + 64 < 0xffff &&
+// the fold's 15-bit entry offsets (3 per pair) and 16-bit pair indices, and the
+// 16-bit (pair << 2 | slot) entries, hold for every element the plan admits
+static_assert(3 * NLA_MAX_PAIRS_PER_K + 4 <= 0x7fff && NLA_MAX_PAIRS_PER_K + 64 < 0xffff &&
                   NLA_MAX_PAIRS_PER_K <= (1 << 14),
               "fold cursors and column entries are 16-bit");
 
-// Adds a chunk's -Mxy (pairs lo..lo+63 of element k, one row of 9 per pair in
-// mxy_l) into the row block R_k[a][c], column by column: each column is owned
-// by one lane, which takes its contributions in pair order (colent: pair index
-// << 2 | inner slot, sorted by pair, from cbase on for this element; padded by
-// four entries).  cn_l packs per column the offset of its next entry (low 16
-// bits: at most 3 * 4096 entries per element) and that entry's pair index
-// (high 16 bits, 0xffff when done), so that a column with nothing in this
-// chunk costs one LDS read (a column's entries fall in one or two of the
-// element's chunks).  An active column's end and next four entries are loaded
-// together, so the walk costs one memory round trip, not one per entry.
-__device__ __forceinline__ void fold_row_block(double *R_l, unsigned *cn_l, int nC, const int32_t *__restrict__ cptr,
-                                               int cbase, const uint16_t *__restrict__ colent,
-                                               const double (*mxy_l)[12], int lo, int lane)
+// One column's walk for fold_row_block: e holds the entries at the column's
+// cursor and r the column's sums so far, both already loaded; further groups
+// of four entries are loaded as needed.
+__device__ __forceinline__ void fold_column(double *__restrict__ Rg, unsigned *cn_l, int nC, int c, unsigned w,
+                                            int end, int cbase, const int (&e0)[4], const double (&r)[3],
+                                            const uint16_t *__restrict__ colent, const double (*mxy_l)[12], int lo,
+                                            int hi)
 {
-    const int hi = lo + 64;
-    for (int c = lane; c < nC; c += 64) {
-        const unsigned w = cn_l[c];
-        if ((int)(w >> 16) >= hi) continue;
-        int cur = cbase + (int)(w & 0xffffu);
-        const int end = cptr[c + 1];
-        double r0 = R_l[c], r1 = R_l[nC + c], r2 = R_l[2 * nC + c];
-        int pl = 0;
-        bool more = true;
-        while (more) {
-            int e[4];
+    int cur = cbase + (int)(w & 0x7fffu);
+    double r0 = r[0], r1 = r[1], r2 = r[2];
+    int e[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) e[j] = e0[j];
+    int pl = 0;
+    bool more = true;
+    while (more) {
+        more = false;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (cur == end) {
+                pl = 0xffff;
+                break;
+            }
+            pl = e[j] >> 2;
+            if (pl >= hi) break;
+            const int b = e[j] & 3;
+            const double *mm = mxy_l[pl - lo];
+            r0 += mm[b];
+            r1 += mm[3 + b];
+            r2 += mm[6 + b];
+            cur++;
+            more = j == 3;
+        }
+        if (more) {
 #pragma unroll
             for (int j = 0; j < 4; j++) e[j] = colent[cur + j];
-            more = false;
+        }
+    }
+    Rg[c] = r0;
+    Rg[nC + c] = r1;
+    Rg[2 * nC + c] = r2;
+    cn_l[c] = ((unsigned)pl << 16) | 0x8000u | (unsigned)(cur - cbase);
+}
+
+// Adds a chunk's -Mxy (pairs lo..lo+63 of element k, one row of 9 per pair in
+// mxy_l) into the row block R_k[a][c] (Rg: this element's [3][nC] block of the
+// output, which only this wavefront touches), column by column: each column is
+// owned by one lane, which takes its contributions in pair order (colent: pair
+// index << 2 | inner slot, sorted by pair, from cbase on for this element;
+// padded by four entries) and carries the column's three sums from one chunk
+// to the next through Rg.  cn_l packs per column the offset of its next entry
+// (low 15 bits: at most 3 * 4096 entries per element), whether the column has
+// sums in Rg yet (bit 15) and its next entry's pair index (high 16 bits,
+// 0xffff when done).  The columns with an entry in this chunk (at most 3 * 64)
+// are first listed densely, entry i at alist[(i / 4) * arow + i % 4], so that
+// the walks spread over all lanes; a lane then takes its listed columns two at
+// a time and loads both columns' sums, end and next four entries before
+// walking either, so a column pair costs one memory round trip.
+__device__ __forceinline__ void fold_row_block(double *__restrict__ Rg, unsigned *cn_l, int nC,
+                                               const int32_t *__restrict__ cptr, int cbase,
+                                               const uint16_t *__restrict__ colent, const double (*mxy_l)[12], int lo,
+                                               int lane, unsigned short *alist, int arow)
+{
+    const int hi = lo + 64;
+    int nact = 0;
+    auto put = [&](int i, int c) { alist[(i >> 2) * arow + (i & 3)] = (unsigned short)c; };
+    // the cursors are read four columns at a time, so one LDS round trip serves four ballots
+    for (int c0 = 0; c0 < nC; c0 += 256) {
+        unsigned w[4];
 #pragma unroll
-            for (int j = 0; j < 4; j++) {
-                if (cur == end) {
-                    pl = 0xffff;
-                    break;
-                }
-                pl = e[j] >> 2;
-                if (pl >= hi) break;
-                const int b = e[j] & 3;
-                const double *mm = mxy_l[pl - lo];
-                r0 += mm[b];
-                r1 += mm[3 + b];
-                r2 += mm[6 + b];
-                cur++;
-                more = j == 3;
+        for (int j = 0; j < 4; j++) {
+            const int c = c0 + 64 * j + lane;
+            w[j] = c < nC ? cn_l[c] : 0xffff0000u;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const bool a = (int)(w[j] >> 16) < hi;
+            const unsigned long long m = __ballot(a);
+            if (a) put(nact + __popcll(m & ((1ull << lane) - 1ull)), c0 + 64 * j + lane);
+            nact += __popcll(m);
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < nact; i += 128) {
+        const bool two = i + 64 < nact;
+        const int c = alist[(i >> 2) * arow + (i & 3)];
+        const int c2 = two ? alist[((i + 64) >> 2) * arow + (i & 3)] : 0;
+        const unsigned w0 = cn_l[c];
+        const unsigned w1 = two ? cn_l[c2] : 0u;
+        int e0[4], e1[4], end1 = 0;
+        double r0[3] = {0.0, 0.0, 0.0}, r1[3] = {0.0, 0.0, 0.0};
+        {
+            const int cur = cbase + (int)(w0 & 0x7fffu);
+#pragma unroll
+            for (int j = 0; j < 4; j++) e0[j] = colent[cur + j];
+            if (w0 & 0x8000u) {
+#pragma unroll
+                for (int a = 0; a < 3; a++) r0[a] = Rg[a * nC + c];
             }
         }
-        R_l[c] = r0;
-        R_l[nC + c] = r1;
-        R_l[2 * nC + c] = r2;
-        cn_l[c] = ((unsigned)pl << 16) | (unsigned)(cur - cbase);
+        const int end0 = cptr[c + 1];
+        if (two) {
+            const int cur = cbase + (int)(w1 & 0x7fffu);
+#pragma unroll
+            for (int j = 0; j < 4; j++) e1[j] = colent[cur + j];
+            if (w1 & 0x8000u) {
+#pragma unroll
+                for (int a = 0; a < 3; a++) r1[a] = Rg[a * nC + c2];
+            }
+            end1 = cptr[c2 + 1];
+        }
+        fold_column(Rg, cn_l, nC, c, w0, end0, cbase, e0, r0, colent, mxy_l, lo, hi);
+        if (two) fold_column(Rg, cn_l, nC, c2, w1, end1, cbase, e1, r1, colent, mxy_l, lo, hi);
     }
 }
 
-// Row-block LDS of one element: R [3][nC] doubles, then the packed fold
-// cursors [nC] (see fold_row_block); returns the cursors.
-__device__ __forceinline__ unsigned *init_row_block(double *dyn, int max_cols, int nC,
+// Fold cursors of one element in LDS [nC] (see fold_row_block); every column
+// starts unvisited at its first entry (a column without entries, which the
+// plan does not make, gets zero sums here).
+__device__ __forceinline__ unsigned *init_row_block(unsigned *dyn, double *__restrict__ Rg, int nC,
                                                     const int32_t *__restrict__ cptr, int cbase,
                                                     const uint16_t *__restrict__ colent, int lane)
 {
-    unsigned *cn_l = (unsigned *)(dyn + 3 * (size_t)max_cols);
     for (int c = lane; c < nC; c += 64) {
-        dyn[c] = 0.0;
-        dyn[nC + c] = 0.0;
-        dyn[2 * nC + c] = 0.0;
         const int e0 = cptr[c];
-        const unsigned nx = e0 < cptr[c + 1] ? (unsigned)(colent[e0] >> 2) : 0xffffu;
-        cn_l[c] = (nx << 16) | (unsigned)(e0 - cbase);
+        const bool any = e0 < cptr[c + 1];
+        const unsigned nx = any ? (unsigned)(colent[e0] >> 2) : 0xffffu;
+        dyn[c] = (nx << 16) | (unsigned)(e0 - cbase);
+        if (!any) Rg[c] = Rg[nC + c] = Rg[2 * nC + c] = 0.0;
     }
-    return cn_l;
+    return dyn;
 }
 
 // One wavefront per outer element k (Eq. (bformhj) restricted to the pairs
@@ -106,12 +173,12 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                                                          const int32_t *__restrict__ colent_ptr,
                                                          const uint16_t *__restrict__ colent, double *__restrict__ Rout,
                                                          double *__restrict__ Cyy, double *__restrict__ Cxx,
-                                                         int max_cols, const int32_t *__restrict__ proc_p,
+                                                         const int32_t *__restrict__ proc_p,
                                                          const int32_t *__restrict__ proc_kp,
                                                          const int32_t *__restrict__ nband,
                                                          unsigned long long *__restrict__ counters)
 {
-    extern __shared__ double dyn[];
+    extern __shared__ unsigned dyn[];
     __shared__ double sW[NQ][4];
     __shared__ double sX[NQ][2];
     // SW: the second outer rule's weights and points (pairs with pair_r2 set); this
@@ -123,7 +190,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     // registers instead, keeps them in LDS
     __shared__ int skp[64];
     __shared__ double sV[SW ? 64 : 1][7];
+    // the phase-2 queue, later the fold's list of active columns (at most 3 * 64)
     __shared__ unsigned short queue[64 * NQ];
+    static_assert(NQ >= 3, "the queue holds the fold's column list");
     // item results of a phase-2 round, later the chunk's -Mxy (never live together)
     __shared__ double res[64][12];
     double (*mxy_l)[12] = res;
@@ -153,9 +222,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     const RuleMom M = load_moments(R);
     const int64_t coff = col_off[k];
     const int nC = (int)(col_off[k + 1] - coff);
-    double *R_l = dyn;                                  // [3][nC]
+    double *Rg = Rout + 3 * coff;                       // [3][nC], this element's row block
     const int cbase = colent_ptr[coff];
-    unsigned *cn_l = init_row_block(dyn, max_cols, nC, colent_ptr + coff, cbase, colent, lane);
+    unsigned *cn_l = init_row_block(dyn, Rg, nC, colent_ptr + coff, cbase, colent, lane);
     double m0[NQ], m0b[SW ? NQ : 1];
 #pragma unroll
     for (int q = 0; q < NQ; q++) m0[q] = 0.0;
@@ -333,10 +402,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * ayy[t];
         }
         __syncthreads();
-        fold_row_block(R_l, cn_l, nC, colent_ptr + coff, cbase, colent, mxy_l, (int)(base - p0), lane);
+        fold_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, mxy_l, (int)(base - p0), lane, queue, 4);
         __syncthreads();
     }
-    for (int i = lane; i < 3 * nC; i += 64) Rout[3 * coff + i] = R_l[i];
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
     // lanes, then lane 0's sum is broadcast
 #pragma unroll
@@ -403,11 +471,13 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
                                                         const int32_t *__restrict__ colent_ptr,
                                                         const uint16_t *__restrict__ colent, double *__restrict__ Rout,
                                                         double *__restrict__ Cyy, double *__restrict__ Cxx,
-                                                        int max_cols, unsigned long long *__restrict__ counters)
+                                                        unsigned long long *__restrict__ counters)
 {
-    extern __shared__ double dyn[];
+    extern __shared__ unsigned dyn[];
     __shared__ double sQ[10];           // the outer rule over E_k: sum W, sum W alpha_a, sum W alpha_a alpha_c
-    __shared__ double res[64][12];      // a lane's cap endpoints, then its pair's -Mxy
+    // a lane's cap endpoints, then its pair's -Mxy (entries 0..8), with the fold's
+    // list of active columns in entries 9..11 of the first 48 rows
+    __shared__ double res[64][12];
     const int k = blockIdx.x, lane = threadIdx.x;
     const double a2k = E.a2[k];
     const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
@@ -427,9 +497,9 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
     const double Vk[6] = {E.vx0[k], E.vy0[k], E.vx1[k], E.vy1[k], E.vx2[k], E.vy2[k]};
     const int64_t coff = col_off[k];
     const int nC = (int)(col_off[k + 1] - coff);
-    double *R_l = dyn;                                  // [3][nC]
+    double *Rg = Rout + 3 * coff;                       // [3][nC], this element's row block
     const int cbase = colent_ptr[coff];
-    unsigned *cn_l = init_row_block(dyn, max_cols, nC, colent_ptr + coff, cbase, colent, lane);
+    unsigned *cn_l = init_row_block(dyn, Rg, nC, colent_ptr + coff, cbase, colent, lane);
     double s0sum = 0.0, mxx[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
@@ -509,10 +579,10 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
             for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * myy[t];
         }
         __syncthreads();
-        fold_row_block(R_l, cn_l, nC, colent_ptr + coff, cbase, colent, res, (int)(base - p0), lane);
+        fold_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, res, (int)(base - p0), lane,
+                       (unsigned short *)&res[0][9], 48);
         __syncthreads();
     }
-    for (int i = lane; i < 3 * nC; i += 64) Rout[3 * coff + i] = R_l[i];
     // Mxx(k): a fixed butterfly over the lanes, lane 0's sum broadcast
     {
         double x = s0sum;
@@ -671,6 +741,30 @@ __global__ __launch_bounds__(256) void k_load_rhs(int n_free, const int32_t *__r
     if (lane == 0) b[i] = s;
 }
 
+// Dynamic LDS for a launch of fn (64 threads per workgroup): `need` bytes,
+// raised when more than wg_per_cu workgroups would otherwise share a CU, so
+// that at most wg_per_cu do (0: no cap).  The latency-bound pair kernels run
+// faster below their register-limited occupancy: fewer waves per CU keep
+// more of each wave's element data in the CU's caches.
+static size_t lds_for_occupancy(const void *fn, size_t need, int wg_per_cu)
+{
+    int n = 0;
+    if (wg_per_cu <= 0 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, 64, need) != hipSuccess ||
+        n <= wg_per_cu)
+        return need;
+    size_t lo = need, hi = 64 * 1024;           // lo gives too many workgroups per CU
+    int nh = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nh, fn, 64, hi) != hipSuccess || nh > wg_per_cu) return need;
+    while (hi - lo > 256) {
+        const size_t mid = (lo + hi) / 2;
+        int nm = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nm, fn, 64, mid) != hipSuccess) return need;
+        if (nm > wg_per_cu) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
 static void nla_mark(nla_plan *P, int i, hipStream_t s)
 {
     if (P->cur_ev) (void)hipEventRecord(P->cur_ev[i], s);
@@ -707,14 +801,15 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         double *Ce = V + 3 * P->n_cols;
         nla_mark(P, NLA_PHASE_MLP, s);
         nla_mark(P, NLA_PHASE_PAIRS, s);
-        const size_t lds = (size_t)P->max_cols * (3 * sizeof(double) + sizeof(unsigned));
+        const size_t lds = (size_t)P->max_cols * sizeof(unsigned);
         const bool cuts = pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT;
         const int ncap = cuts ? pr.cap_edges : 0;
 #define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND, SW)                                                                   \
-    k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, lds, s>>>(                                                  \
+    k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64,                                                             \
+        lds_for_occupancy((const void *)k_pairs_const_fp64<NQ, SYM, POW2, BND, SW>, lds, NLA_PAIRS_WG_PER_CU), s>>>(\
         P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,           \
         pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr,                                         \
-        P->colent, V, Cyy, Cxx, P->max_cols, P->proc_p, P->proc_kp, P->nband, P->counters)
+        P->colent, V, Cyy, Cxx, P->proc_p, P->proc_kp, P->nband, P->counters)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
         const bool bnd = P->rules.in_q2exact != 0 && pr.ball == NLA_BALL_RETRI;
@@ -727,15 +822,17 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         }
         if (pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT) {
             if (pow2)
-                k_pairs_support_fp64<true><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
+                k_pairs_support_fp64<true><<<K, 64, lds_for_occupancy((const void *)k_pairs_support_fp64<true>, lds,
+                                                                       NLA_SUPPORT_WG_PER_CU), s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                               P->max_cols, P->counters);
+                                                               P->counters);
             else
-                k_pairs_support_fp64<false><<<K, 64, lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
+                k_pairs_support_fp64<false><<<K, 64, lds_for_occupancy((const void *)k_pairs_support_fp64<false>, lds,
+                                                                        NLA_SUPPORT_WG_PER_CU), s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                 pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                 P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                                P->max_cols, P->counters);
+                                                                P->counters);
         } else if (sw && bnd) NLA_LAUNCH_PAIRS(8, true, true, true, true);
         else if (sw) NLA_LAUNCH_PAIRS(8, true, true, false, true);
         else if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true, false);
