@@ -244,9 +244,10 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         double V[6] = {0, 0, 0, 0, 0, 0};
         double a2p = 0.0, bxp = 0.0, byp = 0.0;
         const int kp = act ? (proc_kp ? proc_kp[pi] : pair_kp[pi]) : 0;
-        if (act) {
+        if (act) a2p = E.a2[kp];
+        if (act && !deep) {
+            // a deep pair needs only the inner element's area
             V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
-            a2p = E.a2[kp];
             bxp = E.bx[kp];
             byp = E.by[kp];
         }
