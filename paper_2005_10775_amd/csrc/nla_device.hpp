@@ -602,16 +602,25 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
     }
 }
 
-// S0 = int 1, S1_b = int beta_b, S2 = int beta_b beta_b' (upper 00,01,02,11,12,22)
-// over the region from its boundary sums; beta1 = g1 . z, beta2 = g2 . z,
-// beta0 = 1 - beta1 - beta2 with z about vertex 0 and g the rows of the
-// inverse edge matrix of E'.
-__device__ __forceinline__ void region_sums(const RegionMom &R, const double *Vl, double &s0, double (&s1)[3],
-                                            double (&s2)[6])
+// Rows g1, g2 of the inverse edge matrix of E' (vertices Vl): beta1 = g1 . z,
+// beta2 = g2 . z for z about vertex 0.
+__device__ __forceinline__ void inv_edges(const double *Vl, double (&g)[4])
 {
     const double e1x = Vl[2] - Vl[0], e1y = Vl[3] - Vl[1], e2x = Vl[4] - Vl[0], e2y = Vl[5] - Vl[1];
     const double id = 1.0 / (e1x * e2y - e1y * e2x);
-    const double g11 = e2y * id, g12 = -e2x * id, g21 = -e1y * id, g22 = e1x * id;
+    g[0] = e2y * id;
+    g[1] = -e2x * id;
+    g[2] = -e1y * id;
+    g[3] = e1x * id;
+}
+
+// S0 = int 1, S1_b = int beta_b, S2 = int beta_b beta_b' (upper 00,01,02,11,12,22)
+// over the region from its boundary sums; beta0 = 1 - beta1 - beta2 with g
+// from inv_edges.
+__device__ __forceinline__ void region_sums_g(const RegionMom &R, const double (&g)[4], double &s0, double (&s1)[3],
+                                              double (&s2)[6])
+{
+    const double g11 = g[0], g12 = g[1], g21 = g[2], g22 = g[3];
     const double A = 0.5 * R.c;
     const double mx = R.mx * (1.0 / 6.0), my = R.my * (1.0 / 6.0);
     const double Qxx = R.qxx * (1.0 / 12.0), Qyy = R.qyy * (1.0 / 12.0), Qxy = R.qxy * (1.0 / 24.0);
@@ -629,4 +638,12 @@ __device__ __forceinline__ void region_sums(const RegionMom &R, const double *Vl
     s2[3] = Q11;
     s2[4] = Q12;
     s2[5] = Q22;
+}
+
+__device__ __forceinline__ void region_sums(const RegionMom &R, const double *Vl, double &s0, double (&s1)[3],
+                                            double (&s2)[6])
+{
+    double g[4];
+    inv_edges(Vl, g);
+    region_sums_g(R, g, s0, s1, s2);
 }

@@ -185,11 +185,12 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     // variant also integrates exact caps (centroid rule or closed form) when asked
     __shared__ double sW2[SW ? NQ : 1][4];
     __shared__ double sX2[SW ? NQ : 1][2];
-    // each lane's inner element for phase 2: its vertices re-read from memory,
-    // which keeps LDS (and so occupancy) down; the SW variant, bound by its
-    // registers instead, keeps them in LDS
+    // each lane's inner element for phase 2: its vertices (re-read from memory
+    // except in the SW variant, bound by its registers) and, for the boundary
+    // form, the rows of its inverse edge matrix, formed once per pair
     __shared__ int skp[64];
     __shared__ double sV[SW ? 64 : 1][7];
+    __shared__ double sG[BND ? 64 : 1][4];
     // the phase-2 queue, later the fold's list of active columns (at most 3 * 64)
     __shared__ unsigned short queue[64 * NQ];
     static_assert(NQ >= 3, "the queue holds the fold's column list");
@@ -255,6 +256,12 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         if (SW) {
 #pragma unroll
             for (int i = 0; i < 6; i++) sV[SW ? lane : 0][i] = V[i];
+        }
+        if (BND && act && !deep) {
+            double g[4];
+            inv_edges(V, g);
+#pragma unroll
+            for (int i = 0; i < 4; i++) sG[BND ? lane : 0][i] = g[i];
         }
 
         double ws = 0.0, aw[3] = {0.0, 0.0, 0.0};
@@ -350,8 +357,10 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                     // the rule is exact for quadratics: the region's moments from its boundary
                     RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                     partial_boundary<POW2, SW>(qx, qy, Vo, dd, ncap, Rm, ns, &res[lane][0], centroid, delta);
-                    double s0, s1[3], s2[6];
-                    region_sums(Rm, Vo, s0, s1, s2);
+                    double s0, s1[3], s2[6], g[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) g[i] = sG[BND ? owner : 0][i];
+                    region_sums_g(Rm, g, s0, s1, s2);
                     res[lane][0] = s0;
 #pragma unroll
                     for (int t = 0; t < 3; t++) res[lane][1 + t] = s1[t];
