@@ -188,7 +188,11 @@ int nla_load_view(const nla_plan *plan, const double **b);
 int nla_free_nodes_view(const nla_plan *plan, const int32_t **free_nodes);
 
 /* Intermediate blocks (test hook), device views valid as for the CSR views:
- *   myy  [n_pairs][6]  Myy of each pair (b<=b': 00,01,02,11,12,22);
+ *   myy  [n_pairs][6]  Myy of each pair (b<=b': 00,01,02,11,12,22); the FP64
+ *                      assembly of the intersection and overlap balls keeps no
+ *                      record for pairs whose items are all whole (it adds
+ *                      their Myy per element), and this call forms those
+ *                      records in place, after a device synchronization;
  *   mxx  [K][6]        Mxx of each outer element (same order);
  *   elem [K][6]        element block E(k) = Mxx(k) + sum_k' Myy(k', k);
  *   rows               for outer element k, the row block R_k [3][|C_k|] at

@@ -209,6 +209,18 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 }
 inline int64_t xcd_grid(int64_t nb) { return (nb + 7) / 8 * 8; }
 
+// A deep pair: every point of E_k within delta of every point of E_k' with
+// room to spare.  Outer points lie within r_k of b_k and vertices within r_k'
+// of b_k', so |b_k - b_k'| + (r_k + r_k') <= delta (1 - 1e-9) makes every item
+// whole under each ball (the relative margin covers the rounding of these sums
+// and of the outer points).  The test gives the same bits for (k, k') and
+// (k', k), so each element's deep partners are the deep pairs it owns.
+__device__ __forceinline__ bool pair_deep(const ElemSoA &E, int k, int kp, double delta)
+{
+    const double dx = E.bx[k] - E.bx[kp], dy = E.by[k] - E.by[kp];
+    return sqrt(dx * dx + dy * dy) + (E.r[k] + E.r[kp]) <= delta * (1.0 - 1e-9);
+}
+
 // learned cap corrector (nla_mlp.hip)
 struct nla_mlp;
 int nla_mlp_infer_launch(const nla_mlp *M, const float *feat, int64_t n, float *out, hipStream_t s);

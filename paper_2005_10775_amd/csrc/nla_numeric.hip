@@ -175,7 +175,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                                                          double *__restrict__ Cyy, double *__restrict__ Cxx,
                                                          const int32_t *__restrict__ proc_p,
                                                          const int32_t *__restrict__ proc_kp,
-                                                         const int32_t *__restrict__ nband,
+                                                         const int32_t *__restrict__ nband, double *__restrict__ Dk,
                                                          unsigned long long *__restrict__ counters)
 {
     extern __shared__ unsigned dyn[];
@@ -237,6 +237,10 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     // that can have partial items first, then the deep ones, whose items are
     // all whole (chunks of deep pairs skip the classification)
     const int64_t nb = nband ? (int64_t)nband[k] : p1 - p0;
+    // deep pairs leave no Myy record: their inner elements are this element's
+    // deep partners (the deep test is symmetric), so E(k) takes their Myy
+    // from Dk(k) = psi sum_w sum_deep |E_k'| (sum_w: the outer weights' sum)
+    double dsum = 0.0;
     for (int64_t base = p0; base < p1; base += 64) {
         const int64_t pi = base + lane;                                   // processing slot
         const bool act = pi < p1;
@@ -246,6 +250,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         double a2p = 0.0, bxp = 0.0, byp = 0.0;
         const int kp = act ? (proc_kp ? proc_kp[pi] : pair_kp[pi]) : 0;
         if (act) a2p = E.a2[kp];
+        if (deep) dsum += a2p;
         if (act && !deep) {
             // a deep pair needs only the inner element's area
             V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
@@ -408,8 +413,10 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             for (int a = 0; a < 3; a++)
 #pragma unroll
                 for (int b = 0; b < 3; b++) mxy_l[lane][3 * a + b] = -psi * axy[a][b];
+            if (!deep) {
 #pragma unroll
-            for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * ayy[t];
+                for (int t = 0; t < 6; t++) Cyy[6 * p + t] = psi * ayy[t];
+            }
         }
         __syncthreads();
         fold_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, mxy_l, (int)(base - p0), lane, queue, 4);
@@ -440,6 +447,15 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         for (int q = 0; q < (SW ? NQ : 0); q++)
             if (q < nq2) s += sW2[q][1 + a] * R->out2_lam[q][c] * m0b[q];
         Cxx[6 * (int64_t)k + lane] = psi * s;
+    }
+    if (Dk) {
+        double x = dsum;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) {
+            double wsum = 0.0;
+            for (int q = 0; q < nq; q++) wsum += R->out_w[q];
+            Dk[k] = psi * wsum * x;
+        }
     }
     // work counters
     unsigned long long v[5] = {c_whole, c_part, c_empty, c_sub, c_cap};
@@ -630,11 +646,15 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
 
 // Element blocks E(k') = Mxx(k') + sum_k Myy(k, k'): one wavefront per k'
 // over its pairs in the transposed order (k ascending); lane l takes every
-// 64th pair from l, lanes are combined by a fixed butterfly.
+// 64th pair from l, lanes are combined by a fixed butterfly.  With Dk, the
+// transposed order lists band pairs only and the deep pairs' Myy, all of the
+// form psi sum_w |E_k| |E_k'| m2 (every item whole), come as Dk(k') |E_k'| m2.
 template <class T>
 __global__ __launch_bounds__(64) void k_elem_blocks(int K, const int64_t *__restrict__ tptr,
                                                     const int32_t *__restrict__ tperm, const T *__restrict__ Cyy,
-                                                    const T *__restrict__ Cxx, T *__restrict__ Ce)
+                                                    const T *__restrict__ Cxx, T *__restrict__ Ce,
+                                                    const double *__restrict__ Dk, const double *__restrict__ a2,
+                                                    const RuleSet *__restrict__ R)
 {
     const int64_t kb = xcd_block(blockIdx.x, gridDim.x);
     if (kb >= K) return;
@@ -673,7 +693,12 @@ __global__ __launch_bounds__(64) void k_elem_blocks(int K, const int64_t *__rest
 #pragma unroll
         for (int i = 0; i < 6; i++)
             if (i == lane) v = y[i];
-        Ce[6 * (int64_t)k + lane] = (T)(v + (double)Cxx[6 * (int64_t)k + lane]);
+        double x = (double)Cxx[6 * (int64_t)k + lane];
+        if (Dk) {
+            const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+            x += Dk[k] * a2[k] * R->in_m2[jj[lane]][ll[lane]];
+        }
+        Ce[6 * (int64_t)k + lane] = (T)(v + x);
     }
 }
 
@@ -792,7 +817,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
     const int K = P->K;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     if (!P->contrib) {
-        P->n_contrib = 6 * NP + 12 * (int64_t)K + 3 * P->n_cols;
+        P->n_contrib = 6 * NP + 13 * (int64_t)K + 3 * P->n_cols;   // ... | Ce (6K) | Dk (K)
         NLA_TRY(P->arena.alloc(&P->contrib, es * P->n_contrib));
         NLA_TRY(P->arena.alloc(&P->val, es * P->nnz));
         NLA_TRY(P->arena.alloc(&P->a_val, es * (P->nnz_free > 0 ? P->nnz_free : 1)));
@@ -809,6 +834,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         double *Cxx = Cyy + 6 * NP;
         double *V = Cxx + 6 * (int64_t)K;          // [R (3 n_cols) | E (6K)]: the values the codes index
         double *Ce = V + 3 * P->n_cols;
+        double *Dk = P->nband ? Ce + 6 * (int64_t)K : nullptr;   // deep pairs' Myy per element
         nla_mark(P, NLA_PHASE_MLP, s);
         nla_mark(P, NLA_PHASE_PAIRS, s);
         const size_t lds = (size_t)P->max_cols * sizeof(unsigned);
@@ -819,7 +845,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         lds_for_occupancy((const void *)k_pairs_const_fp64<NQ, SYM, POW2, BND, SW>, lds, NLA_PAIRS_WG_PER_CU), s>>>(\
         P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,           \
         pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr,                                         \
-        P->colent, V, Cyy, Cxx, P->proc_p, P->proc_kp, P->nband, P->counters)
+        P->colent, V, Cyy, Cxx, P->proc_p, P->proc_kp, P->nband, Dk, P->counters)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
         const bool bnd = P->rules.in_q2exact != 0 && pr.ball == NLA_BALL_RETRI;
@@ -857,7 +883,8 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         P->ran[NLA_PHASE_PAIRS] = true;
         nla_mark(P, NLA_PHASE_NEAR, s);
         nla_mark(P, NLA_PHASE_SEGSUM, s);
-        k_elem_blocks<double><<<(unsigned)xcd_grid(K), 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
+        k_elem_blocks<double><<<(unsigned)xcd_grid(K), 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce, Dk, P->E.a2,
+                                                                   P->d_rules);
         if (P->n_up > 0)
             k_segsum_f64<<<(unsigned)xcd_grid(grid_for(P->n_up, 256)), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes,
                                                                                    P->up_dst, P->mirror, V,

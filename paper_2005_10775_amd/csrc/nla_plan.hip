@@ -687,21 +687,26 @@ __global__ void k_colset(int64_t nu, const uint64_t *__restrict__ U, int32_t *__
 
 // slot key (global column slot) and value (p_local << 2 | b) of every (pair, b)
 // A pair is deep when every outer point of E_k is within delta of every vertex
-// of E_k' with room to spare: outer points lie within r_k of b_k and vertices
-// within r_k' of b_k', so |b_k - b_k'| + r_k + r_k' <= delta (1 - 1e-9) makes
-// every item whole under each ball (the relative margin covers the rounding of
-// these sums and of the outer points).  Key 2 k + deep orders each element's
-// pairs band first, deep after.
+// of E_k' with room to spare (pair_deep).  Key 2 k + deep orders each
+// element's pairs band first, deep after.
 __global__ void k_deep_keys(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, ElemSoA E,
                             double delta, uint32_t *__restrict__ key, int32_t *__restrict__ val)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const int k = pk[p], kp = pkp[p];
-    const double dx = E.bx[k] - E.bx[kp], dy = E.by[k] - E.by[kp];
-    const bool deep = sqrt(dx * dx + dy * dy) + E.r[k] + E.r[kp] <= delta * (1.0 - 1e-9);
-    key[p] = 2u * (uint32_t)k + (deep ? 1u : 0u);
+    const int k = pk[p];
+    key[p] = 2u * (uint32_t)k + (pair_deep(E, k, pkp[p], delta) ? 1u : 0u);
     val[p] = (int32_t)p;
+}
+
+// Keys of the transposed order: k' for band pairs, K (past every element) for deep ones.
+__global__ void k_tkeys(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, ElemSoA E,
+                        double delta, int K, uint32_t *__restrict__ key)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int kp = pkp[p];
+    key[p] = pair_deep(E, pk[p], kp, delta) ? (uint32_t)K : (uint32_t)kp;
 }
 
 __global__ void k_proc_kp(int64_t P, const int32_t *__restrict__ proc_p, const int32_t *__restrict__ pkp,
@@ -1298,7 +1303,10 @@ int nla_build_pattern(nla_plan *P, hipStream_t s)
         NLA_TRY(P->arena.get(&P->ncodes, nn));
         NLA_HIP(hipMemcpyAsync(P->ncodes, snv, sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s));
     }
-    // transposed pair order (k' major, k ascending within: stable radix sort of k')
+    // transposed pair order (k' major, k ascending within: stable radix sort of
+    // k'); with the processing order on, the deep pairs sort past the last
+    // element (key K) and so drop out: their Myy reaches E(k') as one sum per
+    // element (the pair kernel adds it to Mxx(k'))
     NLA_TRY(P->arena.get(&P->tptr, K + 1));
     NLA_TRY(P->arena.get(&P->tperm, NP));
     if (NP > 0) {
@@ -1307,14 +1315,19 @@ int nla_build_pattern(nla_plan *P, hipStream_t s)
         NLA_TRY(S.get(&skp, NP));
         NLA_TRY(S.get(&iota, NP));
         k_iota<<<grid_for(NP, 256), 256, 0, s>>>(NP, iota);
+        const uint32_t *tkey = (const uint32_t *)P->pair_kp;
+        if (P->nband) {
+            uint32_t *kk;
+            NLA_TRY(S.get(&kk, NP));
+            k_tkeys<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->pair_k, P->pair_kp, P->E, P->prob.delta, K, kk);
+            tkey = kk;
+        }
         size_t tb4 = 0;
-        const int kb = bits_for((uint64_t)K);
-        NLA_HIP(rocprim::radix_sort_pairs(nullptr, tb4, (const uint32_t *)P->pair_kp, skp, iota, P->tperm, (size_t)NP, 0,
-                                          kb, s));
+        const int kb = bits_for((uint64_t)K + 1);
+        NLA_HIP(rocprim::radix_sort_pairs(nullptr, tb4, tkey, skp, iota, P->tperm, (size_t)NP, 0, kb, s));
         void *tmp4;
         NLA_TRY(S.get((char **)&tmp4, tb4));
-        NLA_HIP(rocprim::radix_sort_pairs(tmp4, tb4, (const uint32_t *)P->pair_kp, skp, iota, P->tperm, (size_t)NP, 0,
-                                          kb, s));
+        NLA_HIP(rocprim::radix_sort_pairs(tmp4, tb4, tkey, skp, iota, P->tperm, (size_t)NP, 0, kb, s));
         k_tptr<<<grid_for(K + 1, 256), 256, 0, s>>>(K, skp, NP, P->tptr);
     } else {
         NLA_HIP(hipMemsetAsync(P->tptr, 0, sizeof(int64_t) * (K + 1), s));
@@ -1564,6 +1577,27 @@ extern "C" int nla_free_nodes_view(const nla_plan *P, const int32_t **free_nodes
     return NLA_OK;
 }
 
+// Myy of the deep pairs, which the FP64 assembly folds into one sum per inner
+// element instead of storing: every item whole, so Myy = psi W(k) |E_k'| m2
+// with W(k) the sum of the pair's outer weights over E_k.
+__global__ void k_deep_myy(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, ElemSoA E,
+                           double delta, double psi, const RuleSet *__restrict__ R, const uint8_t *__restrict__ r2,
+                           double *__restrict__ myy)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int k = pk[p], kp = pkp[p];
+    if (!pair_deep(E, k, kp, delta)) return;
+    const bool second = r2 && r2[p] && R->n_out2 > 0;
+    double ws = 0.0;
+    if (second)
+        for (int q = 0; q < R->n_out2; q++) ws += R->out2_w[q] * E.a2[k];
+    else
+        for (int q = 0; q < R->n_out; q++) ws += R->out_w[q] * E.a2[k];
+    const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+    for (int t = 0; t < 6; t++) myy[6 * p + t] = psi * (ws * E.a2[kp] * R->in_m2[jj[t]][ll[t]]);
+}
+
 extern "C" int nla_blocks_view(const nla_plan *P, const void **myy, const void **mxx, const void **elem,
                                const void **rows, const int64_t **col_off, const int32_t **colset, int32_t *dtype)
 {
@@ -1572,6 +1606,15 @@ extern "C" int nla_blocks_view(const nla_plan *P, const void **myy, const void *
         return NLA_E_INVALID;
     }
     if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
+    if (P->nband && P->val_dtype == NLA_DTYPE_F64 && P->n_pairs > 0) {
+        // the deep pairs' records, formed here on request (after the assembly has finished)
+        NLA_HIP(hipDeviceSynchronize());
+        k_deep_myy<<<grid_for(P->n_pairs, 256), 256, 0, 0>>>(P->n_pairs, P->pair_k, P->pair_kp, P->E, P->prob.delta,
+                                                            P->prob.kernel_c, P->d_rules, P->pair_r2,
+                                                            (double *)P->contrib);
+        NLA_HIP(hipGetLastError());
+        NLA_HIP(hipDeviceSynchronize());
+    }
     const size_t es = P->val_dtype == NLA_DTYPE_F64 ? 8 : 4;
     const char *c = (const char *)P->contrib;
     *myy = c;

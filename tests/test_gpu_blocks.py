@@ -1,0 +1,81 @@
+"""The intermediate blocks of the FP64 assembly (nla_blocks_view) on the
+intersection ball, where pairs whose items are all whole (deep pairs) leave no
+Myy record and reach the element blocks as one sum per element:
+
+  * Myy of sampled pairs, deep and band, against the oracle's pair blocks;
+  * E(k) = Mxx(k) + sum over the pairs (k', k) of Myy(k', k), from the GPU's
+    own records;
+  * on the headline problem at h = delta/4 and on the paper's approxcaps
+    workload at h = 0.05 (switched outer rule)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import gpu_assemble, host
+from workloads import Problem, constant_kernel_c, paper_workload, structured_mesh
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    oracle.build(force=False)
+    assert torch.cuda.is_available()
+
+
+def _deep_mask(mesh, pk, kp, delta):
+    """The deep test, evaluated on the host to choose samples."""
+    V = mesh.xy[mesh.tri]
+    b = ((V[:, 0] + V[:, 1]) + V[:, 2]) / 3.0
+    r = np.max(np.hypot(V[:, :, 0] - b[:, None, 0], V[:, :, 1] - b[:, None, 1]), axis=1)
+    d = np.hypot(b[pk, 0] - b[kp, 0], b[pk, 1] - b[kp, 1])
+    return d + (r[pk] + r[kp]) <= delta * (1.0 - 1e-9)
+
+
+def _check(mesh, prob, seed):
+    plan = gpu_assemble(mesh, prob, with_load=False)
+    blk = plan.blocks()
+    myy, mxx, elem = host(blk["myy"]), host(blk["mxx"]), host(blk["elem"])
+    ptr, kp = (host(t) for t in plan.pairs())
+    K = mesh.n_triangles
+    pk = np.repeat(np.arange(K), np.diff(ptr))
+    deep = _deep_mask(mesh, pk, kp, prob.delta)
+    print("pairs", len(kp), "deep", int(deep.sum()), flush=True)
+    assert deep.sum() > 0 and (~deep).sum() > 0
+    # element blocks from the records
+    ref = mxx.copy()
+    np.add.at(ref, kp, myy)
+    scale = np.maximum(np.max(np.abs(ref), axis=1), 1e-300)
+    err = float(np.max(np.max(np.abs(elem - ref), axis=1) / scale))
+    print("element blocks vs Mxx + sum Myy: %.3e" % err, flush=True)
+    assert err < 1e-12
+    # sampled Myy against the oracle
+    op = oracle.OracleProblem(mesh, prob)
+    rng = np.random.default_rng(seed)
+    picks = np.concatenate([rng.choice(np.nonzero(deep)[0], 40, replace=False),
+                            rng.choice(np.nonzero(~deep)[0], 40, replace=False)])
+    iu = np.triu_indices(3)
+    worst = 0.0
+    for p in picks:
+        m = oracle.pair_block(op, int(pk[p]), int(kp[p]))["myy"][iu]
+        # scaled like a row of D: by the typical Myy of the outer element's pairs
+        # (a pair whose region only touches E_k' has Myy = 0 and a rounding residue)
+        k = int(pk[p])
+        typ = float(np.median(np.max(np.abs(myy[ptr[k]:ptr[k + 1]]), axis=1)))
+        e = float(np.max(np.abs(myy[p] - m)) / max(np.max(np.abs(m)), typ))
+        worst = max(worst, e)
+        assert e < 1e-12, ("pair", int(pk[p]), int(kp[p]), bool(deep[p]), e)
+    print("sampled Myy: worst %.3e" % worst, flush=True)
+
+
+def test_blocks_headline_problem():
+    d = 0.1
+    prob = Problem(delta=d, kernel="constant", kernel_c=constant_kernel_c(d), ball="retri", cap_edges=8,
+                   outer="dunavant7", inner="dunavant16")
+    _check(structured_mesh(d, d / 4, jitter=0.1, seed=20051), prob, seed=5)
+
+
+def test_blocks_paper_switched_rule():
+    mesh, prob, _ = paper_workload(0.05, "approxcaps")
+    _check(mesh, prob, seed=6)
