@@ -78,9 +78,10 @@ __device__ __forceinline__ void fold_column(double *__restrict__ Rg, unsigned *c
 __device__ __forceinline__ void fold_row_block(double *__restrict__ Rg, unsigned *cn_l, int nC,
                                                const int32_t *__restrict__ cptr, int cbase,
                                                const uint16_t *__restrict__ colent, const double (*mxy_l)[12], int lo,
-                                               int lane, unsigned short *alist, int arow)
+                                               int lane, unsigned short *alist, int arow, int hi_max = 0x7fffffff)
 {
-    const int hi = lo + 64;
+    // pairs lo .. hi-1 (hi_max: the chunk's pairs beyond it take no part)
+    const int hi = lo + 64 < hi_max ? lo + 64 : hi_max;
     int nact = 0;
     auto put = [&](int i, int c) { alist[(i >> 2) * arow + (i & 3)] = (unsigned short)c; };
     // the cursors are read four columns at a time, so one LDS round trip serves four ballots
@@ -241,9 +242,16 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
     // deep partners (the deep test is symmetric), so E(k) takes their Myy
     // from Dk(k) = psi sum_w sum_deep |E_k'| (sum_w: the outer weights' sum)
     double dsum = 0.0;
-    for (int64_t base = p0; base < p1; base += 64) {
+    // With a symmetric inner rule a deep pair reduces to its inner element's
+    // area: Mxy_ab = psi AW_a m1c |E_k'| (AW_a = sum_q W_q alpha_a(x_q)) and S0 =
+    // wsum |E_k'| at every outer point, and both outer rules integrate these
+    // polynomials exactly; so the chunks take the band pairs only and the deep
+    // ones are summed after them.
+    const bool collapse = SYM && nband != nullptr;
+    const int64_t pend = collapse ? p0 + nb : p1;
+    for (int64_t base = p0; base < pend; base += 64) {
         const int64_t pi = base + lane;                                   // processing slot
-        const bool act = pi < p1;
+        const bool act = pi < pend;
         const int64_t p = (proc_p && act) ? (int64_t)proc_p[pi] : pi;    // the pair's canonical index
         const bool deep = act && pi - p0 >= nb;
         double V[6] = {0, 0, 0, 0, 0, 0};
@@ -419,8 +427,52 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             }
         }
         __syncthreads();
-        fold_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, mxy_l, (int)(base - p0), lane, queue, 4);
+        fold_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, mxy_l, (int)(base - p0), lane, queue, 4,
+                       (int)(pend - p0));
         __syncthreads();
+    }
+    if (collapse) {
+        // the deep pairs: their areas, and each item counted whole
+        for (int64_t pi = pend + lane; pi < p1; pi += 64) {
+            dsum += E.a2[proc_kp[pi]];
+            c_whole += (SW && nq2 > 0 && pair_r2[proc_p[pi]]) ? nq2 : nq;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; q++)
+            if (q < nq) m0[q] += dsum * M.wsum;
+        // row block: R_k[a][c] += -psi m1c AW_a S(c), S(c) the areas of the deep
+        // partners with node c, from each column's remaining entries (all deep)
+        double cf[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < nq; q++) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) cf[a] += sW[q][1 + a];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) cf[a] *= -psi * M.m1c;
+        const int32_t *cptr = colent_ptr + coff;
+        for (int c = lane; c < nC; c += 64) {
+            const unsigned w = cn_l[c];
+            if ((w >> 16) == 0xffffu) continue;
+            int cur = cbase + (int)(w & 0x7fffu);
+            const int end = cptr[c + 1];
+            double S = 0.0;
+            while (cur < end) {
+                // four entries per round trip (colent is padded by four)
+                int e[4];
+                double av[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) e[j] = colent[cur + j];
+#pragma unroll
+                for (int j = 0; j < 4; j++) av[j] = cur + j < end ? E.a2[proc_kp[p0 + (e[j] >> 2)]] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    if (cur + j < end) S += av[j];
+                cur += 4;
+            }
+            const bool vis = (w & 0x8000u) != 0;
+#pragma unroll
+            for (int a = 0; a < 3; a++) Rg[a * nC + c] = (vis ? Rg[a * nC + c] : 0.0) + cf[a] * S;
+        }
     }
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
     // lanes, then lane 0's sum is broadcast
