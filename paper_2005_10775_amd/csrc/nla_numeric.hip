@@ -177,7 +177,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                                                          const int32_t *__restrict__ proc_p,
                                                          const int32_t *__restrict__ proc_kp,
                                                          const int32_t *__restrict__ nband, double *__restrict__ Dk,
-                                                         unsigned long long *__restrict__ counters)
+                                                         int dtab_off, unsigned long long *__restrict__ counters)
 {
     extern __shared__ unsigned dyn[];
     __shared__ double sW[NQ][4];
@@ -432,11 +432,17 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         __syncthreads();
     }
     if (collapse) {
-        // the deep pairs: their areas, and each item counted whole
+        // the deep pairs: their areas (kept in an LDS table by deep slot when the
+        // launch gives room for one), and each item counted whole
+        double *tab = (double *)(dyn + dtab_off);
         for (int64_t pi = pend + lane; pi < p1; pi += 64) {
-            dsum += E.a2[proc_kp[pi]];
+            const double a2 = E.a2[proc_kp[pi]];
+            dsum += a2;
+            if (dtab_off) tab[pi - pend] = a2;
             c_whole += (SW && nq2 > 0 && pair_r2[proc_p[pi]]) ? nq2 : nq;
         }
+        __syncthreads();
+        const int nbr = (int)(pend - p0);
 #pragma unroll
         for (int q = 0; q < NQ; q++)
             if (q < nq) m0[q] += dsum * M.wsum;
@@ -450,28 +456,59 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
 #pragma unroll
         for (int a = 0; a < 3; a++) cf[a] *= -psi * M.m1c;
         const int32_t *cptr = colent_ptr + coff;
-        for (int c = lane; c < nC; c += 64) {
-            const unsigned w = cn_l[c];
-            if ((w >> 16) == 0xffffu) continue;
-            int cur = cbase + (int)(w & 0x7fffu);
-            const int end = cptr[c + 1];
-            double S = 0.0;
-            while (cur < end) {
-                // four entries per round trip (colent is padded by four)
-                int e[4];
+        auto area = [&](int e) -> double {
+            return dtab_off ? tab[(e >> 2) - nbr] : E.a2[proc_kp[p0 + (e >> 2)]];
+        };
+        // four columns per lane at a time: their ends, first four entries and
+        // sums so far are loaded together, so the walks share their round trips
+        for (int c0 = lane; c0 < nC; c0 += 256) {
+            unsigned w[4];
+            int cur[4], end[4], e[4][4];
+            double r[4][3], S[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) w[j] = c0 + 64 * j < nC ? cn_l[c0 + 64 * j] : 0xffff0000u;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int c = c0 + 64 * j;
+                const bool live = (w[j] >> 16) != 0xffffu;
+                cur[j] = cbase + (int)(w[j] & 0x7fffu);
+                end[j] = live ? cptr[c + 1] : cur[j];
+#pragma unroll
+                for (int i = 0; i < 4; i++) e[j][i] = live ? colent[cur[j] + i] : 0;   // padded by four
+#pragma unroll
+                for (int a = 0; a < 3; a++) r[j][a] = (live && (w[j] & 0x8000u)) ? Rg[a * nC + c] : 0.0;
+                S[j] = 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
                 double av[4];
 #pragma unroll
-                for (int j = 0; j < 4; j++) e[j] = colent[cur + j];
+                for (int i = 0; i < 4; i++) av[i] = cur[j] + i < end[j] ? area(e[j][i]) : 0.0;
 #pragma unroll
-                for (int j = 0; j < 4; j++) av[j] = cur + j < end ? E.a2[proc_kp[p0 + (e[j] >> 2)]] : 0.0;
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-                    if (cur + j < end) S += av[j];
-                cur += 4;
+                for (int i = 0; i < 4; i++)
+                    if (cur[j] + i < end[j]) S[j] += av[i];
+                cur[j] += 4;
             }
-            const bool vis = (w & 0x8000u) != 0;
 #pragma unroll
-            for (int a = 0; a < 3; a++) Rg[a * nC + c] = (vis ? Rg[a * nC + c] : 0.0) + cf[a] * S;
+            for (int j = 0; j < 4; j++) {
+                // columns with more than four deep entries
+                while (cur[j] < end[j]) {
+                    int ee[4];
+                    double av[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) ee[i] = colent[cur[j] + i];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) av[i] = cur[j] + i < end[j] ? area(ee[i]) : 0.0;
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        if (cur[j] + i < end[j]) S[j] += av[i];
+                    cur[j] += 4;
+                }
+                if ((w[j] >> 16) != 0xffffu) {
+#pragma unroll
+                    for (int a = 0; a < 3; a++) Rg[a * nC + c0 + 64 * j] = r[j][a] + cf[a] * S[j];
+                }
+            }
         }
     }
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
@@ -852,6 +889,21 @@ static size_t lds_for_occupancy(const void *fn, size_t need, int wg_per_cu)
     return hi;
 }
 
+// Whether `with` bytes of dynamic LDS give fn as many workgroups per CU (at
+// most cap, when cap > 0) as `plain` bytes do.
+static bool table_fits(const void *fn, size_t plain, size_t with, int cap)
+{
+    int a = 0, b = 0;
+    if (with > 64 * 1024 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, fn, 64, plain) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, 64, with) != hipSuccess)
+        return false;
+    if (cap > 0) {
+        a = a < cap ? a : cap;
+        b = b < cap ? b : cap;
+    }
+    return b >= a;
+}
+
 static void nla_mark(nla_plan *P, int i, hipStream_t s)
 {
     if (P->cur_ev) (void)hipEventRecord(P->cur_ev[i], s);
@@ -892,12 +944,23 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         const size_t lds = (size_t)P->max_cols * sizeof(unsigned);
         const bool cuts = pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT;
         const int ncap = cuts ? pr.cap_edges : 0;
+        // the deep pairs' area table follows the cursors in LDS where it costs no occupancy
+        const size_t tab_at = (lds + 7) / 8 * 8;
+        const size_t lds_tab = tab_at + sizeof(double) * (size_t)P->max_deep;
 #define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND, SW)                                                                   \
-    k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64,                                                             \
-        lds_for_occupancy((const void *)k_pairs_const_fp64<NQ, SYM, POW2, BND, SW>, lds, NLA_PAIRS_WG_PER_CU), s>>>(\
-        P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,           \
-        pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr,                                         \
-        P->colent, V, Cyy, Cxx, P->proc_p, P->proc_kp, P->nband, Dk, P->counters)
+    do {                                                                                                           \
+        if (P->pairs_tab < 0) {                                                                                    \
+            const void *fn = (const void *)k_pairs_const_fp64<NQ, SYM, POW2, BND, SW>;                             \
+            const bool tab =                                                                                       \
+                SYM && P->nband && P->max_deep > 0 && table_fits(fn, lds, lds_tab, NLA_PAIRS_WG_PER_CU);            \
+            P->pairs_lds = lds_for_occupancy(fn, tab ? lds_tab : lds, NLA_PAIRS_WG_PER_CU);                         \
+            P->pairs_tab = tab ? (int)(tab_at / sizeof(unsigned)) : 0;                                             \
+        }                                                                                                          \
+        k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, P->pairs_lds, s>>>(                                    \
+            P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,       \
+            pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,            \
+            P->proc_p, P->proc_kp, P->nband, Dk, P->pairs_tab, P->counters);                                       \
+    } while (0)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
         const bool bnd = P->rules.in_q2exact != 0 && pr.ball == NLA_BALL_RETRI;
@@ -909,15 +972,19 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
             return NLA_E_UNSUPPORTED;
         }
         if (pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT) {
+            if (P->pairs_tab < 0) {
+                P->pairs_lds = lds_for_occupancy(pow2 ? (const void *)k_pairs_support_fp64<true>
+                                                      : (const void *)k_pairs_support_fp64<false>,
+                                                 lds, NLA_SUPPORT_WG_PER_CU);
+                P->pairs_tab = 0;
+            }
             if (pow2)
-                k_pairs_support_fp64<true><<<K, 64, lds_for_occupancy((const void *)k_pairs_support_fp64<true>, lds,
-                                                                       NLA_SUPPORT_WG_PER_CU), s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
+                k_pairs_support_fp64<true><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
                                                                P->counters);
             else
-                k_pairs_support_fp64<false><<<K, 64, lds_for_occupancy((const void *)k_pairs_support_fp64<false>, lds,
-                                                                        NLA_SUPPORT_WG_PER_CU), s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
+                k_pairs_support_fp64<false><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                 pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                 P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
                                                                 P->counters);

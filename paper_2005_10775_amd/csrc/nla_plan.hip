@@ -1085,7 +1085,12 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         k_proc_kp<<<grid_for(NP, 256), 256, 0, s>>>(NP, P->proc_p, P->pair_kp, P->proc_kp);
         k_nband<<<grid_for(K, 256), 256, 0, s>>>(K, P->pair_ptr, skey, P->nband);
         NLA_HIP(hipGetLastError());
+        std::vector<int32_t> nb((size_t)K);
+        std::vector<int64_t> pp((size_t)K + 1);
+        NLA_HIP(hipMemcpyAsync(nb.data(), P->nband, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipMemcpyAsync(pp.data(), P->pair_ptr, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, s));
         NLA_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < K; k++) P->max_deep = std::max(P->max_deep, (int32_t)(pp[k + 1] - pp[k] - nb[k]));
     }
     NLA_HIP(hipGetLastError());
     NLA_HIP(hipStreamSynchronize(s));
