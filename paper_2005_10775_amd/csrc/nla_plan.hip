@@ -1058,11 +1058,12 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
                                                               P->rules.switch_dist, P->pair_r2);
     }
     // processing order of the FP64 constant-kernel pair kernel: band pairs first,
-    // then the deep ones (a stable sort of the keys 2 k + deep); the barycenter
-    // ball, whose items cost one distance test and are never partial, keeps the
-    // canonical order
+    // then the deep ones (a stable sort of the keys 2 k + deep); under the
+    // intersection, overlap and barycenter balls every item of a deep pair is
+    // whole (for the barycenter ball: |x_q - b_k'| <= r_k + |b_k - b_k'| <= delta)
     const bool ordered = pr.precision == NLA_FP64 && pr.kernel == NLA_KERNEL_CONSTANT &&
-                         (pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_OVERLAP) &&
+                         (pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_OVERLAP ||
+                          pr.ball == NLA_BALL_BARYCENTER) &&
                          P->n_pairs > 0 && 2 * (int64_t)K < (int64_t)UINT32_MAX;
     if (ordered) {
         const int64_t NP = P->n_pairs;
