@@ -214,15 +214,30 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
 inline int64_t xcd_grid(int64_t nb) { return (nb + 7) / 8 * 8; }
 
 // A deep pair: every point of E_k within delta of every point of E_k' with
-// room to spare.  Outer points lie within r_k of b_k and vertices within r_k'
-// of b_k', so |b_k - b_k'| + (r_k + r_k') <= delta (1 - 1e-9) makes every item
-// whole under each ball (the relative margin covers the rounding of these sums
-// and of the outer points).  The test gives the same bits for (k, k') and
-// (k', k), so each element's deep partners are the deep pairs it owns.
+// room to spare.  The largest distance between two triangles is attained at a
+// pair of vertices, so max |v - w| over the nine vertex pairs <= delta (1 - 1e-9)
+// makes every item whole under the intersection, overlap and barycenter balls
+// (outer points lie in E_k, b_k' in E_k'; the relative margin covers the
+// rounding of these distances and of the outer points).  The squared distances
+// are formed without contraction, and their maximum is the same set's for
+// (k, k') and (k', k), so the test gives the same bits both ways: each
+// element's deep partners are the deep pairs it owns.
 __device__ __forceinline__ bool pair_deep(const ElemSoA &E, int k, int kp, double delta)
 {
-    const double dx = E.bx[k] - E.bx[kp], dy = E.by[k] - E.by[kp];
-    return sqrt(dx * dx + dy * dy) + (E.r[k] + E.r[kp]) <= delta * (1.0 - 1e-9);
+#pragma clang fp contract(off)
+    const double vx[3] = {E.vx0[k], E.vx1[k], E.vx2[k]}, vy[3] = {E.vy0[k], E.vy1[k], E.vy2[k]};
+    const double wx[3] = {E.vx0[kp], E.vx1[kp], E.vx2[kp]}, wy[3] = {E.vy0[kp], E.vy1[kp], E.vy2[kp]};
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const double dx = vx[i] - wx[j], dy = vy[i] - wy[j];
+            const double d2 = dx * dx + dy * dy;
+            m = d2 > m ? d2 : m;
+        }
+    const double lim = delta * (1.0 - 1e-9);
+    return m <= lim * lim;
 }
 
 // learned cap corrector (nla_mlp.hip)

@@ -686,8 +686,8 @@ __global__ void k_colset(int64_t nu, const uint64_t *__restrict__ U, int32_t *__
 }
 
 // slot key (global column slot) and value (p_local << 2 | b) of every (pair, b)
-// A pair is deep when every outer point of E_k is within delta of every vertex
-// of E_k' with room to spare (pair_deep).  Key 2 k + deep orders each
+// A pair is deep when every point of E_k is within delta of every point of
+// E_k' with room to spare (pair_deep).  Key 2 k + deep orders each
 // element's pairs band first, deep after.
 __global__ void k_deep_keys(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, ElemSoA E,
                             double delta, uint32_t *__restrict__ key, int32_t *__restrict__ val)

@@ -25,12 +25,17 @@ def _setup():
 
 
 def _deep_mask(mesh, pk, kp, delta):
-    """The deep test, evaluated on the host to choose samples."""
+    """The deep test (largest vertex-to-vertex distance within delta (1 - 1e-9)),
+    evaluated on the host to choose samples."""
     V = mesh.xy[mesh.tri]
-    b = ((V[:, 0] + V[:, 1]) + V[:, 2]) / 3.0
-    r = np.max(np.hypot(V[:, :, 0] - b[:, None, 0], V[:, :, 1] - b[:, None, 1]), axis=1)
-    d = np.hypot(b[pk, 0] - b[kp, 0], b[pk, 1] - b[kp, 1])
-    return d + (r[pk] + r[kp]) <= delta * (1.0 - 1e-9)
+    d2 = np.zeros(len(pk))
+    for i in range(3):
+        for j in range(3):
+            dx = V[pk, i, 0] - V[kp, j, 0]
+            dy = V[pk, i, 1] - V[kp, j, 1]
+            d2 = np.maximum(d2, dx * dx + dy * dy)
+    lim = delta * (1.0 - 1e-9)
+    return d2 <= lim * lim
 
 
 def _check(mesh, prob, seed):
