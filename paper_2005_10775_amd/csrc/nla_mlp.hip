@@ -90,7 +90,7 @@ struct TrainBuf {
     float *dz1;      // [Bp][128]
     float *dz2f;     // [Bp][128]
     __bf16 *dz2t;    // [128][Bp]
-    float *part;     // [Bp/64][1412] chunk sums of the reduction
+    float *part;     // [Bp/16][1412] chunk sums of the reduction
 };
 
 __global__ void k_mlp_refresh(const float *__restrict__ w, __bf16 *__restrict__ w2, __bf16 *__restrict__ w2t,
@@ -327,8 +327,9 @@ __global__ __launch_bounds__(256) void k_mlp_dw2(TrainBuf T, float *__restrict__
 // the remaining gradients (dW1, b1, b2, dW3, b3) and the batch loss: each
 // block sums a chunk of RCH batch positions for all 1412 values (threads over
 // values, so reads of a position's row are coalesced), then the chunks are
-// added in chunk order
-constexpr int RCH = 64, NRED = 1412;
+// added in chunk order.  Short chunks give a 4096-sample batch 256 blocks, so
+// the sums' load latency is spread over the whole chip.
+constexpr int RCH = 16, NRED = 1412;
 
 __device__ __forceinline__ float red_term(const TrainBuf &T, int r, int64_t p)
 {
@@ -345,6 +346,7 @@ __global__ __launch_bounds__(256) void k_mlp_reduce_part(TrainBuf T, float *__re
     const int64_t p0 = (int64_t)blockIdx.x * RCH;
     for (int r = threadIdx.x; r < NRED; r += blockDim.x) {
         float s = 0.f;
+#pragma unroll
         for (int i = 0; i < RCH; i++) s += red_term(T, r, p0 + i);
         part[(int64_t)blockIdx.x * NRED + r] = s;
     }
@@ -510,7 +512,7 @@ static int mlp_scratch(nla_mlp *M, int64_t Bp, int64_t nloss)
     NLA_TRY(A.get(&T.dz1, H * Bp));
     NLA_TRY(A.get(&T.dz2f, H * Bp));
     NLA_TRY(A.get(&T.dz2t, H * Bp));
-    NLA_TRY(A.get(&T.part, (Bp / 64) * 1412));
+    NLA_TRY(A.get(&T.part, (Bp / RCH) * NRED));
     M->loss_cap = nloss > 1 ? nloss : 1;
     NLA_TRY(A.get(&M->lossb, M->loss_cap));
     return NLA_OK;
