@@ -357,8 +357,16 @@ __global__ void k_mlp_reduce_final(int nchunk, const float *__restrict__ part, f
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= NRED) return;
-    float s = 0.f;
-    for (int c = 0; c < nchunk; c++) s += part[(int64_t)c * NRED + r];
+    // four running sums over chunks c = 0, 1, 2, 3 mod 4 keep four loads in
+    // flight; they are combined in a fixed order
+    float s4[4] = {0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    for (; c + 4 <= nchunk; c += 4) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) s4[j] += part[(int64_t)(c + j) * NRED + r];
+    }
+    for (; c < nchunk; c++) s4[0] += part[(int64_t)c * NRED + r];
+    const float s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     if (r < 768) g[OW1 + r] = s;
     else if (r < 896) g[OB1 + (r - 768)] = s;
     else if (r < 1024) g[OB2 + (r - 896)] = s;
