@@ -200,13 +200,21 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
     for (int q = 0; q < NQ; q++) m0[q].zero();
     unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0, c_learn = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
+    // with the plan's processing order the chunks take the band pairs only: a
+    // deep pair's items are all whole, so its blocks follow from |E_k'| (see
+    // the FP64 pair kernel) and it is summed after the chunks
+    const bool collapse = !FRAC && P.nband != nullptr;
+    const int64_t pend = collapse ? p0 + P.nband[k] : p1;
+    double dsum = 0.0;
     int64_t rrun = LEARN ? P.route_off[k] : 0;   // routed items of k before this chunk
-    for (int64_t base = p0; base < p1; base += 64) {
-        const int64_t p = base + lane;
-        const bool act = p < p1 && !(near_flag && near_flag[p]);
+    for (int64_t base = p0; base < pend; base += 64) {
+        const int64_t pi = base + lane;                                   // processing slot
+        const bool inb = pi < pend;
+        const int64_t p = (P.proc_p && inb) ? (int64_t)P.proc_p[pi] : pi; // the pair's canonical index
+        const bool act = inb && !(near_flag && near_flag[p]);
         double V[6] = {0, 0, 0, 0, 0, 0};
         double bxp = 0.0, byp = 0.0, a2p = 0.0;
-        const int kp = act ? pair_kp[p] : 0;
+        const int kp = act ? (P.proc_kp ? P.proc_kp[pi] : pair_kp[p]) : 0;
         if (act) {
             V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
             bxp = E.bx[kp];
@@ -409,7 +417,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
             }
             __syncthreads();
         }
-        if (p < p1) {
+        if (inb) {
 #pragma unroll
             for (int i = 0; i < 9; i++) mxy_l[lane][i] = -axy[i].s;
 #pragma unroll
@@ -417,7 +425,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         }
         __syncthreads();
         {
-            const int lo = (int)(base - p0), hi = lo + 64;
+            const int lo = (int)(base - p0), hi = lo + 64 < (int)(pend - p0) ? lo + 64 : (int)(pend - p0);
             for (int c = lane; c < nC; c += 64) {
                 // a column's entries fall in one or two chunks: skip it on one LDS read otherwise
                 const unsigned w = cn_l[c];
@@ -462,6 +470,51 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 }
                 cn_l[c] = ((unsigned)pl << 16) | (unsigned)(cur - cbase);
             }
+        }
+        __syncthreads();
+    }
+    if (collapse) {
+        // the deep pairs: S0 = wsum |E_k'| at every outer point; -Mxy_ab = -kc m1c
+        // AW_a |E_k'| added to each column for the deep partners with its node
+        // (its remaining entries); Myy as one factor per element
+        for (int64_t pi = pend + lane; pi < p1; pi += 64) {
+            dsum += E.a2[P.proc_kp[pi]];
+            c_whole += nq;
+        }
+        const float md = (float)(dsum * R->in_wsum) * kc;
+#pragma unroll
+        for (int q = 0; q < NQ; q++)
+            if (q < nq) m0[q].add(md);
+        float cf[3] = {0.f, 0.f, 0.f};
+        for (int q = 0; q < nq; q++) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) cf[a] += sW[q][1 + a];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) cf[a] *= -kc * m1c;
+        for (int c = lane; c < nC; c += 64) {
+            const unsigned w = cn_l[c];
+            if ((w >> 16) == 0xffffu) continue;
+            const int end = colent_ptr[coff + c + 1];
+            double S = 0.0;
+            for (int cur = cbase + (int)(w & 0xffffu); cur < end; cur++)
+                S += E.a2[P.proc_kp[p0 + (colent[cur] >> 2)]];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                KahanF r;
+                r.s = R_s[a * nC + c];
+                r.c = R_c[a * nC + c];
+                r.add((float)((double)cf[a] * S));
+                R_s[a * nC + c] = r.s;
+                R_c[a * nC + c] = r.c;
+            }
+        }
+        double x = dsum;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) {
+            double wsum = 0.0;
+            for (int q = 0; q < nq; q++) wsum += R->out_w[q];
+            P.Dk[k] = (float)((double)kc * wsum * x);
         }
         __syncthreads();
     }
@@ -825,7 +878,9 @@ __global__ __launch_bounds__(64, 3) void k_near(int64_t n_comp, const int64_t *_
 // E(k') = Mxx(k') + sum_k Myy(k, k') in FP32 with compensation (lane-strided
 // partial sums, then lane 0 adds the 64 partials in lane order)
 __device__ void elem_blocks_body(const int k, const int64_t *__restrict__ tptr, const int32_t *__restrict__ tperm,
-                                 const float *__restrict__ Cyy, const float *__restrict__ Cxx, float *__restrict__ Ce)
+                                 const float *__restrict__ Cyy, const float *__restrict__ Cxx, float *__restrict__ Ce,
+                                 const float *__restrict__ Dk, const double *__restrict__ a2,
+                                 const RuleSet *__restrict__ R)
 {
     __shared__ float part[64][6];
     const int lane = threadIdx.x;
@@ -861,6 +916,11 @@ __device__ void elem_blocks_body(const int k, const int64_t *__restrict__ tptr, 
         KahanF s;
         s.zero();
         s.add(Cxx[6 * (int64_t)k + lane]);
+        if (Dk) {
+            // the deep pairs' Myy (with the processing order the transposed list holds band pairs only)
+            const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+            s.add(Dk[k] * (float)a2[k] * (float)R->in_m2[jj[lane]][ll[lane]]);
+        }
         for (int l = 0; l < 64; l++) s.add(part[l][lane]);
         Ce[6 * (int64_t)k + lane] = s.s;
     }
@@ -869,11 +929,13 @@ __device__ void elem_blocks_body(const int k, const int64_t *__restrict__ tptr, 
 
 __global__ __launch_bounds__(64) void k_elem_blocks_f32(int K, const int64_t *__restrict__ tptr,
                                                         const int32_t *__restrict__ tperm, const float *__restrict__ Cyy,
-                                                        const float *__restrict__ Cxx, float *__restrict__ Ce)
+                                                        const float *__restrict__ Cxx, float *__restrict__ Ce,
+                                                        const float *__restrict__ Dk, const double *__restrict__ a2,
+                                                        const RuleSet *__restrict__ R)
 {
     const int64_t kb = xcd_block(blockIdx.x, gridDim.x);
     if (kb >= K) return;
-    elem_blocks_body((int)kb, tptr, tperm, Cyy, Cxx, Ce);
+    elem_blocks_body((int)kb, tptr, tperm, Cyy, Cxx, Ce, Dk, a2, R);
 }
 
 // compensated FP32 sum of every upper entry: its [R | E] codes, then its
@@ -948,6 +1010,10 @@ PairArgs nla_pair_args(const nla_plan *P)
     A.Rout = V;
     A.Cyy = Cyy;
     A.Cxx = Cxx;
+    A.proc_p = P->proc_p;
+    A.proc_kp = P->proc_kp;
+    A.nband = P->nband;
+    A.Dk = P->nband ? V + 3 * P->n_cols + 6 * (int64_t)P->K : nullptr;
     A.max_cols = P->max_cols;
     A.counters = P->counters;
     A.bnd = (!A.frac && pr.ball == NLA_BALL_RETRI && P->rules.in_q2exact) ? 1 : 0;
@@ -1035,7 +1101,8 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
         P->ran[NLA_PHASE_NEAR] = true;
     }
     mark(P, NLA_PHASE_SEGSUM, s);
-    k_elem_blocks_f32<<<(unsigned)xcd_grid(K), 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce);
+    k_elem_blocks_f32<<<(unsigned)xcd_grid(K), 64, 0, s>>>(K, P->tptr, P->tperm, Cyy, Cxx, Ce, A.Dk, P->E.a2,
+                                                           P->d_rules);
     if (P->n_up > 0)
         k_segsum_f32<<<(unsigned)xcd_grid(grid_for(P->n_up, 256)), 256, 0, s>>>(P->n_up, P->up_ptr, P->codes,
                                                            P->n_near > 0 ? P->nup_ptr : nullptr, P->ncodes, P->up_dst,
@@ -1068,6 +1135,7 @@ struct BatchInst {
     const int32_t *tperm;
     const float *Cyy, *Cxx;
     float *Ce;
+    const float *Dk;            // deep pairs' Myy factors (processing order), or null
     // segmented sum
     int64_t n_up;
     const int64_t *up_ptr, *nup_ptr, *up_dst, *mirror;
@@ -1119,7 +1187,7 @@ __global__ __launch_bounds__(64) void k_batch_elem(int n, const BatchInst *__res
     const int64_t g = blockIdx.x;
     const int t = inst_of(off, n, g);
     const BatchInst &I = B[t];
-    elem_blocks_body((int)(g - off[t]), I.tptr, I.tperm, I.Cyy, I.Cxx, I.Ce);
+    elem_blocks_body((int)(g - off[t]), I.tptr, I.tperm, I.Cyy, I.Cxx, I.Ce, I.Dk, I.E.a2, I.R);
 }
 
 __global__ void k_batch_segsum(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off, int64_t total)
@@ -1280,7 +1348,7 @@ static int batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *pr
             return NLA_E_UNSUPPORTED;
         }
         // per-plan value storage (FP32)
-        P->n_contrib = 6 * P->n_pairs + 12 * (int64_t)P->K + 3 * P->n_cols;
+        P->n_contrib = 6 * P->n_pairs + 13 * (int64_t)P->K + 3 * P->n_cols;   // ... | Ce (6K) | Dk (K)
         NLA_TRY(P->arena.alloc(&P->contrib, sizeof(float) * P->n_contrib));
         NLA_TRY(P->arena.alloc(&P->val, sizeof(float) * P->nnz));
         NLA_TRY(P->arena.alloc(&P->a_val, sizeof(float) * (P->nnz_free > 0 ? P->nnz_free : 1)));
@@ -1304,7 +1372,7 @@ static int batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *pr
         I.E = P->E; I.R = P->d_rules; I.delta = P->prob.delta; I.kc = P->prob.kernel_c; I.ks = P->prob.kernel_s;
         I.near_blk = (float *)P->near_blk;
         I.K = P->K; I.tptr = P->tptr; I.tperm = P->tperm;
-        I.Cyy = args[i].Cyy; I.Cxx = args[i].Cxx; I.Ce = args[i].Rout + 3 * P->n_cols;
+        I.Cyy = args[i].Cyy; I.Cxx = args[i].Cxx; I.Ce = args[i].Rout + 3 * P->n_cols; I.Dk = args[i].Dk;
         I.n_up = P->n_up; I.up_ptr = P->up_ptr; I.nup_ptr = P->nup_ptr; I.up_dst = P->up_dst; I.mirror = P->mirror;
         I.codes = P->codes; I.ncodes = P->ncodes; I.V = args[i].Rout; I.val = (float *)P->val;
         I.nnz_free = P->nnz_free; I.a_src = P->a_src; I.a_val = (float *)P->a_val;

@@ -200,6 +200,9 @@ struct PairArgs {
     int64_t n_routed;
     const float *mlp_y;         // [n_routed][3] network outputs
     float mlp_k;                // kc delta^2 scale
+    // processing order (constant kernel): band pairs first, deep ones after
+    const int32_t *proc_p, *proc_kp, *nband;
+    float *Dk;                  // [K] the deep pairs' Myy factor of each element
 };
 PairArgs nla_pair_args(const nla_plan *P);
 

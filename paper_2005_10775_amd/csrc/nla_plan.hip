@@ -1057,11 +1057,11 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         k_pair_rule2<<<grid_for(P->n_pairs, 256), 256, 0, s>>>(P->n_pairs, P->pair_k, P->pair_kp, P->E,
                                                               P->rules.switch_dist, P->pair_r2);
     }
-    // processing order of the FP64 constant-kernel pair kernel: band pairs first,
+    // processing order of the constant-kernel pair kernels: band pairs first,
     // then the deep ones (a stable sort of the keys 2 k + deep); under the
     // intersection, overlap and barycenter balls every item of a deep pair is
     // whole (for the barycenter ball: |x_q - b_k'| <= r_k + |b_k - b_k'| <= delta)
-    const bool ordered = pr.precision == NLA_FP64 && pr.kernel == NLA_KERNEL_CONSTANT &&
+    const bool ordered = pr.kernel == NLA_KERNEL_CONSTANT &&
                          (pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_OVERLAP ||
                           pr.ball == NLA_BALL_BARYCENTER) &&
                          P->n_pairs > 0 && 2 * (int64_t)K < (int64_t)UINT32_MAX;
@@ -1586,9 +1586,10 @@ extern "C" int nla_free_nodes_view(const nla_plan *P, const int32_t **free_nodes
 // Myy of the deep pairs, which the FP64 assembly folds into one sum per inner
 // element instead of storing: every item whole, so Myy = psi W(k) |E_k'| m2
 // with W(k) the sum of the pair's outer weights over E_k.
+template <class T>
 __global__ void k_deep_myy(int64_t P, const int32_t *__restrict__ pk, const int32_t *__restrict__ pkp, ElemSoA E,
                            double delta, double psi, const RuleSet *__restrict__ R, const uint8_t *__restrict__ r2,
-                           double *__restrict__ myy)
+                           T *__restrict__ myy)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
@@ -1601,7 +1602,7 @@ __global__ void k_deep_myy(int64_t P, const int32_t *__restrict__ pk, const int3
     else
         for (int q = 0; q < R->n_out; q++) ws += R->out_w[q] * E.a2[k];
     const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
-    for (int t = 0; t < 6; t++) myy[6 * p + t] = psi * (ws * E.a2[kp] * R->in_m2[jj[t]][ll[t]]);
+    for (int t = 0; t < 6; t++) myy[6 * p + t] = (T)(psi * (ws * E.a2[kp] * R->in_m2[jj[t]][ll[t]]));
 }
 
 extern "C" int nla_blocks_view(const nla_plan *P, const void **myy, const void **mxx, const void **elem,
@@ -1612,12 +1613,17 @@ extern "C" int nla_blocks_view(const nla_plan *P, const void **myy, const void *
         return NLA_E_INVALID;
     }
     if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
-    if (P->nband && P->val_dtype == NLA_DTYPE_F64 && P->n_pairs > 0) {
+    if (P->nband && P->n_pairs > 0) {
         // the deep pairs' records, formed here on request (after the assembly has finished)
         NLA_HIP(hipDeviceSynchronize());
-        k_deep_myy<<<grid_for(P->n_pairs, 256), 256, 0, 0>>>(P->n_pairs, P->pair_k, P->pair_kp, P->E, P->prob.delta,
-                                                            P->prob.kernel_c, P->d_rules, P->pair_r2,
-                                                            (double *)P->contrib);
+        if (P->val_dtype == NLA_DTYPE_F64)
+            k_deep_myy<double><<<grid_for(P->n_pairs, 256), 256, 0, 0>>>(
+                P->n_pairs, P->pair_k, P->pair_kp, P->E, P->prob.delta, P->prob.kernel_c, P->d_rules, P->pair_r2,
+                (double *)P->contrib);
+        else
+            k_deep_myy<float><<<grid_for(P->n_pairs, 256), 256, 0, 0>>>(
+                P->n_pairs, P->pair_k, P->pair_kp, P->E, P->prob.delta, P->prob.kernel_c, P->d_rules, P->pair_r2,
+                (float *)P->contrib);
         NLA_HIP(hipGetLastError());
         NLA_HIP(hipDeviceSynchronize());
     }
