@@ -571,14 +571,18 @@ __global__ __launch_bounds__(64) void k_route(PairArgs P, int64_t *__restrict__ 
     }
     __syncthreads();
     const int64_t p0 = P.pair_ptr[k], p1 = P.pair_ptr[k + 1];
+    // with the processing order only the band pairs can have partial items:
+    // they are taken in the pair kernel's order (canonical among themselves)
+    const int64_t pend = P.nband ? p0 + P.nband[k] : p1;
     int64_t run = FILL ? P.route_off[k] : 0;
-    for (int64_t base = p0; base < p1; base += 64) {
-        const int64_t p = base + lane;
-        const bool act = p < p1 && !(P.near_flag && P.near_flag[p]);
+    for (int64_t base = p0; base < pend; base += 64) {
+        const int64_t pi = base + lane;
+        const int64_t p = (P.proc_p && pi < pend) ? (int64_t)P.proc_p[pi] : pi;
+        const bool act = pi < pend && !(P.near_flag && P.near_flag[p]);
         double V[6] = {0, 0, 0, 0, 0, 0};
         unsigned rmask = 0;
         if (act) {
-            const int kp = P.pair_kp[p];
+            const int kp = P.proc_kp ? P.proc_kp[pi] : P.pair_kp[p];
             V[0] = P.E.vx0[kp]; V[1] = P.E.vy0[kp]; V[2] = P.E.vx1[kp];
             V[3] = P.E.vy1[kp]; V[4] = P.E.vx2[kp]; V[5] = P.E.vy2[kp];
 #pragma unroll
