@@ -5,8 +5,9 @@ Myy record and reach the element blocks as one sum per element:
   * Myy of sampled pairs, deep and band, against the oracle's pair blocks;
   * E(k) = Mxx(k) + sum over the pairs (k', k) of Myy(k', k), from the GPU's
     own records;
-  * on the headline problem at h = delta/4 and on the paper's approxcaps
-    workload at h = 0.05 (switched outer rule)."""
+  * on the headline problem at h = delta/4 (FP64, and FP32 at the FP32 bar),
+    on the barycenter ball, and on the paper's approxcaps workload at
+    h = 0.05 (switched outer rule)."""
 import numpy as np
 import pytest
 import torch
@@ -38,10 +39,10 @@ def _deep_mask(mesh, pk, kp, delta):
     return d2 <= lim * lim
 
 
-def _check(mesh, prob, seed):
+def _check(mesh, prob, seed, tol=1e-12):
     plan = gpu_assemble(mesh, prob, with_load=False)
     blk = plan.blocks()
-    myy, mxx, elem = host(blk["myy"]), host(blk["mxx"]), host(blk["elem"])
+    myy, mxx, elem = (host(blk[n]).astype(np.float64) for n in ("myy", "mxx", "elem"))
     ptr, kp = (host(t) for t in plan.pairs())
     K = mesh.n_triangles
     pk = np.repeat(np.arange(K), np.diff(ptr))
@@ -54,7 +55,7 @@ def _check(mesh, prob, seed):
     scale = np.maximum(np.max(np.abs(ref), axis=1), 1e-300)
     err = float(np.max(np.max(np.abs(elem - ref), axis=1) / scale))
     print("element blocks vs Mxx + sum Myy: %.3e" % err, flush=True)
-    assert err < 1e-12
+    assert err < tol
     # sampled Myy against the oracle
     op = oracle.OracleProblem(mesh, prob)
     rng = np.random.default_rng(seed)
@@ -70,7 +71,7 @@ def _check(mesh, prob, seed):
         typ = float(np.median(np.max(np.abs(myy[ptr[k]:ptr[k + 1]]), axis=1)))
         e = float(np.max(np.abs(myy[p] - m)) / max(np.max(np.abs(m)), typ))
         worst = max(worst, e)
-        assert e < 1e-12, ("pair", int(pk[p]), int(kp[p]), bool(deep[p]), e)
+        assert e < tol, ("pair", int(pk[p]), int(kp[p]), bool(deep[p]), e)
     print("sampled Myy: worst %.3e" % worst, flush=True)
 
 
@@ -84,3 +85,17 @@ def test_blocks_headline_problem():
 def test_blocks_paper_switched_rule():
     mesh, prob, _ = paper_workload(0.05, "approxcaps")
     _check(mesh, prob, seed=6)
+
+
+def test_blocks_headline_problem_fp32():
+    d = 0.1
+    prob = Problem(delta=d, kernel="constant", kernel_c=constant_kernel_c(d), ball="retri", cap_edges=8,
+                   outer="dunavant7", inner="dunavant16", precision="fp32")
+    _check(structured_mesh(d, d / 4, jitter=0.1, seed=20051), prob, seed=7, tol=2e-5)
+
+
+def test_blocks_barycenter_ball():
+    d = 0.1
+    prob = Problem(delta=d, kernel="constant", kernel_c=constant_kernel_c(d), ball="barycenter",
+                   outer="dunavant7", inner="dunavant7")
+    _check(structured_mesh(d, d / 4, jitter=0.1, seed=20052), prob, seed=8)
