@@ -492,21 +492,56 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) cf[a] *= -kc * m1c;
-        for (int c = lane; c < nC; c += 64) {
-            const unsigned w = cn_l[c];
-            if ((w >> 16) == 0xffffu) continue;
-            const int end = colent_ptr[coff + c + 1];
-            double S = 0.0;
-            for (int cur = cbase + (int)(w & 0xffffu); cur < end; cur++)
-                S += E.a2[P.proc_kp[p0 + (colent[cur] >> 2)]];
+        // four columns per lane at a time, four entries per round trip (colent is
+        // padded by four), so the walks share their memory round trips
+        for (int c0 = lane; c0 < nC; c0 += 256) {
+            unsigned w[4];
+            int cur[4], end[4];
+            double S[4];
 #pragma unroll
-            for (int a = 0; a < 3; a++) {
-                KahanF r;
-                r.s = R_s[a * nC + c];
-                r.c = R_c[a * nC + c];
-                r.add((float)((double)cf[a] * S));
-                R_s[a * nC + c] = r.s;
-                R_c[a * nC + c] = r.c;
+            for (int j = 0; j < 4; j++) {
+                const int c = c0 + 64 * j;
+                w[j] = c < nC ? cn_l[c] : 0xffff0000u;
+                const bool live = (w[j] >> 16) != 0xffffu;
+                cur[j] = cbase + (int)(w[j] & 0xffffu);
+                end[j] = live ? colent_ptr[coff + c + 1] : cur[j];
+                S[j] = 0.0;
+            }
+            bool more = true;
+            while (more) {
+                int e[4][4];
+                int kq[4][4];
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) e[j][i] = cur[j] < end[j] ? colent[cur[j] + i] : 0;
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) kq[j][i] = cur[j] + i < end[j] ? P.proc_kp[p0 + (e[j][i] >> 2)] : -1;
+                more = false;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        if (kq[j][i] >= 0) S[j] += E.a2[kq[j][i]];
+                    cur[j] += 4;
+                    more = more || cur[j] < end[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if ((w[j] >> 16) == 0xffffu) continue;
+                const int c = c0 + 64 * j;
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    KahanF r;
+                    r.s = R_s[a * nC + c];
+                    r.c = R_c[a * nC + c];
+                    r.add((float)((double)cf[a] * S[j]));
+                    R_s[a * nC + c] = r.s;
+                    R_c[a * nC + c] = r.c;
+                }
             }
         }
         double x = dsum;
