@@ -130,8 +130,11 @@ struct PairLDS {
 // in the lane, phase 2 retriangulates the queued partial items densely; the
 // results are added per pair in q order (compensated), -Mxy is reduced into
 // the row block R_k in LDS per column in pair order (compensated), Myy per
-// pair and Mxx per element are written.  Pairs flagged near (vertex-sharing,
-// singular kernel) are skipped here.
+// pair and Mxx per element are written.  With the constant kernel and the
+// plan's processing order, the chunks take the band pairs only and the deep
+// ones (every item whole) are summed afterwards from their inner elements'
+// areas, their Myy going to the element blocks through Dk(k).  Pairs flagged
+// near (vertex-sharing, singular kernel) are skipped here.
 template <int NQ, int FM, bool POW2>
 __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, PairLDS<NQ> &S)
 {

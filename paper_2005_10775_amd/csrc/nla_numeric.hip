@@ -159,10 +159,14 @@ __device__ __forceinline__ unsigned *init_row_block(unsigned *dyn, double *__res
 // constants times |E_k'|.  Partial items are queued in LDS.  Phase 2: the
 // wave takes queued items 64 at a time (dense, regardless of owner),
 // retriangulates them, and each owner adds its items' sums in q order.
-// Outputs: per pair Myy (6); per element Mxx (6) from the fixed-order lane
-// reduction of sum_k' S0(x_q), and the row block R_k[a][c] = sum of -Mxy_ab
-// over the pairs whose inner slot b is node C_k[c], reduced in LDS column by
-// column in pair order (each column owned by one lane).
+// With the plan's processing order (nband), the chunks take the band pairs
+// only; deep pairs (every item whole) are summed afterwards from their inner
+// elements' areas (SYM), and their Myy reaches the element blocks through
+// Dk(k).  Outputs: Myy (6) per band pair; per element Mxx (6) from the
+// fixed-order lane reduction of sum_k' S0(x_q), Dk, and the row block
+// R_k[a][c] = sum of -Mxy_ab over the pairs whose inner slot b is node
+// C_k[c], reduced column by column in pair order (each column owned by one
+// lane per chunk, its running sums kept in this element's block of Rout).
 template <int NQ, bool SYM, bool POW2, bool BND, bool SW>
 __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
                                                          const int32_t *__restrict__ pair_kp, ElemSoA E,
