@@ -1106,6 +1106,12 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     const int ncap = pr.ball == NLA_BALL_RETRI ? pr.cap_edges : 0;
     const bool pow2 = (ncap & (ncap - 1)) == 0;
     const size_t lds = (size_t)P->max_cols * (6 * sizeof(float) + sizeof(unsigned));
+    if (lds > 48 * 1024) {
+        // the FP32 row block (compensated sums) lives in LDS beside the kernel's 11 KB
+        nla_set_error("FP32 path: %d columns per element exceed its LDS row block (at most 1755); use FP64",
+                      (int)P->max_cols);
+        return NLA_E_UNSUPPORTED;
+    }
     const bool learn = pr.precision == NLA_FP32_LEARNED;
     PairArgs A = nla_pair_args(P);
     mark(P, NLA_PHASE_MLP, s);
