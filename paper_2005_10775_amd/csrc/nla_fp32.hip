@@ -1122,6 +1122,25 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
         P->ran[NLA_PHASE_MLP] = true;
     }
     mark(P, NLA_PHASE_PAIRS, s);
+    // the singular pairs (their own blocks, read only by the segmented sum) run
+    // on a second stream beside the regular pairs: forked here, joined before
+    // the segmented sum
+    const bool fork = P->n_near_comp > 0;
+    if (fork) {
+        if (!P->aux) {
+            NLA_HIP(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
+            NLA_HIP(hipEventCreateWithFlags(&P->fork, hipEventDisableTiming));
+            NLA_HIP(hipEventCreateWithFlags(&P->join, hipEventDisableTiming));
+        }
+        NLA_HIP(hipEventRecord(P->fork, s));
+        NLA_HIP(hipStreamWaitEvent(P->aux, P->fork, 0));
+        k_near<float><<<(unsigned)P->n_near_comp, 64, 0, P->aux>>>(P->n_near_comp, P->near_comp, P->near_pair,
+                                                                   P->pair_k, P->pair_kp, P->tri, P->E, P->d_rules,
+                                                                   pr.delta, pr.kernel_c, pr.kernel_s,
+                                                                   (float *)P->near_blk);
+        NLA_HIP(hipGetLastError());
+        NLA_HIP(hipEventRecord(P->join, P->aux));
+    }
 #define NLA_LAUNCH32(NQ, FR, P2) k_pairs_fp32<NQ, FR, P2><<<K, 64, lds, s>>>(A)
     if (P->rules.n_out > 8) {
         nla_set_error("the FP32 path supports outer rules of at most 8 points");
@@ -1141,11 +1160,9 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     NLA_HIP(hipGetLastError());
     P->ran[NLA_PHASE_PAIRS] = true;
     mark(P, NLA_PHASE_NEAR, s);
-    if (P->n_near_comp > 0) {
-        k_near<float><<<(unsigned)P->n_near_comp, 64, 0, s>>>(P->n_near_comp, P->near_comp, P->near_pair, P->pair_k,
-                                                              P->pair_kp, P->tri, P->E, P->d_rules, pr.delta,
-                                                              pr.kernel_c, pr.kernel_s, (float *)P->near_blk);
-        NLA_HIP(hipGetLastError());
+    if (fork) {
+        // the phase timer's "near" interval is the wait for the second stream
+        NLA_HIP(hipStreamWaitEvent(s, P->join, 0));
         P->ran[NLA_PHASE_NEAR] = true;
     }
     mark(P, NLA_PHASE_SEGSUM, s);

@@ -167,10 +167,17 @@ struct nla_plan {
     std::vector<hipEvent_t> ev;
     hipEvent_t *cur_ev = nullptr;   // events of the assembly being timed, or null
     bool ran[8] = {};
+    // second stream (default priority) on which the FP32 singular pairs overlap
+    // the regular pairs, with its fork and join events; made at first use
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     ~nla_plan()
     {
         for (auto &e : ev)
             if (e) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (aux) (void)hipStreamDestroy(aux);
     }
     bool assembled = false;
     bool have_load = false;
