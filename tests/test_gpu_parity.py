@@ -88,6 +88,24 @@ def test_retri_several_tiles():
     _full_parity(mesh, _problem(0.1, "retri", 8), name="retri h=0.025")
 
 
+@pytest.mark.parametrize("ball,seed", [("retri", 3), ("retri", 4), ("overlap", 5), ("barycenter", 6)])
+def test_deep_band_split_jittered(ball, seed):
+    """Strongly jittered meshes (jitter 0.25) at h = delta/4: the plan's split
+    of each element's pairs into band and deep ones (every item whole; their
+    blocks summed from element areas) must give the oracle's matrix, whatever
+    the element shapes."""
+    mesh = structured_mesh(0.1, 0.025, jitter=0.25, seed=seed)
+    caps = 8 if ball == "retri" else 0
+    _full_parity(mesh, _problem(0.1, ball, caps), name="%s jitter 0.25 seed %d" % (ball, seed))
+
+
+def test_deep_pairs_dominant():
+    """h = delta/6: most pairs are deep, so most of the row block comes from the
+    deep-pair sums and the element blocks from the per-element deep factor."""
+    mesh = structured_mesh(0.1, 0.1 / 6, jitter=0.1, seed=12)
+    _full_parity(mesh, _problem(0.1, "retri", 8), name="retri h=delta/6")
+
+
 def test_lattice_ties_barycenter_vertex_rule():
     """Outer points on vertices and mid-sides of an unjittered lattice hit
     |x - b_k'| = delta exactly; the pair list must still be bitwise equal."""
