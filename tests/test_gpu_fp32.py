@@ -60,6 +60,18 @@ def test_fp32_constant_kernel_retri():
     _check(mesh, prob, "fp32 const retri")
 
 
+@pytest.mark.parametrize("ball,seed", [("retri", 21), ("barycenter", 22)])
+def test_fp32_constant_kernel_deep_pairs_jittered(ball, seed):
+    """FP32 constant kernel on a strongly jittered mesh at h = delta/6, where
+    most pairs are deep (blocks summed from element areas, their Myy per
+    element)."""
+    d = 0.1
+    mesh = structured_mesh(d, d / 6, jitter=0.25, seed=seed)
+    prob = Problem(delta=d, kernel_c=constant_kernel_c(d), ball=ball, cap_edges=8 if ball == "retri" else 0,
+                   precision="fp32")
+    _check(mesh, prob, "fp32 const %s h=delta/6" % ball)
+
+
 def test_fp32_fractional_retri_with_near_pairs():
     d, s = 0.2, 0.4
     mesh = structured_mesh(d, 0.05, jitter=0.1, seed=13)
