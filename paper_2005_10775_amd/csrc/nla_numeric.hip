@@ -151,6 +151,71 @@ __device__ __forceinline__ unsigned *init_row_block(unsigned *dyn, double *__res
     return dyn;
 }
 
+// The deep pairs' part of the row block: each column's remaining entries
+// (after the band chunks they are all deep) name deep partners k' holding the
+// column's node; the column adds cf_a times the sum of their areas |E_k'|
+// (tab: those areas by deep slot, or null to read them through proc_kp).
+// Four columns per lane at a time: their ends, first four entries and sums
+// so far are loaded together, so the walks share their round trips.
+__device__ __forceinline__ void deep_row_block(double *__restrict__ Rg, const unsigned *cn_l, int nC,
+                                               const int32_t *__restrict__ cptr, int cbase,
+                                               const uint16_t *__restrict__ colent,
+                                               const int32_t *__restrict__ proc_kp, int64_t p0, int nbr,
+                                               const double *__restrict__ a2, const double *tab,
+                                               const double (&cf)[3], int lane)
+{
+    auto area = [&](int e) -> double { return tab ? tab[(e >> 2) - nbr] : a2[proc_kp[p0 + (e >> 2)]]; };
+    for (int c0 = lane; c0 < nC; c0 += 256) {
+        unsigned w[4];
+        int cur[4], end[4], e[4][4];
+        double r[4][3], S[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) w[j] = c0 + 64 * j < nC ? cn_l[c0 + 64 * j] : 0xffff0000u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int c = c0 + 64 * j;
+            const bool live = (w[j] >> 16) != 0xffffu;
+            cur[j] = cbase + (int)(w[j] & 0x7fffu);
+            end[j] = live ? cptr[c + 1] : cur[j];
+#pragma unroll
+            for (int i = 0; i < 4; i++) e[j][i] = live ? colent[cur[j] + i] : 0;   // padded by four
+#pragma unroll
+            for (int a = 0; a < 3; a++) r[j][a] = (live && (w[j] & 0x8000u)) ? Rg[a * nC + c] : 0.0;
+            S[j] = 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            double av[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) av[i] = cur[j] + i < end[j] ? area(e[j][i]) : 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                if (cur[j] + i < end[j]) S[j] += av[i];
+            cur[j] += 4;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            // columns with more than four deep entries
+            while (cur[j] < end[j]) {
+                int ee[4];
+                double av[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) ee[i] = colent[cur[j] + i];
+#pragma unroll
+                for (int i = 0; i < 4; i++) av[i] = cur[j] + i < end[j] ? area(ee[i]) : 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    if (cur[j] + i < end[j]) S[j] += av[i];
+                cur[j] += 4;
+            }
+            if ((w[j] >> 16) != 0xffffu) {
+#pragma unroll
+                for (int a = 0; a < 3; a++) Rg[a * nC + c0 + 64 * j] = r[j][a] + cf[a] * S[j];
+            }
+        }
+    }
+}
+
 // One wavefront per outer element k (Eq. (bformhj) restricted to the pairs
 // of k).  Phase 1: every lane takes one pair (k, k'), classifies its items
 // (x_{k,q}, E_k') as whole / partial / empty; whole items (all of E_k' in the
@@ -459,61 +524,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) cf[a] *= -psi * M.m1c;
-        const int32_t *cptr = colent_ptr + coff;
-        auto area = [&](int e) -> double {
-            return dtab_off ? tab[(e >> 2) - nbr] : E.a2[proc_kp[p0 + (e >> 2)]];
-        };
-        // four columns per lane at a time: their ends, first four entries and
-        // sums so far are loaded together, so the walks share their round trips
-        for (int c0 = lane; c0 < nC; c0 += 256) {
-            unsigned w[4];
-            int cur[4], end[4], e[4][4];
-            double r[4][3], S[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) w[j] = c0 + 64 * j < nC ? cn_l[c0 + 64 * j] : 0xffff0000u;
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int c = c0 + 64 * j;
-                const bool live = (w[j] >> 16) != 0xffffu;
-                cur[j] = cbase + (int)(w[j] & 0x7fffu);
-                end[j] = live ? cptr[c + 1] : cur[j];
-#pragma unroll
-                for (int i = 0; i < 4; i++) e[j][i] = live ? colent[cur[j] + i] : 0;   // padded by four
-#pragma unroll
-                for (int a = 0; a < 3; a++) r[j][a] = (live && (w[j] & 0x8000u)) ? Rg[a * nC + c] : 0.0;
-                S[j] = 0.0;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                double av[4];
-#pragma unroll
-                for (int i = 0; i < 4; i++) av[i] = cur[j] + i < end[j] ? area(e[j][i]) : 0.0;
-#pragma unroll
-                for (int i = 0; i < 4; i++)
-                    if (cur[j] + i < end[j]) S[j] += av[i];
-                cur[j] += 4;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                // columns with more than four deep entries
-                while (cur[j] < end[j]) {
-                    int ee[4];
-                    double av[4];
-#pragma unroll
-                    for (int i = 0; i < 4; i++) ee[i] = colent[cur[j] + i];
-#pragma unroll
-                    for (int i = 0; i < 4; i++) av[i] = cur[j] + i < end[j] ? area(ee[i]) : 0.0;
-#pragma unroll
-                    for (int i = 0; i < 4; i++)
-                        if (cur[j] + i < end[j]) S[j] += av[i];
-                    cur[j] += 4;
-                }
-                if ((w[j] >> 16) != 0xffffu) {
-#pragma unroll
-                    for (int a = 0; a < 3; a++) Rg[a * nC + c0 + 64 * j] = r[j][a] + cf[a] * S[j];
-                }
-            }
-        }
+        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, nbr, E.a2, dtab_off ? tab : nullptr,
+                       cf, lane);
     }
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
     // lanes, then lane 0's sum is broadcast
@@ -590,6 +602,9 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
                                                         const int32_t *__restrict__ colent_ptr,
                                                         const uint16_t *__restrict__ colent, double *__restrict__ Rout,
                                                         double *__restrict__ Cyy, double *__restrict__ Cxx,
+                                                        const int32_t *__restrict__ proc_p,
+                                                        const int32_t *__restrict__ proc_kp,
+                                                        const int32_t *__restrict__ nband, double *__restrict__ Dk,
                                                         unsigned long long *__restrict__ counters)
 {
     extern __shared__ unsigned dyn[];
@@ -622,16 +637,21 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
     double s0sum = 0.0, mxx[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long c_whole = 0, c_part = 0, c_empty = 0, c_sub = 0, c_cap = 0;
     const int64_t p0 = pair_ptr[k], p1 = pair_ptr[k + 1];
-    for (int64_t base = p0; base < p1; base += 64) {
-        const int64_t p = base + lane;
-        const bool act = p < p1;
+    // with the plan's processing order (symmetric inner rule) the chunks take the
+    // band pairs only; a deep pair's region is whole, so its blocks follow from
+    // |E_k'| and it is summed after the chunks (as in k_pairs_const_fp64)
+    const int64_t pend = nband ? p0 + nband[k] : p1;
+    for (int64_t base = p0; base < pend; base += 64) {
+        const int64_t pi = base + lane;                                   // processing slot
+        const bool act = pi < pend;
+        const int64_t p = (proc_p && act) ? (int64_t)proc_p[pi] : pi;    // the pair's canonical index
         double mxy[9], myy[6];
 #pragma unroll
         for (int i = 0; i < 9; i++) mxy[i] = 0.0;
 #pragma unroll
         for (int i = 0; i < 6; i++) myy[i] = 0.0;
         if (act) {
-            const int kp = pair_kp[p];
+            const int kp = proc_kp ? proc_kp[pi] : pair_kp[p];
             const double V[6] = {E.vx0[kp], E.vy0[kp], E.vx1[kp], E.vy1[kp], E.vx2[kp], E.vy2[kp]};
             const double a2p = E.a2[kp];
             const bool shifted = ball == NLA_BALL_SHIFTED;
@@ -699,8 +719,33 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
         }
         __syncthreads();
         fold_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, res, (int)(base - p0), lane,
-                       (unsigned short *)&res[0][9], 48);
+                       (unsigned short *)&res[0][9], 48, (int)(pend - p0));
         __syncthreads();
+    }
+    if (nband) {
+        // deep pairs: S0 sums wsum |E_k'|, -Mxy_ab = -psi m1 sQ_a |E_k'| per column
+        // through its deep partners, Myy per element through Dk
+        double dsum = 0.0;
+        for (int64_t pi = pend + lane; pi < p1; pi += 64) {
+            dsum += E.a2[proc_kp[pi]];
+            c_whole++;
+        }
+        if (ball == NLA_BALL_SHIFTED) {
+            s0sum += dsum * M.wsum;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 6; t++) mxx[t] += sQ[4 + t] * (dsum * M.wsum);
+        }
+        const double cf[3] = {-psi * M.m1c * sQ[1], -psi * M.m1c * sQ[2], -psi * M.m1c * sQ[3]};
+        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, (int)(pend - p0), E.a2, nullptr,
+                       cf, lane);
+        double x = dsum;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) {
+            double wsum = 0.0;
+            for (int q = 0; q < R->n_out; q++) wsum += R->out_w[q];
+            Dk[k] = psi * wsum * x;
+        }
     }
     // Mxx(k): a fixed butterfly over the lanes, lane 0's sum broadcast
     {
@@ -986,12 +1031,12 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
                 k_pairs_support_fp64<true><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                               P->counters);
+                                                               P->proc_p, P->proc_kp, P->nband, Dk, P->counters);
             else
                 k_pairs_support_fp64<false><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                 pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                 P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                                P->counters);
+                                                                P->proc_p, P->proc_kp, P->nband, Dk, P->counters);
         } else if (sw && bnd) NLA_LAUNCH_PAIRS(8, true, true, true, true);
         else if (sw) NLA_LAUNCH_PAIRS(8, true, true, false, true);
         else if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true, false);

@@ -1061,9 +1061,12 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
     // then the deep ones (a stable sort of the keys 2 k + deep); under the
     // intersection, overlap and barycenter balls every item of a deep pair is
     // whole (for the barycenter ball: |x_q - b_k'| <= r_k + |b_k - b_k'| <= delta)
+    // and under the shifted and barycenter-support balls every region of a deep
+    // pair is whole; their kernel sums deep pairs with a symmetric inner rule
     const bool ordered = pr.kernel == NLA_KERNEL_CONSTANT &&
                          (pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_OVERLAP ||
-                          pr.ball == NLA_BALL_BARYCENTER) &&
+                          pr.ball == NLA_BALL_BARYCENTER ||
+                          ((pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT) && P->rules.in_sym)) &&
                          P->n_pairs > 0 && 2 * (int64_t)K < (int64_t)UINT32_MAX;
     if (ordered) {
         const int64_t NP = P->n_pairs;
