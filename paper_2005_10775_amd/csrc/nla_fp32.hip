@@ -582,7 +582,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
         v[i] = x;
     }
-    if (lane == 0) {
+    if (counters && lane == 0) {
         atomicAdd(&counters[0], v[0]);
         atomicAdd(&counters[1], v[1]);
         atomicAdd(&counters[2], v[2]);
@@ -1114,6 +1114,7 @@ int nla_numeric_fp32(nla_plan *P, hipStream_t s, void (*mark)(nla_plan *, int, h
     }
     const bool learn = pr.precision == NLA_FP32_LEARNED;
     PairArgs A = nla_pair_args(P);
+    if (P->counted) A.counters = nullptr;    // counted at the first assembly (geometry only)
     mark(P, NLA_PHASE_MLP, s);
     if (learn && P->n_routed > 0) {
         k_route<8, true><<<K, 64, 0, s>>>(A, nullptr, P->route_feat);

@@ -180,6 +180,7 @@ struct nla_plan {
         if (aux) (void)hipStreamDestroy(aux);
     }
     bool assembled = false;
+    bool counted = false;       // the item counters hold the first assembly's counts (geometry only)
     bool have_load = false;
     int val_dtype = NLA_DTYPE_F64;
 };

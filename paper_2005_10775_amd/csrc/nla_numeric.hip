@@ -570,7 +570,7 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
         v[i] = x;
     }
-    if (lane == 0) {
+    if (counters && lane == 0) {
         atomicAdd(&counters[0], v[0]);
         atomicAdd(&counters[1], v[1]);
         atomicAdd(&counters[2], v[2]);
@@ -773,7 +773,7 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
         for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
         v[i] = x;
     }
-    if (lane == 0) {
+    if (counters && lane == 0) {
         atomicAdd(&counters[0], v[0]);
         atomicAdd(&counters[1], v[1]);
         atomicAdd(&counters[2], v[2]);
@@ -981,7 +981,10 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
     const bool timed = P->timing_count < P->timing_slots;
     P->cur_ev = timed ? &P->ev[(size_t)P->timing_count * (NLA_NPHASE + 1)] : nullptr;
     for (int i = 0; i < NLA_NPHASE; i++) P->ran[i] = false;
-    NLA_HIP(hipMemsetAsync(P->counters, 0, sizeof(unsigned long long) * 6, s));
+    // the item counters depend on the geometry only: the first assembly counts,
+    // later ones pass no counters (and launch no clearing of them)
+    unsigned long long *ctr = P->counted ? nullptr : P->counters;
+    if (ctr) NLA_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * 6, s));
     if (fp64) {
         double *Cyy = (double *)P->contrib;
         double *Cxx = Cyy + 6 * NP;
@@ -1008,7 +1011,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, P->pairs_lds, s>>>(                                    \
             P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,       \
             pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,            \
-            P->proc_p, P->proc_kp, P->nband, Dk, P->pairs_tab, P->counters);                                       \
+            P->proc_p, P->proc_kp, P->nband, Dk, P->pairs_tab, ctr);                                               \
     } while (0)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
@@ -1031,12 +1034,12 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
                 k_pairs_support_fp64<true><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                               P->proc_p, P->proc_kp, P->nband, Dk, P->counters);
+                                                               P->proc_p, P->proc_kp, P->nband, Dk, ctr);
             else
                 k_pairs_support_fp64<false><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                 pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                 P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                                P->proc_p, P->proc_kp, P->nband, Dk, P->counters);
+                                                                P->proc_p, P->proc_kp, P->nband, Dk, ctr);
         } else if (sw && bnd) NLA_LAUNCH_PAIRS(8, true, true, true, true);
         else if (sw) NLA_LAUNCH_PAIRS(8, true, true, false, true);
         else if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true, false);
@@ -1089,5 +1092,6 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
     NLA_HIP(hipGetLastError());
     P->val_dtype = fp64 ? NLA_DTYPE_F64 : NLA_DTYPE_F32;
     P->assembled = true;
+    P->counted = true;
     return NLA_OK;
 }
