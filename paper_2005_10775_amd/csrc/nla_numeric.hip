@@ -4,7 +4,7 @@
 #include <cmath>
 
 // workgroups per CU of the FP64 pair kernels (see lds_for_occupancy)
-#define NLA_PAIRS_WG_PER_CU 10
+#define NLA_PAIRS_WG_PER_CU 0
 #define NLA_SUPPORT_WG_PER_CU 0
 
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -916,9 +916,8 @@ __global__ __launch_bounds__(256) void k_load_rhs(int n_free, const int32_t *__r
 
 // Dynamic LDS for a launch of fn (64 threads per workgroup): `need` bytes,
 // raised when more than wg_per_cu workgroups would otherwise share a CU, so
-// that at most wg_per_cu do (0: no cap).  The latency-bound pair kernels run
-// faster below their register-limited occupancy: fewer waves per CU keep
-// more of each wave's element data in the CU's caches.
+// that at most wg_per_cu do (0: no cap).  The FP64 pair kernels run uncapped:
+// on c2 a cap of 8, 10 or 12 workgroups per CU is as fast or slower than none.
 static size_t lds_for_occupancy(const void *fn, size_t need, int wg_per_cu)
 {
     int n = 0;
