@@ -236,18 +236,19 @@ void nla_plan_destroy(nla_plan *plan);
  * Many independent problems (meshes, horizons, kernels, balls) assembled
  * together.  All instances must use NLA_FP32, outer rules of at most 8
  * points and cap counts that are 0 or powers of two (NLA_E_UNSUPPORTED
- * otherwise).  mode 1 assembles all instances with one persistent launch of
- * the pair kernel (a fixed grid taking (instance, outer element) work items,
- * heaviest first, from a device cursor) followed by instance-batched near-pair,
- * element-block, segmented-sum, extraction and load kernels, captured once in
- * a hipGraph on a private stream and replayed (ordered after and before the
- * caller's stream with events); mode 0 assembles the instances one after the
- * other with their own launches.  Both give bitwise identical values. */
+ * otherwise).  mode 1 replays a hipGraph, captured once on a private stream
+ * (ordered after and before the caller's stream with events), of either one
+ * persistent launch of the pair kernel (a fixed grid taking (instance, outer
+ * element) work items, heaviest first, from a device cursor) followed by
+ * instance-batched near-pair, element-block, segmented-sum, extraction and
+ * load kernels, or (chunk 0, when the autotuner times it faster) every
+ * instance's own launches; mode 0 assembles the instances one after the other
+ * with their own launches.  All give bitwise identical values. */
 typedef struct nla_batch nla_batch;
 typedef struct {
     int32_t n;                   /* instances */
     int64_t total_pairs, total_elements, total_near;   /* total_near: singular-pair blocks integrated */
-    int32_t chunk;               /* work items taken per cursor fetch */
+    int32_t chunk;               /* work items taken per cursor fetch (0: the graph of each instance's launches) */
     int32_t grid;                /* wavefronts of the persistent launch */
 } nla_batch_summary;
 

@@ -1236,7 +1236,7 @@ __global__ void k_batch_zero(int n, const BatchInst *__restrict__ B, int *__rest
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *cursor = 0;
-    if (i < 6 * n) B[i / 6].counters[i % 6] = 0ull;
+    if (i < 6 * n && B[i / 6].counters) B[i / 6].counters[i % 6] = 0ull;
 }
 
 __global__ __launch_bounds__(64, 2) void k_batch_near(int n, const BatchInst *__restrict__ B, const int64_t *__restrict__ off)
@@ -1336,6 +1336,7 @@ struct nla_batch {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     bool graph_ok = false;
+    bool counted = false;                        // the item counters hold a replay's counts
     ~nla_batch()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -1374,8 +1375,22 @@ static int batch_capture(nla_batch *B)
         NLA_HIP(hipGraphDestroy(B->graph));
         B->graph = nullptr;
     }
+    if (B->chunk == 0) {
+        // the graph of each plan's own launches: every plan assembles once outside
+        // the capture first (workspace, first-assembly counters, launch shapes)
+        for (int i = 0; i < B->n; i++)
+            if (!B->plans[i]->counted)
+                NLA_TRY(nla_numeric(B->plans[i], B->h_inst[i].f, B->h_inst[i].g, B->stream));
+        NLA_HIP(hipStreamSynchronize(B->stream));
+    }
     NLA_HIP(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-    int st = batch_launch(B, B->stream);
+    int st = NLA_OK;
+    if (B->chunk == 0) {
+        for (int i = 0; i < B->n && st == NLA_OK; i++)
+            st = nla_numeric(B->plans[i], B->h_inst[i].f, B->h_inst[i].g, B->stream);
+    } else {
+        st = batch_launch(B, B->stream);
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(B->stream, &g);
     if (st != NLA_OK) return st;
@@ -1522,6 +1537,7 @@ static int batch_set_inputs(nla_batch *B, const double *const *f, const double *
         B->h_inst[i].g = gi;
     }
     if (changed) NLA_HIP(hipMemcpy(B->d_inst, B->h_inst.data(), sizeof(BatchInst) * B->n, hipMemcpyHostToDevice));
+    if (changed && B->chunk == 0) B->graph_ok = false;   // that graph holds the pointers as kernel arguments
     return NLA_OK;
 }
 
@@ -1545,6 +1561,19 @@ extern "C" int nla_batch_assemble(nla_batch *B, int32_t mode, const double *cons
     NLA_HIP(hipGraphLaunch(B->exec, B->stream));
     NLA_HIP(hipEventRecord(B->ev_out, B->stream));
     NLA_HIP(hipStreamWaitEvent(s, B->ev_out, 0));
+    if (!B->counted) {
+        // the item counters now hold this replay's counts, which depend on the
+        // geometry only: later replays neither clear nor count them (the
+        // instance and argument tables lose their counter pointers)
+        NLA_HIP(hipStreamSynchronize(B->stream));
+        for (BatchInst &I : B->h_inst) I.counters = nullptr;
+        NLA_HIP(hipMemcpy(B->d_inst, B->h_inst.data(), sizeof(BatchInst) * B->n, hipMemcpyHostToDevice));
+        std::vector<PairArgs> a((size_t)B->n);
+        NLA_HIP(hipMemcpy(a.data(), B->d_args, sizeof(PairArgs) * B->n, hipMemcpyDeviceToHost));
+        for (PairArgs &x : a) x.counters = nullptr;
+        NLA_HIP(hipMemcpy(B->d_args, a.data(), sizeof(PairArgs) * B->n, hipMemcpyHostToDevice));
+        B->counted = true;
+    }
     for (nla_plan *P : B->plans) {
         P->assembled = true;
         P->val_dtype = NLA_DTYPE_F32;
@@ -1588,7 +1617,7 @@ extern "C" int nla_batch_autotune(nla_batch *B, const char *cache_path, void *st
             char k2[128];
             int c, g;
             while (fscanf(f, "%127s %d %d", k2, &c, &g) == 3)
-                if (strcmp(k2, key) == 0 && c > 0 && g > 0) {
+                if (strcmp(k2, key) == 0 && c >= 0 && g > 0) {
                     B->chunk = c;
                     B->grid = g;
                     B->graph_ok = false;
@@ -1598,15 +1627,16 @@ extern "C" int nla_batch_autotune(nla_batch *B, const char *cache_path, void *st
             fclose(f);
         }
     }
-    const int chunks[4] = {1, 2, 4, 8};
+    // chunk 0: the graph of each plan's own launches instead of the persistent kernel
+    const int chunks[5] = {0, 1, 2, 4, 8};
     const int mults[3] = {2, 4, 8};
     hipEvent_t e0, e1;
     NLA_HIP(hipEventCreate(&e0));
     NLA_HIP(hipEventCreate(&e1));
     float best = 1e30f;
     int bc = B->chunk, bg = B->grid;
-    for (int ci = 0; ci < 4; ci++)
-        for (int mi = 0; mi < 3; mi++) {
+    for (int ci = 0; ci < 5; ci++)
+        for (int mi = 0; mi < (chunks[ci] == 0 ? 1 : 3); mi++) {
             B->chunk = chunks[ci];
             B->grid = mults[mi] * B->n_cu;
             B->graph_ok = false;

@@ -1,6 +1,7 @@
 """Batched assembly: one persistent launch over uneven instances, captured in
 a hipGraph, gives bitwise the values of assembling each instance alone; so
-does every (chunk, grid) the autotuner may pick."""
+does every (chunk, grid) the autotuner may pick, and so does the graph of
+every instance's own launches (chunk 0)."""
 import sys
 
 import numpy as np
@@ -60,7 +61,7 @@ def test_batch_bitwise_equals_sequential(tmp_path):
             assert np.array_equal(b0, b1)
         _ = torch.ones(10, device="cuda").sum().item()
     info = b.autotune(str(tmp_path / "tune.txt"))
-    assert info["chunk"] in (1, 2, 4, 8) and info["grid"] > 0
+    assert info["chunk"] in (0, 1, 2, 4, 8) and info["grid"] > 0
     b.assemble(mode=1, f_outer=fs, g_node=gs)
     torch.cuda.synchronize()
     for (v0, _), (v1, _) in zip(seq, _values(b)):
@@ -71,3 +72,27 @@ def test_batch_bitwise_equals_sequential(tmp_path):
     p.assemble(fs[3], gs[3])
     torch.cuda.synchronize()
     assert np.array_equal(host(p.csr(0)[2]).view(np.uint32), seq[3][0].view(np.uint32))
+
+
+def test_batch_graph_of_instance_launches(tmp_path):
+    """chunk 0 (forced through the autotuner's cache file): the graph of each
+    instance's own launches, replayed several times with eager work between
+    the replays, gives the sequential values bitwise."""
+    b = Batch(_instances())
+    fs, gs = _inputs(b)
+    b.assemble(mode=0, f_outer=fs, g_node=gs)
+    torch.cuda.synchronize()
+    seq = _values(b)
+    i = b.info()
+    cu = torch.cuda.get_device_properties(0).multi_processor_count
+    key = "n%d_pairs%d_K%d_near%d_cu%d" % (i["n"], i["total_pairs"], i["total_elements"], i["total_near"], cu)
+    path = tmp_path / "tune.txt"
+    path.write_text("%s 0 1\n" % key)
+    assert b.autotune(str(path))["chunk"] == 0
+    for rep in range(3):
+        b.assemble(mode=1, f_outer=fs, g_node=gs)
+        torch.cuda.synchronize()
+        for (v0, b0), (v1, b1) in zip(seq, _values(b)):
+            assert np.array_equal(v0.view(np.uint32), v1.view(np.uint32))
+            assert np.array_equal(b0, b1)
+        _ = torch.ones(10, device="cuda").sum().item()
