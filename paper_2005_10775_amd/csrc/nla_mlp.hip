@@ -24,13 +24,10 @@ enum { OW1 = 0, OB1 = 768, OW2 = 896, OB2 = 17280, OW3 = 17408, OB3 = 17792, NW 
 
 inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// float -> bfloat16, round to nearest even (finite inputs)
-__device__ __forceinline__ __bf16 to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-    return __builtin_bit_cast(__bf16, (unsigned short)u);
-}
+// float -> bfloat16, round to nearest even: the hardware conversion
+// (v_cvt_pk_bf16_f32, two values per instruction) under the default FP32 mode
+// (round to nearest even, subnormals kept)
+__device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 __device__ __forceinline__ float from_bf16(__bf16 b)
 {
     return __uint_as_float((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
