@@ -523,10 +523,14 @@ static int mlp_scratch(nla_mlp *M, int64_t Bp, int64_t nloss)
     return NLA_OK;
 }
 
-static int fwd_grid(int64_t tiles)
+// Blocks for a forward pass over `tiles` 32-item tiles (four waves a block).
+// Three blocks fit a CU (LDS); a grid of many rounds of resident blocks runs
+// faster than a single round because block starts (the weight loads) stagger
+// against other blocks' arithmetic: 4096 blocks (about 5 rounds on 256 CUs).
+static int fwd_grid(int64_t tiles, int64_t cap = 2048)
 {
     int64_t b = (tiles + 3) / 4;
-    return (int)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 // one gradient evaluation on Bp (multiple of 64) batch positions
@@ -553,8 +557,8 @@ int nla_mlp_infer_launch(const nla_mlp *M, const float *feat, int64_t n, float *
 {
     if (n <= 0) return NLA_OK;
     TrainBuf none{};
-    k_mlp_fwd<0><<<fwd_grid((n + 31) / 32), 256, 0, s>>>(n, feat, nullptr, nullptr, mlp_view(M), 1.f, 0.f, 1, 0, 0, n,
-                                                        out, none);
+    k_mlp_fwd<0><<<fwd_grid((n + 31) / 32, 4096), 256, 0, s>>>(n, feat, nullptr, nullptr, mlp_view(M), 1.f, 0.f, 1, 0,
+                                                              0, n, out, none);
     NLA_HIP(hipGetLastError());
     return NLA_OK;
 }
