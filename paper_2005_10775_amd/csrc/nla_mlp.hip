@@ -354,10 +354,18 @@ __global__ void k_mlp_reduce_final(int nchunk, const float *__restrict__ part, f
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= NRED) return;
-    // four running sums over chunks c = 0, 1, 2, 3 mod 4 keep four loads in
-    // flight; they are combined in a fixed order
+    // four running sums over chunks c = 0, 1, 2, 3 mod 4, combined in a fixed
+    // order; 32 chunks' loads are issued before their additions (each sum still
+    // takes its chunks in increasing order)
     float s4[4] = {0.f, 0.f, 0.f, 0.f};
     int c = 0;
+    for (; c + 32 <= nchunk; c += 32) {
+        float v[32];
+#pragma unroll
+        for (int j = 0; j < 32; j++) v[j] = part[(int64_t)(c + j) * NRED + r];
+#pragma unroll
+        for (int j = 0; j < 32; j++) s4[j & 3] += v[j];
+    }
     for (; c + 4 <= nchunk; c += 4) {
 #pragma unroll
         for (int j = 0; j < 4; j++) s4[j] += part[(int64_t)(c + j) * NRED + r];
