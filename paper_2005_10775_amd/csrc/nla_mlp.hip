@@ -338,15 +338,17 @@ __device__ __forceinline__ float red_term(const TrainBuf &T, int r, int64_t p)
     return T.sq[p];
 }
 
+// block (chunk x, value range y): one value per thread, so the chunk's values
+// are summed by many waves at once
 __global__ __launch_bounds__(256) void k_mlp_reduce_part(TrainBuf T, float *__restrict__ part)
 {
     const int64_t p0 = (int64_t)blockIdx.x * RCH;
-    for (int r = threadIdx.x; r < NRED; r += blockDim.x) {
-        float s = 0.f;
+    const int r = blockIdx.y * blockDim.x + threadIdx.x;
+    if (r >= NRED) return;
+    float s = 0.f;
 #pragma unroll
-        for (int i = 0; i < RCH; i++) s += red_term(T, r, p0 + i);
-        part[(int64_t)blockIdx.x * NRED + r] = s;
-    }
+    for (int i = 0; i < RCH; i++) s += red_term(T, r, p0 + i);
+    part[(int64_t)blockIdx.x * NRED + r] = s;
 }
 
 __global__ void k_mlp_reduce_final(int nchunk, const float *__restrict__ part, float *__restrict__ g,
@@ -555,7 +557,7 @@ static int mlp_grad(nla_mlp *M, int mode, int64_t nB, const float *feat, const f
     k_mlp_bwd<<<fwd_grid(tiles), 256, 0, s>>>(W, M->T);
     k_mlp_dw2<<<16, 256, 0, s>>>(M->T, M->g);
     const int nchunk = (int)(M->T.Bp / RCH);
-    k_mlp_reduce_part<<<nchunk, 256, 0, s>>>(M->T, M->T.part);
+    k_mlp_reduce_part<<<dim3(nchunk, (NRED + 255) / 256), 256, 0, s>>>(M->T, M->T.part);
     k_mlp_reduce_final<<<grid_for(NRED, 256), 256, 0, s>>>(nchunk, M->T.part, M->g, loss_slot);
     NLA_HIP(hipGetLastError());
     return NLA_OK;
