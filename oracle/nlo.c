@@ -37,7 +37,9 @@
  * analytic caps, brute-force region moments, matrix invariants, load vector,
  * the paper's printed L2 errors of Sec. 8 for the nocaps, approxcaps, overlap,
  * shifted and barycenter-support balls, the x <-> y identity between the
- * shifted and barycenter-support matrices, grid (b)'s printed element sizes).
+ * shifted and barycenter-support matrices, grid (b)'s printed element sizes,
+ * the one-point centroid caps of Sec. 5.2 against the exact intersection's
+ * area and first moments, which a centroid rule integrates exactly).
  * Parity unpinned: the printed barycenter column of Sec. 8.1 and the grid (b)
  * columns are not reproduced (lattice ties; the unstated diagonal direction).
  */

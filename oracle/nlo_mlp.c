@@ -32,7 +32,8 @@
  * pass against the backward pass; the saturated-GELU affine special case
  * against a matrix product; the tanh-GELU against the erf-GELU within the
  * approximation's error; cap labels against the shoelace area and centroid of
- * the 8-arc cap polygon; routing band and closure structure).
+ * the 8-arc cap polygon; routing band; the closure against the centroid
+ * rule at the shoelace centroid of the 8-arc cap polygons).
  */
 #include "nlo.h"
 #include <math.h>

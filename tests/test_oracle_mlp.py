@@ -178,3 +178,84 @@ def test_features_rotation_invariant():
         assert np.allclose(ob.mlp_features(x0, W, d), f0, atol=1e-11)
         n1, m1 = ob.cap_moments(d, x0, W, 8)
         assert n1 == n0 and np.allclose(m1 / d ** 2, m0, rtol=1e-9)
+
+
+def _caps_inside(x, V, d, n_arc):
+    """The n_arc-arc approximations of the circular segments that lie in the
+    triangle V (CCW) around x, as polygons: the circle's angle intervals
+    inside the triangle, from the three half-plane constraints, each cut into
+    n_arc equal arcs."""
+    allowed = [(0.0, 2 * math.pi)]
+    for a in range(3):
+        A, B = V[a], V[(a + 1) % 3]
+        e = B - A
+        nrm = np.array([e[1], -e[0]])
+        c = -(nrm @ (x - A)) / (np.linalg.norm(nrm) * d)
+        if c >= 1.0:
+            continue
+        if c <= -1.0:
+            return []
+        lo = (math.atan2(nrm[1], nrm[0]) + math.acos(c)) % (2 * math.pi)
+        span = 2 * math.pi - 2 * math.acos(c)
+        pieces = [(lo, min(lo + span, 2 * math.pi))] + ([(0.0, lo + span - 2 * math.pi)]
+                                                       if lo + span > 2 * math.pi else [])
+        allowed = [(max(u0, v0), min(u1, v1)) for (u0, u1) in allowed for (v0, v1) in pieces
+                   if min(u1, v1) > max(u0, v0)]
+    # an arc through angle 0 comes as two intervals: join them
+    if len(allowed) > 1 and allowed[0][0] == 0.0 and allowed[-1][1] == 2 * math.pi:
+        allowed = [(allowed[-1][0], allowed[0][1] + 2 * math.pi)] + allowed[1:-1]
+    out = []
+    for lo, hi in allowed:
+        t = lo + (hi - lo) * np.arange(n_arc + 1) / n_arc
+        out.append(np.stack([x[0] + d * np.cos(t), x[1] + d * np.sin(t)], axis=1))
+    return out
+
+
+def test_learned_closure_is_the_centroid_rule_of_the_caps():
+    """The learned caps feed S2 through the one-point centroid closure of
+    Sec. 5.2: the caps' mass sum(m) sits where the basis takes the values
+    m / sum(m).  With a network whose output is fixed (all weights zero, the
+    last bias set) to the exact 8-arc cap integrals m_b = |C| beta_b(c) of
+    the item, the learned contribution must be psi (|C|, |C| beta(c),
+    |C| beta(c) beta(c)^T) with |C| and c the total area and centroid of the
+    8-arc cap polygons, computed here independently by the shoelace formula;
+    it is what the learned sums add over the polygon-only (nocaps) sums."""
+    from workloads import Problem, structured_mesh
+    from workloads.learned import OFFSETS, N_WEIGHTS
+    d, psi = 0.1, 3.5
+    mesh = structured_mesh(d, 0.05)
+    rng = np.random.default_rng(5)
+    base = Problem(delta=d, kernel_c=psi, ball="retri", cap_edges=0, outer="dunavant7", inner="gauss3")
+    op0 = ob.OracleProblem(mesh, base)
+    tested = two = 0
+    while tested < 40:
+        V = rng.uniform(-0.002, 0.002, size=(3, 2)) + np.array([[0, 0], [0.0125, 0], [0.0125, 0.0125]])
+        V = V + rng.uniform(-0.11, 0.11, size=2)
+        x = np.zeros(2)
+        dv = np.linalg.norm(V - x, axis=1)
+        if np.all(dv < d) or not ob.routed(d, 0.02, x, V):
+            continue
+        caps = _caps_inside(x, V, d, 8)
+        if not caps:
+            continue
+        area, first = 0.0, np.zeros(2)
+        for P in caps:
+            a, c = _shoelace(P)
+            area += a
+            first += a * c
+        cen = first / area
+        M = np.vstack([V.T, np.ones(3)])
+        beta = np.linalg.solve(M, np.array([cen[0], cen[1], 1.0]))
+        w = np.zeros(N_WEIGHTS)
+        w[OFFSETS["b3"][0]:OFFSETS["b3"][0] + 3] = area * beta / (d * d)
+        opL = ob.OracleProblem(mesh, Problem(delta=d, kernel_c=psi, ball="retri", cap_edges=8,
+                                             outer="dunavant7", inner="gauss3", precision="learned"),
+                               mlp_w=w, mlp_scale=1.0)
+        p0, p1, p2 = ob.inner_sums(op0, x, V)
+        l0, l1, l2 = ob.inner_sums(opL, x, V)
+        s = psi * area
+        assert abs((l0 - p0) - s) < 1e-12 * psi * 0.5 * 0.0125 ** 2
+        assert np.max(np.abs((l1 - p1) - s * beta)) < 1e-12 * psi * 0.5 * 0.0125 ** 2
+        assert np.max(np.abs((l2 - p2) - s * np.outer(beta, beta))) < 1e-12 * psi * 0.5 * 0.0125 ** 2
+        two += len(caps) > 1
+        tested += 1

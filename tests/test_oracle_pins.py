@@ -545,3 +545,53 @@ def test_analytic_caps_whole_ball():
         assert abs(m2 - math.pi * d ** 4 / 2) < 1e-13 * m2
         psi = constant_kernel_c(d)
         assert abs(-2 * psi * m2 - 4 * psi * (x @ m1) + 4.0) < 1e-11
+
+
+# ------------------------------- exact caps by the one-point centroid rule
+def _psd_gap(A):
+    """Smallest eigenvalue of the symmetric part of A."""
+    return float(np.min(np.linalg.eigvalsh(0.5 * (A + A.T))))
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_centroid_caps_integrate_affine_functions_exactly(seed):
+    """Sec. 5.2: each true cap (a circular segment, Eq. (areacap) area) is
+    integrated by one point at its centroid with the segment's area as the
+    weight.  A one-point centroid rule is exact for affine integrands, and the
+    polygon part is integrated by a rule exact for quadratics, so with psi = 1
+    the region's S0 = |E' n B| and S1_b = int beta_b must equal the exact
+    intersection moments (Green's theorem on the true boundary, computed
+    independently) to rounding.  A wrong weight (the printed quarter), a wrong
+    centroid distance or a wrong bisector angle moves S0 or S1 off them.  For
+    the quadratic S2 the centroid rule drops each segment's central second
+    moment, so exact S2 minus the oracle's S2 is positive semidefinite and
+    nonzero."""
+    d = 0.1
+    rng = np.random.default_rng(seed)
+    op = oracle.OracleProblem(structured_mesh(d, 0.05),
+                              Problem(delta=d, kernel_c=1.0, ball="retri", cap_mode="centroid",
+                                      outer="dunavant7", inner="gauss3"))
+    tested = gaps = 0
+    while tested < 60:
+        V = rng.uniform(-0.004, 0.004, size=(3, 2)) + np.array([[0, 0], [0.0125, 0], [0.0125, 0.0125]])
+        a2 = (V[1, 0] - V[0, 0]) * (V[2, 1] - V[0, 1]) - (V[1, 1] - V[0, 1]) * (V[2, 0] - V[0, 0])
+        lmax = max(np.linalg.norm(V[a] - V[(a + 1) % 3]) for a in range(3))
+        if a2 <= 0.4 * lmax * lmax:
+            continue
+        x = rng.uniform(-0.12, 0.13, size=2)
+        dv = np.linalg.norm(V - x, axis=1)
+        if np.all(dv < d) or np.min(np.abs(dv - d)) < 1e-6:
+            continue
+        mom = _green_moments(x, V, d)
+        if mom[0] < 1e-12:
+            continue
+        ex0, ex1, ex2 = _beta_moments(x, V, mom)
+        s0, s1, s2 = oracle.inner_sums(op, x, V)
+        scale = 0.5 * a2
+        assert abs(s0 - ex0) < 2e-11 * scale, (s0, ex0)
+        assert np.max(np.abs(s1 - ex1)) < 2e-11 * scale, (s1, ex1)
+        gap = ex2 - s2
+        assert _psd_gap(gap) > -2e-11 * scale, gap
+        gaps += np.max(np.abs(gap)) > 1e-9 * scale
+        tested += 1
+    assert gaps > 10       # the centroid rule does lose second moments on most cut items
