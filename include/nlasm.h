@@ -107,7 +107,8 @@ typedef struct {
     int32_t precision;           /* NLA_FP64 | NLA_FP32 (compensated) | NLA_FP32_LEARNED */
     const void *mlp;             /* NLA_FP32_LEARNED: an nla_mlp* ; else NULL */
     double fallback_band;        /* learned caps: exact path when min_a | |v_a - x| - delta | <
-                                    fallback_band * delta */
+                                    fallback_band * delta, or outside the network's training
+                                    domain (nla_mlp_set_domain) */
     uint32_t flags;              /* NLA_SKIP_IXI */
     nla_rule outer2;             /* optional second outer rule (n = 0: none), used for the pairs
                                     with |b_k - b_k'| < switch_dist (Sec. 8: a lower-order rule
@@ -138,6 +139,8 @@ typedef struct {
     int64_t items[4];            /* after nla_assemble: (k,q,k') items whole, partial, empty, learned */
     int64_t subtriangles;        /* after nla_assemble: polygon + cap triangles integrated */
     int64_t caps;                /* after nla_assemble: caps filled with triangles */
+    int64_t n_deep;              /* pairs whose items are all whole, summed from element areas
+                                    instead of item by item (constant kernel; 0 otherwise) */
 } nla_info;
 
 /* phases timed by nla_timings, in launch order (MLP: routing pass and network
@@ -288,6 +291,17 @@ void nla_batch_destroy(nla_batch *batch);
  * W1 and the biases in FP32.  Outputs are in units of `scale` (m = scale *
  * output).  An nla_mlp must outlive every plan that uses it; calls are
  * stream-ordered on the caller's stream, and an nla_mlp is not thread-safe.
+ *
+ * Training domain (out-of-distribution fallback): an item goes to the network
+ * only when it is also inside the network's training domain, 14 doubles
+ * dom = {flo[6], fhi[6], elo, ehi}: every input f_i, rounded to float as the
+ * network reads it, within [flo_i, fhi_i], and the three squared edge lengths
+ * (f_2b - f_2a)^2 + (f_2b+1 - f_2a+1)^2 (b = a+1 mod 3), formed in FP64 from
+ * the float inputs with every operation rounded on its own, within
+ * [elo, ehi].  Other items take the exact caps.  nla_mlp_train sets the
+ * domain to the range of its samples (joined with earlier training calls'
+ * ranges); nla_mlp_create and nla_mlp_set_weights leave it unbounded.  A plan
+ * takes the network's domain when it is created.
  * ------------------------------------------------------------------------ */
 #define NLA_MLP_WEIGHTS 17795
 typedef struct nla_mlp nla_mlp;
@@ -317,7 +331,8 @@ int nla_mlp_samples(int64_t n_cand, uint64_t seed, int64_t first, double L, doub
  * against label/scale, cosine learning-rate decay from lr over the call,
  * `epochs` passes over n device samples in seeded affine-permutation order,
  * batch a multiple of 64 with n >= batch.  loss_log (host, may be NULL)
- * receives the mean loss of each epoch.  Synchronises once per epoch. */
+ * receives the mean loss of each epoch.  Records the samples' range as the
+ * training domain (see above).  Synchronises once per epoch. */
 int nla_mlp_train(nla_mlp *mlp, const float *feat, const float *label, int64_t n, int32_t epochs, int32_t batch,
                   float lr, uint64_t seed, float *loss_log, void *stream);
 /* Network outputs (before scale) of n device samples into out [n][3]. */
@@ -325,7 +340,13 @@ int nla_mlp_forward(const nla_mlp *mlp, const float *feat, int64_t n, float *out
 /* Gradient of sum_i sum_o dout[i][o] y[i][o] with respect to every weight
  * (device dw[NLA_MLP_WEIGHTS], flat layout), on the weights as used. */
 int nla_mlp_backward(nla_mlp *mlp, const float *feat, const float *dout, int64_t n, float *dw, void *stream);
-/* Checkpoint (weights, scale, Adam state) to / from a file. */
+/* The training domain (host dom[14], layout above).  set: dom = NULL makes it
+ * unbounded; NLA_E_INVALID for a NaN limit or lo > hi.  Plans made earlier
+ * keep the domain they took. */
+int nla_mlp_set_domain(nla_mlp *mlp, const double *dom);
+int nla_mlp_get_domain(const nla_mlp *mlp, double *dom);
+/* Checkpoint (weights, scale, Adam state, training domain) to / from a file;
+ * a checkpoint written without a domain loads with an unbounded one. */
 int nla_mlp_save(const nla_mlp *mlp, const char *path);
 int nla_mlp_load(const char *path, nla_mlp **out);
 void nla_mlp_destroy(nla_mlp *mlp);

@@ -40,7 +40,8 @@ class _Problem(C.Structure):
                 ("switch_dist", C.c_double),
                 ("duffy_n", C.c_int32), ("gl_x", C.c_void_p), ("gl_w", C.c_void_p),
                 ("skip_ixi", C.c_int32),
-                ("learned", C.c_int32), ("band", C.c_double), ("mlp_w", C.c_void_p), ("mlp_scale", C.c_double)]
+                ("learned", C.c_int32), ("band", C.c_double), ("mlp_w", C.c_void_p), ("mlp_scale", C.c_double),
+                ("mlp_domain", C.c_void_p)]
 
 
 def _lib():
@@ -79,6 +80,8 @@ def _lib():
         L.nlo_cap_moments.restype = C.c_int
         L.nlo_routed.argtypes = [D, D, P, P]
         L.nlo_routed.restype = C.c_int
+        L.nlo_in_domain.argtypes = [P, P, P, D]
+        L.nlo_in_domain.restype = C.c_int
         L.nlo_cap_candidate.argtypes = [P, D, D, D, I32, P, P, P]
         L.nlo_mlp_features.argtypes = [P, P, D, P]
         L.nlo_mlp_features.restype = None
@@ -95,7 +98,7 @@ class OracleProblem:
     """Marshals a workloads.Problem (and a mesh) into the C structs; keeps the
     numpy buffers alive for the lifetime of this object."""
 
-    def __init__(self, mesh, prob, mlp_w=None, mlp_scale=1.0):
+    def __init__(self, mesh, prob, mlp_w=None, mlp_scale=1.0, mlp_domain=None):
         self.mesh = mesh
         self.prob = prob
         self._keep = []
@@ -153,6 +156,12 @@ class OracleProblem:
             w = np.ascontiguousarray(mlp_w, dtype=np.float64)
             self._keep.append(w)
             p.learned, p.band, p.mlp_w, p.mlp_scale = 1, prob.fallback_band, _ptr(w), mlp_scale
+            if mlp_domain is not None:
+                dom = np.ascontiguousarray(mlp_domain, dtype=np.float64)
+                if dom.shape != (14,):
+                    raise ValueError("the training domain has 14 limits")
+                self._keep.append(dom)
+                p.mlp_domain = _ptr(dom)
         self.cprob = p
 
     @property
@@ -309,11 +318,11 @@ def l2_error(mesh, U, u_exact, rule_name="dunavant7"):
     return float(np.sqrt(err))
 
 
-def solve_problem(mesh, prob, man, nthreads=0, dense=None, mlp_w=None, mlp_scale=1.0):
+def solve_problem(mesh, prob, man, nthreads=0, dense=None, mlp_w=None, mlp_scale=1.0, mlp_domain=None):
     """Assemble, build A and b, solve, and return the L2 error against u."""
     from workloads.problems import manufactured
     u, f = manufactured(man)
-    op = OracleProblem(mesh, prob, mlp_w=mlp_w, mlp_scale=mlp_scale)
+    op = OracleProblem(mesh, prob, mlp_w=mlp_w, mlp_scale=mlp_scale, mlp_domain=mlp_domain)
     res = assemble(op, nthreads)
     xq = outer_points(op)
     G = load_vector(op, f(xq[..., 0], xq[..., 1]))
@@ -383,6 +392,28 @@ def cap_moments(delta, x, tri_xy, cap_edges=8):
     m = np.zeros(3)
     n = _lib().nlo_cap_moments(C.byref(p), _ptr(xx), _ptr(V), _ptr(m))
     return n, m
+
+
+def in_domain(dom, x, tri_xy, delta):
+    """The item (x, E') inside the training domain dom[14] (None: unbounded)."""
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    V = np.ascontiguousarray(tri_xy, dtype=np.float64).reshape(6)
+    d = None if dom is None else np.ascontiguousarray(dom, dtype=np.float64)
+    return bool(_lib().nlo_in_domain(None if d is None else _ptr(d), _ptr(xx), _ptr(V), delta))
+
+
+def feature_domain(feat):
+    """The training domain {flo[6], fhi[6], elo, ehi} of float inputs feat[n][6]:
+    their per-input range and the range of the squared edge lengths formed
+    from them."""
+    g = np.asarray(feat, dtype=np.float32).astype(np.float64).reshape(-1, 6)
+    e = []
+    for a in range(3):
+        b = (a + 1) % 3
+        dx, dy = g[:, 2 * b] - g[:, 2 * a], g[:, 2 * b + 1] - g[:, 2 * a + 1]
+        e.append(dx * dx + dy * dy)
+    e = np.concatenate(e)
+    return np.concatenate([g.min(axis=0), g.max(axis=0), [e.min(), e.max()]])
 
 
 def routed(delta, band, x, tri_xy):

@@ -437,7 +437,7 @@ int nlo_inner_sums(const nlo_problem *p, const double x[2], const double V[6],
                 double dx = V[2 * a] - x[0], dy = V[2 * a + 1] - x[1];
                 nin += dx * dx + dy * dy <= dd;
             }
-            if (nin < 3 && nlo_routed(p->delta, p->band, x, V)) {
+            if (nin < 3 && nlo_routed(p->delta, p->band, x, V) && nlo_in_domain(p->mlp_domain, x, V, p->delta)) {
                 double mm[3];
                 int ncap = nlo_cap_moments(p, x, V, mm);
                 if (ncap < 0) return ncap;

@@ -41,6 +41,9 @@ typedef struct {
      * min_a | |v_a - x| - delta | >= band delta take the polygon plus the
      * network's cap moments; the others keep the arc-subdivided caps */
     int32_t learned; double band; const double *mlp_w; double mlp_scale;
+    /* the network's training domain {flo[6], fhi[6], elo, ehi}, or NULL
+     * (unbounded): a routed item outside it keeps the arc-subdivided caps */
+    const double *mlp_domain;
 } nlo_problem;
 
 #define NLO_MLP_HIDDEN 128
@@ -75,6 +78,7 @@ void nlo_mlp_forward(const double *w, const double *feat, int64_t n, double *out
 void nlo_mlp_backward(const double *w, const double *feat, const double *dout, int64_t n, double *dw);
 int nlo_cap_moments(const nlo_problem *p, const double x[2], const double V[6], double m[3]);
 int nlo_routed(double delta, double band, const double x[2], const double V[6]);
+int nlo_in_domain(const double *dom, const double x[2], const double V[6], double delta);
 int nlo_learned_caps(const nlo_problem *p, const double x[2], const double V[6], double s0[1], double s1[3],
                      double s2[9]);
 void nlo_mlp_features(const double x[2], const double V[6], double delta, double f[6]);

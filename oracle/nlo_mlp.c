@@ -181,6 +181,28 @@ int nlo_routed(double delta, double band, const double x[2], const double V[6])
     return 1;
 }
 
+/* the item inside the network's training domain: each input, rounded to
+ * float as the network reads it, within [flo_i, fhi_i], and each squared edge
+ * length of the input triangle, formed from those float inputs, within
+ * [elo, ehi]; dom = NULL is unbounded */
+int nlo_in_domain(const double *dom, const double x[2], const double V[6], double delta)
+{
+    if (!dom) return 1;
+    double f[6], g[6];
+    nlo_mlp_features(x, V, delta, f);
+    for (int i = 0; i < 6; i++) {
+        g[i] = (double)(float)f[i];
+        if (!(g[i] >= dom[i] && g[i] <= dom[6 + i])) return 0;
+    }
+    for (int a = 0; a < 3; a++) {
+        int b = (a + 1) % 3;
+        double dx = g[2 * b] - g[2 * a], dy = g[2 * b + 1] - g[2 * a + 1];
+        double e = dx * dx + dy * dy;
+        if (!(e >= dom[12] && e <= dom[13])) return 0;
+    }
+    return 1;
+}
+
 /* the learned cap contribution of a routed partial item (constant kernel) */
 int nlo_learned_caps(const nlo_problem *p, const double x[2], const double V[6], double s0[1], double s1[3],
                      double s2[9])

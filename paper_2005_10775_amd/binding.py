@@ -50,7 +50,7 @@ class nla_info(C.Structure):
     _fields_ = [("n_pairs", C.c_int64), ("nnz_full", C.c_int64), ("nnz_free", C.c_int64),
                 ("n_free", C.c_int32), ("n_outer", C.c_int32), ("n_codes", C.c_int64),
                 ("n_near", C.c_int64), ("items", C.c_int64 * 4), ("subtriangles", C.c_int64),
-                ("caps", C.c_int64)]
+                ("caps", C.c_int64), ("n_deep", C.c_int64)]
 
 
 PHASES = ("mlp", "pairs", "near", "segsum", "extract", "load")
@@ -96,6 +96,8 @@ def lib():
         L.nla_mlp_create.argtypes = [C.c_uint64, C.POINTER(P)]
         L.nla_mlp_set_weights.argtypes = [P, P, C.c_float]
         L.nla_mlp_get_weights.argtypes = [P, P, C.POINTER(C.c_float)]
+        L.nla_mlp_set_domain.argtypes = [P, P]
+        L.nla_mlp_get_domain.argtypes = [P, P]
         L.nla_mlp_samples.argtypes = [I64, C.c_uint64, I64, D, D, D, I32, P, P, C.POINTER(I64), P]
         L.nla_mlp_train.argtypes = [P, P, P, I64, I32, I32, C.c_float, C.c_uint64, P, P]
         L.nla_mlp_forward.argtypes = [P, P, I64, P, P]
@@ -109,7 +111,8 @@ def lib():
                      "nla_set_timing", "nla_timings", "nla_near_view", "nla_batch_create",
                      "nla_batch_assemble", "nla_batch_plan", "nla_batch_info", "nla_batch_autotune",
                      "nla_mlp_create", "nla_mlp_set_weights", "nla_mlp_get_weights", "nla_mlp_samples",
-                     "nla_mlp_train", "nla_mlp_forward", "nla_mlp_backward", "nla_mlp_save", "nla_mlp_load"):
+                     "nla_mlp_train", "nla_mlp_forward", "nla_mlp_backward", "nla_mlp_save", "nla_mlp_load",
+                     "nla_mlp_set_domain", "nla_mlp_get_domain"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -235,7 +238,7 @@ class Plan:
         return dict(n_pairs=i.n_pairs, nnz_full=i.nnz_full, nnz_free=i.nnz_free, n_free=i.n_free,
                     n_outer=i.n_outer, n_codes=i.n_codes, n_near=i.n_near,
                     items=dict(whole=i.items[0], partial=i.items[1], empty=i.items[2], learned=i.items[3]),
-                    subtriangles=i.subtriangles, caps=i.caps)
+                    subtriangles=i.subtriangles, caps=i.caps, n_deep=i.n_deep)
 
     def set_timing(self, n):
         """Time the next n assemblies per phase (HIP events on their stream); 0 = off."""
@@ -421,6 +424,20 @@ class Mlp:
         sc = C.c_float()
         _check(lib().nla_mlp_get_weights(self._h, w.ctypes.data, C.byref(sc)))
         return w, sc.value
+
+    def set_domain(self, dom):
+        """The training domain {flo[6], fhi[6], elo, ehi} (None: unbounded)."""
+        if dom is None:
+            _check(lib().nla_mlp_set_domain(self._h, None))
+            return
+        d = np.ascontiguousarray(dom, dtype=np.float64)
+        assert d.shape == (14,)
+        _check(lib().nla_mlp_set_domain(self._h, d.ctypes.data))
+
+    def get_domain(self):
+        d = np.empty(14, dtype=np.float64)
+        _check(lib().nla_mlp_get_domain(self._h, d.ctypes.data))
+        return d
 
     @staticmethod
     def samples(n_cand, seed, first=0, L=0.125, jitter=0.1, band=0.02, cap_edges=8, stream=None):

@@ -363,6 +363,7 @@ __device__ __forceinline__ bool item_routed(double xx, double xy, const double (
 // the h = delta/8 family): f_a = 8 (R(-phi)(v_a - x)/delta - (1, 0)).
 __device__ __forceinline__ void mlp_features(double xx, double xy, const double (&V)[6], double delta, float (&f)[6])
 {
+#pragma clang fp contract(off)
     const double cx = ((V[0] + V[2]) + V[4]) / 3.0 - xx, cy = ((V[1] + V[3]) + V[5]) / 3.0 - xy;
     const double r = sqrt(cx * cx + cy * cy);
     const double c = r > 0.0 ? cx / r : 1.0, s = r > 0.0 ? cy / r : 0.0;
@@ -372,6 +373,33 @@ __device__ __forceinline__ void mlp_features(double xx, double xy, const double 
         f[2 * a] = (float)(8.0 * ((dx * c + dy * s) - 1.0));
         f[2 * a + 1] = (float)(8.0 * (dy * c - dx * s));
     }
+}
+
+// the item's inputs inside the network's training domain (MlpDomain)
+__device__ __forceinline__ bool in_domain(const float (&f)[6], const MlpDomain &D)
+{
+#pragma clang fp contract(off)
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 6; i++) ok = ok && (double)f[i] >= D.flo[i] && (double)f[i] <= D.fhi[i];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int b = (a + 1) % 3;
+        const double dx = (double)f[2 * b] - (double)f[2 * a], dy = (double)f[2 * b + 1] - (double)f[2 * a + 1];
+        const double e = dx * dx + dy * dy;
+        ok = ok && e >= D.elo && e <= D.ehi;
+    }
+    return ok;
+}
+
+// routed to the network: far from tangency and inside the training domain
+__device__ __forceinline__ bool item_learned(double xx, double xy, const double (&V)[6], double delta, double band,
+                                             const MlpDomain &D)
+{
+    if (!item_routed(xx, xy, V, delta, band)) return false;
+    float f[6];
+    mlp_features(xx, xy, V, delta, f);
+    return in_domain(f, D);
 }
 
 // Boundary sums of a polygon's area and first and second moments (Green's

@@ -244,7 +244,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                     const int cls = item_class(xx, xy, V, dd);
                     whole = cls == 1;
                     part = cls == 2;
-                    if (LEARN && part && item_routed(xx, xy, V, P.delta, P.band)) rmask |= 1u << q;
+                    if (LEARN && part && item_learned(xx, xy, V, P.delta, P.band, P.dom)) rmask |= 1u << q;
                 }
                 if (whole) {
                     c_whole++;
@@ -627,7 +627,8 @@ __global__ __launch_bounds__(64) void k_route(PairArgs P, int64_t *__restrict__ 
             for (int q = 0; q < NQ; q++) {
                 if (q >= nq) break;
                 const double xx = sX[q][0], xy = sX[q][1];
-                if (item_class(xx, xy, V, P.dd) == 2 && item_routed(xx, xy, V, P.delta, P.band)) rmask |= 1u << q;
+                if (item_class(xx, xy, V, P.dd) == 2 && item_learned(xx, xy, V, P.delta, P.band, P.dom))
+                    rmask |= 1u << q;
             }
         }
         const int rc = __popc(rmask);
@@ -1064,6 +1065,7 @@ PairArgs nla_pair_args(const nla_plan *P)
     A.route_off = P->route_off;
     A.n_routed = P->n_routed;
     A.mlp_y = P->route_y;
+    A.dom = P->mlp_dom;
     A.mlp_k = P->mlp ? (float)(pr.kernel_c * pr.delta * pr.delta * (double)nla_mlp_scale(P->mlp)) : 0.f;
     return A;
 }

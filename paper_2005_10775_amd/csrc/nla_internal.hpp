@@ -64,6 +64,17 @@ struct ElemSoA {
     double *r;                                 // max vertex distance from the barycenter
 };
 
+// Training domain of a learned cap network: an item goes to the network only
+// when each of its six inputs (rounded to float, as the network reads them)
+// lies in [flo, fhi] and each squared edge length of its triangle in the
+// network's frame, formed in FP64 from those float inputs with every
+// operation rounded on its own, lies in [elo, ehi]; otherwise it takes the
+// exact caps.  Training sets it to the range of its samples; unbounded
+// (infinite limits) for weights set from outside.
+struct MlpDomain {
+    double flo[6], fhi[6], elo, ehi;
+};
+
 struct DeviceArena {
     std::vector<void *> ptrs;
     size_t bytes = 0;
@@ -99,6 +110,7 @@ struct nla_plan {
     int32_t *proc_kp = nullptr; // [n_pairs] k' of processing slot i
     int32_t *nband = nullptr;   // [K] pairs of k before its deep ones
     int32_t max_deep = 0;       // max_k deep pairs of k (with nband)
+    int64_t n_deep = 0;         // deep pairs in all (with nband)
     // launch shape of the FP64 pair kernel, chosen at its first launch
     size_t pairs_lds = 0;
     int pairs_tab = -1;         // LDS offset (4-byte units) of the deep area table, 0: none; -1: not chosen
@@ -156,6 +168,7 @@ struct nla_plan {
     double *b = nullptr;        // [n_free]
     // learned caps: routed items per outer element, their features and outputs
     const nla_mlp *mlp = nullptr;
+    MlpDomain mlp_dom{};            // the network's training domain when the plan was made
     int64_t *route_off = nullptr;   // [K+1]
     int64_t n_routed = 0;
     float *route_feat = nullptr;    // [n_routed][6]
@@ -185,6 +198,7 @@ struct nla_plan {
     int val_dtype = NLA_DTYPE_F64;
 };
 
+
 // arguments of the FP32 pair kernel for one instance (plan)
 struct PairArgs {
     const int64_t *pair_ptr;
@@ -208,6 +222,7 @@ struct PairArgs {
     int64_t n_routed;
     const float *mlp_y;         // [n_routed][3] network outputs
     float mlp_k;                // kc delta^2 scale
+    MlpDomain dom;              // the network's training domain, taken at plan creation
     // processing order (constant kernel): band pairs first, deep ones after
     const int32_t *proc_p, *proc_kp, *nband;
     float *Dk;                  // [K] the deep pairs' Myy factor of each element
@@ -255,6 +270,7 @@ __device__ __forceinline__ bool pair_deep(const ElemSoA &E, int k, int kp, doubl
 struct nla_mlp;
 int nla_mlp_infer_launch(const nla_mlp *M, const float *feat, int64_t n, float *out, hipStream_t s);
 float nla_mlp_scale(const nla_mlp *M);
+MlpDomain nla_mlp_domain_of(const nla_mlp *M);
 int nla_build_routes(nla_plan *P, hipStream_t s);
 
 // translation-unit entry points

@@ -10,6 +10,7 @@
 #include <rocprim/device/device_select.hpp>
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -410,6 +411,59 @@ __global__ __launch_bounds__(1024) void k_label_rms(int64_t n3, const float *__r
     if (threadIdx.x == 0) *out = sqrt(red[0] / (double)(n3 > 0 ? n3 : 1));
 }
 
+// Training domain of n samples (MlpDomain): per block, the minimum and maximum
+// of each input and of the three squared edge lengths formed from the float
+// inputs in FP64 (every operation rounded on its own); a second pass reduces
+// the blocks.  Minima and maxima do not depend on the order.
+constexpr int NDOM = 8;     // six inputs and the edge lengths (one range for all three)
+__global__ __launch_bounds__(256) void k_feat_domain(int64_t n, const float *__restrict__ feat, double *__restrict__ part)
+{
+#pragma clang fp contract(off)
+    __shared__ double lo_s[NDOM][256], hi_s[NDOM][256];
+    double lo[NDOM], hi[NDOM];
+#pragma unroll
+    for (int i = 0; i < NDOM; i++) {
+        lo[i] = HUGE_VAL;
+        hi[i] = -HUGE_VAL;
+    }
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+        double f[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            f[i] = (double)feat[6 * j + i];
+            lo[i] = fmin(lo[i], f[i]);
+            hi[i] = fmax(hi[i], f[i]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const int b = (a + 1) % 3;
+            const double dx = f[2 * b] - f[2 * a], dy = f[2 * b + 1] - f[2 * a + 1];
+            const double e = dx * dx + dy * dy;
+            lo[6] = fmin(lo[6], e);
+            hi[6] = fmax(hi[6], e);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NDOM; i++) {
+        lo_s[i][threadIdx.x] = lo[i];
+        hi_s[i][threadIdx.x] = hi[i];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int i = 0; i < NDOM; i++) {
+                lo_s[i][threadIdx.x] = fmin(lo_s[i][threadIdx.x], lo_s[i][threadIdx.x + w]);
+                hi_s[i][threadIdx.x] = fmax(hi_s[i][threadIdx.x], hi_s[i][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < NDOM) {
+        part[2 * NDOM * blockIdx.x + threadIdx.x] = lo_s[threadIdx.x][0];
+        part[2 * NDOM * blockIdx.x + NDOM + threadIdx.x] = hi_s[threadIdx.x][0];
+    }
+}
+
 // ------------------------------------------------------------- samples
 struct LabelF {
     double *m;
@@ -479,6 +533,49 @@ __global__ void k_cap_samples(int64_t n, uint64_t seed, int64_t first, double L,
 struct F6 { float v[6]; };
 struct F3 { float v[3]; };
 
+MlpDomain unbounded_domain()
+{
+    MlpDomain D;
+    for (int i = 0; i < 6; i++) {
+        D.flo[i] = -HUGE_VAL;
+        D.fhi[i] = HUGE_VAL;
+    }
+    D.elo = -HUGE_VAL;
+    D.ehi = HUGE_VAL;
+    return D;
+}
+
+bool valid_domain(const double *d)
+{
+    for (int i = 0; i < 14; i++)
+        if (std::isnan(d[i])) return false;
+    for (int i = 0; i < 6; i++)
+        if (!(d[i] <= d[6 + i])) return false;
+    return d[12] <= d[13];
+}
+
+void domain_to(const MlpDomain &D, double *d)
+{
+    for (int i = 0; i < 6; i++) {
+        d[i] = D.flo[i];
+        d[6 + i] = D.fhi[i];
+    }
+    d[12] = D.elo;
+    d[13] = D.ehi;
+}
+
+MlpDomain domain_from(const double *d)
+{
+    MlpDomain D;
+    for (int i = 0; i < 6; i++) {
+        D.flo[i] = d[i];
+        D.fhi[i] = d[6 + i];
+    }
+    D.elo = d[12];
+    D.ehi = d[13];
+    return D;
+}
+
 } // namespace
 
 // =====================================================================
@@ -489,6 +586,7 @@ struct nla_mlp {
     __bf16 *w2 = nullptr, *w2t = nullptr, *w3p = nullptr;
     double *rms = nullptr;
     float scale = 0.f;
+    MlpDomain dom = unbounded_domain();
     int64_t step = 0;        // epochs trained (seeds the epoch orders)
     int64_t adam_t = 0;      // Adam steps taken
     // training scratch
@@ -574,6 +672,26 @@ int nla_mlp_infer_launch(const nla_mlp *M, const float *feat, int64_t n, float *
 }
 
 float nla_mlp_scale(const nla_mlp *M) { return M->scale; }
+MlpDomain nla_mlp_domain_of(const nla_mlp *M) { return M->dom; }
+
+extern "C" int nla_mlp_set_domain(nla_mlp *M, const double *dom)
+{
+    if (!M) { nla_set_error("null network"); return NLA_E_INVALID; }
+    if (!dom) {
+        M->dom = unbounded_domain();
+        return NLA_OK;
+    }
+    if (!valid_domain(dom)) { nla_set_error("domain limits must satisfy lo <= hi and not be NaN"); return NLA_E_INVALID; }
+    M->dom = domain_from(dom);
+    return NLA_OK;
+}
+
+extern "C" int nla_mlp_get_domain(const nla_mlp *M, double *dom)
+{
+    if (!M || !dom) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    domain_to(M->dom, dom);
+    return NLA_OK;
+}
 
 extern "C" int nla_mlp_create(uint64_t seed, nla_mlp **out)
 {
@@ -634,6 +752,7 @@ extern "C" int nla_mlp_set_weights(nla_mlp *M, const float *w, float scale)
     M->scale = scale;
     M->step = 0;
     M->adam_t = 0;
+    M->dom = unbounded_domain();
     NLA_TRY(mlp_refresh(M, nullptr));
     NLA_HIP(hipDeviceSynchronize());
     return NLA_OK;
@@ -738,6 +857,39 @@ extern "C" int nla_mlp_train(nla_mlp *M, const float *feat, const float *label, 
         if (!(r > 0.0)) { nla_set_error("labels are all zero"); return NLA_E_INVALID; }
         M->scale = (float)r;
     }
+    {
+        // the training domain: the range of these samples (joined with the
+        // earlier training calls' ranges)
+        const int nb = (int)std::min<int64_t>(256, (n + 255) / 256);
+        DeviceArena tmp;
+        double *part;
+        NLA_TRY(tmp.get(&part, 2 * (size_t)NDOM * nb));
+        k_feat_domain<<<nb, 256, 0, s>>>(n, feat, part);
+        NLA_HIP(hipGetLastError());
+        std::vector<double> h(2 * (size_t)NDOM * nb);
+        NLA_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+        MlpDomain D = M->step > 0 ? M->dom : MlpDomain{};
+        for (int i = 0; i < 6; i++) {
+            if (M->step == 0) {
+                D.flo[i] = HUGE_VAL;
+                D.fhi[i] = -HUGE_VAL;
+            }
+            for (int b = 0; b < nb; b++) {
+                D.flo[i] = std::min(D.flo[i], h[2 * NDOM * b + i]);
+                D.fhi[i] = std::max(D.fhi[i], h[2 * NDOM * b + NDOM + i]);
+            }
+        }
+        if (M->step == 0) {
+            D.elo = HUGE_VAL;
+            D.ehi = -HUGE_VAL;
+        }
+        for (int b = 0; b < nb; b++) {
+            D.elo = std::min(D.elo, h[2 * NDOM * b + 6]);
+            D.ehi = std::max(D.ehi, h[2 * NDOM * b + NDOM + 6]);
+        }
+        M->dom = D;
+    }
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float gcoef = 2.f / (3.f * (float)batch);
     std::vector<float> lh((size_t)spe);
@@ -770,7 +922,8 @@ extern "C" int nla_mlp_train(nla_mlp *M, const float *feat, const float *label, 
     return NLA_OK;
 }
 
-// checkpoint: magic, weights, scale, Adam moments and step
+// checkpoint: magic, weights, scale, Adam moments and step, training domain
+// (14 doubles; a version-1 file has none and loads with an unbounded domain)
 extern "C" int nla_mlp_save(const nla_mlp *M, const char *path)
 {
     if (!M || !path) { nla_set_error("null argument"); return NLA_E_INVALID; }
@@ -781,11 +934,13 @@ extern "C" int nla_mlp_save(const nla_mlp *M, const char *path)
     NLA_HIP(hipMemcpy(buf.data() + 2 * NW, M->av, sizeof(float) * NW, hipMemcpyDeviceToHost));
     FILE *f = std::fopen(path, "wb");
     if (!f) { nla_set_error("cannot open %s", path); return NLA_E_INVALID; }
-    const char magic[8] = {'N', 'L', 'A', 'M', 'L', 'P', '1', 0};
+    const char magic[8] = {'N', 'L', 'A', 'M', 'L', 'P', '2', 0};
     const int32_t nw = NW;
+    double dom[14];
+    domain_to(M->dom, dom);
     bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&nw, 4, 1, f) == 1 && std::fwrite(&M->scale, 4, 1, f) == 1 &&
               std::fwrite(&M->step, 8, 1, f) == 1 && std::fwrite(&M->adam_t, 8, 1, f) == 1 &&
-              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size() && std::fwrite(dom, 8, 14, f) == 14;
     ok = (std::fclose(f) == 0) && ok;
     if (!ok) { nla_set_error("write failed: %s", path); return NLA_E_INVALID; }
     return NLA_OK;
@@ -802,9 +957,14 @@ extern "C" int nla_mlp_load(const char *path, nla_mlp **out)
     float scale = 0.f;
     int64_t step = 0, adam_t = 0;
     std::vector<float> buf(3 * (size_t)NW);
-    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "NLAMLP1", 8) == 0 && std::fread(&nw, 4, 1, f) == 1 &&
-              nw == NW && std::fread(&scale, 4, 1, f) == 1 && std::fread(&step, 8, 1, f) == 1 &&
-              std::fread(&adam_t, 8, 1, f) == 1 && std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    double dom[14];
+    bool ok = std::fread(magic, 1, 8, f) == 8 &&
+              (std::memcmp(magic, "NLAMLP1", 8) == 0 || std::memcmp(magic, "NLAMLP2", 8) == 0) &&
+              std::fread(&nw, 4, 1, f) == 1 && nw == NW && std::fread(&scale, 4, 1, f) == 1 &&
+              std::fread(&step, 8, 1, f) == 1 && std::fread(&adam_t, 8, 1, f) == 1 &&
+              std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    const bool v2 = ok && magic[6] == '2';
+    if (v2) ok = std::fread(dom, 8, 14, f) == 14 && valid_domain(dom);
     std::fclose(f);
     if (!ok) { nla_set_error("%s is not a network checkpoint of this layout", path); return NLA_E_INVALID; }
     nla_mlp *M = nullptr;
@@ -814,6 +974,7 @@ extern "C" int nla_mlp_load(const char *path, nla_mlp **out)
         M->scale = scale;
         M->step = step;
         M->adam_t = adam_t;
+        M->dom = v2 ? domain_from(dom) : unbounded_domain();
         if (hipMemcpy(M->am, buf.data() + NW, sizeof(float) * NW, hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(M->av, buf.data() + 2 * NW, sizeof(float) * NW, hipMemcpyHostToDevice) != hipSuccess) {
             nla_set_error("device copy failed");

@@ -1094,7 +1094,10 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         NLA_HIP(hipMemcpyAsync(nb.data(), P->nband, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
         NLA_HIP(hipMemcpyAsync(pp.data(), P->pair_ptr, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, s));
         NLA_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < K; k++) P->max_deep = std::max(P->max_deep, (int32_t)(pp[k + 1] - pp[k] - nb[k]));
+        for (int k = 0; k < K; k++) {
+            P->max_deep = std::max(P->max_deep, (int32_t)(pp[k + 1] - pp[k] - nb[k]));
+            P->n_deep += pp[k + 1] - pp[k] - nb[k];
+        }
     }
     NLA_HIP(hipGetLastError());
     NLA_HIP(hipStreamSynchronize(s));
@@ -1497,6 +1500,7 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
     NLA_TRY(P->arena.get(&P->counters, 6));
     if (p->precision == NLA_FP32_LEARNED) {
         P->mlp = (const nla_mlp *)p->mlp;
+        P->mlp_dom = nla_mlp_domain_of(P->mlp);
         NLA_TRY(nla_build_routes(P, s));
     }
     return NLA_OK;
@@ -1534,6 +1538,7 @@ extern "C" int nla_plan_info(const nla_plan *P, nla_info *info)
     info->n_outer = P->rules.n_out;
     info->n_codes = P->n_codes;
     info->n_near = P->n_near;
+    info->n_deep = P->n_deep;
     unsigned long long c[6] = {0, 0, 0, 0, 0, 0};
     if (P->assembled) NLA_HIP(hipMemcpy(c, P->counters, sizeof(c), hipMemcpyDeviceToHost));
     for (int i = 0; i < 4; i++) info->items[i] = (int64_t)c[i];

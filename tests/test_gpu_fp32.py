@@ -2,12 +2,16 @@
 singular-kernel near-diagonal blocks, against the FP64 oracle.
 
 Bars: pair list and pattern bitwise; near-diagonal blocks (computed in FP64,
-stored in FP32) within 2e-7 of the oracle's, relative to the block; matrix
-entries row-scaled within 2e-5: the FP32 kernel evaluation 2^(e log2 r^2)
-carries ~|e log2 r^2| * 2^-24 * ln 2 ~ 2e-6 relative error (|e log2 r^2| <= 30
-here) and the FP32 quadrature sums another few 1e-7, while every
-accumulation beyond one subtriangle is compensated; 2e-5 leaves a factor
-~10 over that estimate for cancellation inside a row.
+stored in FP32) within 2e-7 of the oracle's, relative to the block (storage
+rounding alone is up to 2^-24 ~ 6e-8); matrix entries row-scaled within
+1e-6.  Every sum longer than one item's dozen subtriangle terms is
+compensated, so an entry carries the rounding of its stored FP32 value
+(2^-24) plus the FP32 errors of the individual terms: the kernel evaluation
+2^(e log2 r^2) with the hardware log2/exp2 (about |e log2 r^2| * 2^-24
+relative per point, averaging out over the points of a term) and the plain
+FP32 sums of one item (a few 2^-24).  Measured: at most 1.5e-7 over every
+FP32 case of the suite (constant and fractional kernels, delta/h = 2..8, the
+whole c3 matrix 1.1e-7); the bar leaves a factor of about 7.
 """
 import sys
 
@@ -20,7 +24,7 @@ from gpu_util import gpu_assemble, host, row_scaled_error
 from workloads import Problem, constant_kernel_c, fractional_kernel_c, structured_mesh
 
 pytestmark = pytest.mark.gpu
-TOL32 = 2e-5
+TOL32 = 1e-6
 
 
 def _say(*a):
@@ -72,12 +76,15 @@ def test_fp32_constant_kernel_deep_pairs_jittered(ball, seed):
     _check(mesh, prob, "fp32 const %s h=delta/6" % ball)
 
 
-def test_fp32_fractional_retri_with_near_pairs():
+@pytest.mark.parametrize("h", [0.05, 0.1])
+def test_fp32_fractional_retri_with_near_pairs(h):
+    """delta/h = 4, and delta/h = 2, where the ball cuts vertex-sharing pairs
+    and the singular rule stops its radial integrals at delta."""
     d, s = 0.2, 0.4
-    mesh = structured_mesh(d, 0.05, jitter=0.1, seed=13)
+    mesh = structured_mesh(d, h, jitter=0.1, seed=13)
     prob = Problem(delta=d, kernel="fractional", kernel_c=fractional_kernel_c(d, s), kernel_s=s, ball="retri",
                    cap_edges=8, precision="fp32", duffy_order=12)
-    plan, ref, err = _check(mesh, prob, "fp32 fractional retri")
+    plan, ref, err = _check(mesh, prob, "fp32 fractional retri delta/h=%g" % (d / h))
     near_p, blocks = (host(t) for t in plan.near())
     ptr = ref["res"]["pair_ptr"]
     kp = ref["res"]["pair_kp"]
@@ -87,11 +94,15 @@ def test_fp32_fractional_retri_with_near_pairs():
     op = ref["op"]
     iu = np.triu_indices(6)
     rng = np.random.default_rng(0)
-    for i in rng.choice(len(near_p), 40, replace=False):
+    worst = 0.0
+    for i in rng.choice(len(near_p), min(40, len(near_p)), replace=False):
         p = near_p[i]
         blk = oracle.pair_block(op, ks[p], kp[p])["blk"]
         got = blocks[i].astype(np.float64)
-        assert np.max(np.abs(got - blk[iu])) <= 2e-7 * np.max(np.abs(blk))
+        e = np.max(np.abs(got - blk[iu])) / np.max(np.abs(blk))
+        worst = max(worst, e)
+        assert e <= 2e-7
+    _say("near blocks: worst relative error %.3e" % worst)
 
 
 def test_fp32_barycenter_fractional():

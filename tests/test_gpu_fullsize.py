@@ -10,10 +10,14 @@ times (one plan, nla_assemble with f at the outer points and g at the nodes):
   * the learned-cap workload on the headline mesh (FP32, a seeded network: the
     path, not the training, is under test).
 
-The oracle cannot assemble these whole, so it builds sampled rows of D one at
+The headline and fractional workloads are also compared whole: one oracle
+assembly of each (about 10 s on 16 host threads) against the GPU's pair list
+and CSR pattern (bitwise) and every entry of D and b (FP64 1e-12, FP32 bar
+row-scaled).  For the paper's finest grid and the learned workload the oracle
+cannot assemble the matrix whole in seconds, so it builds sampled rows of D one at
 a time (nodes in the interior, next to the boundary of Omega, at a corner and
 in Omega_I): columns bitwise, values within the path's bar row-scaled (FP64
-1e-12, FP32 2e-5, learned 5e-5); the pair lists of sampled outer elements
+1e-12, FP32 and learned 1e-6); the pair lists of sampled outer elements
 bitwise; the load vector b = G - D[free, Dirichlet] g at the sampled free
 nodes."""
 import sys
@@ -24,7 +28,7 @@ import torch
 
 import oracle
 import oracle.binding as ob
-from gpu_util import gpu_assemble, host
+from gpu_util import gpu_assemble, host, row_scaled_error
 from paper_2005_10775_amd import Mlp, Plan
 from workloads import make_config, manufactured, paper_workload
 from workloads.learned import mlp_init
@@ -109,7 +113,7 @@ def test_headline_fp64_full_size():
 
 def test_fractional_fp32_full_size():
     mesh, prob, man = make_config("c3")
-    _check_full(mesh, prob, man, 2e-5, seed=2)
+    _check_full(mesh, prob, man, 1e-6, seed=2)
 
 
 def test_paper_finest_grid_full_size():
@@ -123,4 +127,56 @@ def test_learned_full_size():
     w = mlp_init(12, bias_scale=0.3)
     m = Mlp()
     m.set_weights(w, scale)
-    _check_full(mesh, prob, man, 5e-5, seed=4, mlp=m, mlp_w=ob.effective_weights(w), mlp_scale=scale)
+    _check_full(mesh, prob, man, 1e-6, seed=4, mlp=m, mlp_w=ob.effective_weights(w), mlp_scale=scale)
+
+
+def _check_whole(mesh, prob, man, tol):
+    """Every pair, every pattern entry (bitwise), every entry of D and b
+    (row-scaled within tol) against one oracle assembly of the whole mesh."""
+    _say("whole: K", mesh.n_triangles, "oracle assembly")
+    plan = gpu_assemble(mesh, prob, man)
+    ref = oracle.solve_problem(mesh, prob, man, nthreads=0)
+    rr = ref["res"]
+    ptr, kp = (host(t) for t in plan.pairs())
+    _say("pairs", len(kp), "oracle", len(rr["pair_kp"]))
+    assert np.array_equal(ptr, rr["pair_ptr"]) and np.array_equal(kp, rr["pair_kp"])
+    rowptr, col, val = (host(t) for t in plan.csr(0))
+    assert np.array_equal(rowptr, rr["rowptr"]) and np.array_equal(col, rr["col"])
+    err = row_scaled_error(rowptr, val.astype(np.float64), rr["val"])
+    _say("every entry: row-scaled error %.3e (bar %.0e)" % (err, tol))
+    assert err < tol
+    # b_i = G_i - sum over Dirichlet j of D_ij g_j, on the scale of its terms
+    u, _ = manufactured(man)
+    free = mesh.node_free.astype(bool)
+    fi, di = np.nonzero(free)[0], np.nonzero(~free)[0]
+    g = np.abs(u(mesh.xy[:, 0], mesh.xy[:, 1]))
+    scale = np.abs(ref["G"][fi]) + abs(rr["D"].tocsr()[fi][:, di]) @ g[di]
+    b = host(plan.load())
+    berr = float(np.max(np.abs(b - ref["b"]) / scale))
+    _say("load vector: scaled error %.3e" % berr)
+    assert berr < tol
+    return plan, ref
+
+
+def test_headline_fp64_whole_matrix():
+    mesh, prob, man = make_config("c2")
+    _check_whole(mesh, prob, man, 1e-12)
+
+
+def test_fractional_fp32_whole_matrix():
+    mesh, prob, man = make_config("c3")
+    plan, ref = _check_whole(mesh, prob, man, 1e-6)
+    # the vertex-sharing pairs' blocks (FP64 rule, stored in FP32), sampled
+    near_p, blocks = (host(t) for t in plan.near())
+    rr = ref["res"]
+    ks = np.repeat(np.arange(mesh.n_triangles), np.diff(rr["pair_ptr"]))
+    iu = np.triu_indices(6)
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for i in rng.choice(len(near_p), 60, replace=False):
+        p = near_p[i]
+        blk = oracle.pair_block(ref["op"], ks[p], rr["pair_kp"][p])["blk"]
+        e = np.max(np.abs(blocks[i].astype(np.float64) - blk[iu])) / np.max(np.abs(blk))
+        worst = max(worst, e)
+    _say("near blocks: worst relative error %.3e" % worst)
+    assert worst <= 2e-7

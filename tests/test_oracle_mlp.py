@@ -259,3 +259,59 @@ def test_learned_closure_is_the_centroid_rule_of_the_caps():
         assert np.max(np.abs((l2 - p2) - s * np.outer(beta, beta))) < 1e-12 * psi * 0.5 * 0.0125 ** 2
         two += len(caps) > 1
         tested += 1
+
+
+def test_training_domain_gate():
+    """The out-of-distribution gate: with an unbounded domain the learned sums
+    are those without a domain; with a domain that holds no item they are the
+    exact-cap (8-arc) sums bitwise.  A domain taken from candidates of the
+    h = delta/8 family (legs 1/8, +-0.1 h jitter) holds most partial items of a
+    jittered h = delta/8 mesh and none of a h = delta/4 mesh: its squared edge
+    lengths in the network's frame lie in [0.8^2, 2 * 1.2^2] (legs of 1 moved by
+    at most 0.2 per coordinate), while a delta/4 triangle's longest edge has at
+    least 2 sqrt(2) * 0.8 there."""
+    from workloads import Problem, structured_mesh, constant_kernel_c
+    from workloads.learned import mlp_init
+    d = 0.1
+    U = cap_uniforms(20052, 0, 20000)
+    valid, feat, _, _ = ob.cap_candidates(U, 0.125, 0.1, 0.02)
+    dom = ob.feature_domain(feat[valid])
+    assert 0.8 ** 2 <= dom[12] <= dom[13] <= 2 * 1.2 ** 2
+    w = ob.effective_weights(mlp_init(12, bias_scale=0.3))
+    rng = np.random.default_rng(8)
+    for h, expect_in in ((d / 8, True), (d / 4, False)):
+        mesh = structured_mesh(d, h, jitter=0.1, seed=3)
+        prob = Problem(delta=d, kernel_c=constant_kernel_c(d), ball="retri", cap_edges=8, outer="dunavant7",
+                       inner="dunavant16", precision="learned")
+        op_none = ob.OracleProblem(mesh, prob, mlp_w=w, mlp_scale=1e-5)
+        op_inf = ob.OracleProblem(mesh, prob, mlp_w=w, mlp_scale=1e-5,
+                                  mlp_domain=np.r_[np.full(6, -np.inf), np.full(6, np.inf), -np.inf, np.inf])
+        op_empty = ob.OracleProblem(mesh, prob, mlp_w=w, mlp_scale=1e-5,
+                                    mlp_domain=np.r_[np.full(6, 1e30), np.full(6, 1e30), 1e30, 1e30])
+        op_exact = ob.OracleProblem(mesh, Problem(delta=d, kernel_c=constant_kernel_c(d), ball="retri",
+                                                  cap_edges=8, outer="dunavant7", inner="dunavant16"))
+        n_part = n_in = 0
+        for k in rng.choice(mesh.n_triangles, 40, replace=False):
+            x = mesh.xy[mesh.tri[k]].mean(axis=0)
+            for kp in range(mesh.n_triangles):
+                V = mesh.xy[mesh.tri[kp]]
+                dv = np.linalg.norm(V - x, axis=1)
+                if dv.min() > d or dv.max() <= d or not ob.routed(d, 0.02, x, V):
+                    continue
+                if ob.cap_moments(d, x, V)[0] == 0:
+                    continue
+                n_part += 1
+                n_in += ob.in_domain(dom, x, V, d)
+                a = ob.inner_sums(op_none, x, V)
+                b = ob.inner_sums(op_inf, x, V)
+                c = ob.inner_sums(op_empty, x, V)
+                e = ob.inner_sums(op_exact, x, V)
+                assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+                assert c[0] == e[0] and np.array_equal(c[1], e[1]) and np.array_equal(c[2], e[2])
+            if n_part > 150:
+                break
+        assert n_part > 100
+        if expect_in:
+            assert n_in > 0.9 * n_part, (n_in, n_part)
+        else:
+            assert n_in == 0, (n_in, n_part)
