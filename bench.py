@@ -4,9 +4,13 @@ One step = one nla_assemble (pair quadrature, segmented sum into the CSR of
 D, extraction of A, load vector) of the 8-arc-cap retriangulated-ball
 workload on the jittered h = delta/8 mesh (delta = 0.1, constant kernel,
 7-point outer x 16-point inner rules, FP64), inputs resident on the GPU.
-Prints one JSON line.
+The same line carries the learned-cap comparison on that mesh (network
+trained on the GPU first, outside the timed region): FP32 learned-cap
+assembly time against this FP64 exact-cap time, and the solutions' L2
+differences.  Prints one JSON line.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-learned]
+       [--config c2|c3|c4|c5|paper]
 """
 import argparse
 import hashlib
@@ -22,7 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "element-pair quadratures/s + assembly time, learned/FP32 vs FP64 plain at L2 err"
-FP64_PEAK_TFLOPS = 78.6   # MI355X vector FP64
+FP64_PEAK_TFLOPS = 78.6    # MI355X vector FP64 (published)
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (published; packed FP32, which this build does not use)
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix cores (published, no sparsity)
+LEARNED_TARGET_SPEEDUP = 3.0
+LEARNED_TARGET_L2 = 1e-4
 
 # Algorithmic FP64 operations of the pair kernel per unit of work (counted
 # from the arithmetic the method needs per unit; an FMA counts 2, sqrt, div
@@ -45,12 +53,58 @@ COST_BOUNDARY = dict(item=15, whole=6,
                      pair=45)
 
 
-def algorithmic_flops(info, n_pairs, ncap, cost=COST):
+# A deep pair (every item whole, R35) is not classified item by item in the
+# pair kernel: the plan's vertex-distance test selects it and the kernel adds
+# its inner element's area into the element sum and into the row-block
+# columns of its three nodes.
+COST_DEEP_PAIR = 4
+
+
+def algorithmic_flops(info, n_pairs, ncap, cost=COST, nq=7):
+    """Work of the pair kernel per launch: the per-unit costs above times the
+    plan's counters.  Deep pairs count COST_DEEP_PAIR each instead of their
+    items' classification (their items appear in the whole count)."""
+    it = info["items"]
+    n_deep = info.get("n_deep", 0)
+    whole = it["whole"] - n_deep * nq
+    items = whole + it["partial"] + it["empty"]
+    return (cost["item"] * items + cost["whole"] * whole + cost["partial"] * it["partial"] +
+            cost["subtriangle"] * info["subtriangles"] + cost["cap"] * info["caps"] +
+            cost["arc_point"] * info["caps"] * max(ncap - 1, 0) + cost["pair"] * (n_pairs - n_deep) +
+            COST_DEEP_PAIR * n_deep)
+
+
+def method_point_flops(info, n_in, ncap):
+    """The method's work with every region retriangulated and every partial
+    subtriangle integrated point by point (the per-unit costs of the method:
+    15 flops to classify an item and 31 to accumulate it; a partial item's
+    polygon walk 66; a cap's arc points 14 each; a subtriangle 10 plus 40 per
+    inner point; whole items by their closed form, 0 per point).  With a rule
+    exact for quadratics and the constant kernel the pair kernel integrates
+    the same regions through their boundaries (R27), which needs a fraction of
+    this: the ratio of the two is how much the boundary form saves.  The
+    subtriangle count follows from the kernel's counters: a partial item with
+    n polygon vertices and c caps has n - 2 + ncap c subtriangles and
+    n - c + ncap c boundary segments."""
     it = info["items"]
     items = it["whole"] + it["partial"] + it["empty"]
-    return (cost["item"] * items + cost["whole"] * it["whole"] + cost["partial"] * it["partial"] +
-            cost["subtriangle"] * info["subtriangles"] + cost["cap"] * info["caps"] +
-            cost["arc_point"] * info["caps"] * max(ncap - 1, 0) + cost["pair"] * n_pairs)
+    subtri = info["subtriangles"] + info["caps"] - 2 * it["partial"]
+    return 46 * items + 66 * it["partial"] + 14 * ncap * info["caps"] + (10 + 40 * n_in) * subtri
+
+
+def fp32_point_flops(info, n_pairs, n_in, ncap, frac):
+    """FP32 pair kernel with the point rule (fractional kernel): per inner point
+    61 flops (map 12, basis 18, distance 3, weight 3, sums 25) and, with the
+    fractional kernel, 2 transcendentals (log2, exp2); per subtriangle 20 set-up
+    flops; whole items integrate all of E_k' by the rule; classification 15
+    and accumulation 30 per item; polygon walk 114; cap 30 + 16 per arc point;
+    pair 45.  Returns (flops, transcendentals)."""
+    it = info["items"]
+    items = it["whole"] + it["partial"] + it["empty"]
+    tris = it["whole"] + info["subtriangles"]
+    flops = (15 * items + 30 * (it["whole"] + it["partial"]) + 114 * it["partial"] + (20 + 61 * n_in) * tris +
+             (30 + 16 * max(ncap - 1, 0)) * info["caps"] + 45 * n_pairs)
+    return flops, (2 * n_in * tris if frac else 0)
 
 
 def l2_error(mesh, U, u_exact):
@@ -94,26 +148,57 @@ def traffic_from_profile(kernel, digest):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(mesh, prob, sample_elems):
-    """The FP64 oracle timed on a bounded sample of outer elements (all their
-    pairs: search + local blocks), on this host's cores."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads():
+    """Threads this job may use on the host: the cores it is bound to, capped
+    by OMP_NUM_THREADS when that is set (the host's share for this job)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_baseline(mesh, prob, sample_elems, sample_elems_1t):
+    """The FP64 oracle (pair search by an all-pairs loop with a conservative
+    reject, then every pair's local blocks) timed on a bounded sample of outer
+    elements with all their pairs: on every thread this job may use, and on
+    one thread over a smaller sample."""
     import oracle
     oracle.build(force=False)
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
     op = oracle.OracleProblem(mesh, prob)
     K = mesh.n_triangles
-    n = min(sample_elems, K)
-    k0 = (K - n) // 2            # a band of whole mesh rows through the middle (layer and Omega)
-    t0 = time.perf_counter()
-    total, _ = oracle.blocks_range(op, k0, k0 + n, cores)
-    dt = time.perf_counter() - t0
-    return {"value": total / dt, "unit": "pairs/s", "cores": cores, "kind": "oracle",
-            "sample": "outer elements [%d, %d) of %d with all their pairs (%d pairs), %.2f s wall" % (
-                k0, k0 + n, K, total, dt)}
+    threads = _host_threads()
+
+    def run(n, nthreads):
+        n = min(n, K)
+        k0 = (K - n) // 2        # a band of whole mesh rows through the middle (layer and Omega)
+        t0 = time.perf_counter()
+        total, _ = oracle.blocks_range(op, k0, k0 + n, nthreads)
+        dt = time.perf_counter() - t0
+        return total / dt, "outer elements [%d, %d) of %d with all their pairs (%d pairs), %.2f s wall" % (
+            k0, k0 + n, K, total, dt)
+
+    v1, s1 = run(sample_elems_1t, 1)
+    vn, sn = run(sample_elems, threads)
+    return {"value": vn, "unit": "pairs/s", "cores": threads, "kind": "oracle", "sample": sn,
+            "single_thread": {"value": v1, "sample": s1},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "what": "pair search + local blocks (no CSR merge), FP64, gcc -O2 -ffp-contract=off, OpenMP over "
+                    "outer elements"}
 
 
 def bench_batch(args):
@@ -151,6 +236,25 @@ def bench_batch(args):
     ms = timed(1)
     ms_seq = timed(0)
     info = b.info()
+    # work of the regular pairs over all instances (each plan's counters); the
+    # batched step also integrates the singular pairs, so this fraction of the
+    # FP32 peak is a lower bound for the pair kernels
+    from workloads import get_rule
+    flops = trans = 0
+    for (mesh, prob), plan in zip(b.instances, b.plans):
+        pi = plan.info()
+        ncap = prob.cap_edges if prob.ball == "retri" else 0
+        if prob.kernel == "fractional":
+            fl, tr = fp32_point_flops(pi, pi["n_pairs"], get_rule(prob.inner).n, ncap, True)
+        else:
+            fl, tr = algorithmic_flops(pi, pi["n_pairs"], ncap, COST, get_rule(prob.outer).n), 0
+        flops += fl
+        trans += tr
+    ach = flops / (ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "whole batched step (pair kernels + singular pairs + sums)",
+                "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                "traffic": None, "flops_per_launch": flops, "transcendentals_per_launch": trans,
+                "kernel_ms": ms}
     pairs = info["total_pairs"]
     ks = [m.n_triangles for m, _ in inst]
     return {"metric": METRIC, "value": pairs / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -162,7 +266,7 @@ def bench_batch(args):
                        "near_pairs": info["total_near"], "K_min": min(ks), "K_max": max(ks)},
             "batched_ms": ms, "sequential_ms": ms_seq, "sequential_value": pairs / (ms_seq * 1e-3),
             "speedup_vs_sequential": ms_seq / ms, "autotune": {"chunk": tune["chunk"], "grid": tune["grid"]},
-            "plan_ms": plan_ms}
+            "plan_ms": plan_ms, "roofline": roofline}
 
 
 def _timed_assembly(plan, fo, g, steps, warmup):
@@ -194,24 +298,19 @@ def _solve(plan, mesh, u):
     U, its, rel = plan.cg(plan.load(), rtol=1e-12)
     Ufull = u(mesh.xy[:, 0], mesh.xy[:, 1]).copy()
     Ufull[plan.free_nodes().cpu().numpy()] = U.cpu().numpy()
-    return Ufull, its
+    return Ufull, (its, rel)
 
 
 def _l2_diff(mesh, U1, U2):
     return l2_error(mesh, U1 - U2, lambda x, y: 0.0 * x)
 
 
-def bench_learned(args):
-    """Learned caps on the c2 mesh: train the network on the GPU (outside the
-    timed region), then time the FP32 learned assembly against the FP64 and
-    FP32 exact-cap assemblies and the FP32 no-cap one, and compare solutions."""
+def train_network(args):
+    """The learned-cap network trained on the GPU with the workload's recipe
+    (samples of the h = delta/8 family labelled by the FP64 8-arc caps)."""
     import torch
-    from dataclasses import replace
-    from paper_2005_10775_amd import Mlp, Plan
-    from workloads import make_config, manufactured
+    from paper_2005_10775_amd import Mlp
     from workloads.learned import TRAIN
-    mesh, p64, man = make_config("c2")
-    u, f = manufactured(man)
     t0 = time.perf_counter()
     feat, lab = Mlp.samples(int(TRAIN["samples"] / 0.17), TRAIN["seed"], L=TRAIN["L"], jitter=TRAIN["jitter"],
                             band=TRAIN["band"], cap_edges=TRAIN["cap_edges"])
@@ -227,46 +326,105 @@ def bench_learned(args):
     w, sc = net.get_weights()
     pred = net.forward(fh) * sc
     held = float(torch.sqrt(torch.mean((pred - lh) ** 2)) / torch.sqrt(torch.mean(lh ** 2)))
+    info = {"samples": int(feat.shape[0]), "epochs": args.epochs, "batch": TRAIN["batch"], "samples_s": t_samples,
+            "train_s": t_train, "loss_first": log[0], "loss_last": log[-1], "heldout_rel_rms": held, "scale": sc}
+    return net, feat, info
 
-    variants = {"fp64_exactcap": p64, "fp32_exactcap": replace(p64, precision="fp32"),
-                "fp32_nocaps": replace(p64, precision="fp32", cap_edges=0),
-                "fp32_learned": replace(p64, precision="learned")}
+
+def network_roofline(net, feat, n_items, steps):
+    """k_mlp_fwd alone on n_items inputs (the count one learned assembly
+    routes), timed with HIP events on the launch stream: 2 (128*128 + 3*128)
+    matrix-core flops per item against the dense bf16 peak (the 6 -> 128 first
+    layer and the 256 activations run on the vector unit and are not counted)."""
+    import torch
+    n = min(n_items, feat.shape[0])
+    if n <= 0:
+        return None
+    x = feat[:n].contiguous()
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        net.forward(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        net.forward(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    flops = n * 2.0 * (128 * 128 + 3 * 128)
+    ach = flops / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": "k_mlp_fwd", "achieved": ach, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / BF16_PEAK_TFLOPS, "traffic": None, "flops_per_launch": flops, "kernel_ms": ms,
+            "items": n}
+
+
+def learned_compare(args, mesh, p64, man, fp64_ms, U_exact):
+    """The learned-cap form on the headline mesh against the FP64 exact-cap
+    assembly already timed (fp64_ms, solution U_exact): train, then time the
+    FP32 learned assembly; solve; compare with the exact-cap and the FP32
+    no-cap solutions (what the network gains)."""
+    import torch
+    from dataclasses import replace
+    from paper_2005_10775_amd import Plan
+    from workloads import manufactured
+    u, f = manufactured(man)
+    net, feat, tinfo = train_network(args)
     res = {}
     sols = {}
-    for name, prob in variants.items():
+    for name, prob in (("fp32_learned", replace(p64, precision="learned")),
+                       ("fp32_nocaps", replace(p64, precision="fp32", cap_edges=0))):
         plan = Plan(mesh, prob, mlp=net if prob.precision == "learned" else None)
         xq = plan.outer_points()
         fo = f(xq[..., 0], xq[..., 1]).contiguous()
         g = torch.tensor(u(mesh.xy[:, 0], mesh.xy[:, 1]), dtype=torch.float64, device="cuda")
         ms, phase = _timed_assembly(plan, fo, g, args.steps, args.warmup)
         info = plan.info()
-        U, its = _solve(plan, mesh, u)
-        sols[name] = U
-        res[name] = {"ms": ms, "pairs_per_s": info["n_pairs"] / (ms * 1e-3), "phase_ms": phase,
-                     "items": info["items"], "l2_err": l2_error(mesh, U, u), "cg_iters": its}
+        sols[name], _ = _solve(plan, mesh, u)
+        res[name] = {"ms": ms, "phase_ms": phase, "items": info["items"]}
         plan.close()
-    for name in res:
-        res[name]["l2_diff_vs_fp64_exactcap"] = _l2_diff(mesh, sols[name], sols["fp64_exactcap"])
     L = res["fp32_learned"]
-    n_learned = L["items"]["learned"]
-    # the MLP phase: routing pass + network inference over the routed items
-    mfma_flops = n_learned * 2.0 * (128 * 128 + 3 * 128)
-    mlp_ms = L["phase_ms"]["mlp"]
-    out = {"metric": METRIC, "value": L["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": L["ms"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
-           "config": {"workload": "c5: c2 mesh (delta=0.1, h=delta/8 jittered, K=%d), 8-arc caps, 7x16 rules, "
-                                  "constant kernel; learned caps (6-128-128-3 tanh-GELU, bf16 MFMA) outside the "
-                                  "0.02 delta band, FP32 compensated sums" % mesh.n_triangles,
-                      "train_samples": int(feat.shape[0]), "epochs": args.epochs, "batch": TRAIN["batch"]},
-           "speedup_vs_fp64_exactcap": res["fp64_exactcap"]["ms"] / L["ms"],
-           "speedup_vs_fp32_exactcap": res["fp32_exactcap"]["ms"] / L["ms"],
-           "variants": res, "train": {"samples_s": t_samples, "train_s": t_train, "loss": log,
-                                      "heldout_rel_rms": held, "scale": sc},
-           "mlp_phase": {"routed_items": n_learned, "ms": mlp_ms,
-                         "mfma_tflops": mfma_flops / (mlp_ms * 1e-3) / 1e12 if mlp_ms > 0 else None,
-                         "mfma_frac_of_bf16_dense_peak": mfma_flops / (mlp_ms * 1e-3) / 2.5e15 if mlp_ms > 0 else None}}
-    return out
+    d_learn = _l2_diff(mesh, sols["fp32_learned"], U_exact)
+    d_nocap = _l2_diff(mesh, sols["fp32_nocaps"], U_exact)
+    speedup = fp64_ms / L["ms"]
+    return {"workload": "c5: the headline mesh and rules; caps outside the 0.02 delta band and inside the "
+                        "network's training domain from a 6-128-128-3 tanh-GELU network (bf16 matrix cores), "
+                        "the rest exact; FP32 compensated sums",
+            "fp64_exactcap_ms": fp64_ms, "fp32_learned_ms": L["ms"], "fp32_nocaps_ms": res["fp32_nocaps"]["ms"],
+            "speedup_vs_fp64_exactcap": speedup, "target_speedup": LEARNED_TARGET_SPEEDUP,
+            "speedup_target_met": speedup >= LEARNED_TARGET_SPEEDUP,
+            "l2_learned_vs_exactcap": d_learn, "l2_nocaps_vs_exactcap": d_nocap, "target_l2": LEARNED_TARGET_L2,
+            "l2_target_met": d_learn <= LEARNED_TARGET_L2,
+            "gain_vs_nocaps": d_nocap / d_learn if d_learn > 0 else None,
+            "routed_items": L["items"]["learned"], "partial_items": L["items"]["partial"],
+            "network_phase_ms": L["phase_ms"]["mlp"], "learned_phase_ms": L["phase_ms"],
+            "network_roofline": network_roofline(net, feat, L["items"]["learned"], args.steps),
+            "train": tinfo}
+
+
+def bench_learned(args):
+    """--config c5: the FP64 exact-cap assembly of the headline mesh, then the
+    learned comparison; the line's value is the learned form's pairs/s."""
+    import torch
+    from paper_2005_10775_amd import Plan
+    from workloads import make_config, manufactured
+    mesh, p64, man = make_config("c2")
+    u, f = manufactured(man)
+    plan = Plan(mesh, p64)
+    xq = plan.outer_points()
+    fo = f(xq[..., 0], xq[..., 1]).contiguous()
+    g = torch.tensor(u(mesh.xy[:, 0], mesh.xy[:, 1]), dtype=torch.float64, device="cuda")
+    ms64, _ = _timed_assembly(plan, fo, g, args.steps, args.warmup)
+    n_pairs = plan.info()["n_pairs"]
+    U64, _ = _solve(plan, mesh, u)
+    plan.close()
+    cmp = learned_compare(args, mesh, p64, man, ms64, U64)
+    ms = cmp["fp32_learned_ms"]
+    return {"metric": METRIC, "value": n_pairs / (ms * 1e-3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+            "config": {"workload": cmp["workload"], "n_pairs": n_pairs},
+            "roofline": cmp["network_roofline"], "learned": cmp}
 
 
 PAPER_BALLS = ("exactcaps", "approxcaps", "nocaps", "barycenter", "overlap", "shifted", "barynocaps",
@@ -308,7 +466,7 @@ def bench_paper(args):
         g = torch.tensor(u(mesh.xy[:, 0], mesh.xy[:, 1]), dtype=torch.float64, device="cuda")
         ms, phase = _timed_assembly(plan, fo, g, args.steps, args.warmup)
         info = plan.info()
-        U, its = _solve(plan, mesh, u)
+        U, (its, _) = _solve(plan, mesh, u)
         l2 = l2_error(mesh, U, u)
         rows[ball] = {"assembly_ms": ms, "pairs_ms": phase["pairs"], "plan_ms": plan_ms,
                       "n_pairs": info["n_pairs"], "pairs_per_s": info["n_pairs"] / (ms * 1e-3),
@@ -332,6 +490,41 @@ def bench_paper(args):
             "balls": rows}
 
 
+def pair_roofline(prob, info, n_pairs, phase):
+    """Roofline line of the configuration's dominant kernel, the pair
+    quadrature: FP64 boundary form (constant kernel, intersection ball, rule
+    exact for quadratics), otherwise the point-rule kernels (FP64 or FP32)."""
+    from workloads import get_rule
+    ri = get_rule(prob.inner)
+    ncap = prob.cap_edges if prob.ball == "retri" else 0
+    nq = get_rule(prob.outer).n
+    q2 = abs(ri.w.sum() - 0.5) < 1e-14 and all(abs((ri.w * ri.lam[:, i]).sum() - 1 / 6) < 1e-14 for i in range(3))
+    t = phase["pairs"] * 1e-3
+    if prob.precision == "fp64":
+        boundary = prob.ball == "retri" and q2 and prob.kernel == "constant"
+        flops = algorithmic_flops(info, n_pairs, ncap, COST_BOUNDARY if boundary else COST, nq)
+        ach = flops / t / 1e12
+        digest = source_digest()
+        out = {"bound": "alu", "kernel": "k_pairs_const_fp64", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+               "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+               "traffic": traffic_from_profile("k_pairs_const_fp64", digest) if boundary else None,
+               "flops_per_launch": flops, "kernel_ms": phase["pairs"],
+               "cost_model": "boundary form (partial items by boundary moments)" if boundary else "point rule"}
+        if boundary:
+            mf = method_point_flops(info, ri.n, ncap)
+            out["method_point_flops"] = mf
+            out["method_point_frac"] = mf / t / 1e12 / FP64_PEAK_TFLOPS
+        return out
+    flops, trans = fp32_point_flops(info, n_pairs, ri.n, ncap, prob.kernel == "fractional")
+    ach = flops / t / 1e12
+    return {"bound": "alu", "kernel": "k_pairs_fp32", "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / FP32_PEAK_TFLOPS, "traffic": None, "flops_per_launch": flops,
+            "transcendentals_per_launch": trans,
+            "transcendentals_per_s": trans / t if trans else 0.0, "kernel_ms": phase["pairs"],
+            "note": "FP32 peak is the packed rate; packed FP32 is disabled in this build, so unpacked FP32 "
+                    "issues at half of it"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,9 +532,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="c2: leave out the learned-cap comparison")
     ap.add_argument("--duffy", type=int, default=0, help="override the singular-pair rule order")
     ap.add_argument("--cpu-sample", type=int, default=12288, help="outer elements in the CPU-baseline sample")
-    ap.add_argument("--epochs", type=int, default=20, help="c5: training epochs")
+    ap.add_argument("--cpu-sample-1t", type=int, default=3072,
+                    help="outer elements in the single-thread CPU-baseline sample")
+    ap.add_argument("--epochs", type=int, default=20, help="learned caps: training epochs")
     ap.add_argument("--paper-h", type=float, default=0.00625, help="paper: grid spacing of the Sec. 8 workloads")
     ap.add_argument("--paper-balls", default="", help="paper: comma-separated subset of the balls (default: all)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -386,26 +582,10 @@ def main():
     info = plan.info()
     n_pairs = info["n_pairs"]
     value = n_pairs / (ms * 1e-3)
-
-    # roofline of the dominant kernel (pair quadrature): algorithmic FP64 work per launch
-    from workloads import get_rule
-    ri = get_rule(prob.inner)
-    q2 = abs(ri.w.sum() - 0.5) < 1e-14 and all(abs((ri.w * ri.lam[:, i]).sum() - 1 / 6) < 1e-14 for i in range(3))
-    boundary = prob.precision == "fp64" and prob.ball == "retri" and q2
-    flops = algorithmic_flops(info, n_pairs, prob.cap_edges if prob.ball == "retri" else 0,
-                              COST_BOUNDARY if boundary else COST)
-    t_pair = phase["pairs"] * 1e-3
-    achieved = flops / t_pair / 1e12
-    digest = source_digest()
-    roofline = {"bound": "alu", "kernel": "k_pairs_const_fp64", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                "traffic": traffic_from_profile("k_pairs_const_fp64", digest),
-                "flops_per_launch": flops, "kernel_ms": phase["pairs"]}
+    roofline = pair_roofline(prob, info, n_pairs, phase)
 
     # validation solve and L2 error (outside the timed region)
-    U, its, rel = plan.cg(plan.load(), rtol=1e-12)
-    Ufull = u(mesh.xy[:, 0], mesh.xy[:, 1]).copy()
-    Ufull[plan.free_nodes().cpu().numpy()] = U.cpu().numpy()
+    Ufull, (its, rel) = _solve(plan, mesh, u)
     l2 = l2_error(mesh, Ufull, u)
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
@@ -417,11 +597,15 @@ def main():
                "n_pairs": n_pairs, "nnz_full": info["nnz_full"], "n_free": info["n_free"],
                "jitter": mesh.meta.get("jitter", 0.0)},
            "assembly_ms": ms, "plan_ms": plan_ms, "phase_ms": phase,
-           "items": info["items"], "subtriangles": info["subtriangles"], "caps": info["caps"],
-           "l2_err": l2, "cg": {"iters": its, "relres": rel},
-           "roofline": roofline, "source_digest": digest}
+           "items": info["items"], "n_deep": info["n_deep"], "subtriangles": info["subtriangles"],
+           "caps": info["caps"], "l2_err": l2, "cg": {"iters": its, "relres": rel},
+           "roofline": roofline, "source_digest": source_digest()}
+    if args.config == "c2" and not args.no_learned:
+        plan.close()
+        torch.cuda.empty_cache()
+        out["learned"] = learned_compare(args, mesh, prob, man, ms, Ufull)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mesh, prob, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(mesh, prob, args.cpu_sample, args.cpu_sample_1t)
     if args.calibrate_copy:
         n = args.calibrate_copy << 20
         src = torch.ones(n // 8, dtype=torch.float64, device="cuda")

@@ -225,6 +225,7 @@ int nla_near_view(const nla_plan *plan, int64_t *n_near, const int64_t **near_pa
 int nla_cg(const nla_plan *plan, const double *b, double *u, double rtol, int32_t maxit,
            int32_t *iters, double *relres, void *stream);
 
+
 /* Timing: nla_set_timing(plan, n) with n > 0 makes the next n calls of
  * nla_assemble record HIP events on their stream around each phase (n = 0
  * turns it off).  nla_timings waits for the last recorded event and writes
@@ -293,15 +294,17 @@ void nla_batch_destroy(nla_batch *batch);
  * stream-ordered on the caller's stream, and an nla_mlp is not thread-safe.
  *
  * Training domain (out-of-distribution fallback): an item goes to the network
- * only when it is also inside the network's training domain, 14 doubles
- * dom = {flo[6], fhi[6], elo, ehi}: every input f_i, rounded to float as the
- * network reads it, within [flo_i, fhi_i], and the three squared edge lengths
- * (f_2b - f_2a)^2 + (f_2b+1 - f_2a+1)^2 (b = a+1 mod 3), formed in FP64 from
- * the float inputs with every operation rounded on its own, within
- * [elo, ehi].  Other items take the exact caps.  nla_mlp_train sets the
- * domain to the range of its samples (joined with earlier training calls'
- * ranges); nla_mlp_create and nla_mlp_set_weights leave it unbounded.  A plan
- * takes the network's domain when it is created.
+ * only when it is also inside the network's training domain, 4 doubles
+ * dom = {rlo, rhi, elo, ehi}: every squared vertex distance |v_a - x|^2 within
+ * [rlo delta^2, rhi delta^2] and every squared edge length |v_b - v_a|^2
+ * within [elo delta^2, ehi delta^2] (the triangle's size and place relative
+ * to the ball, whatever its rotation), tested in FP64 with every product and
+ * sum rounded on its own (the limits times delta^2 included).  Other items
+ * take the exact caps.  nla_mlp_train sets the domain to the range of its
+ * samples, read back from their inputs (|v_a|^2 = (f_a0/8 + 1)^2 +
+ * (f_a1/8)^2, |v_b - v_a|^2 = |f_b - f_a|^2 / 64 with delta = 1), joined with
+ * earlier training calls' ranges; nla_mlp_create and nla_mlp_set_weights
+ * leave it unbounded.  A plan takes the network's domain when it is created.
  * ------------------------------------------------------------------------ */
 #define NLA_MLP_WEIGHTS 17795
 typedef struct nla_mlp nla_mlp;
@@ -340,7 +343,7 @@ int nla_mlp_forward(const nla_mlp *mlp, const float *feat, int64_t n, float *out
 /* Gradient of sum_i sum_o dout[i][o] y[i][o] with respect to every weight
  * (device dw[NLA_MLP_WEIGHTS], flat layout), on the weights as used. */
 int nla_mlp_backward(nla_mlp *mlp, const float *feat, const float *dout, int64_t n, float *dw, void *stream);
-/* The training domain (host dom[14], layout above).  set: dom = NULL makes it
+/* The training domain (host dom[4], layout above).  set: dom = NULL makes it
  * unbounded; NLA_E_INVALID for a NaN limit or lo > hi.  Plans made earlier
  * keep the domain they took. */
 int nla_mlp_set_domain(nla_mlp *mlp, const double *dom);

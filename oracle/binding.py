@@ -158,8 +158,8 @@ class OracleProblem:
             p.learned, p.band, p.mlp_w, p.mlp_scale = 1, prob.fallback_band, _ptr(w), mlp_scale
             if mlp_domain is not None:
                 dom = np.ascontiguousarray(mlp_domain, dtype=np.float64)
-                if dom.shape != (14,):
-                    raise ValueError("the training domain has 14 limits")
+                if dom.shape != (4,):
+                    raise ValueError("the training domain has 4 limits")
                 self._keep.append(dom)
                 p.mlp_domain = _ptr(dom)
         self.cprob = p
@@ -395,7 +395,7 @@ def cap_moments(delta, x, tri_xy, cap_edges=8):
 
 
 def in_domain(dom, x, tri_xy, delta):
-    """The item (x, E') inside the training domain dom[14] (None: unbounded)."""
+    """The item (x, E') inside the training domain dom[4] (None: unbounded)."""
     xx = np.ascontiguousarray(x, dtype=np.float64)
     V = np.ascontiguousarray(tri_xy, dtype=np.float64).reshape(6)
     d = None if dom is None else np.ascontiguousarray(dom, dtype=np.float64)
@@ -403,17 +403,20 @@ def in_domain(dom, x, tri_xy, delta):
 
 
 def feature_domain(feat):
-    """The training domain {flo[6], fhi[6], elo, ehi} of float inputs feat[n][6]:
-    their per-input range and the range of the squared edge lengths formed
-    from them."""
+    """The training domain {rlo, rhi, elo, ehi} of samples given by their float
+    network inputs feat[n][6] (delta = 1, x = 0): the range of the squared
+    vertex distances |v_a|^2 = (f_a0/8 + 1)^2 + (f_a1/8)^2 and of the squared
+    edge lengths |f_b - f_a|^2 / 64."""
     g = np.asarray(feat, dtype=np.float32).astype(np.float64).reshape(-1, 6)
-    e = []
+    r, e = [], []
     for a in range(3):
         b = (a + 1) % 3
+        px, py = g[:, 2 * a] * 0.125 + 1.0, g[:, 2 * a + 1] * 0.125
+        r.append(px * px + py * py)
         dx, dy = g[:, 2 * b] - g[:, 2 * a], g[:, 2 * b + 1] - g[:, 2 * a + 1]
-        e.append(dx * dx + dy * dy)
-    e = np.concatenate(e)
-    return np.concatenate([g.min(axis=0), g.max(axis=0), [e.min(), e.max()]])
+        e.append((dx * dx + dy * dy) * (1.0 / 64.0))
+    r, e = np.concatenate(r), np.concatenate(e)
+    return np.array([r.min(), r.max(), e.min(), e.max()])
 
 
 def routed(delta, band, x, tri_xy):

@@ -41,7 +41,7 @@ typedef struct {
      * min_a | |v_a - x| - delta | >= band delta take the polygon plus the
      * network's cap moments; the others keep the arc-subdivided caps */
     int32_t learned; double band; const double *mlp_w; double mlp_scale;
-    /* the network's training domain {flo[6], fhi[6], elo, ehi}, or NULL
+    /* the network's training domain {rlo, rhi, elo, ehi}, or NULL
      * (unbounded): a routed item outside it keeps the arc-subdivided caps */
     const double *mlp_domain;
 } nlo_problem;

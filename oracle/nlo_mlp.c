@@ -181,24 +181,21 @@ int nlo_routed(double delta, double band, const double x[2], const double V[6])
     return 1;
 }
 
-/* the item inside the network's training domain: each input, rounded to
- * float as the network reads it, within [flo_i, fhi_i], and each squared edge
- * length of the input triangle, formed from those float inputs, within
- * [elo, ehi]; dom = NULL is unbounded */
+/* the item inside the network's training domain {rlo, rhi, elo, ehi}: every
+ * squared vertex distance |v_a - x|^2 within [rlo, rhi] delta^2 and every
+ * squared edge length within [elo, ehi] delta^2; dom = NULL is unbounded */
 int nlo_in_domain(const double *dom, const double x[2], const double V[6], double delta)
 {
     if (!dom) return 1;
-    double f[6], g[6];
-    nlo_mlp_features(x, V, delta, f);
-    for (int i = 0; i < 6; i++) {
-        g[i] = (double)(float)f[i];
-        if (!(g[i] >= dom[i] && g[i] <= dom[6 + i])) return 0;
-    }
+    double dd = delta * delta;
+    double rlo = dom[0] * dd, rhi = dom[1] * dd, elo = dom[2] * dd, ehi = dom[3] * dd;
     for (int a = 0; a < 3; a++) {
         int b = (a + 1) % 3;
-        double dx = g[2 * b] - g[2 * a], dy = g[2 * b + 1] - g[2 * a + 1];
-        double e = dx * dx + dy * dy;
-        if (!(e >= dom[12] && e <= dom[13])) return 0;
+        double dx = V[2 * a] - x[0], dy = V[2 * a + 1] - x[1];
+        double d2 = dx * dx + dy * dy;
+        double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        double e2 = ex * ex + ey * ey;
+        if (!(d2 >= rlo && d2 <= rhi && e2 >= elo && e2 <= ehi)) return 0;
     }
     return 1;
 }

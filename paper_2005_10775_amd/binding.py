@@ -426,16 +426,16 @@ class Mlp:
         return w, sc.value
 
     def set_domain(self, dom):
-        """The training domain {flo[6], fhi[6], elo, ehi} (None: unbounded)."""
+        """The training domain {rlo, rhi, elo, ehi} (None: unbounded)."""
         if dom is None:
             _check(lib().nla_mlp_set_domain(self._h, None))
             return
         d = np.ascontiguousarray(dom, dtype=np.float64)
-        assert d.shape == (14,)
+        assert d.shape == (4,)
         _check(lib().nla_mlp_set_domain(self._h, d.ctypes.data))
 
     def get_domain(self):
-        d = np.empty(14, dtype=np.float64)
+        d = np.empty(4, dtype=np.float64)
         _check(lib().nla_mlp_get_domain(self._h, d.ctypes.data))
         return d
 

@@ -375,31 +375,22 @@ __device__ __forceinline__ void mlp_features(double xx, double xy, const double 
     }
 }
 
-// the item's inputs inside the network's training domain (MlpDomain)
-__device__ __forceinline__ bool in_domain(const float (&f)[6], const MlpDomain &D)
+// the item (x, E') inside the network's training domain (MlpDomain)
+__device__ __forceinline__ bool in_domain(double xx, double xy, const double (&V)[6], double dd, const MlpDomain &D)
 {
 #pragma clang fp contract(off)
+    const double rlo = D.rlo * dd, rhi = D.rhi * dd, elo = D.elo * dd, ehi = D.ehi * dd;
     bool ok = true;
-#pragma unroll
-    for (int i = 0; i < 6; i++) ok = ok && (double)f[i] >= D.flo[i] && (double)f[i] <= D.fhi[i];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const int b = (a + 1) % 3;
-        const double dx = (double)f[2 * b] - (double)f[2 * a], dy = (double)f[2 * b + 1] - (double)f[2 * a + 1];
-        const double e = dx * dx + dy * dy;
-        ok = ok && e >= D.elo && e <= D.ehi;
+        const double dx = V[2 * a] - xx, dy = V[2 * a + 1] - xy;
+        const double d2 = dx * dx + dy * dy;
+        const double ex = V[2 * b] - V[2 * a], ey = V[2 * b + 1] - V[2 * a + 1];
+        const double e2 = ex * ex + ey * ey;
+        ok = ok && d2 >= rlo && d2 <= rhi && e2 >= elo && e2 <= ehi;
     }
     return ok;
-}
-
-// routed to the network: far from tangency and inside the training domain
-__device__ __forceinline__ bool item_learned(double xx, double xy, const double (&V)[6], double delta, double band,
-                                             const MlpDomain &D)
-{
-    if (!item_routed(xx, xy, V, delta, band)) return false;
-    float f[6];
-    mlp_features(xx, xy, V, delta, f);
-    return in_domain(f, D);
 }
 
 // Boundary sums of a polygon's area and first and second moments (Green's

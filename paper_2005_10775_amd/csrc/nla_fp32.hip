@@ -232,6 +232,8 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         for (int i = 0; i < 6; i++) ayy[i].zero();
         float ws = 0.f, aw[3] = {0.f, 0.f, 0.f};
         unsigned pmask = 0, rmask = 0;
+        // the routing pass's decision for this pair's outer points
+        const unsigned rm_in = (LEARN && act) ? (unsigned)P.route_mask[pi] : 0u;
         if (act) {
 #pragma unroll
             for (int q = 0; q < NQ; q++) {
@@ -244,7 +246,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                     const int cls = item_class(xx, xy, V, dd);
                     whole = cls == 1;
                     part = cls == 2;
-                    if (LEARN && part && item_learned(xx, xy, V, P.delta, P.band, P.dom)) rmask |= 1u << q;
+                    if (LEARN && part && ((rm_in >> q) & 1u)) rmask |= 1u << q;
                 }
                 if (whole) {
                     c_whole++;
@@ -291,50 +293,41 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
             for (int e = 0; e < 6; e++) ayy[e].add(ws * ka * (o + (jj[e] == ll[e] ? dm : 0.f)));
         }
         // queue: items with arc-subdivided caps first, then (learned) routed
-        // items, each in (pair, q) order, so that a batch of 64 is uniform
+        // items, each outer point by outer point (point 0 of every lane in lane
+        // order, then point 1, ...), so that a batch of 64 is uniform and holds
+        // at most a few items of any one lane; a lane's items keep their q order
         const unsigned emask = pmask & ~rmask;
-        const int cnt = __popc(emask);
-        int pre = cnt;
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        int totE = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(pre, off, 64);
-            if (lane >= off) pre += v;
+        for (int q = 0; q < NQ; q++) {
+            const bool mine = (emask >> q) & 1u;
+            const unsigned long long bq = __ballot(mine);
+            if (mine) queue[totE + __popcll(bq & lt)] = (unsigned short)((lane << 8) | q);
+            totE += __popcll(bq);
         }
-        const int totE = __shfl(pre, 63, 64);
-        pre -= cnt;
-        int cntR = 0, preR = 0, totR = 0;
+        int totR = 0;
         if (LEARN) {
-            // routed items in (pair, q) order: the same order as the routing pass
-            cntR = __popc(rmask);
+            // the network's outputs follow the routing pass's (pair, q) order
+            const int cntR = __popc(rmask);
             int rp = cntR;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const int v = __shfl_up(rp, off, 64);
                 if (lane >= off) rp += v;
             }
-            totR = __shfl(rp, 63, 64);
-            preR = rp - cntR;
-            rbase_l[lane] = rrun + preR;
+            rbase_l[lane] = rrun + rp - cntR;
             rmsk_l[lane] = rmask;
-            rrun += totR;
+            rrun += __shfl(rp, 63, 64);
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                const bool mine = (rmask >> q) & 1u;
+                const unsigned long long bq = __ballot(mine);
+                if (mine) queue[totE + totR + __popcll(bq & lt)] = (unsigned short)((lane << 8) | q);
+                totR += __popcll(bq);
+            }
         }
         const int total = totE + totR;
-        {
-            int oo = pre;
-            unsigned mm = emask;
-            while (mm) {
-                const int q = __ffs(mm) - 1;
-                mm &= mm - 1;
-                queue[oo++] = (unsigned short)((lane << 8) | q);
-            }
-            oo = totE + preR;
-            mm = LEARN ? rmask : 0u;
-            while (mm) {
-                const int q = __ffs(mm) - 1;
-                mm &= mm - 1;
-                queue[oo++] = (unsigned short)((lane << 8) | q);
-            }
-        }
         __syncthreads();
         for (int ib = 0; ib < total; ib += 64) {
             const int i = ib + lane;
@@ -376,17 +369,25 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 c_cap += ns >> 16;
             }
             __syncthreads();
-            // each lane adds its own items of this batch: its cap segment, then its routed one
+            // each lane adds its own items of this batch in queue order: its capped
+            // items, then its routed ones, each in q order; the outer points with
+            // none in the batch are skipped by the whole wave
 #pragma unroll
             for (int seg = 0; seg < (LEARN ? 2 : 1); seg++) {
-                const int s0 = seg == 0 ? pre : totE + preR, s1 = s0 + (seg == 0 ? cnt : cntR);
-                const int j0 = s0 > ib ? s0 : ib;
-                const int j1 = s1 < (ib + 64) ? s1 : (ib + 64);
-                for (int j = j0; j < j1; j++) {
-                    const int q = queue[j] & 0xff;
+                const unsigned smask = seg == 0 ? emask : rmask;
+                int qbase = seg == 0 ? 0 : totE;
+#pragma unroll
+                for (int q = 0; q < NQ; q++) {
+                    const bool mine = (smask >> q) & 1u;
+                    const unsigned long long bq = __ballot(mine);
+                    const int pos = qbase + __popcll(bq & lt);
+                    const bool inr = mine && pos >= ib && pos < ib + 64;
+                    qbase += __popcll(bq);
+                    if (__ballot(inr) == 0ull) continue;
+                    if (!inr) continue;
                     float r[10];
 #pragma unroll
-                    for (int t = 0; t < 10; t++) r[t] = res[j - ib][t];
+                    for (int t = 0; t < 10; t++) r[t] = res[pos - ib][t];
                     if (LEARN && seg == 1) {
                         // polygon sums plus the network's cap moments m_b (units of kc
                         // delta^2 scale); second moments by the one-point centroid closure
@@ -407,9 +408,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                         }
                         c_learn++;
                     }
-#pragma unroll
-                    for (int qq = 0; qq < NQ; qq++)
-                        if (qq == q) m0[qq].add(r[0]);
+                    m0[q].add(r[0]);
 #pragma unroll
                     for (int a = 0; a < 3; a++)
 #pragma unroll
@@ -594,9 +593,12 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
 }
 
 // Routing pass of the learned caps, one wavefront per outer element, with the
-// pair kernel's classification and item order (pair, then outer point):
-// FILL = false counts the routed items of k, FILL = true writes their
-// network inputs (mlp_features) at the element's offset.
+// pair kernel's classification and item order (pair, then outer point): a
+// partial item far from tangency and inside the network's training domain
+// goes to the network.  Writes each band pair's routed outer points as a bit
+// mask (route_mask, by processing slot: the pair kernel reads it instead of
+// deciding again); FILL = false counts the routed items of k, FILL = true
+// writes their network inputs (mlp_features) at the element's offset.
 template <int NQ, bool FILL>
 __global__ __launch_bounds__(64) void k_route(PairArgs P, int64_t *__restrict__ count, float *__restrict__ feat)
 {
@@ -627,10 +629,12 @@ __global__ __launch_bounds__(64) void k_route(PairArgs P, int64_t *__restrict__ 
             for (int q = 0; q < NQ; q++) {
                 if (q >= nq) break;
                 const double xx = sX[q][0], xy = sX[q][1];
-                if (item_class(xx, xy, V, P.dd) == 2 && item_learned(xx, xy, V, P.delta, P.band, P.dom))
+                if (item_class(xx, xy, V, P.dd) == 2 && item_routed(xx, xy, V, P.delta, P.band) &&
+                    in_domain(xx, xy, V, P.dd, P.dom))
                     rmask |= 1u << q;
             }
         }
+        if (pi < pend) P.route_mask[pi] = (uint8_t)rmask;
         const int rc = __popc(rmask);
         int rp = rc;
 #pragma unroll
@@ -1063,6 +1067,7 @@ PairArgs nla_pair_args(const nla_plan *P)
     A.delta = pr.delta;
     A.band = pr.fallback_band;
     A.route_off = P->route_off;
+    A.route_mask = P->route_mask;
     A.n_routed = P->n_routed;
     A.mlp_y = P->route_y;
     A.dom = P->mlp_dom;
@@ -1075,6 +1080,7 @@ int nla_build_routes(nla_plan *P, hipStream_t s)
 {
     const int K = P->K;
     NLA_TRY(P->arena.get(&P->route_off, (size_t)K + 1));
+    NLA_TRY(P->arena.get(&P->route_mask, (size_t)(P->n_pairs > 0 ? P->n_pairs : 1)));
     DeviceArena tmp;
     int64_t *cnt;
     NLA_TRY(tmp.get(&cnt, (size_t)K));

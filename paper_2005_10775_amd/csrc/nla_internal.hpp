@@ -65,14 +65,15 @@ struct ElemSoA {
 };
 
 // Training domain of a learned cap network: an item goes to the network only
-// when each of its six inputs (rounded to float, as the network reads them)
-// lies in [flo, fhi] and each squared edge length of its triangle in the
-// network's frame, formed in FP64 from those float inputs with every
-// operation rounded on its own, lies in [elo, ehi]; otherwise it takes the
-// exact caps.  Training sets it to the range of its samples; unbounded
-// (infinite limits) for weights set from outside.
+// when each squared vertex distance |v_a - x|^2 lies in [rlo, rhi] delta^2
+// and each squared edge length |v_b - v_a|^2 in [elo, ehi] delta^2 (the
+// shape and place of the triangle relative to the ball, whatever its
+// rotation), tested in FP64 with every operation rounded on its own;
+// otherwise it takes the exact caps.  Training sets the ranges to those of
+// its samples; they are unbounded (infinite limits) for weights set from
+// outside.
 struct MlpDomain {
-    double flo[6], fhi[6], elo, ehi;
+    double rlo, rhi, elo, ehi;
 };
 
 struct DeviceArena {
@@ -170,6 +171,7 @@ struct nla_plan {
     const nla_mlp *mlp = nullptr;
     MlpDomain mlp_dom{};            // the network's training domain when the plan was made
     int64_t *route_off = nullptr;   // [K+1]
+    uint8_t *route_mask = nullptr;  // [n_pairs] by processing slot: outer points routed to the network
     int64_t n_routed = 0;
     float *route_feat = nullptr;    // [n_routed][6]
     float *route_y = nullptr;       // [n_routed][3]
@@ -219,6 +221,7 @@ struct PairArgs {
     // learned caps: routed partial items take the network's cap moments
     double delta, band;
     const int64_t *route_off;   // [K+1] first routed item of each outer element
+    uint8_t *route_mask;        // [n_pairs] by processing slot: routed outer points (the routing pass's)
     int64_t n_routed;
     const float *mlp_y;         // [n_routed][3] network outputs
     float mlp_k;                // kc delta^2 scale

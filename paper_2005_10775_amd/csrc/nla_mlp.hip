@@ -412,10 +412,13 @@ __global__ __launch_bounds__(1024) void k_label_rms(int64_t n3, const float *__r
 }
 
 // Training domain of n samples (MlpDomain): per block, the minimum and maximum
-// of each input and of the three squared edge lengths formed from the float
-// inputs in FP64 (every operation rounded on its own); a second pass reduces
-// the blocks.  Minima and maxima do not depend on the order.
-constexpr int NDOM = 8;     // six inputs and the edge lengths (one range for all three)
+// of the squared vertex distances and squared edge lengths of the samples'
+// triangles in units of delta, recovered from the float inputs f
+// (v_a = R^-1 (f_a / 8 + (1, 0)), so |v_a|^2 = (f_a0 / 8 + 1)^2 + (f_a1 / 8)^2
+// and |v_b - v_a|^2 = |f_b - f_a|^2 / 64) in FP64 with every operation rounded
+// on its own; a second pass reduces the blocks.  Minima and maxima do not
+// depend on the order.
+constexpr int NDOM = 2;     // squared vertex distances, squared edge lengths
 __global__ __launch_bounds__(256) void k_feat_domain(int64_t n, const float *__restrict__ feat, double *__restrict__ part)
 {
 #pragma clang fp contract(off)
@@ -429,18 +432,18 @@ __global__ __launch_bounds__(256) void k_feat_domain(int64_t n, const float *__r
     for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
         double f[6];
 #pragma unroll
-        for (int i = 0; i < 6; i++) {
-            f[i] = (double)feat[6 * j + i];
-            lo[i] = fmin(lo[i], f[i]);
-            hi[i] = fmax(hi[i], f[i]);
-        }
+        for (int i = 0; i < 6; i++) f[i] = (double)feat[6 * j + i];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             const int b = (a + 1) % 3;
+            const double px = f[2 * a] * 0.125 + 1.0, py = f[2 * a + 1] * 0.125;
+            const double r = px * px + py * py;
             const double dx = f[2 * b] - f[2 * a], dy = f[2 * b + 1] - f[2 * a + 1];
-            const double e = dx * dx + dy * dy;
-            lo[6] = fmin(lo[6], e);
-            hi[6] = fmax(hi[6], e);
+            const double e = (dx * dx + dy * dy) * (1.0 / 64.0);
+            lo[0] = fmin(lo[0], r);
+            hi[0] = fmax(hi[0], r);
+            lo[1] = fmin(lo[1], e);
+            hi[1] = fmax(hi[1], e);
         }
     }
 #pragma unroll
@@ -533,48 +536,25 @@ __global__ void k_cap_samples(int64_t n, uint64_t seed, int64_t first, double L,
 struct F6 { float v[6]; };
 struct F3 { float v[3]; };
 
-MlpDomain unbounded_domain()
-{
-    MlpDomain D;
-    for (int i = 0; i < 6; i++) {
-        D.flo[i] = -HUGE_VAL;
-        D.fhi[i] = HUGE_VAL;
-    }
-    D.elo = -HUGE_VAL;
-    D.ehi = HUGE_VAL;
-    return D;
-}
+MlpDomain unbounded_domain() { return MlpDomain{-HUGE_VAL, HUGE_VAL, -HUGE_VAL, HUGE_VAL}; }
 
+// {rlo, rhi, elo, ehi}: no NaN, lo <= hi
 bool valid_domain(const double *d)
 {
-    for (int i = 0; i < 14; i++)
+    for (int i = 0; i < 4; i++)
         if (std::isnan(d[i])) return false;
-    for (int i = 0; i < 6; i++)
-        if (!(d[i] <= d[6 + i])) return false;
-    return d[12] <= d[13];
+    return d[0] <= d[1] && d[2] <= d[3];
 }
 
 void domain_to(const MlpDomain &D, double *d)
 {
-    for (int i = 0; i < 6; i++) {
-        d[i] = D.flo[i];
-        d[6 + i] = D.fhi[i];
-    }
-    d[12] = D.elo;
-    d[13] = D.ehi;
+    d[0] = D.rlo;
+    d[1] = D.rhi;
+    d[2] = D.elo;
+    d[3] = D.ehi;
 }
 
-MlpDomain domain_from(const double *d)
-{
-    MlpDomain D;
-    for (int i = 0; i < 6; i++) {
-        D.flo[i] = d[i];
-        D.fhi[i] = d[6 + i];
-    }
-    D.elo = d[12];
-    D.ehi = d[13];
-    return D;
-}
+MlpDomain domain_from(const double *d) { return MlpDomain{d[0], d[1], d[2], d[3]}; }
 
 } // namespace
 
@@ -869,24 +849,12 @@ extern "C" int nla_mlp_train(nla_mlp *M, const float *feat, const float *label, 
         std::vector<double> h(2 * (size_t)NDOM * nb);
         NLA_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
         NLA_HIP(hipStreamSynchronize(s));
-        MlpDomain D = M->step > 0 ? M->dom : MlpDomain{};
-        for (int i = 0; i < 6; i++) {
-            if (M->step == 0) {
-                D.flo[i] = HUGE_VAL;
-                D.fhi[i] = -HUGE_VAL;
-            }
-            for (int b = 0; b < nb; b++) {
-                D.flo[i] = std::min(D.flo[i], h[2 * NDOM * b + i]);
-                D.fhi[i] = std::max(D.fhi[i], h[2 * NDOM * b + NDOM + i]);
-            }
-        }
-        if (M->step == 0) {
-            D.elo = HUGE_VAL;
-            D.ehi = -HUGE_VAL;
-        }
+        MlpDomain D = M->step > 0 ? M->dom : MlpDomain{HUGE_VAL, -HUGE_VAL, HUGE_VAL, -HUGE_VAL};
         for (int b = 0; b < nb; b++) {
-            D.elo = std::min(D.elo, h[2 * NDOM * b + 6]);
-            D.ehi = std::max(D.ehi, h[2 * NDOM * b + NDOM + 6]);
+            D.rlo = std::min(D.rlo, h[2 * NDOM * b + 0]);
+            D.rhi = std::max(D.rhi, h[2 * NDOM * b + NDOM + 0]);
+            D.elo = std::min(D.elo, h[2 * NDOM * b + 1]);
+            D.ehi = std::max(D.ehi, h[2 * NDOM * b + NDOM + 1]);
         }
         M->dom = D;
     }
@@ -923,7 +891,7 @@ extern "C" int nla_mlp_train(nla_mlp *M, const float *feat, const float *label, 
 }
 
 // checkpoint: magic, weights, scale, Adam moments and step, training domain
-// (14 doubles; a version-1 file has none and loads with an unbounded domain)
+// (4 doubles; a version-1 file has none and loads with an unbounded domain)
 extern "C" int nla_mlp_save(const nla_mlp *M, const char *path)
 {
     if (!M || !path) { nla_set_error("null argument"); return NLA_E_INVALID; }
@@ -936,11 +904,11 @@ extern "C" int nla_mlp_save(const nla_mlp *M, const char *path)
     if (!f) { nla_set_error("cannot open %s", path); return NLA_E_INVALID; }
     const char magic[8] = {'N', 'L', 'A', 'M', 'L', 'P', '2', 0};
     const int32_t nw = NW;
-    double dom[14];
+    double dom[4];
     domain_to(M->dom, dom);
     bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&nw, 4, 1, f) == 1 && std::fwrite(&M->scale, 4, 1, f) == 1 &&
               std::fwrite(&M->step, 8, 1, f) == 1 && std::fwrite(&M->adam_t, 8, 1, f) == 1 &&
-              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size() && std::fwrite(dom, 8, 14, f) == 14;
+              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size() && std::fwrite(dom, 8, 4, f) == 4;
     ok = (std::fclose(f) == 0) && ok;
     if (!ok) { nla_set_error("write failed: %s", path); return NLA_E_INVALID; }
     return NLA_OK;
@@ -957,14 +925,14 @@ extern "C" int nla_mlp_load(const char *path, nla_mlp **out)
     float scale = 0.f;
     int64_t step = 0, adam_t = 0;
     std::vector<float> buf(3 * (size_t)NW);
-    double dom[14];
+    double dom[4];
     bool ok = std::fread(magic, 1, 8, f) == 8 &&
               (std::memcmp(magic, "NLAMLP1", 8) == 0 || std::memcmp(magic, "NLAMLP2", 8) == 0) &&
               std::fread(&nw, 4, 1, f) == 1 && nw == NW && std::fread(&scale, 4, 1, f) == 1 &&
               std::fread(&step, 8, 1, f) == 1 && std::fread(&adam_t, 8, 1, f) == 1 &&
               std::fread(buf.data(), 4, buf.size(), f) == buf.size();
     const bool v2 = ok && magic[6] == '2';
-    if (v2) ok = std::fread(dom, 8, 14, f) == 14 && valid_domain(dom);
+    if (v2) ok = std::fread(dom, 8, 4, f) == 4 && valid_domain(dom);
     std::fclose(f);
     if (!ok) { nla_set_error("%s is not a network checkpoint of this layout", path); return NLA_E_INVALID; }
     nla_mlp *M = nullptr;

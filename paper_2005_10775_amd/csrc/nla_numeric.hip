@@ -393,24 +393,18 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
 #pragma unroll
             for (int t = 0; t < 6; t++) ayy[t] = ws * a2p * M.m2[jj[t]][ll[t]];
         }
-        // queue the partial items: exclusive prefix over lanes of popcounts
-        const int cnt = __popc(pmask);
-        int pre = cnt;
+        // queue the partial items outer point by outer point (point 0 of every
+        // lane in lane order, then point 1, ...), so that a round of 64 queued
+        // items holds at most a few of any one lane: its owner then collects
+        // them in a short loop.  A lane's items keep their q order.
+        const unsigned long long lt = (1ull << lane) - 1ull;
+        int total = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            int v = __shfl_up(pre, off, 64);
-            if (lane >= off) pre += v;
-        }
-        const int total = __shfl(pre, 63, 64);
-        pre -= cnt;
-        {
-            int o = pre;
-            unsigned mm = pmask;
-            while (mm) {
-                int q = __ffs(mm) - 1;
-                mm &= mm - 1;
-                queue[o++] = (unsigned short)((lane << 8) | (r2 ? 0x80 : 0) | q);
-            }
+        for (int q = 0; q < NQ; q++) {
+            const bool mine = (pmask >> q) & 1u;
+            const unsigned long long bq = __ballot(mine);
+            if (mine) queue[total + __popcll(bq & lt)] = (unsigned short)((lane << 8) | (r2 ? 0x80 : 0) | q);
+            total += __popcll(bq);
         }
         __syncthreads();
         for (int ib = 0; ib < total; ib += 64) {
@@ -462,26 +456,30 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 c_cap += ns >> 16;
             }
             __syncthreads();
-            const int j0 = pre > ib ? pre : ib;
-            const int j1 = (pre + cnt) < (ib + 64) ? (pre + cnt) : (ib + 64);
-            for (int j = j0; j < j1; j++) {
-                const int q = queue[j] & 0x0f;
-                const bool rr = SW && (queue[j] & 0x80);
-                const double *r = res[j - ib];
+            // each owner adds its items of this round in q order; the outer
+            // points with none in the round are skipped by the whole wave
+            int qbase = 0;
 #pragma unroll
-                for (int qq = 0; qq < NQ; qq++)
-                    if (qq == q) {
-                        if (rr) m0b[qq] += r[0];
-                        else m0[qq] += r[0];
-                    }
-                const double *w4 = rr ? sW2[q] : sW[q];
-                const double W = w4[0];
+            for (int q = 0; q < NQ; q++) {
+                const bool mine = (pmask >> q) & 1u;
+                const unsigned long long bq = __ballot(mine);
+                const int pos = qbase + __popcll(bq & lt);
+                const bool inr = mine && pos >= ib && pos < ib + 64;
+                qbase += __popcll(bq);
+                if (__ballot(inr) == 0ull) continue;
+                if (inr) {
+                    const double *r = res[pos - ib];
+                    if (r2) m0b[SW ? q : 0] += r[0];
+                    else m0[q] += r[0];
+                    const double *w4 = r2 ? sW2[SW ? q : 0] : sW[q];
+                    const double W = w4[0];
 #pragma unroll
-                for (int a = 0; a < 3; a++)
+                    for (int a = 0; a < 3; a++)
 #pragma unroll
-                    for (int b = 0; b < 3; b++) axy[a][b] += w4[1 + a] * r[1 + b];
+                        for (int b = 0; b < 3; b++) axy[a][b] += w4[1 + a] * r[1 + b];
 #pragma unroll
-                for (int t = 0; t < 6; t++) ayy[t] += W * r[4 + t];
+                    for (int t = 0; t < 6; t++) ayy[t] += W * r[4 + t];
+                }
             }
             __syncthreads();
         }

@@ -128,11 +128,17 @@ def _learned_problem(d, band=0.02):
 
 
 def _narrow_domain():
-    """A training domain from 30 oracle candidates of the h = delta/4 family:
-    narrow enough that part of a delta/4 mesh's routed items fall outside."""
+    """The training domain of 400 oracle candidates of the h = delta/4 family
+    with its edge-length range narrowed by a tenth of its width at each end:
+    about a quarter of a jittered delta/4 mesh's far-from-tangency items fall
+    outside it."""
     U = cap_uniforms(20053, 0, 2500)
     valid, feat, _, _ = ob.cap_candidates(U, 0.25, 0.1, 0.02)
-    return ob.feature_domain(feat[valid][:30])
+    dom = ob.feature_domain(feat[valid][:400])
+    w = dom[3] - dom[2]
+    dom[2] += 0.1 * w
+    dom[3] -= 0.1 * w
+    return dom
 
 
 @pytest.mark.parametrize("domain", ["unbounded", "narrow"])

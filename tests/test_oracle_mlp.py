@@ -267,16 +267,17 @@ def test_training_domain_gate():
     exact-cap (8-arc) sums bitwise.  A domain taken from candidates of the
     h = delta/8 family (legs 1/8, +-0.1 h jitter) holds most partial items of a
     jittered h = delta/8 mesh and none of a h = delta/4 mesh: its squared edge
-    lengths in the network's frame lie in [0.8^2, 2 * 1.2^2] (legs of 1 moved by
-    at most 0.2 per coordinate), while a delta/4 triangle's longest edge has at
-    least 2 sqrt(2) * 0.8 there."""
+    lengths lie in [0.8^2, 2 * 1.2^2] / 64 (legs of 1/8 moved by at most 0.2/8
+    per coordinate), while a delta/4 triangle's longest edge has at least
+    2 sqrt(2) * 0.8 / 8."""
     from workloads import Problem, structured_mesh, constant_kernel_c
     from workloads.learned import mlp_init
     d = 0.1
     U = cap_uniforms(20052, 0, 20000)
     valid, feat, _, _ = ob.cap_candidates(U, 0.125, 0.1, 0.02)
     dom = ob.feature_domain(feat[valid])
-    assert 0.8 ** 2 <= dom[12] <= dom[13] <= 2 * 1.2 ** 2
+    assert 0.8 ** 2 / 64 <= dom[2] <= dom[3] <= 2 * 1.2 ** 2 / 64
+    assert (1 - 2 * 2 ** 0.5 / 8) ** 2 <= dom[0] <= 1 <= dom[1] <= (1 + 2 * 2 ** 0.5 / 8) ** 2
     w = ob.effective_weights(mlp_init(12, bias_scale=0.3))
     rng = np.random.default_rng(8)
     for h, expect_in in ((d / 8, True), (d / 4, False)):
@@ -285,9 +286,9 @@ def test_training_domain_gate():
                        inner="dunavant16", precision="learned")
         op_none = ob.OracleProblem(mesh, prob, mlp_w=w, mlp_scale=1e-5)
         op_inf = ob.OracleProblem(mesh, prob, mlp_w=w, mlp_scale=1e-5,
-                                  mlp_domain=np.r_[np.full(6, -np.inf), np.full(6, np.inf), -np.inf, np.inf])
+                                  mlp_domain=np.array([-np.inf, np.inf, -np.inf, np.inf]))
         op_empty = ob.OracleProblem(mesh, prob, mlp_w=w, mlp_scale=1e-5,
-                                    mlp_domain=np.r_[np.full(6, 1e30), np.full(6, 1e30), 1e30, 1e30])
+                                    mlp_domain=np.array([1e30, 1e30, 1e30, 1e30]))
         op_exact = ob.OracleProblem(mesh, Problem(delta=d, kernel_c=constant_kernel_c(d), ball="retri",
                                                   cap_edges=8, outer="dunavant7", inner="dunavant16"))
         n_part = n_in = 0
