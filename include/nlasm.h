@@ -225,6 +225,20 @@ int nla_near_view(const nla_plan *plan, int64_t *n_near, const int64_t **near_pa
 int nla_cg(const nla_plan *plan, const double *b, double *u, double rtol, int32_t maxit,
            int32_t *iters, double *relres, void *stream);
 
+/* nla_cg for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * iteration and kernels, bitwise the same results, with its scratch (r, p, Ap
+ * and the dot products' partial sums) in a device array of the library that
+ * every device it runs on holds from the module's load until the process ends
+ * (24 MiB), instead of memory allocated per call.  Calls no hipMalloc or
+ * hipFree.  n_free at most NLA_CG_NOALLOC_MAX_FREE, else NLA_E_INVALID; the
+ * plan's device must be current (NLA_E_DEVICE otherwise).  Every call on a
+ * device shares that device's scratch, so calls that overlap on one device
+ * (two streams, two threads) race: serialise them.  No scratch value is read
+ * before the call writes it.  Other arguments and errors as nla_cg. */
+#define NLA_CG_NOALLOC_MAX_FREE 1048576
+int nla_cg_noalloc(const nla_plan *plan, const double *b, double *u, double rtol, int32_t maxit,
+                   int32_t *iters, double *relres, void *stream);
 
 /* Timing: nla_set_timing(plan, n) with n > 0 makes the next n calls of
  * nla_assemble record HIP events on their stream around each phase (n = 0

@@ -81,6 +81,7 @@ def lib():
         L.nla_blocks_view.argtypes = [P, C.POINTER(P), C.POINTER(P), C.POINTER(P), C.POINTER(P),
                                       C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
         L.nla_cg.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P]
+        L.nla_cg_noalloc.argtypes = [P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P]
         L.nla_near_view.argtypes = [P, C.POINTER(I64), C.POINTER(P), C.POINTER(P), C.POINTER(I32)]
         L.nla_batch_create.argtypes = [I32, P, P, P, C.POINTER(P)]
         L.nla_batch_assemble.argtypes = [P, I32, P, P, P]
@@ -107,7 +108,7 @@ def lib():
         L.nla_mlp_destroy.argtypes = [P]
         L.nla_mlp_destroy.restype = None
         for name in ("nla_plan_create", "nla_plan_info", "nla_pairs_view", "nla_outer_points", "nla_assemble",
-                     "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg",
+                     "nla_csr_view", "nla_load_view", "nla_free_nodes_view", "nla_blocks_view", "nla_cg", "nla_cg_noalloc",
                      "nla_set_timing", "nla_timings", "nla_near_view", "nla_batch_create",
                      "nla_batch_assemble", "nla_batch_plan", "nla_batch_info", "nla_batch_autotune",
                      "nla_mlp_create", "nla_mlp_set_weights", "nla_mlp_get_weights", "nla_mlp_samples",
@@ -321,12 +322,14 @@ class Plan:
         return (_copy_from_device(a.value, n.value, torch.int64, stream),
                 _copy_from_device(b.value, 21 * n.value, t, stream).view(-1, 21))
 
-    def cg(self, b, u0=None, rtol=1e-12, maxit=10000, stream=None):
+    def cg(self, b, u0=None, rtol=1e-12, maxit=10000, stream=None, noalloc=False):
+        """noalloc: nla_cg_noalloc (scratch in the library's device array)."""
         n = self.info()["n_free"]
         u = torch.zeros(n, dtype=torch.float64, device="cuda") if u0 is None else u0.clone()
         it, rr = C.c_int32(), C.c_double()
-        code = lib().nla_cg(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(u.data_ptr()), rtol, maxit,
-                            C.byref(it), C.byref(rr), _stream(stream))
+        fn = lib().nla_cg_noalloc if noalloc else lib().nla_cg
+        code = fn(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(u.data_ptr()), rtol, maxit,
+                  C.byref(it), C.byref(rr), _stream(stream))
         _check(code)
         return u, it.value, rr.value
 

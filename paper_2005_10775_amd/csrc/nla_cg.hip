@@ -3,6 +3,7 @@
 // vectors and residuals whatever the precision of the matrix values.
 #include "nla_internal.hpp"
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 static inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -103,20 +104,12 @@ static int dot(int n, const double *x, const double *y, double *part, double *ou
     return NLA_OK;
 }
 
-int nla_cg_run(const nla_plan *P, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
-               double *relres, hipStream_t s)
+// The iteration on caller-provided scratch: r, p, Ap [n], part [ceil(n/256)],
+// out [1]; every value is written before it is read.
+static int cg_solve(const nla_plan *P, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+                    double *relres, hipStream_t s, double *r, double *p, double *Ap, double *part, double *out)
 {
     const int n = P->n_free;
-    *iters = 0;
-    *relres = 0.0;
-    if (n == 0) return NLA_OK;
-    CgScratch S;
-    double *r, *p, *Ap, *part, *out;
-    NLA_TRY(S.get(&r, n));
-    NLA_TRY(S.get(&p, n));
-    NLA_TRY(S.get(&Ap, n));
-    NLA_TRY(S.get(&part, grid_for(n, 256)));
-    NLA_TRY(S.get(&out, 1));
     const unsigned g = grid_for(n, 256);
     auto spmv = [&](const double *x, double *y) {
         if (P->val_dtype == NLA_DTYPE_F64)
@@ -155,4 +148,88 @@ int nla_cg_run(const nla_plan *P, const double *b, double *u, double rtol, int32
         return NLA_E_NOT_CONVERGED;
     }
     return NLA_OK;
+}
+
+int nla_cg_run(const nla_plan *P, const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+               double *relres, hipStream_t s)
+{
+    const int n = P->n_free;
+    *iters = 0;
+    *relres = 0.0;
+    if (n == 0) return NLA_OK;
+    CgScratch S;
+    double *r, *p, *Ap, *part, *out;
+    NLA_TRY(S.get(&r, n));
+    NLA_TRY(S.get(&p, n));
+    NLA_TRY(S.get(&Ap, n));
+    NLA_TRY(S.get(&part, grid_for(n, 256)));
+    NLA_TRY(S.get(&out, 1));
+    return cg_solve(P, b, u, rtol, maxit, iters, relres, s, r, p, Ap, part, out);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free CG.  Its scratch (r, p, Ap for up to NLA_CG_NOALLOC_MAX_FREE
+// free nodes, the dot products' block sums and their result) is a file-scope
+// device array: each device the library runs on holds its own copy, 24 MiB and
+// 32 KiB, from the module's load until the process ends.  Host code never
+// passes the array's name to a kernel: the name is a host-side stand-in, and
+// the copy's device address comes from hipGetSymbolAddress, taken once per
+// device with that device current and kept in cg_scratch_ptr.
+namespace {
+constexpr size_t CG_PART_MAX = (NLA_CG_NOALLOC_MAX_FREE + 255) / 256;
+constexpr size_t CG_SCRATCH_DOUBLES = 3 * (size_t)NLA_CG_NOALLOC_MAX_FREE + CG_PART_MAX + 32;
+constexpr int CG_MAX_DEVICES = 64;
+std::mutex cg_scratch_mu;
+double *cg_scratch_ptr[CG_MAX_DEVICES] = {};
+} // namespace
+
+static __device__ __align__(256) double scratch[CG_SCRATCH_DOUBLES];
+
+// the device address of `scratch` on device dev (the current device)
+static int cg_scratch_on(int dev, double **out)
+{
+    std::lock_guard<std::mutex> lock(cg_scratch_mu);
+    if (dev < 0 || dev >= CG_MAX_DEVICES) {
+        nla_set_error("device %d is beyond the %d devices the allocation-free CG serves", dev, CG_MAX_DEVICES);
+        return NLA_E_DEVICE;
+    }
+    if (!cg_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            nla_set_error("hipGetSymbolAddress of the CG scratch failed on device %d: %s", dev, hipGetErrorString(e));
+            return NLA_E_DEVICE;
+        }
+        cg_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = cg_scratch_ptr[dev];
+    return NLA_OK;
+}
+
+extern "C" int nla_cg_noalloc(const nla_plan *P, const double *b, double *u, double rtol, int32_t maxit,
+                              int32_t *iters, double *relres, void *stream)
+{
+    if (!P || !b || !u || !iters || !relres) { nla_set_error("null argument"); return NLA_E_INVALID; }
+    if (!P->assembled) { nla_set_error("nla_assemble has not run"); return NLA_E_STATE; }
+    if (maxit < 1 || !(rtol > 0)) { nla_set_error("maxit >= 1 and rtol > 0 required"); return NLA_E_INVALID; }
+    const int n = P->n_free;
+    if (n > NLA_CG_NOALLOC_MAX_FREE) {
+        nla_set_error("%d free nodes exceed the allocation-free CG's scratch (at most %d); use nla_cg", n,
+                      NLA_CG_NOALLOC_MAX_FREE);
+        return NLA_E_INVALID;
+    }
+    int dev = -1;
+    NLA_HIP(hipGetDevice(&dev));
+    if (dev != P->device) {
+        nla_set_error("the plan lives on device %d but device %d is current", P->device, dev);
+        return NLA_E_DEVICE;
+    }
+    *iters = 0;
+    *relres = 0.0;
+    if (n == 0) return NLA_OK;
+    double *base = nullptr;
+    NLA_TRY(cg_scratch_on(dev, &base));
+    double *r = base, *p = r + NLA_CG_NOALLOC_MAX_FREE, *Ap = p + NLA_CG_NOALLOC_MAX_FREE;
+    double *part = Ap + NLA_CG_NOALLOC_MAX_FREE, *out = part + CG_PART_MAX;
+    return cg_solve(P, b, u, rtol, maxit, iters, relres, (hipStream_t)stream, r, p, Ap, part, out);
 }
