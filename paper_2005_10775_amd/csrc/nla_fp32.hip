@@ -1340,6 +1340,10 @@ struct nla_batch {
     int max_cols = 0;
     int chunk = 1, grid = 0;
     hipStream_t stream = nullptr;
+    // second stream (default priority) on which the singular pairs run beside
+    // the persistent regular-pair launch, forked and joined by events in the graph
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -1351,6 +1355,9 @@ struct nla_batch {
         if (graph) (void)hipGraphDestroy(graph);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
         if (stream) (void)hipStreamDestroy(stream);
         for (nla_plan *p : plans) nla_plan_destroy(p);
     }
@@ -1361,9 +1368,17 @@ static int batch_launch(nla_batch *B, hipStream_t s)
     const int n = B->n;
     k_batch_zero<<<grid_for(6 * n + 1, 256), 256, 0, s>>>(n, B->d_inst, B->d_cursor);
     const size_t lds = (size_t)B->max_cols * (6 * sizeof(float) + sizeof(unsigned));
+    // the singular pairs (their own blocks, read only by the segmented sum) run on
+    // the side stream beside the regular pairs and the element blocks
+    if (B->tot_near > 0) {
+        NLA_HIP(hipEventRecord(B->ev_fork, s));
+        NLA_HIP(hipStreamWaitEvent(B->side, B->ev_fork, 0));
+        k_batch_near<<<(unsigned)B->tot_near, 64, 0, B->side>>>(n, B->d_inst, B->d_off_near);
+        NLA_HIP(hipEventRecord(B->ev_join, B->side));
+    }
     k_pairs_fp32_persistent<8, true><<<B->grid, 64, lds, s>>>(B->d_args, B->d_work, B->n_work, B->chunk, B->d_cursor);
-    if (B->tot_near > 0) k_batch_near<<<(unsigned)B->tot_near, 64, 0, s>>>(n, B->d_inst, B->d_off_near);
     k_batch_elem<<<(unsigned)B->tot_k, 64, 0, s>>>(n, B->d_inst, B->d_off_k);
+    if (B->tot_near > 0) NLA_HIP(hipStreamWaitEvent(s, B->ev_join, 0));
     k_batch_segsum<<<grid_for(B->tot_up, 256), 256, 0, s>>>(n, B->d_inst, B->d_off_up, B->tot_up);
     if (B->tot_a > 0) k_batch_extract<<<grid_for(B->tot_a, 256), 256, 0, s>>>(n, B->d_inst, B->d_off_a, B->tot_a);
     k_batch_load_elem<<<grid_for(B->tot_k, 256), 256, 0, s>>>(n, B->d_inst, B->d_off_k, B->tot_k);
@@ -1507,6 +1522,9 @@ static int batch_create(int32_t n, const nla_mesh *meshes, const nla_problem *pr
     B->chunk = 1;
     B->grid = 8 * B->n_cu;
     NLA_HIP(hipStreamCreate(&B->stream));
+    NLA_HIP(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    NLA_HIP(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+    NLA_HIP(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
     NLA_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
     NLA_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
     return NLA_OK;

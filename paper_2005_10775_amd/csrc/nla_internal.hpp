@@ -62,6 +62,10 @@ struct ElemSoA {
     double *bx, *by;                           // barycenter ((v0+v1)+v2)/3
     double *a2;                                // twice the area
     double *r;                                 // max vertex distance from the barycenter
+    // the same per element as one 128-byte record (one cache line): v0x, v0y,
+    // v1x, v1y, v2x, v2y, bx, by, a2, r, then padding; kernels that gather an
+    // inner element's data by index read it in five 16-byte loads
+    double *pk;                                // [K][16]
 };
 
 // Training domain of a learned cap network: an item goes to the network only

@@ -141,12 +141,24 @@ __device__ __forceinline__ unsigned *init_row_block(unsigned *dyn, double *__res
                                                     const int32_t *__restrict__ cptr, int cbase,
                                                     const uint16_t *__restrict__ colent, int lane)
 {
-    for (int c = lane; c < nC; c += 64) {
-        const int e0 = cptr[c];
-        const bool any = e0 < cptr[c + 1];
-        const unsigned nx = any ? (unsigned)(colent[e0] >> 2) : 0xffffu;
-        dyn[c] = (nx << 16) | (unsigned)(e0 - cbase);
-        if (!any) Rg[c] = Rg[nC + c] = Rg[2 * nC + c] = 0.0;
+    // four columns per lane at a time, so that their loads share the round trips
+    for (int c0 = lane; c0 < nC; c0 += 256) {
+        int e0[4], e1[4], nx[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int c = c0 + 64 * j;
+            e0[j] = c < nC ? cptr[c] : 0;
+            e1[j] = c < nC ? cptr[c + 1] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) nx[j] = e0[j] < e1[j] ? (int)(colent[e0[j]] >> 2) : 0xffff;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int c = c0 + 64 * j;
+            if (c >= nC) continue;
+            dyn[c] = ((unsigned)nx[j] << 16) | (unsigned)(e0[j] - cbase);
+            if (e0[j] >= e1[j]) Rg[c] = Rg[nC + c] = Rg[2 * nC + c] = 0.0;
+        }
     }
     return dyn;
 }
@@ -326,14 +338,19 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         double V[6] = {0, 0, 0, 0, 0, 0};
         double a2p = 0.0, bxp = 0.0, byp = 0.0;
         const int kp = act ? (proc_kp ? proc_kp[pi] : pair_kp[pi]) : 0;
-        if (act) a2p = E.a2[kp];
-        if (deep) dsum += a2p;
         if (act && !deep) {
+            // the inner element's record in five 16-byte loads
+            const double2 *rec = (const double2 *)(E.pk + 16 * (int64_t)kp);
+            const double2 r0 = rec[0], r1 = rec[1], r2v = rec[2], r3 = rec[3], r4 = rec[4];
+            V[0] = r0.x; V[1] = r0.y; V[2] = r1.x; V[3] = r1.y; V[4] = r2v.x; V[5] = r2v.y;
+            bxp = r3.x;
+            byp = r3.y;
+            a2p = r4.x;
+        } else if (act) {
             // a deep pair needs only the inner element's area
-            V[0] = E.vx0[kp]; V[1] = E.vy0[kp]; V[2] = E.vx1[kp]; V[3] = E.vy1[kp]; V[4] = E.vx2[kp]; V[5] = E.vy2[kp];
-            bxp = E.bx[kp];
-            byp = E.by[kp];
+            a2p = E.a2[kp];
         }
+        if (deep) dsum += a2p;
         skp[lane] = kp;
         if (SW) {
 #pragma unroll
@@ -418,9 +435,9 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
 #pragma unroll
                     for (int i = 0; i < 6; i++) Vo[i] = sV[SW ? owner : 0][i];
                 } else {
-                    const int kq = skp[owner];
-                    Vo[0] = E.vx0[kq]; Vo[1] = E.vy0[kq]; Vo[2] = E.vx1[kq]; Vo[3] = E.vy1[kq]; Vo[4] = E.vx2[kq];
-                    Vo[5] = E.vy2[kq];
+                    const double2 *rec = (const double2 *)(E.pk + 16 * (int64_t)skp[owner]);
+                    const double2 r0 = rec[0], r1 = rec[1], r2v = rec[2];
+                    Vo[0] = r0.x; Vo[1] = r0.y; Vo[2] = r1.x; Vo[3] = r1.y; Vo[4] = r2v.x; Vo[5] = r2v.y;
                 }
                 Acc A;
                 A.a2 = 0.0;
@@ -502,11 +519,23 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
         // the deep pairs: their areas (kept in an LDS table by deep slot when the
         // launch gives room for one), and each item counted whole
         double *tab = (double *)(dyn + dtab_off);
-        for (int64_t pi = pend + lane; pi < p1; pi += 64) {
-            const double a2 = E.a2[proc_kp[pi]];
-            dsum += a2;
-            if (dtab_off) tab[pi - pend] = a2;
-            c_whole += (SW && nq2 > 0 && pair_r2[proc_p[pi]]) ? nq2 : nq;
+        // four pairs per lane at a time: their indices, then their areas, then
+        // the sums in the lane's pair order
+        for (int64_t pi0 = pend + lane; pi0 < p1; pi0 += 256) {
+            int kq[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) kq[j] = pi0 + 64 * j < p1 ? proc_kp[pi0 + 64 * j] : -1;
+            double av[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) av[j] = kq[j] >= 0 ? E.a2[kq[j]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                if (kq[j] < 0) continue;
+                const int64_t pi = pi0 + 64 * j;
+                dsum += av[j];
+                if (dtab_off) tab[pi - pend] = av[j];
+                c_whole += (SW && nq2 > 0 && pair_r2[proc_p[pi]]) ? nq2 : nq;
+            }
         }
         __syncthreads();
         const int nbr = (int)(pend - p0);

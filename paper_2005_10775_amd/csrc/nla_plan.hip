@@ -306,6 +306,13 @@ __global__ void k_elem(int K, const double *__restrict__ xy, const int32_t *__re
         r = fmax(r, sqrt(dx * dx + dy * dy));
     }
     E.r[k] = r;
+    double2 *rec = (double2 *)(E.pk + 16 * (int64_t)k);
+    rec[0] = make_double2(x0, y0);
+    rec[1] = make_double2(x1, y1);
+    rec[2] = make_double2(x2, y2);
+    rec[3] = make_double2(bx, by);
+    rec[4] = make_double2(E.a2[k], r);
+    rec[5] = rec[6] = rec[7] = make_double2(0.0, 0.0);
     const int nq = R->n_out;
     for (int q = 0; q < nq; q++) {
         const double l0 = R->out_lam[q][0], l1 = R->out_lam[q][1], l2 = R->out_lam[q][2];
@@ -1446,6 +1453,7 @@ static int plan_create(const nla_mesh *m, const nla_problem *p, hipStream_t s, n
     double **f[10] = {&P->E.vx0, &P->E.vy0, &P->E.vx1, &P->E.vy1, &P->E.vx2, &P->E.vy2,
                       &P->E.bx, &P->E.by, &P->E.a2, &P->E.r};
     for (int i = 0; i < 10; i++) *f[i] = eb + (size_t)i * K;
+    NLA_TRY(P->arena.get(&P->E.pk, 16 * (size_t)K));
     NLA_TRY(P->arena.get(&P->xq, 2 * (size_t)K * P->rules.n_out));
     if (P->rules.n_out2 > 0) NLA_TRY(P->arena.get(&P->xq2, 2 * (size_t)K * P->rules.n_out2));
     NLA_HIP(hipMemcpyAsync(P->d_rules, &P->rules, sizeof(RuleSet), hipMemcpyHostToDevice, s));
