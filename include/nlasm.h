@@ -258,10 +258,11 @@ void nla_plan_destroy(nla_plan *plan);
  * (ordered after and before the caller's stream with events), of either one
  * persistent launch of the pair kernel (a fixed grid taking (instance, outer
  * element) work items, heaviest first, from a device cursor) followed by
- * instance-batched near-pair, element-block, segmented-sum, extraction and
- * load kernels, or (chunk 0, when the autotuner times it faster) every
- * instance's own launches; mode 0 assembles the instances one after the other
- * with their own launches.  All give bitwise identical values. */
+ * instance-batched near-pair (on a second stream beside the pair kernel),
+ * element-block, segmented-sum, extraction and load kernels, or (chunk 0,
+ * when the autotuner times it faster) every instance's own launches; mode 0
+ * assembles the instances one after the other with their own launches.  All
+ * give bitwise identical values. */
 typedef struct nla_batch nla_batch;
 typedef struct {
     int32_t n;                   /* instances */

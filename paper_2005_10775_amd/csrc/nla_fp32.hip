@@ -48,52 +48,62 @@ struct AccF {
 
 // Inner rule on one subtriangle t (vertices relative to x, basis values at the
 // vertices).  FRAC: psi = kc r^(2*ex) evaluated at every rule point y in FP32
-// (r^2 = |y - x|^2); otherwise psi = kc and the rule is applied through its
-// moments (sym form, as in the FP64 kernel).
+// (r^2 = |y - x|^2, hardware log2 and exp2); the point's weight times the
+// monomials 1, xi, eta, xi^2, xi eta, eta^2 of its coordinates (xi, eta) about
+// vertex 0 of E' (at (ox, oy) from x) are summed in FP64 into mono, which
+// mono_sums turns into the basis integrals once per item: the basis is affine
+// in (xi, eta), so the same numbers follow with a third of the work per point.
+// Otherwise psi = kc and the rule is applied through its moments (sym form, as
+// in the FP64 kernel).
 template <int FM>
 struct TriF32 {
     const RuleSet *R;
     float kc, ex, m1c, o, dm;
     AccF *A;
     bool frac_rt;   // FM == 2: kernel chosen at run time (uniform per instance)
+    double ox, oy;  // FRAC: vertex 0 of E' relative to x
+    double *mono;   // FRAC: the item's monomial sums [6]
     __device__ __forceinline__ void operator()(const double (&t)[3][5]) const
     {
         const bool FRAC = FM == 2 ? frac_rt : FM == 1;
         const double a2d = fabs((t[1][0] - t[0][0]) * (t[2][1] - t[0][1]) - (t[1][1] - t[0][1]) * (t[2][0] - t[0][0]));
         const float a2 = (float)a2d;
-        float tb[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int l = 0; l < 3; l++) tb[i][l] = (float)t[i][2 + l];
         const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
         if (FRAC) {
-            const float tx[3] = {(float)t[0][0], (float)t[1][0], (float)t[2][0]};
-            const float ty[3] = {(float)t[0][1], (float)t[1][1], (float)t[2][1]};
-            float q0 = 0.f, q1[3] = {0.f, 0.f, 0.f}, q2[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const float tx[3] = {(float)(t[0][0] - ox), (float)(t[1][0] - ox), (float)(t[2][0] - ox)};
+            const float ty[3] = {(float)(t[0][1] - oy), (float)(t[1][1] - oy), (float)(t[2][1] - oy)};
+            const float oxf = (float)ox, oyf = (float)oy;
+            double q0 = 0.0, qx = 0.0, qy = 0.0, qxx = 0.0, qxy = 0.0, qyy = 0.0;
             const int n = R->n_in;
             for (int q = 0; q < n; q++) {
                 const float m0 = R->in_lamf[q][0], m1 = R->in_lamf[q][1], m2 = R->in_lamf[q][2];
-                const float yx = m0 * tx[0] + m1 * tx[1] + m2 * tx[2];
-                const float yy = m0 * ty[0] + m1 * ty[1] + m2 * ty[2];
-                float b[3];
-#pragma unroll
-                for (int l = 0; l < 3; l++) b[l] = m0 * tb[0][l] + m1 * tb[1][l] + m2 * tb[2][l];
-                const float r2 = yx * yx + yy * yy;
+                const float xi = m0 * tx[0] + m1 * tx[1] + m2 * tx[2];
+                const float eta = m0 * ty[0] + m1 * ty[1] + m2 * ty[2];
+                const float dx = xi + oxf, dy = eta + oyf;
+                const float r2 = dx * dx + dy * dy;
                 // hardware log2 / exp2 (v_log_f32, v_exp_f32): r^(2 ex) = 2^(ex log2 r^2)
                 const float wp = R->in_wf[q] * kc * __builtin_amdgcn_exp2f(ex * __builtin_amdgcn_logf(r2));
-                q0 += wp;
-#pragma unroll
-                for (int l = 0; l < 3; l++) q1[l] += wp * b[l];
-#pragma unroll
-                for (int e = 0; e < 6; e++) q2[e] += wp * b[jj[e]] * b[ll[e]];
+                const double wd = (double)wp, xd = (double)xi, yd = (double)eta;
+                const double wx = wd * xd, wy = wd * yd;
+                q0 += wd;
+                qx += wx;
+                qy += wy;
+                qxx += wx * xd;
+                qxy += wx * yd;
+                qyy += wy * yd;
             }
-            A->s0.add(a2 * q0);
-#pragma unroll
-            for (int l = 0; l < 3; l++) A->s1[l].add(a2 * q1[l]);
-#pragma unroll
-            for (int e = 0; e < 6; e++) A->s2[e].add(a2 * q2[e]);
+            mono[0] += a2d * q0;
+            mono[1] += a2d * qx;
+            mono[2] += a2d * qy;
+            mono[3] += a2d * qxx;
+            mono[4] += a2d * qxy;
+            mono[5] += a2d * qyy;
         } else {
+            float tb[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int l = 0; l < 3; l++) tb[i][l] = (float)t[i][2 + l];
             float cs[3];
 #pragma unroll
             for (int l = 0; l < 3; l++) cs[l] = tb[0][l] + tb[1][l] + tb[2][l];
@@ -110,6 +120,24 @@ struct TriF32 {
         }
     }
 };
+
+// The basis integrals S0, S1_b, S2_bc of an item (into A, FP32) from the FP64
+// sums of its points' weights times the monomials about vertex 0 of E'
+// (TriF32, FRAC), through the rows g of the inverse edge matrix of E': the
+// conversion of the boundary form (region_sums_g) with the sums in its scaling.
+__device__ __forceinline__ void mono_sums(const double (&m)[6], const double *Vl, AccF &A)
+{
+    double g[4];
+    inv_edges(Vl, g);
+    const RegionMom Rm = {2.0 * m[0], 6.0 * m[1], 6.0 * m[2], 12.0 * m[3], 24.0 * m[4], 12.0 * m[5]};
+    double s0, s1[3], s2[6];
+    region_sums_g(Rm, g, s0, s1, s2);
+    A.s0.s = (float)s0;
+#pragma unroll
+    for (int t = 0; t < 3; t++) A.s1[t].s = (float)s1[t];
+#pragma unroll
+    for (int t = 0; t < 6; t++) A.s2[t].s = (float)s2[t];
+}
 
 // LDS of one pair-kernel wavefront (declared by the kernels, so that the
 // persistent kernel's two bodies share it)
@@ -254,12 +282,14 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                         // psi varies: the inner rule over all of E_k'
                         AccF A;
                         A.zero();
-                        TriF32<1> tri{R, kc, ex, m1c, o, dm, &A, true};
+                        double mono[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                        TriF32<1> tri{R, kc, ex, m1c, o, dm, &A, true, V[0] - xx, V[1] - xy, mono};
                         double t[3][5];
                         set5(t[0], V[0] - xx, V[1] - xy, 1.0, 0.0, 0.0);
                         set5(t[1], V[2] - xx, V[3] - xy, 0.0, 1.0, 0.0);
                         set5(t[2], V[4] - xx, V[5] - xy, 0.0, 0.0, 1.0);
                         tri(t);
+                        mono_sums(mono, V, A);
                         m0[q].add(A.s0.s);
 #pragma unroll
                         for (int a = 0; a < 3; a++)
@@ -337,7 +367,8 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 const double Vo[6] = {E.vx0[kq], E.vy0[kq], E.vx1[kq], E.vy1[kq], E.vx2[kq], E.vy2[kq]};
                 AccF A;
                 A.zero();
-                TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC};
+                double mono[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC, Vo[0] - sX[q][0], Vo[1] - sX[q][1], mono};
                 int ns = 0;
                 // routed items: the inscribed polygon only here; the owner adds the
                 // network's cap moments when it collects the result
@@ -359,6 +390,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 } else {
                     partial_item<POW2>(sX[q][0], sX[q][1], Vo, dd, routed ? 0 : ncap, tri, ns,
                                        &capbuf[lane][0]);
+                    if (FRAC) mono_sums(mono, Vo, A);
                     res[lane][0] = A.s0.s;
 #pragma unroll
                     for (int t = 0; t < 3; t++) res[lane][1 + t] = A.s1[t].s;
@@ -712,6 +744,104 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
 // r^(m-1-2s), m = 0,1,2, is exact between the entry and exit radii (exit
 // capped at delta).  Per outer point the ray sums reduce to six angular
 // moments, then to the 21 upper entries of the block.  One wavefront per pair.
+// ---------------------------------------------------------------------------
+// Elementary functions of the singular-pair rule (FP64), each written from its
+// series for the bounded arguments the rule produces: cheaper than the general
+// library forms, accurate to a few units in the last place.
+
+// sin and cos of t, |t| < 8 pi: t = k pi/2 + r with pi/2 in two parts (the
+// first of 33 significant bits, so k times it is exact), |r| <= pi/4 up to
+// rounding; Taylor series of sin r to r^17 and of cos r to r^16 (the first
+// omitted terms are below 1e-19 and 3e-18), then the quadrant k mod 4.
+__device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
+{
+    const double k = rint(t * 0.63661977236758134308);          // 2/pi
+    const double r = (t - k * 1.5707963267341256) - k * 6.077100506506192e-11;
+    const double z = r * r;
+    double ps = 1.0 / 355687428096000.0;                         // 1/17!
+    ps = fma(ps, z, -1.0 / 1307674368000.0);                     // -1/15!
+    ps = fma(ps, z, 1.0 / 6227020800.0);                         // 1/13!
+    ps = fma(ps, z, -1.0 / 39916800.0);                          // -1/11!
+    ps = fma(ps, z, 1.0 / 362880.0);                             // 1/9!
+    ps = fma(ps, z, -1.0 / 5040.0);                              // -1/7!
+    ps = fma(ps, z, 1.0 / 120.0);                                // 1/5!
+    ps = fma(ps, z, -1.0 / 6.0);                                 // -1/3!
+    ps = fma(ps, z, 1.0);
+    double pc = 1.0 / 20922789888000.0;                          // 1/16!
+    pc = fma(pc, z, -1.0 / 87178291200.0);                       // -1/14!
+    pc = fma(pc, z, 1.0 / 479001600.0);                          // 1/12!
+    pc = fma(pc, z, -1.0 / 3628800.0);                           // -1/10!
+    pc = fma(pc, z, 1.0 / 40320.0);                              // 1/8!
+    pc = fma(pc, z, -1.0 / 720.0);                               // -1/6!
+    pc = fma(pc, z, 1.0 / 24.0);                                 // 1/4!
+    pc = fma(pc, z, -0.5);                                       // -1/2!
+    pc = fma(pc, z, 1.0);
+    const double s0 = r * ps, c0 = pc;
+    const int q = ((int)k) & 3;
+    sn = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
+    cs = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+}
+
+// log2 of a positive normal r: r = 2^e m with m in [sqrt(1/2), sqrt(2)),
+// ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 0.1716, by its series to
+// s^19 (the first omitted term is below 4e-18 relative)
+__device__ __forceinline__ double log2_pos(double r)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(r);
+    int e = (int)((b >> 52) & 0x7ffull) - 1023;
+    double m = __longlong_as_double((long long)((b & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+    if (m > 1.4142135623730951) {
+        m *= 0.5;
+        e += 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0), z = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    return (double)e + (2.0 * s * p) * 1.4426950408889634074;   // 1/ln 2
+}
+
+// 2^y for |y| < 1000: y = n + f with |f| <= 1/2, e^(f ln 2) by its Taylor
+// series to degree 13 (the first omitted term is below 5e-18), times 2^n built
+// from its exponent bits
+__device__ __forceinline__ double exp2_bounded(double y)
+{
+    const double n = rint(y);
+    const double g = (y - n) * 0.69314718055994530942;           // ln 2
+    double p = 1.0 / 6227020800.0;                               // 1/13!
+    p = fma(p, g, 1.0 / 479001600.0);
+    p = fma(p, g, 1.0 / 39916800.0);
+    p = fma(p, g, 1.0 / 3628800.0);
+    p = fma(p, g, 1.0 / 362880.0);
+    p = fma(p, g, 1.0 / 40320.0);
+    p = fma(p, g, 1.0 / 5040.0);
+    p = fma(p, g, 1.0 / 720.0);
+    p = fma(p, g, 1.0 / 120.0);
+    p = fma(p, g, 1.0 / 24.0);
+    p = fma(p, g, 1.0 / 6.0);
+    p = fma(p, g, 0.5);
+    p = fma(p, g, 1.0);
+    p = fma(p, g, 1.0);
+    return p * __longlong_as_double((long long)((unsigned long long)((long long)n + 1023) << 52));
+}
+
+// 1/x to about an ulp: the hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 template <class T>
 __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__restrict__ near_pair, const int32_t *__restrict__ pk,
                           const int32_t *__restrict__ pkp, const int32_t *__restrict__ tri, const ElemSoA &E,
@@ -850,7 +980,7 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
                 const double th = lo[pc] + (hi[pc] - lo[pc]) * (u * u * (3.0 - 2.0 * u));
                 const double wt = (hi[pc] - lo[pc]) * R->duffy_w[it] * 6.0 * u * (1.0 - u);
                 double sn, cs;
-                sincos(th, &sn, &cs);
+                sincos_bounded(th, sn, cs);
                 double rin = 0.0, rout = 1e300;
                 bool empty = false;
                 for (int a = 0; a < 3; a++) {
@@ -858,15 +988,16 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
                     const double nx = Vp[2 * b + 1] - Vp[2 * a + 1], ny = -(Vp[2 * b] - Vp[2 * a]);
                     const double f0 = nx * (x[0] - Vp[2 * a]) + ny * (x[1] - Vp[2 * a + 1]);
                     const double f1 = nx * cs + ny * sn;
-                    if (f1 > 0.0) rout = fmin(rout, -f0 / f1);
-                    else if (f1 < 0.0) rin = fmax(rin, -f0 / f1);
+                    if (f1 > 0.0) rout = fmin(rout, -f0 * rcp_nr(f1));
+                    else if (f1 < 0.0) rin = fmax(rin, -f0 * rcp_nr(f1));
                     else if (f0 > 0.0) empty = true;
                 }
                 rout = fmin(rout, delta);
                 if (empty || !(rout > rin)) continue;
                 // J_m = kc (rout^(m+e0) - rin^(m+e0)) / (m + e0)
                 double J[3];
-                const double po = exp2(e0 * log2(rout)), pi = rin > 0.0 ? exp2(e0 * log2(rin)) : 0.0;
+                const double po = exp2_bounded(e0 * log2_pos(rout));
+                const double pi = rin > 0.0 ? exp2_bounded(e0 * log2_pos(rin)) : 0.0;
                 double ro = 1.0, ri = 1.0;
                 for (int m = 0; m < 3; m++) {
                     const double ex = m + e0;
