@@ -753,33 +753,54 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
 // first of 33 significant bits, so k times it is exact), |r| <= pi/4 up to
 // rounding; Taylor series of sin r to r^17 and of cos r to r^16 (the first
 // omitted terms are below 1e-19 and 3e-18), then the quadrant k mod 4.
+// a*b + c as one VOP3 fused multiply-add: a Horner step whose constant addend
+// sits in a register then needs no copy of it
+__device__ __forceinline__ double fma_v(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 __device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
 {
     const double k = rint(t * 0.63661977236758134308);          // 2/pi
     const double r = (t - k * 1.5707963267341256) - k * 6.077100506506192e-11;
-    const double z = r * r;
+    // both series in w = -r^2, so that their coefficients 1/k! are positive and
+    // shared with the exponential's
+    const double w = -(r * r);
     double ps = 1.0 / 355687428096000.0;                         // 1/17!
-    ps = fma(ps, z, -1.0 / 1307674368000.0);                     // -1/15!
-    ps = fma(ps, z, 1.0 / 6227020800.0);                         // 1/13!
-    ps = fma(ps, z, -1.0 / 39916800.0);                          // -1/11!
-    ps = fma(ps, z, 1.0 / 362880.0);                             // 1/9!
-    ps = fma(ps, z, -1.0 / 5040.0);                              // -1/7!
-    ps = fma(ps, z, 1.0 / 120.0);                                // 1/5!
-    ps = fma(ps, z, -1.0 / 6.0);                                 // -1/3!
-    ps = fma(ps, z, 1.0);
+    ps = fma_v(ps, w, 1.0 / 1307674368000.0);                      // 1/15!
+    ps = fma_v(ps, w, 1.0 / 6227020800.0);                         // 1/13!
+    ps = fma_v(ps, w, 1.0 / 39916800.0);                           // 1/11!
+    ps = fma_v(ps, w, 1.0 / 362880.0);                             // 1/9!
+    ps = fma_v(ps, w, 1.0 / 5040.0);                               // 1/7!
+    ps = fma_v(ps, w, 1.0 / 120.0);                                // 1/5!
+    ps = fma_v(ps, w, 1.0 / 6.0);                                  // 1/3!
+    ps = fma_v(ps, w, 1.0);
     double pc = 1.0 / 20922789888000.0;                          // 1/16!
-    pc = fma(pc, z, -1.0 / 87178291200.0);                       // -1/14!
-    pc = fma(pc, z, 1.0 / 479001600.0);                          // 1/12!
-    pc = fma(pc, z, -1.0 / 3628800.0);                           // -1/10!
-    pc = fma(pc, z, 1.0 / 40320.0);                              // 1/8!
-    pc = fma(pc, z, -1.0 / 720.0);                               // -1/6!
-    pc = fma(pc, z, 1.0 / 24.0);                                 // 1/4!
-    pc = fma(pc, z, -0.5);                                       // -1/2!
-    pc = fma(pc, z, 1.0);
+    pc = fma_v(pc, w, 1.0 / 87178291200.0);                        // 1/14!
+    pc = fma_v(pc, w, 1.0 / 479001600.0);                          // 1/12!
+    pc = fma_v(pc, w, 1.0 / 3628800.0);                            // 1/10!
+    pc = fma_v(pc, w, 1.0 / 40320.0);                              // 1/8!
+    pc = fma_v(pc, w, 1.0 / 720.0);                                // 1/6!
+    pc = fma_v(pc, w, 1.0 / 24.0);                                 // 1/4!
+    pc = fma_v(pc, w, 0.5);                                        // 1/2!
+    pc = fma_v(pc, w, 1.0);
     const double s0 = r * ps, c0 = pc;
     const int q = ((int)k) & 3;
     sn = q == 0 ? s0 : (q == 1 ? c0 : (q == 2 ? -s0 : -c0));
     cs = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
+}
+
+// 1/x to about an ulp: the hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
 }
 
 // log2 of a positive normal r: r = 2^e m with m in [sqrt(1/2), sqrt(2)),
@@ -794,17 +815,17 @@ __device__ __forceinline__ double log2_pos(double r)
         m *= 0.5;
         e += 1;
     }
-    const double s = (m - 1.0) / (m + 1.0), z = s * s;
+    const double s = (m - 1.0) * rcp_nr(m + 1.0), z = s * s;
     double p = 1.0 / 19.0;
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
-    p = fma(p, z, 1.0);
+    p = fma_v(p, z, 1.0 / 17.0);
+    p = fma_v(p, z, 1.0 / 15.0);
+    p = fma_v(p, z, 1.0 / 13.0);
+    p = fma_v(p, z, 1.0 / 11.0);
+    p = fma_v(p, z, 1.0 / 9.0);
+    p = fma_v(p, z, 1.0 / 7.0);
+    p = fma_v(p, z, 1.0 / 5.0);
+    p = fma_v(p, z, 1.0 / 3.0);
+    p = fma_v(p, z, 1.0);
     return (double)e + (2.0 * s * p) * 1.4426950408889634074;   // 1/ln 2
 }
 
@@ -816,30 +837,20 @@ __device__ __forceinline__ double exp2_bounded(double y)
     const double n = rint(y);
     const double g = (y - n) * 0.69314718055994530942;           // ln 2
     double p = 1.0 / 6227020800.0;                               // 1/13!
-    p = fma(p, g, 1.0 / 479001600.0);
-    p = fma(p, g, 1.0 / 39916800.0);
-    p = fma(p, g, 1.0 / 3628800.0);
-    p = fma(p, g, 1.0 / 362880.0);
-    p = fma(p, g, 1.0 / 40320.0);
-    p = fma(p, g, 1.0 / 5040.0);
-    p = fma(p, g, 1.0 / 720.0);
-    p = fma(p, g, 1.0 / 120.0);
-    p = fma(p, g, 1.0 / 24.0);
-    p = fma(p, g, 1.0 / 6.0);
-    p = fma(p, g, 0.5);
-    p = fma(p, g, 1.0);
-    p = fma(p, g, 1.0);
+    p = fma_v(p, g, 1.0 / 479001600.0);
+    p = fma_v(p, g, 1.0 / 39916800.0);
+    p = fma_v(p, g, 1.0 / 3628800.0);
+    p = fma_v(p, g, 1.0 / 362880.0);
+    p = fma_v(p, g, 1.0 / 40320.0);
+    p = fma_v(p, g, 1.0 / 5040.0);
+    p = fma_v(p, g, 1.0 / 720.0);
+    p = fma_v(p, g, 1.0 / 120.0);
+    p = fma_v(p, g, 1.0 / 24.0);
+    p = fma_v(p, g, 1.0 / 6.0);
+    p = fma_v(p, g, 0.5);
+    p = fma_v(p, g, 1.0);
+    p = fma_v(p, g, 1.0);
     return p * __longlong_as_double((long long)((unsigned long long)((long long)n + 1023) << 52));
-}
-
-// 1/x to about an ulp: the hardware estimate and two Newton steps
-__device__ __forceinline__ double rcp_nr(double x)
-{
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
 }
 
 template <class T>
@@ -901,6 +912,8 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
     double kce[3];
 #pragma unroll
     for (int m = 0; m < 3; m++) kce[m] = fabs(m + e0) < 1e-14 ? 0.0 : kc / (m + e0);
+    // an integer exponent m + e0 = 0 (s = 0, 1/2 or 1) takes the logarithm
+    const bool logm = fabs(e0) < 1e-14 || fabs(1.0 + e0) < 1e-14 || fabs(2.0 + e0) < 1e-14;
     // The 21 upper entries are formed after the rays, cooperatively: each outer
     // point leaves its weight, six angular moments and six basis offsets in
     // LDS, and lane l < 63 sums entry l % 21 over a third of the points (the
@@ -974,6 +987,17 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
         }
         // angular moments: A0 = sum w J0, A1 = sum w J1 e, A2 = sum w J2 e e^T
         double A0 = 0, A1x = 0, A1y = 0, Axx = 0, Axy = 0, Ayy = 0;
+        // the edges of E_k' seen from x: a ray x + r e leaves the half-plane of
+        // edge a at r = -f0 / f1 (f0: x's offset, f1: e's component along the
+        // edge normal), entering where f1 < 0 and leaving where f1 > 0
+        double enx[3], eny[3], mf0[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const int b = a == 2 ? 0 : a + 1;
+            enx[a] = Vp[2 * b + 1] - Vp[2 * a + 1];
+            eny[a] = -(Vp[2 * b] - Vp[2 * a]);
+            mf0[a] = -(enx[a] * (x[0] - Vp[2 * a]) + eny[a] * (x[1] - Vp[2 * a + 1]));
+        }
         for (int pc = 0; pc < (pact ? npc : 0); pc++)
             for (int it = 0; it < n; it++) {
                 const double u = R->duffy_x[it];
@@ -981,31 +1005,42 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
                 const double wt = (hi[pc] - lo[pc]) * R->duffy_w[it] * 6.0 * u * (1.0 - u);
                 double sn, cs;
                 sincos_bounded(th, sn, cs);
-                double rin = 0.0, rout = 1e300;
+                double rin = 0.0, rout = delta;
                 bool empty = false;
+#pragma unroll
                 for (int a = 0; a < 3; a++) {
-                    const int b = a == 2 ? 0 : a + 1;
-                    const double nx = Vp[2 * b + 1] - Vp[2 * a + 1], ny = -(Vp[2 * b] - Vp[2 * a]);
-                    const double f0 = nx * (x[0] - Vp[2 * a]) + ny * (x[1] - Vp[2 * a + 1]);
-                    const double f1 = nx * cs + ny * sn;
-                    if (f1 > 0.0) rout = fmin(rout, -f0 * rcp_nr(f1));
-                    else if (f1 < 0.0) rin = fmax(rin, -f0 * rcp_nr(f1));
-                    else if (f0 > 0.0) empty = true;
+                    const double f1 = enx[a] * cs + eny[a] * sn;
+                    const double t = mf0[a] * rcp_nr(f1);
+                    rout = f1 > 0.0 ? fmin(rout, t) : rout;
+                    rin = f1 < 0.0 ? fmax(rin, t) : rin;
+                    empty = empty || (!(f1 > 0.0) && !(f1 < 0.0) && mf0[a] < 0.0);
                 }
-                rout = fmin(rout, delta);
                 if (empty || !(rout > rin)) continue;
                 // J_m = kc (rout^(m+e0) - rin^(m+e0)) / (m + e0)
                 double J[3];
                 const double po = exp2_bounded(e0 * log2_pos(rout));
                 const double pi = rin > 0.0 ? exp2_bounded(e0 * log2_pos(rin)) : 0.0;
-                double ro = 1.0, ri = 1.0;
-                for (int m = 0; m < 3; m++) {
-                    const double ex = m + e0;
-                    if (fabs(ex) < 1e-14) J[m] = rin > 0.0 ? kc * log(rout / rin) : 0.0;
-                    else if (rin > 0.0) J[m] = kce[m] * (ro * po - ri * pi);
-                    else J[m] = ex > 0.0 ? kce[m] * ro * po : 0.0;
-                    ro *= rout;
-                    ri *= rin;
+                if (!logm) {
+                    const double r2o = rout * rout, r2i = rin * rin;
+                    if (rin > 0.0) {
+                        J[0] = kce[0] * (po - pi);
+                        J[1] = kce[1] * (rout * po - rin * pi);
+                        J[2] = kce[2] * (r2o * po - r2i * pi);
+                    } else {
+                        J[0] = e0 > 0.0 ? kce[0] * po : 0.0;
+                        J[1] = 1.0 + e0 > 0.0 ? kce[1] * rout * po : 0.0;
+                        J[2] = 2.0 + e0 > 0.0 ? kce[2] * r2o * po : 0.0;
+                    }
+                } else {
+                    double ro = 1.0, ri = 1.0;
+                    for (int m = 0; m < 3; m++) {
+                        const double ex = m + e0;
+                        if (fabs(ex) < 1e-14) J[m] = rin > 0.0 ? kc * log(rout / rin) : 0.0;
+                        else if (rin > 0.0) J[m] = kce[m] * (ro * po - ri * pi);
+                        else J[m] = ex > 0.0 ? kce[m] * ro * po : 0.0;
+                        ro *= rout;
+                        ri *= rin;
+                    }
                 }
                 A0 += wt * J[0];
                 A1x += wt * J[1] * cs;
