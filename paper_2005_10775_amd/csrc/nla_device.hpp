@@ -423,6 +423,16 @@ __device__ __forceinline__ void edge_mom(RegionMom &R, double ax, double ay, dou
 // the fan of the region gives exactly these moments.  Coordinates about
 // vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.  cb: 12
 // doubles of scratch per call.
+// 1/x to about an ulp: the hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 // 1/sqrt(v) to about an ulp: the hardware estimate and two Newton steps (for
 // values that decide nothing: the exact decisions use the rounded sqrt)
 __device__ __forceinline__ double rsqrt_nr(double v)
@@ -585,21 +595,73 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
             nseg += 1 << 16;
             continue;
         }
-        // rotation by phi = span / ncap
-        double cc, ss;
         if (POW2) {
-            // half angles: cos(t/2) = sqrt((1 + cos t)/2), sin(t/2) = sin t / (2 cos(t/2)),
-            // both from one reciprocal square root
-            const double r = rsqrt_nr((ax * ax + ay * ay) * (bx * bx + by * by));
-            cc = dt * r;
-            ss = cr * r;
-            for (int m = ncap; m > 1; m >>= 1) {
+            // The inscribed arc X = P_0, ..., P_ncap = N in closed form: the chord
+            // X N joins the region's polygon, and the closed polygon P_0 ... P_ncap
+            // (the fan of triangles (x, P_j, P_j+1) less the triangle (x, X, N))
+            // adds its area and moments.  In the frame of the span's bisector (u
+            // along it, v across; the v and uv moments vanish by symmetry), with
+            // t the span, phi = t / ncap, alpha_j = -t/2 + j phi and sums over
+            // j = 0..ncap:
+            //   A    = delta^2 (ncap sin phi - sin t) / 2
+            //   I_u  = delta^3 (sin phi (S - cos(t/2)) - sin t cos(t/2)) / 3,
+            //          S = sum cos alpha_j = sin((ncap+1) phi/2) / sin(phi/2)
+            //   I_uu = delta^4 (sin phi (2 C - 2 cos^2(t/2) + ncap cos(phi)/2) + sin t/2 - 3 sin t cos^2(t/2)) / 12
+            //   I_vv = delta^4 (sin phi (2 C' - 2 sin^2(t/2) + ncap cos(phi)/2) - sin t/2 - sin t sin^2(t/2)) / 12
+            //   C, C' = sum cos^2, sin^2 alpha_j = (ncap+1)/2 +- sin((ncap+1) phi) / (2 sin phi)
+            // (fan triangles (0, a, b): area a x b / 2, first moment area (a + b)/3,
+            // second area (a a^T + b b^T + (a b^T + b a^T)/2)/6).  The half span
+            // comes from the chord lengths, |X + N| = 2 delta cos(t/2) and
+            // |X - N| = 2 delta sin(t/2) (accurate at either end of (0, pi)),
+            // the smaller angles by halving: cos(s/2) = sqrt((1 + cos s)/2),
+            // sin(s/2) = sin s / (2 cos(s/2)), both from one reciprocal square
+            // root.  The bisector is X + N, or X - N turned by a right angle
+            // when the span is past a right angle.
+            edge_mom(R, ax - ox, ay - oy, bx - ox, by - oy);
+            const double sx = ax + bx, sy = ay + by, qx = ax - bx, qy = ay - by;
+            const double P = sx * sx + sy * sy, Q = qx * qx + qy * qy;
+            const double rho = rsqrt_nr(P + Q), rP = rsqrt_nr(P), rQ = rsqrt_nr(Q);   // rho = 1 / (2 delta)
+            const double ch = P * rP * rho, sh = Q * rQ * rho;                       // t/2
+            const double st = 2.0 * sh * ch, ct = (ch - sh) * (ch + sh);
+            double cc = ch, ss = sh, cp = ch, sp = sh;
+            for (int lvl = 2; lvl < 2 * ncap; lvl <<= 1) {
                 const double h = 0.5 * (1.0 + cc);
                 const double rh = rsqrt_nr(h);
                 ss = 0.5 * ss * rh;
                 cc = h * rh;
+                if (2 * lvl == ncap) {
+                    cp = cc;                                                        // phi
+                    sp = ss;
+                }
             }
-        } else {
+            const double n = (double)ncap;
+            const double S = (sh * cc + ch * ss) * rcp_nr(ss);                      // (cc, ss): phi/2
+            const double Sc = (st * cp + ct * sp) * rcp_nr(sp);
+            const double C = 0.5 * (n + 1.0) + 0.5 * Sc, Cs = 0.5 * (n + 1.0) - 0.5 * Sc;
+            const double nc = 0.5 * n * cp, ch2 = ch * ch, sh2 = sh * sh;
+            const double A = 0.5 * dd * (n * sp - st);
+            const double iu = dd * (1.0 / 3.0) * (sp * (S - ch) - st * ch);          // I_u / delta
+            const double d4 = dd * dd * (1.0 / 12.0);
+            const double iuu = d4 * (sp * (2.0 * C - 2.0 * ch2 + nc) + 0.5 * st - 3.0 * st * ch2);
+            const double ivv = d4 * (sp * (2.0 * Cs - 2.0 * sh2 + nc) - 0.5 * st - st * sh2);
+            const bool wide = Q > P;
+            const double ux = wide ? -qy * rQ : sx * rP, uy = wide ? qx * rQ : sy * rP;
+            const double dl = 2.0 * rho * dd;                                        // delta
+            const double m1x = iu * ux * dl, m1y = iu * uy * dl;
+            const double m2xx = iuu * ux * ux + ivv * uy * uy, m2yy = iuu * uy * uy + ivv * ux * ux;
+            const double m2xy = (iuu - ivv) * ux * uy;
+            R.c += 2.0 * A;
+            R.mx += 6.0 * (m1x - A * ox);
+            R.my += 6.0 * (m1y - A * oy);
+            R.qxx += 12.0 * (m2xx - 2.0 * m1x * ox + A * ox * ox);
+            R.qyy += 12.0 * (m2yy - 2.0 * m1y * oy + A * oy * oy);
+            R.qxy += 24.0 * (m2xy - m1x * oy - m1y * ox + A * ox * oy);
+            nseg += (1 << 16) + ncap;
+            continue;
+        }
+        // rotation by phi = span / ncap
+        double cc, ss;
+        {
             const double D = atan2(cr, dt);
             sincos(D / (double)ncap, &ss, &cc);
         }

@@ -793,16 +793,6 @@ __device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
     cs = q == 0 ? c0 : (q == 1 ? -s0 : (q == 2 ? -c0 : s0));
 }
 
-// 1/x to about an ulp: the hardware estimate and two Newton steps
-__device__ __forceinline__ double rcp_nr(double x)
-{
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
-}
-
 // log2 of a positive normal r: r = 2^e m with m in [sqrt(1/2), sqrt(2)),
 // ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 0.1716, by its series to
 // s^19 (the first omitted term is below 4e-18 relative)
