@@ -102,9 +102,9 @@ __device__ __forceinline__ void set5(double (&d)[5], double x, double y, double 
 // |p + lambda e|^2 = delta^2 (entry el1 < exit el2; 2 when absent).  Every
 // product and sum is rounded on its own, so that vertices exactly on the circle
 // (uniform grids put many there) are decided as the pair predicate and the
-// oracle decide them.
+// oracle decide them.  iLp: 1 / |e|^2 when the caller has it (else <= 0).
 __device__ __forceinline__ bool edge_roots(double epx, double epy, double eex, double eey, double dd, double &el1,
-                                           double &el2)
+                                           double &el2, double iLp = 0.0)
 {
 #pragma clang fp contract(off)
     const double r2 = epx * epx + epy * epy;
@@ -123,7 +123,7 @@ __device__ __forceinline__ bool edge_roots(double epx, double epy, double eex, d
         const double n1 = -Bq - sq, n2 = -Bq + sq, tiny = L * 0x1p-54;
         const bool in1 = n1 > 0.0 && n1 - L < -tiny, in2 = n2 > 0.0 && n2 - L < -tiny;
         if (in1 || in2) {
-            const double iL = 1.0 / L;
+            const double iL = iLp > 0.0 ? iLp : 1.0 / L;
             if (in1) el1 = n1 * iL;
             if (in2) el2 = n2 * iL;
         }
@@ -422,7 +422,8 @@ __device__ __forceinline__ void edge_mom(RegionMom &R, double ax, double ay, dou
 // psi constant and an inner rule exact for quadratics, the composite rule over
 // the fan of the region gives exactly these moments.  Coordinates about
 // vertex 0 of E'.  nseg counts boundary segments, plus 2^16 per cap.  cb: 12
-// doubles of scratch per call.
+// doubles of scratch per call.  iLv: the reciprocal squared lengths of the
+// edges v0->v1, v1->v2, v2->v0 when the caller has them.
 // 1/x to about an ulp: the hardware estimate and two Newton steps
 __device__ __forceinline__ double rcp_nr(double x)
 {
@@ -506,7 +507,7 @@ __device__ __attribute__((noinline)) RegionMom analytic_cap(double ax, double ay
 
 template <bool POW2, bool CEN = false>
 __device__ void partial_boundary(double xx, double xy, const double *Vl, double dd, int ncap, RegionMom &R, int &nseg,
-                                 double *cb, int centroid_rt = 0, double delta = 0.0)
+                                 double *cb, int centroid_rt = 0, double delta = 0.0, const double *iLv = nullptr)
 {
     // CEN: the instantiation that can take exact caps (centroid_rt selects them at run
     // time: 1 the one-point centroid rule, 2 closed-form segment moments)
@@ -550,7 +551,7 @@ __device__ void partial_boundary(double xx, double xy, const double *Vl, double 
         const double epx = Vl[2 * a] - xx, epy = Vl[2 * a + 1] - xy;
         const double eex = Vl[2 * b] - Vl[2 * a], eey = Vl[2 * b + 1] - Vl[2 * a + 1];
         double el1, el2;
-        if (edge_roots(epx, epy, eex, eey, dd, el1, el2)) emit(epx, epy, 0);
+        if (edge_roots(epx, epy, eex, eey, dd, el1, el2, iLv ? iLv[a] : 0.0)) emit(epx, epy, 0);
         if (el1 < 1.5) emit(epx + el1 * eex, epy + el1 * eey, 1);
         if (el2 < 1.5) emit(epx + el2 * eex, epy + el2 * eey, 2);
     }

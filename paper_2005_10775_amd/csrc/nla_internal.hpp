@@ -63,8 +63,9 @@ struct ElemSoA {
     double *a2;                                // twice the area
     double *r;                                 // max vertex distance from the barycenter
     // the same per element as one 128-byte record (one cache line): v0x, v0y,
-    // v1x, v1y, v2x, v2y, bx, by, a2, r, then padding; kernels that gather an
-    // inner element's data by index read it in five 16-byte loads
+    // v1x, v1y, v2x, v2y, bx, by, a2, r, the reciprocal squared lengths of the
+    // edges v0->v1, v1->v2, v2->v0, then padding; kernels that gather an inner
+    // element's data by index read it in 16-byte loads
     double *pk;                                // [K][16]
 };
 

@@ -245,7 +245,7 @@ __device__ __forceinline__ void deep_row_block(double *__restrict__ Rg, const un
 // C_k[c], reduced column by column in pair order (each column owned by one
 // lane per chunk, its running sums kept in this element's block of Rout).
 template <int NQ, bool SYM, bool POW2, bool BND, bool SW>
-__global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
+__global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pairs_const_fp64(const int64_t *__restrict__ pair_ptr,
                                                          const int32_t *__restrict__ pair_kp, ElemSoA E,
                                                          const double *__restrict__ xq, const RuleSet *__restrict__ R,
                                                          double dd, double psi, int ball, int ncap, int centroid,
@@ -430,14 +430,15 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 const int e = queue[i], owner = e >> 8, q = e & 0x0f;
                 const bool rr = SW && (e & 0x80);
                 const double qx = rr ? sX2[q][0] : sX[q][0], qy = rr ? sX2[q][1] : sX[q][1];
-                double Vo[6];
+                double Vo[6], iLo[3] = {0.0, 0.0, 0.0};
                 if (SW) {
 #pragma unroll
                     for (int i = 0; i < 6; i++) Vo[i] = sV[SW ? owner : 0][i];
                 } else {
                     const double2 *rec = (const double2 *)(E.pk + 16 * (int64_t)skp[owner]);
-                    const double2 r0 = rec[0], r1 = rec[1], r2v = rec[2];
+                    const double2 r0 = rec[0], r1 = rec[1], r2v = rec[2], r5 = rec[5], r6 = rec[6];
                     Vo[0] = r0.x; Vo[1] = r0.y; Vo[2] = r1.x; Vo[3] = r1.y; Vo[4] = r2v.x; Vo[5] = r2v.y;
+                    iLo[0] = r5.x; iLo[1] = r5.y; iLo[2] = r6.x;
                 }
                 Acc A;
                 A.a2 = 0.0;
@@ -449,7 +450,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
                 if (BND) {
                     // the rule is exact for quadratics: the region's moments from its boundary
                     RegionMom Rm = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    partial_boundary<POW2, SW>(qx, qy, Vo, dd, ncap, Rm, ns, &res[lane][0], centroid, delta);
+                    partial_boundary<POW2, SW>(qx, qy, Vo, dd, ncap, Rm, ns, &res[lane][0], centroid, delta,
+                                               SW ? nullptr : iLo);
                     double s0, s1[3], s2[6], g[4];
 #pragma unroll
                     for (int i = 0; i < 4; i++) g[i] = sG[BND ? owner : 0][i];
@@ -480,10 +482,11 @@ __global__ __launch_bounds__(64, 2) void k_pairs_const_fp64(const int64_t *__res
             for (int q = 0; q < NQ; q++) {
                 const bool mine = (pmask >> q) & 1u;
                 const unsigned long long bq = __ballot(mine);
-                const int pos = qbase + __popcll(bq & lt);
+                const int qb = qbase, nqi = __popcll(bq);
+                qbase += nqi;
+                if (qb + nqi <= ib || qb >= ib + 64) continue;      // point q's items lie outside the round
+                const int pos = qb + __popcll(bq & lt);
                 const bool inr = mine && pos >= ib && pos < ib + 64;
-                qbase += __popcll(bq);
-                if (__ballot(inr) == 0ull) continue;
                 if (inr) {
                     const double *r = res[pos - ib];
                     if (r2) m0b[SW ? q : 0] += r[0];

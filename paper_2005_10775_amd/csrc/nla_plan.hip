@@ -312,7 +312,14 @@ __global__ void k_elem(int K, const double *__restrict__ xy, const int32_t *__re
     rec[2] = make_double2(x2, y2);
     rec[3] = make_double2(bx, by);
     rec[4] = make_double2(E.a2[k], r);
-    rec[5] = rec[6] = rec[7] = make_double2(0.0, 0.0);
+    // reciprocal squared edge lengths (v0->v1, v1->v2, v2->v0), rounded as the
+    // pair kernels' edge roots form them
+    const double l0 = (x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0);
+    const double l1 = (x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1);
+    const double l2 = (x0 - x2) * (x0 - x2) + (y0 - y2) * (y0 - y2);
+    rec[5] = make_double2(1.0 / l0, 1.0 / l1);
+    rec[6] = make_double2(1.0 / l2, 0.0);
+    rec[7] = make_double2(0.0, 0.0);
     const int nq = R->n_out;
     for (int q = 0; q < nq; q++) {
         const double l0 = R->out_lam[q][0], l1 = R->out_lam[q][1], l2 = R->out_lam[q][2];
