@@ -115,11 +115,9 @@ struct nla_plan {
     int32_t *proc_p = nullptr;  // [n_pairs] canonical pair index of processing slot i
     int32_t *proc_kp = nullptr; // [n_pairs] k' of processing slot i
     int32_t *nband = nullptr;   // [K] pairs of k before its deep ones
-    int32_t max_deep = 0;       // max_k deep pairs of k (with nband)
     int64_t n_deep = 0;         // deep pairs in all (with nband)
     // launch shape of the FP64 pair kernel, chosen at its first launch
-    size_t pairs_lds = 0;
-    int pairs_tab = -1;         // LDS offset (4-byte units) of the deep area table, 0: none; -1: not chosen
+    size_t pairs_lds = 0;       // dynamic LDS per workgroup (0: not chosen yet)
     // pattern of D
     int64_t nnz = 0;
     int64_t *rowptr = nullptr;

@@ -165,18 +165,16 @@ __device__ __forceinline__ unsigned *init_row_block(unsigned *dyn, double *__res
 
 // The deep pairs' part of the row block: each column's remaining entries
 // (after the band chunks they are all deep) name deep partners k' holding the
-// column's node; the column adds cf_a times the sum of their areas |E_k'|
-// (tab: those areas by deep slot, or null to read them through proc_kp).
+// column's node; the column adds cf_a times the sum of their areas |E_k'|.
 // Four columns per lane at a time: their ends, first four entries and sums
 // so far are loaded together, so the walks share their round trips.
 __device__ __forceinline__ void deep_row_block(double *__restrict__ Rg, const unsigned *cn_l, int nC,
                                                const int32_t *__restrict__ cptr, int cbase,
                                                const uint16_t *__restrict__ colent,
-                                               const int32_t *__restrict__ proc_kp, int64_t p0, int nbr,
-                                               const double *__restrict__ a2, const double *tab,
-                                               const double (&cf)[3], int lane)
+                                               const int32_t *__restrict__ proc_kp, int64_t p0,
+                                               const double *__restrict__ a2, const double (&cf)[3], int lane)
 {
-    auto area = [&](int e) -> double { return tab ? tab[(e >> 2) - nbr] : a2[proc_kp[p0 + (e >> 2)]]; };
+    auto area = [&](int e) -> double { return a2[proc_kp[p0 + (e >> 2)]]; };
     for (int c0 = lane; c0 < nC; c0 += 256) {
         unsigned w[4];
         int cur[4], end[4], e[4][4];
@@ -258,7 +256,7 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
                                                          const int32_t *__restrict__ proc_p,
                                                          const int32_t *__restrict__ proc_kp,
                                                          const int32_t *__restrict__ nband, double *__restrict__ Dk,
-                                                         int dtab_off, unsigned long long *__restrict__ counters)
+                                                         unsigned long long *__restrict__ counters)
 {
     extern __shared__ unsigned dyn[];
     __shared__ double sW[NQ][4];
@@ -330,14 +328,19 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
     // ones are summed after them.
     const bool collapse = SYM && nband != nullptr;
     const int64_t pend = collapse ? p0 + nb : p1;
+    // each chunk's inner-element indices are loaded one chunk ahead, so that a
+    // chunk starts with one round trip to memory (its elements' records)
+    const int32_t *kp_src = proc_kp ? proc_kp : pair_kp;
+    int kp_next = p0 + lane < pend ? kp_src[p0 + lane] : 0;
     for (int64_t base = p0; base < pend; base += 64) {
         const int64_t pi = base + lane;                                   // processing slot
         const bool act = pi < pend;
+        const int kp = kp_next;
+        kp_next = pi + 64 < pend ? kp_src[pi + 64] : 0;
         const int64_t p = (proc_p && act) ? (int64_t)proc_p[pi] : pi;    // the pair's canonical index
         const bool deep = act && pi - p0 >= nb;
         double V[6] = {0, 0, 0, 0, 0, 0};
         double a2p = 0.0, bxp = 0.0, byp = 0.0;
-        const int kp = act ? (proc_kp ? proc_kp[pi] : pair_kp[pi]) : 0;
         if (act && !deep) {
             // the inner element's record in five 16-byte loads
             const double2 *rec = (const double2 *)(E.pk + 16 * (int64_t)kp);
@@ -519,11 +522,9 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
         __syncthreads();
     }
     if (collapse) {
-        // the deep pairs: their areas (kept in an LDS table by deep slot when the
-        // launch gives room for one), and each item counted whole
-        double *tab = (double *)(dyn + dtab_off);
-        // four pairs per lane at a time: their indices, then their areas, then
-        // the sums in the lane's pair order
+        // the deep pairs: their areas, each item counted whole; four pairs per
+        // lane at a time: their indices, then their areas, then the sums in the
+        // lane's pair order
         for (int64_t pi0 = pend + lane; pi0 < p1; pi0 += 256) {
             int kq[4];
 #pragma unroll
@@ -536,12 +537,10 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
                 if (kq[j] < 0) continue;
                 const int64_t pi = pi0 + 64 * j;
                 dsum += av[j];
-                if (dtab_off) tab[pi - pend] = av[j];
                 c_whole += (SW && nq2 > 0 && pair_r2[proc_p[pi]]) ? nq2 : nq;
             }
         }
         __syncthreads();
-        const int nbr = (int)(pend - p0);
 #pragma unroll
         for (int q = 0; q < NQ; q++)
             if (q < nq) m0[q] += dsum * M.wsum;
@@ -554,8 +553,7 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) cf[a] *= -psi * M.m1c;
-        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, nbr, E.a2, dtab_off ? tab : nullptr,
-                       cf, lane);
+        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, E.a2, cf, lane);
     }
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
     // lanes, then lane 0's sum is broadcast
@@ -767,8 +765,7 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
             for (int t = 0; t < 6; t++) mxx[t] += sQ[4 + t] * (dsum * M.wsum);
         }
         const double cf[3] = {-psi * M.m1c * sQ[1], -psi * M.m1c * sQ[2], -psi * M.m1c * sQ[3]};
-        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, (int)(pend - p0), E.a2, nullptr,
-                       cf, lane);
+        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, E.a2, cf, lane);
         double x = dsum;
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
         if (lane == 0) {
@@ -967,21 +964,6 @@ static size_t lds_for_occupancy(const void *fn, size_t need, int wg_per_cu)
     return hi;
 }
 
-// Whether `with` bytes of dynamic LDS give fn as many workgroups per CU (at
-// most cap, when cap > 0) as `plain` bytes do.
-static bool table_fits(const void *fn, size_t plain, size_t with, int cap)
-{
-    int a = 0, b = 0;
-    if (with > 64 * 1024 || hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, fn, 64, plain) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, 64, with) != hipSuccess)
-        return false;
-    if (cap > 0) {
-        a = a < cap ? a : cap;
-        b = b < cap ? b : cap;
-    }
-    return b >= a;
-}
-
 static void nla_mark(nla_plan *P, int i, hipStream_t s)
 {
     if (P->cur_ev) (void)hipEventRecord(P->cur_ev[i], s);
@@ -1025,22 +1007,16 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         const size_t lds = (size_t)P->max_cols * sizeof(unsigned);
         const bool cuts = pr.ball == NLA_BALL_RETRI || pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT;
         const int ncap = cuts ? pr.cap_edges : 0;
-        // the deep pairs' area table follows the cursors in LDS where it costs no occupancy
-        const size_t tab_at = (lds + 7) / 8 * 8;
-        const size_t lds_tab = tab_at + sizeof(double) * (size_t)P->max_deep;
 #define NLA_LAUNCH_PAIRS(NQ, SYM, POW2, BND, SW)                                                                   \
     do {                                                                                                           \
-        if (P->pairs_tab < 0) {                                                                                    \
+        if (P->pairs_lds == 0) {                                                                                   \
             const void *fn = (const void *)k_pairs_const_fp64<NQ, SYM, POW2, BND, SW>;                             \
-            const bool tab =                                                                                       \
-                SYM && P->nband && P->max_deep > 0 && table_fits(fn, lds, lds_tab, NLA_PAIRS_WG_PER_CU);            \
-            P->pairs_lds = lds_for_occupancy(fn, tab ? lds_tab : lds, NLA_PAIRS_WG_PER_CU);                         \
-            P->pairs_tab = tab ? (int)(tab_at / sizeof(unsigned)) : 0;                                             \
+            P->pairs_lds = lds_for_occupancy(fn, lds, NLA_PAIRS_WG_PER_CU);                                        \
         }                                                                                                          \
         k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, P->pairs_lds, s>>>(                                    \
             P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,       \
             pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,            \
-            P->proc_p, P->proc_kp, P->nband, Dk, P->pairs_tab, ctr);                                               \
+            P->proc_p, P->proc_kp, P->nband, Dk, ctr);                                                             \
     } while (0)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
@@ -1053,12 +1029,10 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
             return NLA_E_UNSUPPORTED;
         }
         if (pr.ball == NLA_BALL_SHIFTED || pr.ball == NLA_BALL_BARYSUPPORT) {
-            if (P->pairs_tab < 0) {
+            if (P->pairs_lds == 0)
                 P->pairs_lds = lds_for_occupancy(pow2 ? (const void *)k_pairs_support_fp64<true>
                                                       : (const void *)k_pairs_support_fp64<false>,
                                                  lds, NLA_SUPPORT_WG_PER_CU);
-                P->pairs_tab = 0;
-            }
             if (pow2)
                 k_pairs_support_fp64<true><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,

@@ -1108,10 +1108,7 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         NLA_HIP(hipMemcpyAsync(nb.data(), P->nband, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
         NLA_HIP(hipMemcpyAsync(pp.data(), P->pair_ptr, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, s));
         NLA_HIP(hipStreamSynchronize(s));
-        for (int k = 0; k < K; k++) {
-            P->max_deep = std::max(P->max_deep, (int32_t)(pp[k + 1] - pp[k] - nb[k]));
-            P->n_deep += pp[k + 1] - pp[k] - nb[k];
-        }
+        for (int k = 0; k < K; k++) P->n_deep += pp[k + 1] - pp[k] - nb[k];
     }
     NLA_HIP(hipGetLastError());
     NLA_HIP(hipStreamSynchronize(s));
