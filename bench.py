@@ -525,6 +525,29 @@ def pair_roofline(prob, info, n_pairs, phase):
                     "issues at half of it"}
 
 
+def bench_plan(args):
+    """Wall time of plan creation (pair build, pattern, codes, processing order):
+    the first plan in the process also loads the library's code objects and
+    warms the allocator, the later ones show the steady cost.  A kernel and
+    runtime-call trace of this run splits the time further."""
+    import torch
+    from paper_2005_10775_amd import Plan
+    from workloads import make_config
+    mesh, prob, _ = make_config(args.config)
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        plan = Plan(mesh, prob)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        info = plan.info()
+        plan.close()
+    return {"config": args.config, "plan_first_ms": times[0], "plan_later_ms": times[1:],
+            "n_pairs": info["n_pairs"], "nnz_full": info["nnz_full"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -542,6 +565,8 @@ def main():
     ap.add_argument("--paper-balls", default="", help="paper: comma-separated subset of the balls (default: all)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-MiB device buffer 3 times (reference kernel for HBM counters)")
+    ap.add_argument("--plan-only", action="store_true",
+                    help="time plan creation only: the first plan of the process, then two more of the same mesh")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -554,6 +579,9 @@ def main():
     from workloads import make_config, manufactured
 
     torch.cuda.set_device(0)
+    if args.plan_only:
+        print(json.dumps(bench_plan(args)))
+        return
     if args.config == "c4":
         print(json.dumps(bench_batch(args)))
         return
