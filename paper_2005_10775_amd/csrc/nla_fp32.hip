@@ -749,10 +749,6 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
 // series for the bounded arguments the rule produces: cheaper than the general
 // library forms, accurate to a few units in the last place.
 
-// sin and cos of t, |t| < 8 pi: t = k pi/2 + r with pi/2 in two parts (the
-// first of 33 significant bits, so k times it is exact), |r| <= pi/4 up to
-// rounding; Taylor series of sin r to r^17 and of cos r to r^16 (the first
-// omitted terms are below 1e-19 and 3e-18), then the quadrant k mod 4.
 // a*b + c as one VOP3 fused multiply-add: a Horner step whose constant addend
 // sits in a register then needs no copy of it
 __device__ __forceinline__ double fma_v(double a, double b, double c)
@@ -762,6 +758,10 @@ __device__ __forceinline__ double fma_v(double a, double b, double c)
     return d;
 }
 
+// sin and cos of t, |t| < 8 pi: t = k pi/2 + r with pi/2 in two parts (the
+// first of 33 significant bits, so k times it is exact), |r| <= pi/4 up to
+// rounding; Taylor series of sin r to r^17 and of cos r to r^16 (the first
+// omitted terms are below 1e-19 and 3e-18), then the quadrant k mod 4.
 __device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
 {
     const double k = rint(t * 0.63661977236758134308);          // 2/pi
@@ -770,22 +770,22 @@ __device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
     // shared with the exponential's
     const double w = -(r * r);
     double ps = 1.0 / 355687428096000.0;                         // 1/17!
-    ps = fma_v(ps, w, 1.0 / 1307674368000.0);                      // 1/15!
-    ps = fma_v(ps, w, 1.0 / 6227020800.0);                         // 1/13!
-    ps = fma_v(ps, w, 1.0 / 39916800.0);                           // 1/11!
-    ps = fma_v(ps, w, 1.0 / 362880.0);                             // 1/9!
-    ps = fma_v(ps, w, 1.0 / 5040.0);                               // 1/7!
-    ps = fma_v(ps, w, 1.0 / 120.0);                                // 1/5!
-    ps = fma_v(ps, w, 1.0 / 6.0);                                  // 1/3!
+    ps = fma_v(ps, w, 1.0 / 1307674368000.0);                    // 1/15!
+    ps = fma_v(ps, w, 1.0 / 6227020800.0);                       // 1/13!
+    ps = fma_v(ps, w, 1.0 / 39916800.0);                         // 1/11!
+    ps = fma_v(ps, w, 1.0 / 362880.0);                           // 1/9!
+    ps = fma_v(ps, w, 1.0 / 5040.0);                             // 1/7!
+    ps = fma_v(ps, w, 1.0 / 120.0);                              // 1/5!
+    ps = fma_v(ps, w, 1.0 / 6.0);                                // 1/3!
     ps = fma_v(ps, w, 1.0);
     double pc = 1.0 / 20922789888000.0;                          // 1/16!
-    pc = fma_v(pc, w, 1.0 / 87178291200.0);                        // 1/14!
-    pc = fma_v(pc, w, 1.0 / 479001600.0);                          // 1/12!
-    pc = fma_v(pc, w, 1.0 / 3628800.0);                            // 1/10!
-    pc = fma_v(pc, w, 1.0 / 40320.0);                              // 1/8!
-    pc = fma_v(pc, w, 1.0 / 720.0);                                // 1/6!
-    pc = fma_v(pc, w, 1.0 / 24.0);                                 // 1/4!
-    pc = fma_v(pc, w, 0.5);                                        // 1/2!
+    pc = fma_v(pc, w, 1.0 / 87178291200.0);                      // 1/14!
+    pc = fma_v(pc, w, 1.0 / 479001600.0);                        // 1/12!
+    pc = fma_v(pc, w, 1.0 / 3628800.0);                          // 1/10!
+    pc = fma_v(pc, w, 1.0 / 40320.0);                            // 1/8!
+    pc = fma_v(pc, w, 1.0 / 720.0);                              // 1/6!
+    pc = fma_v(pc, w, 1.0 / 24.0);                               // 1/4!
+    pc = fma_v(pc, w, 0.5);                                      // 1/2!
     pc = fma_v(pc, w, 1.0);
     const double s0 = r * ps, c0 = pc;
     const int q = ((int)k) & 3;
