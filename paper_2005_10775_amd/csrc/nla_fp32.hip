@@ -63,6 +63,7 @@ struct TriF32 {
     bool frac_rt;   // FM == 2: kernel chosen at run time (uniform per instance)
     double ox, oy;  // FRAC: vertex 0 of E' relative to x
     double *mono;   // FRAC: the item's monomial sums [6]
+    const float4 *rl;   // FRAC: the inner rule in LDS, (lambda_0, lambda_1, lambda_2, w kc) per point
     __device__ __forceinline__ void operator()(const double (&t)[3][5]) const
     {
         const bool FRAC = FM == 2 ? frac_rt : FM == 1;
@@ -76,13 +77,14 @@ struct TriF32 {
             double q0 = 0.0, qx = 0.0, qy = 0.0, qxx = 0.0, qxy = 0.0, qyy = 0.0;
             const int n = R->n_in;
             for (int q = 0; q < n; q++) {
-                const float m0 = R->in_lamf[q][0], m1 = R->in_lamf[q][1], m2 = R->in_lamf[q][2];
+                const float4 rq = rl[q];
+                const float m0 = rq.x, m1 = rq.y, m2 = rq.z;
                 const float xi = m0 * tx[0] + m1 * tx[1] + m2 * tx[2];
                 const float eta = m0 * ty[0] + m1 * ty[1] + m2 * ty[2];
                 const float dx = xi + oxf, dy = eta + oyf;
                 const float r2 = dx * dx + dy * dy;
                 // hardware log2 / exp2 (v_log_f32, v_exp_f32): r^(2 ex) = 2^(ex log2 r^2)
-                const float wp = R->in_wf[q] * kc * __builtin_amdgcn_exp2f(ex * __builtin_amdgcn_logf(r2));
+                const float wp = rq.w * __builtin_amdgcn_exp2f(ex * __builtin_amdgcn_logf(r2));
                 const double wd = (double)wp, xd = (double)xi, yd = (double)eta;
                 const double wx = wd * xd, wy = wd * yd;
                 q0 += wd;
@@ -149,6 +151,7 @@ struct PairLDS {
     unsigned short queue[64 * NQ];
     float res[64][10];
     double capbuf[64][12];
+    float4 rule[NLA_MAX_INNER];   // the inner rule of the fractional kernel's point quadrature
     int64_t rbase_l[64];
     unsigned rmsk_l[64];
 };
@@ -205,6 +208,10 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         sX[lane][0] = xq[2 * ((int64_t)k * nq + lane)];
         sX[lane][1] = xq[2 * ((int64_t)k * nq + lane) + 1];
     }
+    // the point rule in LDS (the weight times kc as the point loop forms it),
+    // read there by every subtriangle instead of through global memory
+    if (FRAC && lane < R->n_in)
+        S.rule[lane] = make_float4(R->in_lamf[lane][0], R->in_lamf[lane][1], R->in_lamf[lane][2], R->in_wf[lane] * kc);
     const int64_t coff = col_off[k];
     const int nC = (int)(col_off[k + 1] - coff);
     float *R_s = (float *)dyn;                                // [3][nC] sums
@@ -283,7 +290,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                         AccF A;
                         A.zero();
                         double mono[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                        TriF32<1> tri{R, kc, ex, m1c, o, dm, &A, true, V[0] - xx, V[1] - xy, mono};
+                        TriF32<1> tri{R, kc, ex, m1c, o, dm, &A, true, V[0] - xx, V[1] - xy, mono, S.rule};
                         double t[3][5];
                         set5(t[0], V[0] - xx, V[1] - xy, 1.0, 0.0, 0.0);
                         set5(t[1], V[2] - xx, V[3] - xy, 0.0, 1.0, 0.0);
@@ -368,7 +375,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 AccF A;
                 A.zero();
                 double mono[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC, Vo[0] - sX[q][0], Vo[1] - sX[q][1], mono};
+                TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC, Vo[0] - sX[q][0], Vo[1] - sX[q][1], mono, S.rule};
                 int ns = 0;
                 // routed items: the inscribed polygon only here; the owner adds the
                 // network's cap moments when it collects the result
