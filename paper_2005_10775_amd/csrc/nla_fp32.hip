@@ -918,12 +918,22 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
     // per lane instead of 21 leaves the ray loop room for three waves per SIMD.
     __shared__ double sg[12];                  // basis gradients of the six slots: x, then y
     __shared__ double spt[64][14];             // per point: W, A0, A1x, A1y, Axx, Axy, Ayy, c0[6]
+    // the angular rule's nodes u, weights w and clustering map u^2 (3 - 2u), read
+    // by every ray from LDS (the rule may come through a table of instances)
+    __shared__ double sdu[3][NLA_MAX_DUFFY];
 #pragma unroll
     for (int a = 0; a < 6; a++)
         if (lane == a) {
             sg[a] = gxs[a];
             sg[6 + a] = gys[a];
         }
+    if (lane < n) {
+        const double u = R->duffy_x[lane];
+        sdu[0][lane] = u;
+        sdu[1][lane] = R->duffy_w[lane];
+        sdu[2][lane] = u * u * (3.0 - 2.0 * u);
+    }
+    __syncthreads();
     const int tt = lane % 21, part = lane / 21;
     int ti = 0, tj = 0;
     for (int ii = 0, t = 0; ii < 6; ii++)
@@ -997,9 +1007,9 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
         }
         for (int pc = 0; pc < (pact ? npc : 0); pc++)
             for (int it = 0; it < n; it++) {
-                const double u = R->duffy_x[it];
-                const double th = lo[pc] + (hi[pc] - lo[pc]) * (u * u * (3.0 - 2.0 * u));
-                const double wt = (hi[pc] - lo[pc]) * R->duffy_w[it] * 6.0 * u * (1.0 - u);
+                const double u = sdu[0][it];
+                const double th = lo[pc] + (hi[pc] - lo[pc]) * sdu[2][it];
+                const double wt = (hi[pc] - lo[pc]) * sdu[1][it] * 6.0 * u * (1.0 - u);
                 double sn, cs;
                 sincos_bounded(th, sn, cs);
                 double rin = 0.0, rout = delta;
