@@ -377,9 +377,16 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 double mono[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 TriF32<FM> tri{R, kc, ex, m1c, o, dm, &A, FRAC, Vo[0] - sX[q][0], Vo[1] - sX[q][1], mono, S.rule};
                 int ns = 0;
-                // routed items: the inscribed polygon only here; the owner adds the
-                // network's cap moments when it collects the result
+                // routed items: the inscribed polygon, plus the network's cap moments
+                // m_b (fetched here, so that the load overlaps the walk)
                 const bool routed = LEARN && i >= totE;
+                float mb[3] = {0.f, 0.f, 0.f};
+                if (LEARN && routed) {
+                    int64_t idx = rbase_l[owner] + __popc(rmsk_l[owner] & ((1u << q) - 1u));
+                    idx = idx < 0 ? 0 : (idx < P.n_routed ? idx : P.n_routed - 1);
+#pragma unroll
+                    for (int b = 0; b < 3; b++) mb[b] = fmaxf(P.mlp_y[3 * idx + b], 0.f) * P.mlp_k;
+                }
                 if (!FRAC && P.bnd) {
                     // constant kernel, rule exact for quadratics: moments of the region from its
                     // boundary (FP64 geometry), item sums rounded to FP32
@@ -404,6 +411,21 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
 #pragma unroll
                     for (int t = 0; t < 6; t++) res[lane][4 + t] = A.s2[t].s;
                 }
+                if (LEARN && routed) {
+                    // polygon sums plus the network's cap moments (units of kc delta^2
+                    // scale); second moments by the one-point centroid closure
+                    const float sm = (mb[0] + mb[1]) + mb[2];
+                    res[lane][0] += sm;
+#pragma unroll
+                    for (int b = 0; b < 3; b++) res[lane][1 + b] += mb[b];
+                    if (sm > 0.f) {
+                        const float is = 1.f / sm;
+                        const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                        for (int e = 0; e < 6; e++) res[lane][4 + e] += mb[jj[e]] * mb[ll[e]] * is;
+                    }
+                    c_learn++;
+                }
                 c_sub += ns & 0xffff;
                 c_cap += ns >> 16;
             }
@@ -427,26 +449,6 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                     float r[10];
 #pragma unroll
                     for (int t = 0; t < 10; t++) r[t] = res[pos - ib][t];
-                    if (LEARN && seg == 1) {
-                        // polygon sums plus the network's cap moments m_b (units of kc
-                        // delta^2 scale); second moments by the one-point centroid closure
-                        int64_t idx = rbase_l[lane] + __popc(rmask & ((1u << q) - 1u));
-                        idx = idx < 0 ? 0 : (idx < P.n_routed ? idx : P.n_routed - 1);
-                        float mb[3];
-#pragma unroll
-                        for (int b = 0; b < 3; b++) mb[b] = fmaxf(P.mlp_y[3 * idx + b], 0.f) * P.mlp_k;
-                        const float sm = (mb[0] + mb[1]) + mb[2];
-                        r[0] += sm;
-#pragma unroll
-                        for (int b = 0; b < 3; b++) r[1 + b] += mb[b];
-                        if (sm > 0.f) {
-                            const float is = 1.f / sm;
-                            const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-                            for (int e = 0; e < 6; e++) r[4 + e] += mb[jj[e]] * mb[ll[e]] * is;
-                        }
-                        c_learn++;
-                    }
                     m0[q].add(r[0]);
 #pragma unroll
                     for (int a = 0; a < 3; a++)
