@@ -329,21 +329,12 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
 #pragma unroll
             for (int e = 0; e < 6; e++) ayy[e].add(ws * ka * (o + (jj[e] == ll[e] ? dm : 0.f)));
         }
-        // queue: items with arc-subdivided caps first, then (learned) routed
-        // items, each outer point by outer point (point 0 of every lane in lane
-        // order, then point 1, ...), so that a batch of 64 is uniform and holds
-        // at most a few items of any one lane; a lane's items keep their q order
-        const unsigned emask = pmask & ~rmask;
+        // queue: the partial items outer point by outer point (point 0 of every
+        // lane in lane order, then point 1, ...), so that a batch of 64 holds at
+        // most a few items of any one lane; a lane's items keep their q order.
+        // A routed item (learned caps) carries a flag: it gets the inscribed
+        // polygon and the network's cap moments instead of the arc caps.
         const unsigned long long lt = (1ull << lane) - 1ull;
-        int totE = 0;
-#pragma unroll
-        for (int q = 0; q < NQ; q++) {
-            const bool mine = (emask >> q) & 1u;
-            const unsigned long long bq = __ballot(mine);
-            if (mine) queue[totE + __popcll(bq & lt)] = (unsigned short)((lane << 8) | q);
-            totE += __popcll(bq);
-        }
-        int totR = 0;
         if (LEARN) {
             // the network's outputs follow the routing pass's (pair, q) order
             const int cntR = __popc(rmask);
@@ -356,20 +347,22 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
             rbase_l[lane] = rrun + rp - cntR;
             rmsk_l[lane] = rmask;
             rrun += __shfl(rp, 63, 64);
-#pragma unroll
-            for (int q = 0; q < NQ; q++) {
-                const bool mine = (rmask >> q) & 1u;
-                const unsigned long long bq = __ballot(mine);
-                if (mine) queue[totE + totR + __popcll(bq & lt)] = (unsigned short)((lane << 8) | q);
-                totR += __popcll(bq);
-            }
         }
-        const int total = totE + totR;
+        int total = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            const bool mine = (pmask >> q) & 1u;
+            const unsigned long long bq = __ballot(mine);
+            if (mine)
+                queue[total + __popcll(bq & lt)] =
+                    (unsigned short)((lane << 8) | (((rmask >> q) & 1u) ? 0x80 : 0) | q);
+            total += __popcll(bq);
+        }
         __syncthreads();
         for (int ib = 0; ib < total; ib += 64) {
             const int i = ib + lane;
             if (i < total) {
-                const int e = queue[i], owner = e >> 8, q = e & 0xff;
+                const int e = queue[i], owner = e >> 8, q = e & 0x0f;
                 const int kq = skp[owner];
                 const double Vo[6] = {E.vx0[kq], E.vy0[kq], E.vx1[kq], E.vy1[kq], E.vx2[kq], E.vy2[kq]};
                 AccF A;
@@ -379,7 +372,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 int ns = 0;
                 // routed items: the inscribed polygon, plus the network's cap moments
                 // m_b (fetched here, so that the load overlaps the walk)
-                const bool routed = LEARN && i >= totE;
+                const bool routed = LEARN && (e & 0x80);
                 float mb[3] = {0.f, 0.f, 0.f};
                 if (LEARN && routed) {
                     int64_t idx = rbase_l[owner] + __popc(rmsk_l[owner] & ((1u << q) - 1u));
@@ -430,16 +423,13 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
                 c_cap += ns >> 16;
             }
             __syncthreads();
-            // each lane adds its own items of this batch in queue order: its capped
-            // items, then its routed ones, each in q order; the outer points with
-            // none in the batch are skipped by the whole wave
-#pragma unroll
-            for (int seg = 0; seg < (LEARN ? 2 : 1); seg++) {
-                const unsigned smask = seg == 0 ? emask : rmask;
-                int qbase = seg == 0 ? 0 : totE;
+            // each lane adds its own items of this batch in q order; the outer
+            // points with none in the batch are skipped by the whole wave
+            {
+                int qbase = 0;
 #pragma unroll
                 for (int q = 0; q < NQ; q++) {
-                    const bool mine = (smask >> q) & 1u;
+                    const bool mine = (pmask >> q) & 1u;
                     const unsigned long long bq = __ballot(mine);
                     const int pos = qbase + __popcll(bq & lt);
                     const bool inr = mine && pos >= ib && pos < ib + 64;
