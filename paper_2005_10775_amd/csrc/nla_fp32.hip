@@ -149,12 +149,84 @@ struct PairLDS {
     float sW[NQ][4];
     int skp[64];                // each lane's inner element (phase 2 re-reads its vertices)
     unsigned short queue[64 * NQ];
-    float res[64][10];
+    union {
+        float res[64][10];
+        double dtab[320];       // after the chunks: the deep pairs' areas, when they fit
+    };
     double capbuf[64][12];
     float4 rule[NLA_MAX_INNER];   // the inner rule of the fractional kernel's point quadrature
     int64_t rbase_l[64];
     unsigned rmsk_l[64];
 };
+
+// The deep pairs' part of the FP32 row block: each column's remaining entries
+// (all deep after the chunks) name deep partners k' holding its node; the
+// column adds cf_a times the sum of their areas |E_k'| (compensated, into R_s
+// and R_c).  NC columns per lane at a time, four entries per round trip
+// (colent is padded by four), so the walks share their memory round trips.
+// TAB: the deep pairs' areas are in LDS (dtab, by pair index from nb on), one
+// LDS read per entry instead of two dependent memory loads.
+template <bool TAB, int NC>
+__device__ __forceinline__ void fp32_deep_rows(float *R_s, float *R_c, const unsigned *cn_l, int nC, int cbase,
+                                               const int32_t *__restrict__ cptr, const uint16_t *__restrict__ colent,
+                                               const int32_t *__restrict__ proc_kp, int64_t p0,
+                                               const double *__restrict__ a2, const float (&cf)[3], int lane,
+                                               const double *dtab, int nb)
+{
+    for (int c0 = lane; c0 < nC; c0 += 64 * NC) {
+        unsigned w[NC];
+        int cur[NC], end[NC];
+        double S[NC];
+#pragma unroll
+        for (int j = 0; j < NC; j++) {
+            const int c = c0 + 64 * j;
+            w[j] = c < nC ? cn_l[c] : 0xffff0000u;
+            const bool live = (w[j] >> 16) != 0xffffu;
+            cur[j] = cbase + (int)(w[j] & 0xffffu);
+            end[j] = live ? cptr[c + 1] : cur[j];
+            S[j] = 0.0;
+        }
+        bool more = true;
+        while (more) {
+            int e[NC][4];
+            double av[NC][4];
+#pragma unroll
+            for (int j = 0; j < NC; j++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) e[j][i] = cur[j] < end[j] ? colent[cur[j] + i] : 0;
+#pragma unroll
+            for (int j = 0; j < NC; j++)
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    av[j][i] = cur[j] + i < end[j]
+                                   ? (TAB ? dtab[(e[j][i] >> 2) - nb] : a2[proc_kp[p0 + (e[j][i] >> 2)]])
+                                   : 0.0;
+            more = false;
+#pragma unroll
+            for (int j = 0; j < NC; j++) {
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    if (cur[j] + i < end[j]) S[j] += av[j][i];
+                cur[j] += 4;
+                more = more || cur[j] < end[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NC; j++) {
+            if ((w[j] >> 16) == 0xffffu) continue;
+            const int c = c0 + 64 * j;
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                KahanF r;
+                r.s = R_s[a * nC + c];
+                r.c = R_c[a * nC + c];
+                r.add((float)((double)cf[a] * S[j]));
+                R_s[a * nC + c] = r.s;
+                R_c[a * nC + c] = r.c;
+            }
+        }
+    }
+}
 
 // One wavefront per outer element k, FP32 sums (structure as the FP64 kernel):
 // phase 1 classifies the items of each lane's pair and integrates whole items
@@ -510,10 +582,15 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         // the deep pairs: S0 = wsum |E_k'| at every outer point; -Mxy_ab = -kc m1c
         // AW_a |E_k'| added to each column for the deep partners with its node
         // (its remaining entries); Myy as one factor per element
+        // (their areas are kept in LDS, over res, when they fit)
+        const bool tab = p1 - pend <= 320;
         for (int64_t pi = pend + lane; pi < p1; pi += 64) {
-            dsum += E.a2[P.proc_kp[pi]];
+            const double av = E.a2[P.proc_kp[pi]];
+            dsum += av;
+            if (tab) S.dtab[pi - pend] = av;
             c_whole += nq;
         }
+        __syncthreads();
         const float md = (float)(dsum * R->in_wsum) * kc;
 #pragma unroll
         for (int q = 0; q < NQ; q++)
@@ -525,58 +602,12 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) cf[a] *= -kc * m1c;
-        // four columns per lane at a time, four entries per round trip (colent is
-        // padded by four), so the walks share their memory round trips
-        for (int c0 = lane; c0 < nC; c0 += 256) {
-            unsigned w[4];
-            int cur[4], end[4];
-            double S[4];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const int c = c0 + 64 * j;
-                w[j] = c < nC ? cn_l[c] : 0xffff0000u;
-                const bool live = (w[j] >> 16) != 0xffffu;
-                cur[j] = cbase + (int)(w[j] & 0xffffu);
-                end[j] = live ? colent_ptr[coff + c + 1] : cur[j];
-                S[j] = 0.0;
-            }
-            bool more = true;
-            while (more) {
-                int e[4][4];
-                int kq[4][4];
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-#pragma unroll
-                    for (int i = 0; i < 4; i++) e[j][i] = cur[j] < end[j] ? colent[cur[j] + i] : 0;
-#pragma unroll
-                for (int j = 0; j < 4; j++)
-#pragma unroll
-                    for (int i = 0; i < 4; i++) kq[j][i] = cur[j] + i < end[j] ? P.proc_kp[p0 + (e[j][i] >> 2)] : -1;
-                more = false;
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-#pragma unroll
-                    for (int i = 0; i < 4; i++)
-                        if (kq[j][i] >= 0) S[j] += E.a2[kq[j][i]];
-                    cur[j] += 4;
-                    more = more || cur[j] < end[j];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                if ((w[j] >> 16) == 0xffffu) continue;
-                const int c = c0 + 64 * j;
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    KahanF r;
-                    r.s = R_s[a * nC + c];
-                    r.c = R_c[a * nC + c];
-                    r.add((float)((double)cf[a] * S[j]));
-                    R_s[a * nC + c] = r.s;
-                    R_c[a * nC + c] = r.c;
-                }
-            }
-        }
+        if (tab)
+            fp32_deep_rows<true, 5>(R_s, R_c, cn_l, nC, cbase, colent_ptr + coff, colent, P.proc_kp, p0, E.a2, cf,
+                                    lane, S.dtab, (int)(pend - p0));
+        else
+            fp32_deep_rows<false, 4>(R_s, R_c, cn_l, nC, cbase, colent_ptr + coff, colent, P.proc_kp, p0, E.a2, cf,
+                                     lane, nullptr, 0);
         double x = dsum;
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
         if (lane == 0) {

@@ -166,23 +166,27 @@ __device__ __forceinline__ unsigned *init_row_block(unsigned *dyn, double *__res
 // The deep pairs' part of the row block: each column's remaining entries
 // (after the band chunks they are all deep) name deep partners k' holding the
 // column's node; the column adds cf_a times the sum of their areas |E_k'|.
-// Four columns per lane at a time: their ends, first four entries and sums
-// so far are loaded together, so the walks share their round trips.
+// NC columns per lane at a time: their ends, first four entries and sums so
+// far are loaded together, so the walks share their round trips.  TAB: the
+// deep pairs' areas are in LDS (dtab, by pair index from nb on), so an entry's
+// area costs one LDS read instead of two dependent memory loads.
+template <bool TAB, int NC = 4>
 __device__ __forceinline__ void deep_row_block(double *__restrict__ Rg, const unsigned *cn_l, int nC,
                                                const int32_t *__restrict__ cptr, int cbase,
                                                const uint16_t *__restrict__ colent,
                                                const int32_t *__restrict__ proc_kp, int64_t p0,
-                                               const double *__restrict__ a2, const double (&cf)[3], int lane)
+                                               const double *__restrict__ a2, const double (&cf)[3], int lane,
+                                               const double *dtab = nullptr, int nb = 0)
 {
-    auto area = [&](int e) -> double { return a2[proc_kp[p0 + (e >> 2)]]; };
-    for (int c0 = lane; c0 < nC; c0 += 256) {
-        unsigned w[4];
-        int cur[4], end[4], e[4][4];
-        double r[4][3], S[4];
+    auto area = [&](int e) -> double { return TAB ? dtab[(e >> 2) - nb] : a2[proc_kp[p0 + (e >> 2)]]; };
+    for (int c0 = lane; c0 < nC; c0 += 64 * NC) {
+        unsigned w[NC];
+        int cur[NC], end[NC], e[NC][4];
+        double r[NC][3], S[NC];
 #pragma unroll
-        for (int j = 0; j < 4; j++) w[j] = c0 + 64 * j < nC ? cn_l[c0 + 64 * j] : 0xffff0000u;
+        for (int j = 0; j < NC; j++) w[j] = c0 + 64 * j < nC ? cn_l[c0 + 64 * j] : 0xffff0000u;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < NC; j++) {
             const int c = c0 + 64 * j;
             const bool live = (w[j] >> 16) != 0xffffu;
             cur[j] = cbase + (int)(w[j] & 0x7fffu);
@@ -194,7 +198,7 @@ __device__ __forceinline__ void deep_row_block(double *__restrict__ Rg, const un
             S[j] = 0.0;
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < NC; j++) {
             double av[4];
 #pragma unroll
             for (int i = 0; i < 4; i++) av[i] = cur[j] + i < end[j] ? area(e[j][i]) : 0.0;
@@ -204,7 +208,7 @@ __device__ __forceinline__ void deep_row_block(double *__restrict__ Rg, const un
             cur[j] += 4;
         }
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
+        for (int j = 0; j < NC; j++) {
             // columns with more than four deep entries
             while (cur[j] < end[j]) {
                 int ee[4];
@@ -525,6 +529,9 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
         // the deep pairs: their areas, each item counted whole; four pairs per
         // lane at a time: their indices, then their areas, then the sums in the
         // lane's pair order
+        // (the areas are kept in LDS, in res, free after the chunks, when they fit)
+        double *dtab = &res[0][0];
+        const bool tab = p1 - pend <= 64 * 12;
         for (int64_t pi0 = pend + lane; pi0 < p1; pi0 += 256) {
             int kq[4];
 #pragma unroll
@@ -537,6 +544,7 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
                 if (kq[j] < 0) continue;
                 const int64_t pi = pi0 + 64 * j;
                 dsum += av[j];
+                if (tab) dtab[pi - pend] = av[j];
                 c_whole += (SW && nq2 > 0 && pair_r2[proc_p[pi]]) ? nq2 : nq;
             }
         }
@@ -553,7 +561,11 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
         }
 #pragma unroll
         for (int a = 0; a < 3; a++) cf[a] *= -psi * M.m1c;
-        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, E.a2, cf, lane);
+        if (tab)
+            deep_row_block<true, 5>(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, E.a2, cf, lane,
+                                    dtab, (int)nb);
+        else
+            deep_row_block<false>(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, E.a2, cf, lane);
     }
     // Mxx(k) = sum_q W_q alpha alpha^T psi sum_k' S0: a fixed butterfly over the
     // lanes, then lane 0's sum is broadcast
@@ -765,7 +777,7 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
             for (int t = 0; t < 6; t++) mxx[t] += sQ[4 + t] * (dsum * M.wsum);
         }
         const double cf[3] = {-psi * M.m1c * sQ[1], -psi * M.m1c * sQ[2], -psi * M.m1c * sQ[3]};
-        deep_row_block(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, E.a2, cf, lane);
+        deep_row_block<false>(Rg, cn_l, nC, colent_ptr + coff, cbase, colent, proc_kp, p0, E.a2, cf, lane);
         double x = dsum;
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
         if (lane == 0) {
