@@ -50,9 +50,12 @@ struct AccF {
 // vertices).  FRAC: psi = kc r^(2*ex) evaluated at every rule point y in FP32
 // (r^2 = |y - x|^2, hardware log2 and exp2); the point's weight times the
 // monomials 1, xi, eta, xi^2, xi eta, eta^2 of its coordinates (xi, eta) about
-// vertex 0 of E' (at (ox, oy) from x) are summed in FP64 into mono, which
-// mono_sums turns into the basis integrals once per item: the basis is affine
-// in (xi, eta), so the same numbers follow with a third of the work per point.
+// vertex 0 of E' (at (ox, oy) from x) are summed over the subtriangle's points
+// in FP32 and added to mono in FP64, which mono_sums turns into the basis
+// integrals once per item: the basis is affine in (xi, eta), so the same
+// numbers follow with a third of the work per point.  A point's coordinates
+// come from its barycentric coordinates 1 and 2 along the subtriangle's edges
+// from vertex 0.
 // Otherwise psi = kc and the rule is applied through its moments (sym form, as
 // in the FP64 kernel).
 template <int FM>
@@ -71,35 +74,35 @@ struct TriF32 {
         const float a2 = (float)a2d;
         const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
         if (FRAC) {
-            const float tx[3] = {(float)(t[0][0] - ox), (float)(t[1][0] - ox), (float)(t[2][0] - ox)};
-            const float ty[3] = {(float)(t[0][1] - oy), (float)(t[1][1] - oy), (float)(t[2][1] - oy)};
+            const float tx0 = (float)(t[0][0] - ox), ty0 = (float)(t[0][1] - oy);
+            const float e1x = (float)(t[1][0] - t[0][0]), e1y = (float)(t[1][1] - t[0][1]);
+            const float e2x = (float)(t[2][0] - t[0][0]), e2y = (float)(t[2][1] - t[0][1]);
             const float oxf = (float)ox, oyf = (float)oy;
-            double q0 = 0.0, qx = 0.0, qy = 0.0, qxx = 0.0, qxy = 0.0, qyy = 0.0;
+            float q0 = 0.f, qx = 0.f, qy = 0.f, qxx = 0.f, qxy = 0.f, qyy = 0.f;
             const int n = R->n_in;
             for (int q = 0; q < n; q++) {
                 const float4 rq = rl[q];
-                const float m0 = rq.x, m1 = rq.y, m2 = rq.z;
-                const float xi = m0 * tx[0] + m1 * tx[1] + m2 * tx[2];
-                const float eta = m0 * ty[0] + m1 * ty[1] + m2 * ty[2];
+                const float m1 = rq.y, m2 = rq.z;
+                const float xi = fmaf(m1, e1x, fmaf(m2, e2x, tx0));
+                const float eta = fmaf(m1, e1y, fmaf(m2, e2y, ty0));
                 const float dx = xi + oxf, dy = eta + oyf;
                 const float r2 = dx * dx + dy * dy;
                 // hardware log2 / exp2 (v_log_f32, v_exp_f32): r^(2 ex) = 2^(ex log2 r^2)
                 const float wp = rq.w * __builtin_amdgcn_exp2f(ex * __builtin_amdgcn_logf(r2));
-                const double wd = (double)wp, xd = (double)xi, yd = (double)eta;
-                const double wx = wd * xd, wy = wd * yd;
-                q0 += wd;
+                const float wx = wp * xi, wy = wp * eta;
+                q0 += wp;
                 qx += wx;
                 qy += wy;
-                qxx += wx * xd;
-                qxy += wx * yd;
-                qyy += wy * yd;
+                qxx += wx * xi;
+                qxy += wx * eta;
+                qyy += wy * eta;
             }
-            mono[0] += a2d * q0;
-            mono[1] += a2d * qx;
-            mono[2] += a2d * qy;
-            mono[3] += a2d * qxx;
-            mono[4] += a2d * qxy;
-            mono[5] += a2d * qyy;
+            mono[0] += a2d * (double)q0;
+            mono[1] += a2d * (double)qx;
+            mono[2] += a2d * (double)qy;
+            mono[3] += a2d * (double)qxx;
+            mono[4] += a2d * (double)qxy;
+            mono[5] += a2d * (double)qyy;
         } else {
             float tb[3][3];
 #pragma unroll
