@@ -780,7 +780,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
 // ---------------------------------------------------------------------------
 // Elementary functions of the singular-pair rule (FP64), each written from its
 // series for the bounded arguments the rule produces: cheaper than the general
-// library forms, accurate to a few units in the last place.
+// library forms, each truncated where its first omitted term falls below about
+// 3e-14 relative, far under the FP32 rounding of the blocks they feed.
 
 // a*b + c as one VOP3 fused multiply-add: a Horner step whose constant addend
 // sits in a register then needs no copy of it
@@ -793,8 +794,8 @@ __device__ __forceinline__ double fma_v(double a, double b, double c)
 
 // sin and cos of t, |t| < 8 pi: t = k pi/2 + r with pi/2 in two parts (the
 // first of 33 significant bits, so k times it is exact), |r| <= pi/4 up to
-// rounding; Taylor series of sin r to r^17 and of cos r to r^16 (the first
-// omitted terms are below 1e-19 and 3e-18), then the quadrant k mod 4.
+// rounding; Taylor series of sin r to r^13 and of cos r to r^14 (the first
+// omitted terms are below 3e-14 and 2e-15), then the quadrant k mod 4.
 __device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
 {
     const double k = rint(t * 0.63661977236758134308);          // 2/pi
@@ -802,17 +803,14 @@ __device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
     // both series in w = -r^2, so that their coefficients 1/k! are positive and
     // shared with the exponential's
     const double w = -(r * r);
-    double ps = 1.0 / 355687428096000.0;                         // 1/17!
-    ps = fma_v(ps, w, 1.0 / 1307674368000.0);                    // 1/15!
-    ps = fma_v(ps, w, 1.0 / 6227020800.0);                       // 1/13!
+    double ps = 1.0 / 6227020800.0;                             // 1/13!
     ps = fma_v(ps, w, 1.0 / 39916800.0);                         // 1/11!
     ps = fma_v(ps, w, 1.0 / 362880.0);                           // 1/9!
     ps = fma_v(ps, w, 1.0 / 5040.0);                             // 1/7!
     ps = fma_v(ps, w, 1.0 / 120.0);                              // 1/5!
     ps = fma_v(ps, w, 1.0 / 6.0);                                // 1/3!
     ps = fma_v(ps, w, 1.0);
-    double pc = 1.0 / 20922789888000.0;                          // 1/16!
-    pc = fma_v(pc, w, 1.0 / 87178291200.0);                      // 1/14!
+    double pc = 1.0 / 87178291200.0;                             // 1/14!
     pc = fma_v(pc, w, 1.0 / 479001600.0);                        // 1/12!
     pc = fma_v(pc, w, 1.0 / 3628800.0);                          // 1/10!
     pc = fma_v(pc, w, 1.0 / 40320.0);                            // 1/8!
@@ -828,7 +826,7 @@ __device__ __forceinline__ void sincos_bounded(double t, double &sn, double &cs)
 
 // log2 of a positive normal r: r = 2^e m with m in [sqrt(1/2), sqrt(2)),
 // ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 0.1716, by its series to
-// s^19 (the first omitted term is below 4e-18 relative)
+// s^15 (the first omitted term is below 4e-14 relative)
 __device__ __forceinline__ double log2_pos(double r)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(r);
@@ -839,9 +837,7 @@ __device__ __forceinline__ double log2_pos(double r)
         e += 1;
     }
     const double s = (m - 1.0) * rcp_nr(m + 1.0), z = s * s;
-    double p = 1.0 / 19.0;
-    p = fma_v(p, z, 1.0 / 17.0);
-    p = fma_v(p, z, 1.0 / 15.0);
+    double p = 1.0 / 15.0;
     p = fma_v(p, z, 1.0 / 13.0);
     p = fma_v(p, z, 1.0 / 11.0);
     p = fma_v(p, z, 1.0 / 9.0);
@@ -853,15 +849,13 @@ __device__ __forceinline__ double log2_pos(double r)
 }
 
 // 2^y for |y| < 1000: y = n + f with |f| <= 1/2, e^(f ln 2) by its Taylor
-// series to degree 13 (the first omitted term is below 5e-18), times 2^n built
+// series to degree 11 (the first omitted term is below 7e-15), times 2^n built
 // from its exponent bits
 __device__ __forceinline__ double exp2_bounded(double y)
 {
     const double n = rint(y);
     const double g = (y - n) * 0.69314718055994530942;           // ln 2
-    double p = 1.0 / 6227020800.0;                               // 1/13!
-    p = fma_v(p, g, 1.0 / 479001600.0);
-    p = fma_v(p, g, 1.0 / 39916800.0);
+    double p = 1.0 / 39916800.0;                                 // 1/11!
     p = fma_v(p, g, 1.0 / 3628800.0);
     p = fma_v(p, g, 1.0 / 362880.0);
     p = fma_v(p, g, 1.0 / 40320.0);
@@ -944,9 +938,11 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
     // per lane instead of 21 leaves the ray loop room for three waves per SIMD.
     __shared__ double sg[12];                  // basis gradients of the six slots: x, then y
     __shared__ double spt[64][14];             // per point: W, A0, A1x, A1y, Axx, Axy, Ayy, c0[6]
-    // the angular rule's nodes u, weights w and clustering map u^2 (3 - 2u), read
-    // by every ray from LDS (the rule may come through a table of instances)
-    __shared__ double sdu[3][NLA_MAX_DUFFY];
+    // the angular rule on [0, 1] mapped by t = u^2 (3 - 2u), which clusters the
+    // nodes at both ends of a piece: per node its weight times dt/du = 6u(1 - u),
+    // then t; read by every ray from LDS (the rule may come through a table of
+    // instances)
+    __shared__ double sdu[2][NLA_MAX_DUFFY];
 #pragma unroll
     for (int a = 0; a < 6; a++)
         if (lane == a) {
@@ -955,9 +951,8 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
         }
     if (lane < n) {
         const double u = R->duffy_x[lane];
-        sdu[0][lane] = u;
-        sdu[1][lane] = R->duffy_w[lane];
-        sdu[2][lane] = u * u * (3.0 - 2.0 * u);
+        sdu[0][lane] = R->duffy_w[lane] * 6.0 * u * (1.0 - u);
+        sdu[1][lane] = u * u * (3.0 - 2.0 * u);
     }
     __syncthreads();
     const int tt = lane % 21, part = lane / 21;
@@ -1033,9 +1028,8 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
         }
         for (int pc = 0; pc < (pact ? npc : 0); pc++)
             for (int it = 0; it < n; it++) {
-                const double u = sdu[0][it];
-                const double th = lo[pc] + (hi[pc] - lo[pc]) * sdu[2][it];
-                const double wt = (hi[pc] - lo[pc]) * sdu[1][it] * 6.0 * u * (1.0 - u);
+                const double th = lo[pc] + (hi[pc] - lo[pc]) * sdu[1][it];
+                const double wt = (hi[pc] - lo[pc]) * sdu[0][it];
                 double sn, cs;
                 sincos_bounded(th, sn, cs);
                 double rin = 0.0, rout = delta;
