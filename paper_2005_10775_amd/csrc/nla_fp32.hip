@@ -848,6 +848,26 @@ __device__ __forceinline__ double log2_pos(double r)
     return (double)e + (2.0 * s * p) * 1.4426950408889634074;   // 1/ln 2
 }
 
+// log2 of a positive normal r through a 64-entry table (built per pair by
+// log2_pos, in LDS): r = 2^e m with m in [1, 2) and c_j the midpoint of m's
+// interval of width 1/64, m = c_j (1 + t) with |t| < 2^-7 (tab[j] = (1/c_j,
+// log2 c_j)), log2(1 + t) by its series to t^5 (the first omitted term is
+// below 6e-14 absolute)
+__device__ __forceinline__ double log2_tab(double r, const double2 *tab)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(r);
+    const int e = (int)((b >> 52) & 0x7ffull) - 1023;
+    const double m = __longlong_as_double((long long)((b & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+    const double2 c = tab[(b >> 46) & 63ull];
+    const double t = fma(m, c.x, -1.0);
+    double p = 0.2;
+    p = fma(p, t, -0.25);
+    p = fma(p, t, 1.0 / 3.0);
+    p = fma(p, t, -0.5);
+    p = fma(p, t, 1.0);
+    return ((double)e + c.y) + (t * p) * 1.4426950408889634074;   // 1/ln 2
+}
+
 // 2^y for |y| < 1000: y = n + f with |f| <= 1/2, e^(f ln 2) by its Taylor
 // series to degree 11 (the first omitted term is below 7e-15), times 2^n built
 // from its exponent bits
@@ -943,6 +963,12 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
     // then t; read by every ray from LDS (the rule may come through a table of
     // instances)
     __shared__ double sdu[2][NLA_MAX_DUFFY];
+    // the radial powers' log2 table (see log2_tab)
+    __shared__ double2 slg[64];
+    {
+        const double cj = 1.0 + (lane + 0.5) * (1.0 / 64.0);
+        slg[lane] = make_double2(1.0 / cj, log2_pos(cj));
+    }
 #pragma unroll
     for (int a = 0; a < 6; a++)
         if (lane == a) {
@@ -1045,8 +1071,8 @@ __device__ __forceinline__ void near_body(const int64_t i, const int64_t *__rest
                 if (empty || !(rout > rin)) continue;
                 // J_m = kc (rout^(m+e0) - rin^(m+e0)) / (m + e0)
                 double J[3];
-                const double po = exp2_bounded(e0 * log2_pos(rout));
-                const double pi = rin > 0.0 ? exp2_bounded(e0 * log2_pos(rin)) : 0.0;
+                const double po = exp2_bounded(e0 * log2_tab(rout, slg));
+                const double pi = rin > 0.0 ? exp2_bounded(e0 * log2_tab(rin, slg)) : 0.0;
                 if (!logm) {
                     const double r2o = rout * rout, r2i = rin * rin;
                     if (rin > 0.0) {
