@@ -734,7 +734,7 @@ __global__ __launch_bounds__(64, (FM == 1 && POW2) ? 3 : 2) void k_pairs_fp32(Pa
 {
     extern __shared__ double dyn[];
     __shared__ PairLDS<NQ> S;
-    pairs_fp32_body<NQ, FM, POW2>(P, blockIdx.x, dyn, S);
+    pairs_fp32_body<NQ, FM, POW2>(P, P.korder[blockIdx.x], dyn, S);
 }
 
 // Persistent form for a batch of instances: a fixed grid of wavefronts takes
@@ -1279,6 +1279,7 @@ PairArgs nla_pair_args(const nla_plan *P)
     A.proc_p = P->proc_p;
     A.proc_kp = P->proc_kp;
     A.nband = P->nband;
+    A.korder = P->korder;
     A.Dk = P->nband ? V + 3 * P->n_cols + 6 * (int64_t)P->K : nullptr;
     A.max_cols = P->max_cols;
     A.counters = P->counters;

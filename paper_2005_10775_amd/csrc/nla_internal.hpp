@@ -115,6 +115,7 @@ struct nla_plan {
     int32_t *proc_p = nullptr;  // [n_pairs] canonical pair index of processing slot i
     int32_t *proc_kp = nullptr; // [n_pairs] k' of processing slot i
     int32_t *nband = nullptr;   // [K] pairs of k before its deep ones
+    int32_t *korder = nullptr;  // [K] launch order of the pair kernels: outer elements by decreasing work
     int64_t n_deep = 0;         // deep pairs in all (with nband)
     // launch shape of the FP64 pair kernel, chosen at its first launch
     size_t pairs_lds = 0;       // dynamic LDS per workgroup (0: not chosen yet)
@@ -231,6 +232,7 @@ struct PairArgs {
     MlpDomain dom;              // the network's training domain, taken at plan creation
     // processing order (constant kernel): band pairs first, deep ones after
     const int32_t *proc_p, *proc_kp, *nband;
+    const int32_t *korder;      // [K] launch order: outer elements by decreasing work
     float *Dk;                  // [K] the deep pairs' Myy factor of each element
 };
 PairArgs nla_pair_args(const nla_plan *P);

@@ -260,7 +260,8 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
                                                          const int32_t *__restrict__ proc_p,
                                                          const int32_t *__restrict__ proc_kp,
                                                          const int32_t *__restrict__ nband, double *__restrict__ Dk,
-                                                         unsigned long long *__restrict__ counters)
+                                                         unsigned long long *__restrict__ counters,
+                                                         const int32_t *__restrict__ korder)
 {
     extern __shared__ unsigned dyn[];
     __shared__ double sW[NQ][4];
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(64, (SYM && POW2 && BND && !SW) ? 3 : 2) void k_pai
     // item results of a phase-2 round, later the chunk's -Mxy (never live together)
     __shared__ double res[64][12];
     double (*mxy_l)[12] = res;
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int k = korder[blockIdx.x], lane = threadIdx.x;
     const int nq = R->n_out;
     const double a2k = E.a2[k];
     if (lane < nq) {
@@ -645,14 +646,15 @@ __global__ __launch_bounds__(64) void k_pairs_support_fp64(const int64_t *__rest
                                                         const int32_t *__restrict__ proc_p,
                                                         const int32_t *__restrict__ proc_kp,
                                                         const int32_t *__restrict__ nband, double *__restrict__ Dk,
-                                                        unsigned long long *__restrict__ counters)
+                                                        unsigned long long *__restrict__ counters,
+                                                        const int32_t *__restrict__ korder)
 {
     extern __shared__ unsigned dyn[];
     __shared__ double sQ[10];           // the outer rule over E_k: sum W, sum W alpha_a, sum W alpha_a alpha_c
     // a lane's cap endpoints, then its pair's -Mxy (entries 0..8), with the fold's
     // list of active columns in entries 9..11 of the first 48 rows
     __shared__ double res[64][12];
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int k = korder[blockIdx.x], lane = threadIdx.x;
     const double a2k = E.a2[k];
     const int jj[6] = {0, 0, 0, 1, 1, 2}, ll[6] = {0, 1, 2, 1, 2, 2};
     if (lane < 10) {
@@ -1028,7 +1030,7 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
         k_pairs_const_fp64<NQ, SYM, POW2, BND, SW><<<K, 64, P->pairs_lds, s>>>(                                    \
             P->pair_ptr, P->pair_kp, P->E, P->xq, P->d_rules, pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,       \
             pr.cap_mode, pr.delta, P->xq2, P->pair_r2, P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,            \
-            P->proc_p, P->proc_kp, P->nband, Dk, ctr);                                                             \
+            P->proc_p, P->proc_kp, P->nband, Dk, ctr, P->korder);                                                  \
     } while (0)
         const bool sym = P->rules.in_sym != 0;
         const bool pow2 = (ncap & (ncap - 1)) == 0;     // 0 (no caps) counts as a power of two
@@ -1049,12 +1051,12 @@ int nla_numeric(nla_plan *P, const double *f_outer, const double *g_node, hipStr
                 k_pairs_support_fp64<true><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                               P->proc_p, P->proc_kp, P->nband, Dk, ctr);
+                                                               P->proc_p, P->proc_kp, P->nband, Dk, ctr, P->korder);
             else
                 k_pairs_support_fp64<false><<<K, 64, P->pairs_lds, s>>>(P->pair_ptr, P->pair_kp, P->E, P->d_rules,
                                                                 pr.delta * pr.delta, pr.kernel_c, pr.ball, ncap,
                                                                 P->col_off, P->colent_ptr, P->colent, V, Cyy, Cxx,
-                                                                P->proc_p, P->proc_kp, P->nband, Dk, ctr);
+                                                                P->proc_p, P->proc_kp, P->nband, Dk, ctr, P->korder);
         } else if (sw && bnd) NLA_LAUNCH_PAIRS(8, true, true, true, true);
         else if (sw) NLA_LAUNCH_PAIRS(8, true, true, false, true);
         else if (P->rules.n_out <= 8 && bnd && pow2) NLA_LAUNCH_PAIRS(8, true, true, true, false);

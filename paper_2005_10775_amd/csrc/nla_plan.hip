@@ -1110,6 +1110,22 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         NLA_HIP(hipStreamSynchronize(s));
         for (int k = 0; k < K; k++) P->n_deep += pp[k + 1] - pp[k] - nb[k];
     }
+    // launch order of the pair kernels: outer elements by decreasing work (their
+    // band pairs when deep pairs are collapsed, else all their pairs; ties by
+    // index), so that the heaviest start first and the light ones fill the end
+    // of the launch instead of a few heavy ones trailing it
+    NLA_TRY(P->arena.get(&P->korder, K > 0 ? K : 1));
+    if (K > 0) {
+        std::vector<int64_t> pp((size_t)K + 1);
+        std::vector<int32_t> nb(P->nband ? (size_t)K : 0), ord((size_t)K);
+        NLA_HIP(hipMemcpyAsync(pp.data(), P->pair_ptr, sizeof(int64_t) * (K + 1), hipMemcpyDeviceToHost, s));
+        if (P->nband) NLA_HIP(hipMemcpyAsync(nb.data(), P->nband, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
+        NLA_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < K; k++) ord[k] = k;
+        auto work = [&](int k) { return P->nband ? (int64_t)nb[k] : pp[k + 1] - pp[k]; };
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
+        NLA_HIP(hipMemcpyAsync(P->korder, ord.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
+    }
     NLA_HIP(hipGetLastError());
     NLA_HIP(hipStreamSynchronize(s));
     return NLA_OK;
