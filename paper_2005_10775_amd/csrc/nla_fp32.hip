@@ -667,7 +667,7 @@ __device__ void pairs_fp32_body(const PairArgs &P, const int k, double *dyn, Pai
 template <int NQ, bool FILL>
 __global__ __launch_bounds__(64) void k_route(PairArgs P, int64_t *__restrict__ count, float *__restrict__ feat)
 {
-    const int k = blockIdx.x, lane = threadIdx.x;
+    const int k = P.korder[blockIdx.x], lane = threadIdx.x;   // heaviest elements first, as the pair kernels
     const int nq = P.R->n_out;
     __shared__ double sX[NQ][2];
     if (lane < nq) {
