@@ -122,10 +122,11 @@ def l2_error(mesh, U, u_exact):
 
 
 def source_digest():
-    """Digest of every source the FP64 pair kernel is compiled from: counters
-    taken on other source are not reported."""
+    """Digest of every source the FP64 pair kernel is compiled from, and of
+    the plan that orders its launch: counters taken on other source are not
+    reported."""
     h = hashlib.sha256()
-    for name in ("nla_numeric.hip", "nla_device.hpp", "nla_internal.hpp"):
+    for name in ("nla_numeric.hip", "nla_device.hpp", "nla_internal.hpp", "nla_plan.hip"):
         with open(os.path.join(ROOT, "paper_2005_10775_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     with open(os.path.join(ROOT, "include", "nlasm.h"), "rb") as f:

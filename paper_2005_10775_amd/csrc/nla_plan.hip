@@ -1111,9 +1111,11 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         for (int k = 0; k < K; k++) P->n_deep += pp[k + 1] - pp[k] - nb[k];
     }
     // launch order of the pair kernels: outer elements by decreasing work (their
-    // band pairs when deep pairs are collapsed, else all their pairs; ties by
-    // index), so that the heaviest start first and the light ones fill the end
-    // of the launch instead of a few heavy ones trailing it
+    // band pairs when deep pairs are collapsed, else all their pairs), so that
+    // the heaviest start first and the light ones fill the end of the launch
+    // instead of a few heavy ones trailing it; the work is counted in groups of
+    // 16 pairs and a group keeps index order, so that neighbouring elements,
+    // which share their partners' records, still run side by side
     NLA_TRY(P->arena.get(&P->korder, K > 0 ? K : 1));
     if (K > 0) {
         std::vector<int64_t> pp((size_t)K + 1);
@@ -1122,7 +1124,7 @@ int nla_build_pairs(nla_plan *P, hipStream_t s)
         if (P->nband) NLA_HIP(hipMemcpyAsync(nb.data(), P->nband, sizeof(int32_t) * K, hipMemcpyDeviceToHost, s));
         NLA_HIP(hipStreamSynchronize(s));
         for (int k = 0; k < K; k++) ord[k] = k;
-        auto work = [&](int k) { return P->nband ? (int64_t)nb[k] : pp[k + 1] - pp[k]; };
+        auto work = [&](int k) { return (P->nband ? (int64_t)nb[k] : pp[k + 1] - pp[k]) >> 4; };
         std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
         NLA_HIP(hipMemcpyAsync(P->korder, ord.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
     }
