@@ -781,7 +781,8 @@ __global__ __launch_bounds__(64, 2) void k_pairs_fp32_persistent(const PairArgs 
 // Elementary functions of the singular-pair rule (FP64), each written from its
 // series for the bounded arguments the rule produces: cheaper than the general
 // library forms, each truncated where its first omitted term falls below about
-// 3e-14 relative, far under the FP32 rounding of the blocks they feed.
+// 1e-13 (relative; absolute for the logarithms, whose values feed exp2), far
+// under the FP32 rounding of the blocks they feed.
 
 // a*b + c as one VOP3 fused multiply-add: a Horner step whose constant addend
 // sits in a register then needs no copy of it
