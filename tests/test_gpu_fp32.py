@@ -76,6 +76,17 @@ def test_fp32_constant_kernel_deep_pairs_jittered(ball, seed):
     _check(mesh, prob, "fp32 const %s h=delta/6" % ball)
 
 
+def test_fp32_constant_kernel_many_deep_pairs():
+    """FP32 constant kernel at delta/h = 10: 320 to about 500 deep pairs per
+    interior element, so that the FP32 deep row-block walk takes both its
+    paths, the areas kept in LDS (up to 320) and read from memory beyond."""
+    h = 1.0 / 30
+    d = 10 * h
+    mesh = structured_mesh(d, h, jitter=0.1, seed=32)
+    prob = Problem(delta=d, kernel_c=constant_kernel_c(d), ball="retri", cap_edges=8, precision="fp32")
+    _check(mesh, prob, "fp32 const retri delta/h=10")
+
+
 @pytest.mark.parametrize("h", [0.05, 0.1])
 def test_fp32_fractional_retri_with_near_pairs(h):
     """delta/h = 4, and delta/h = 2, where the ball cuts vertex-sharing pairs

@@ -75,6 +75,16 @@ def test_c1_barycenter():
     _say("c1 ok: err %.2e, cg %d its, relres %.1e" % (err, its, rel))
 
 
+def test_many_deep_pairs_per_element():
+    """delta/h = 13: up to about 900 deep pairs per outer element, so that the
+    pair kernel's deep row-block walk takes both its paths, the deep pairs'
+    areas kept in LDS (up to 768 of them) and read from memory beyond that."""
+    h = 1.0 / 25
+    d = 13 * h
+    mesh = structured_mesh(d, h, jitter=0.1, seed=31)
+    _full_parity(mesh, _problem(d, "retri", caps=8), name="retri-8 delta/h=13")
+
+
 @pytest.mark.parametrize("caps", [0, 2, 8, 64])
 def test_retri_small(caps):
     """Retriangulated ball, jittered mesh, every cap count (0 = inscribed polygon)."""
